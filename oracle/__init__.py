@@ -1,0 +1,217 @@
+"""ctypes view of the CPU FP64 oracle (oracle/liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline call this to check and time the HIP library.  The product package
+never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+MAX_SLOTS = 21
+TP06_ENDO, TP06_MID, TP06_EPI, CRN, STEWART, PASSIVE = range(6)
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_up = C.POINTER(C.c_uint8)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_model_n_slots.argtypes = [C.c_int]
+        L.orc_model_slot_name.argtypes = [C.c_int, C.c_int]
+        L.orc_model_slot_name.restype = C.c_char_p
+        L.orc_model_init.argtypes = [C.c_int, _dp]
+        L.orc_model_step.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _dp]
+        L.orc_model_step.restype = C.c_double
+        L.orc_create.argtypes = [C.c_int64, _dp, C.c_int64, _ip, _dp, C.c_double,
+                                 C.c_double, _dp, _up, C.c_double, C.c_double,
+                                 C.c_double]
+        L.orc_create.restype = C.c_void_p
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_ionic_scale.argtypes = [C.c_void_p, _dp]
+        L.orc_add_stimulus.argtypes = [C.c_void_p, C.c_int64, _ip, C.c_double,
+                                       C.c_double, C.c_double, C.c_double, C.c_int32]
+        L.orc_set_detection.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_get_step.argtypes = [C.c_void_p]
+        L.orc_get_step.restype = C.c_int64
+        L.orc_set_step.argtypes = [C.c_void_p, C.c_int64]
+        for name in ("orc_get_vm", "orc_get_activation", "orc_get_apd90",
+                     "orc_get_states", "orc_set_states"):
+            getattr(L, name).argtypes = [C.c_void_p, _dp]
+        L.orc_mean_vm.argtypes = [C.c_void_p]
+        L.orc_mean_vm.restype = C.c_double
+        L.orc_geometry.argtypes = [C.c_void_p, _dp, _dp, _ip]
+        for name in ("orc_node_values", "orc_cell_gradients", "orc_apply_diffusion"):
+            getattr(L, name).argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_detect_waveform.argtypes = [_dp, C.c_int64, C.c_double, C.c_double,
+                                          C.c_double, _dp, _dp]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def n_slots(model: int) -> int:
+    return lib().orc_model_n_slots(model)
+
+
+def slot_names(model: int) -> list[str]:
+    return [lib().orc_model_slot_name(model, i).decode() for i in range(n_slots(model))]
+
+
+def model_init(model: int) -> np.ndarray:
+    y = np.zeros(MAX_SLOTS)
+    lib().orc_model_init(model, _d(y))
+    return y[:n_slots(model)].copy()
+
+
+def model_step(model: int, y: np.ndarray, dt: float, istim: float = 0.0,
+               gscale=None) -> float:
+    """Advance one cell one step in place (V not updated); returns I_ion."""
+    buf = np.zeros(MAX_SLOTS)
+    buf[:y.size] = y
+    gs = None if gscale is None else np.ascontiguousarray(gscale, dtype=np.float64)
+    r = lib().orc_model_step(model, _d(buf), dt, istim, None if gs is None else _d(gs))
+    y[:] = buf[:y.size]
+    return r
+
+
+def single_cell(model: int, t_end: float, dt: float, stim_amp: float = -52.0,
+                stim_dur: float = 1.0, stim_t0: float = 0.0, gscale=None):
+    """Single-cell trace (no diffusion): returns (t, V) sampled every step."""
+    y = model_init(model)
+    n = int(round(t_end / dt))
+    n0, nd = int(round(stim_t0 / dt)), int(round(stim_dur / dt))
+    vs = np.empty(n + 1)
+    vs[0] = y[0]
+    for i in range(n):
+        ist = stim_amp if n0 <= i < n0 + nd else 0.0
+        iion = model_step(model, y, dt, ist, gscale)
+        y[0] = y[0] + dt * (-iion - ist)
+        vs[i + 1] = y[0]
+    return np.arange(n + 1) * dt, vs
+
+
+def detect_waveform(v: np.ndarray, dt: float, threshold: float = 0.0,
+                    repol_frac: float = 0.9):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    ta, apd = C.c_double(), C.c_double()
+    lib().orc_detect_waveform(_d(v), v.size, dt, threshold, repol_frac,
+                              C.byref(ta), C.byref(apd))
+    return ta.value, apd.value
+
+
+class Sim:
+    """Oracle tissue simulation of a meshgen.Workload (or explicit arrays)."""
+
+    def __init__(self, w, model=None):
+        self.w = w
+        L = lib()
+        self.nc, self.nn = w.n_tets, w.n_nodes
+        self._xyz = np.ascontiguousarray(w.xyz, dtype=np.float64)
+        self._tets = np.ascontiguousarray(w.tets, dtype=np.int32)
+        self._fib = np.ascontiguousarray(w.fibre, dtype=np.float64)
+        self._model = np.ascontiguousarray(w.model if model is None else model,
+                                           dtype=np.uint8)
+        self._scale = None if w.scale is None else np.ascontiguousarray(w.scale, np.float64)
+        self.h = L.orc_create(self.nn, _d(self._xyz), self.nc,
+                              self._tets.ctypes.data_as(_ip), _d(self._fib),
+                              w.sigma_l, w.sigma_t,
+                              None if self._scale is None else _d(self._scale),
+                              self._model.ctypes.data_as(_up), w.dt, w.chi, w.cm)
+        for st in w.stimuli:
+            if st.domain != 0:
+                continue
+            ids = np.ascontiguousarray(st.ids, dtype=np.int32)
+            L.orc_add_stimulus(self.h, ids.size, ids.ctypes.data_as(_ip), st.t0,
+                               st.dur, st.amp, st.period, st.count)
+        if w.ionic_scale:
+            gs = np.array([w.ionic_scale.get(k, 1.0) for k in ("GKr", "GKs", "GCaL", "GNa")])
+            L.orc_set_ionic_scale(self.h, _d(gs))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def step(self, n: int):
+        lib().orc_step(self.h, int(n))
+
+    @property
+    def step_index(self) -> int:
+        return lib().orc_get_step(self.h)
+
+    def set_step(self, n: int):
+        lib().orc_set_step(self.h, int(n))
+
+    def _vec(self, fn):
+        out = np.empty(self.nc)
+        fn(self.h, _d(out))
+        return out
+
+    def vm(self):
+        return self._vec(lib().orc_get_vm)
+
+    def activation(self):
+        return self._vec(lib().orc_get_activation)
+
+    def apd90(self):
+        return self._vec(lib().orc_get_apd90)
+
+    def mean_vm(self) -> float:
+        return lib().orc_mean_vm(self.h)
+
+    def states(self) -> np.ndarray:
+        out = np.empty((MAX_SLOTS, self.nc))
+        lib().orc_get_states(self.h, _d(out))
+        return out
+
+    def set_states(self, st: np.ndarray):
+        st = np.ascontiguousarray(st, dtype=np.float64)
+        assert st.shape == (MAX_SLOTS, self.nc)
+        lib().orc_set_states(self.h, _d(st))
+
+    def geometry(self):
+        vol = np.empty(self.nc)
+        S = np.empty((self.nc, 4, 3))
+        nbr = np.empty((self.nc, 4), dtype=np.int32)
+        lib().orc_geometry(self.h, _d(vol), _d(S), nbr.ctypes.data_as(_ip))
+        return vol, S, nbr
+
+    def node_values(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.empty(self.nn)
+        lib().orc_node_values(self.h, _d(v), _d(out))
+        return out
+
+    def gradients(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.empty((self.nc, 3))
+        lib().orc_cell_gradients(self.h, _d(v), _d(out))
+        return out
+
+    def apply_diffusion(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.empty(self.nc)
+        lib().orc_apply_diffusion(self.h, _d(v), _d(out))
+        return out
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

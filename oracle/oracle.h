@@ -1,0 +1,90 @@
+/* CPU FP64 oracle of one explicit monodomain time step on tetrahedra.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is a plain, slow, obviously
+ * correct reference that the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark call to check the HIP library.  Nothing on the product
+ * path may link, load or call it.  It shares no code with the HIP library.
+ *
+ * What it computes (Del Corso, Verzicco, Viola, "A fast computational model
+ * for the electrophysiology of the whole human heart"):
+ *   - the cell-centred finite-volume monodomain equation on tetrahedra
+ *     (Sec. 3.2, eqs. electro5 and electro2_3dmono), with the node values,
+ *     face values, Gauss-Green cell gradients, interpolated face gradients
+ *     and the stabilised face gradient of eq. gra2bis;
+ *   - the transversely isotropic fibre tensor M = A diag(m_l, m_t, m_t) A^T
+ *     (Sec. 3.1, eq. tensor);
+ *   - forward Euler for v and the non-gating cell states, Rush-Larsen for the
+ *     gating variables, all right-hand sides at level n (Sec. 3.2);
+ *   - the stimulus of eq. stimulus as an integer step window;
+ *   - activation time (first upward crossing of 0 mV, Sec. 4) and APD90.
+ * Units: mm, ms, mV, mS/mm, 1/mm, uF/mm^2, pA/pF.  All arithmetic is FP64.
+ *
+ * State slots (a per-cell exchange format): slot 0 is V; the cell model's
+ * states follow in the order listed by orc_model_slot_name().
+ */
+#ifndef ORACLE_H
+#define ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_TP06_ENDO = 0, ORC_TP06_MID = 1, ORC_TP06_EPI = 2, ORC_CRN = 3,
+       ORC_STEWART = 4, ORC_PASSIVE = 5 };
+#define ORC_MAX_SLOTS 21
+
+typedef struct orc_sim orc_sim;
+
+/* ------------------------------------------------------------ cell models */
+int         orc_model_n_slots(int model);              /* incl. V          */
+const char *orc_model_slot_name(int model, int slot);
+void        orc_model_init(int model, double *y);      /* standard state   */
+/* One step of a single cell: currents at level n from y, Rush-Larsen gates,
+ * forward-Euler concentrations.  y[0] (V) is read, not written.  gscale
+ * holds the multipliers of G_Kr, G_Ks, G_CaL, G_Na (NULL = 1).
+ * Returns the total ionic current I_ion at level n in pA/pF. */
+double orc_model_step(int model, double *y, double dt, double istim,
+                      const double *gscale);
+
+/* ------------------------------------------------------------- tissue */
+orc_sim *orc_create(int64_t n_nodes, const double *xyz, int64_t n_tets,
+                    const int32_t *tets, const double *fibre, double sigma_l,
+                    double sigma_t, const double *scale, const uint8_t *model,
+                    double dt, double chi, double cm);
+void orc_destroy(orc_sim *s);
+void orc_set_ionic_scale(orc_sim *s, const double gscale[4]);
+int  orc_add_stimulus(orc_sim *s, int64_t n_ids, const int32_t *ids, double t0,
+                      double dur, double amp, double period, int32_t count);
+void orc_set_detection(orc_sim *s, double threshold, double repol_frac);
+void orc_step(orc_sim *s, int64_t n_steps);
+int64_t orc_get_step(const orc_sim *s);
+void orc_get_vm(const orc_sim *s, double *out);
+void orc_get_activation(const orc_sim *s, double *out);   /* NaN = never   */
+void orc_get_apd90(const orc_sim *s, double *out);        /* NaN = undef.  */
+double orc_mean_vm(const orc_sim *s);                     /* int v dV / V  */
+/* states as [ORC_MAX_SLOTS][n_tets]; unused slots are NaN on output */
+void orc_get_states(const orc_sim *s, double *out);
+void orc_set_states(orc_sim *s, const double *in);
+void orc_set_step(orc_sim *s, int64_t step);
+
+/* ---------------------------------------- operator probes (for pinning) */
+/* Per tet: volume, 4 outward area vectors S_j (face opposite local node j),
+ * 4 face neighbours (-1 = boundary face). */
+void orc_geometry(const orc_sim *s, double *vol, double *area_vec,
+                  int32_t *nbr);
+void orc_node_values(const orc_sim *s, const double *v, double *vn);
+void orc_cell_gradients(const orc_sim *s, const double *v, double *g);
+/* L_c = sum_faces A (M_f grad v_f).n / (chi cm V_c), mV/ms */
+void orc_apply_diffusion(const orc_sim *s, const double *v, double *L);
+
+/* Detection on one sampled waveform v[0..n-1] at spacing dt. */
+void orc_detect_waveform(const double *v, int64_t n, double dt,
+                         double threshold, double repol_frac, double *t_act,
+                         double *apd90);
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,548 @@
+/* Tissue part of the FP64 oracle: geometry, the cell-centred finite-volume
+ * diffusion operator, the explicit time step, stimulus and detection.
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * The operator follows Sec. 3.2 of the paper step by step:
+ *   (a) node values v_n: inverse-distance weighted mean of the cells that
+ *       share the node (weights 1/d_k, d_k = node-to-cell-centre distance);
+ *   (b) face values v_f: mean of the three node values of the face;
+ *   (c) cell gradients by Gauss-Green: grad v_c = (1/V_c) sum_j v_fj S_fj n_fj;
+ *   (d) face gradient: alpha-weighted mean of the two cell gradients,
+ *       alpha from the position of the face centroid between the centres;
+ *   (e) the stabilised face gradient of eq. gra2bis, which replaces the
+ *       component along the centre-to-centre unit vector e by the two-point
+ *       difference (v_c' - v_c)/d;
+ *   (f) flux A_f (M_f grad v_f).n_f through every interior face; boundary
+ *       faces carry no flux; the cell balance of eq. electro2_3dmono gives
+ *       dv_c/dt = sum_f flux / (chi Cm V_c) - I_ion - I_stim.
+ * Every loop writes only its own entries and sums in a fixed order, so the
+ * result does not depend on the number of OpenMP threads.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include "oracle.h"
+#include "orc_models.h"
+
+typedef struct {
+    int32_t *ids;
+    int64_t n;
+    int64_t n0, ndur, nper;
+    int32_t count;
+    double amp;
+} orc_stim;
+
+struct orc_sim {
+    int64_t nn, nc;
+    double *xyz;
+    int32_t *tet;
+    double *fib, *scale;
+    uint8_t *model;
+    double sigma_l, sigma_t, dt, chi, cm;
+    /* geometry */
+    double *vol, *cen, *S;      /* S[(c*4+j)*3+k] outward area vector      */
+    int32_t *nbr;               /* nbr[c*4+j], -1 boundary                 */
+    int64_t *inc_off;           /* node -> cells                           */
+    int32_t *inc_cell;
+    double *inc_w;
+    /* state */
+    double *y;                  /* y[c*ORC_MAX_SLOTS + slot]               */
+    double *vn, *g, *L;
+    double *istim;
+    /* detection */
+    uint8_t *status;
+    double *t_act, *v_max, *t_rep, *v_rest;
+    double thr, repol;
+    orc_stim *stims;
+    int n_stims;
+    double gscale[4];
+    int64_t step;
+};
+
+/* ------------------------------------------------------------- models -- */
+int orc_model_n_slots(int model)
+{
+    switch (model) {
+    case ORC_TP06_ENDO: case ORC_TP06_MID: case ORC_TP06_EPI: return 19;
+    case ORC_CRN: return 21;
+    case ORC_STEWART: return 20;
+    case ORC_PASSIVE: return 1;
+    default: return 0;
+    }
+}
+
+const char *orc_model_slot_name(int model, int slot)
+{
+    switch (model) {
+    case ORC_TP06_ENDO: case ORC_TP06_MID: case ORC_TP06_EPI:
+        return orc_tp06_slot_name(slot);
+    case ORC_CRN: return orc_crn_slot_name(slot);
+    case ORC_STEWART: return orc_stewart_slot_name(slot);
+    case ORC_PASSIVE: return slot == 0 ? "V" : NULL;
+    default: return NULL;
+    }
+}
+
+void orc_model_init(int model, double *y)
+{
+    for (int i = 0; i < ORC_MAX_SLOTS; ++i) y[i] = 0.0;
+    switch (model) {
+    case ORC_TP06_ENDO: case ORC_TP06_MID: case ORC_TP06_EPI:
+        orc_tp06_init(y); break;
+    case ORC_CRN: orc_crn_init(y); break;
+    case ORC_STEWART: orc_stewart_init(y); break;
+    default: y[0] = -86.2; break;   /* PASSIVE: any constant works */
+    }
+}
+
+double orc_model_step(int model, double *y, double dt, double istim,
+                      const double *gscale)
+{
+    switch (model) {
+    case ORC_TP06_ENDO: case ORC_TP06_MID: case ORC_TP06_EPI:
+        return orc_tp06_step(model, y, dt, istim, gscale);
+    case ORC_CRN: return orc_crn_step(y, dt, istim, gscale);
+    case ORC_STEWART: return orc_stewart_step(y, dt, istim, gscale);
+    default: return 0.0;
+    }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ----------------------------------------------------------- geometry -- */
+static void sub3(const double *a, const double *b, double *o)
+{
+    o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static double dot3(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+
+static int tet_has_node(const int32_t *t, int32_t n)
+{
+    return t[0] == n || t[1] == n || t[2] == n || t[3] == n;
+}
+
+static void build_geometry(orc_sim *s)
+{
+    const int64_t nc = s->nc, nn = s->nn;
+    /* node -> incident cells (cells listed in increasing id order) */
+    s->inc_off = calloc((size_t)nn + 1, sizeof(int64_t));
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 4; ++k) s->inc_off[s->tet[4 * c + k] + 1]++;
+    for (int64_t n = 0; n < nn; ++n) s->inc_off[n + 1] += s->inc_off[n];
+    s->inc_cell = malloc(sizeof(int32_t) * (size_t)(4 * nc));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)nn);
+    memcpy(fill, s->inc_off, sizeof(int64_t) * (size_t)nn);
+    for (int64_t c = 0; c < nc; ++c)
+        for (int k = 0; k < 4; ++k) s->inc_cell[fill[s->tet[4 * c + k]]++] = (int32_t)c;
+    free(fill);
+
+    s->vol = malloc(sizeof(double) * (size_t)nc);
+    s->cen = malloc(sizeof(double) * (size_t)nc * 3);
+    s->S = malloc(sizeof(double) * (size_t)nc * 12);
+    s->nbr = malloc(sizeof(int32_t) * (size_t)nc * 4);
+
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        const int32_t *t = s->tet + 4 * c;
+        const double *p[4];
+        for (int k = 0; k < 4; ++k) p[k] = s->xyz + 3 * (int64_t)t[k];
+        /* centroid: mean of the four vertices */
+        for (int a = 0; a < 3; ++a)
+            s->cen[3 * c + a] = 0.25 * (p[0][a] + p[1][a] + p[2][a] + p[3][a]);
+        /* volume |det[x1-x0, x2-x0, x3-x0]| / 6 */
+        double e1[3], e2[3], e3[3], cr[3];
+        sub3(p[1], p[0], e1); sub3(p[2], p[0], e2); sub3(p[3], p[0], e3);
+        cr[0] = e2[1] * e3[2] - e2[2] * e3[1];
+        cr[1] = e2[2] * e3[0] - e2[0] * e3[2];
+        cr[2] = e2[0] * e3[1] - e2[1] * e3[0];
+        s->vol[c] = fabs(dot3(e1, cr)) / 6.0;
+        /* faces: face j is the triangle opposite local vertex j */
+        for (int j = 0; j < 4; ++j) {
+            int q[3], m = 0;
+            for (int k = 0; k < 4; ++k) if (k != j) q[m++] = k;
+            double u[3], v[3], A[3], out[3];
+            sub3(p[q[1]], p[q[0]], u);
+            sub3(p[q[2]], p[q[0]], v);
+            A[0] = 0.5 * (u[1] * v[2] - u[2] * v[1]);
+            A[1] = 0.5 * (u[2] * v[0] - u[0] * v[2]);
+            A[2] = 0.5 * (u[0] * v[1] - u[1] * v[0]);
+            /* outward: away from the opposite vertex */
+            sub3(p[q[0]], p[j], out);
+            const double sg = dot3(A, out) > 0.0 ? 1.0 : -1.0;
+            for (int a = 0; a < 3; ++a) s->S[(c * 4 + j) * 3 + a] = sg * A[a];
+            /* neighbour: the other cell holding all three face vertices */
+            int32_t na = t[q[0]], nb = t[q[1]], nd = t[q[2]];
+            int32_t found = -1;
+            for (int64_t i = s->inc_off[na]; i < s->inc_off[na + 1]; ++i) {
+                int32_t k = s->inc_cell[i];
+                if (k == (int32_t)c) continue;
+                const int32_t *tk = s->tet + 4 * (int64_t)k;
+                if (tet_has_node(tk, nb) && tet_has_node(tk, nd)) { found = k; break; }
+            }
+            s->nbr[4 * c + j] = found;
+        }
+    }
+
+    /* inverse-distance node weights */
+    s->inc_w = malloc(sizeof(double) * (size_t)(4 * nc));
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < nn; ++n) {
+        double sum = 0.0;
+        for (int64_t i = s->inc_off[n]; i < s->inc_off[n + 1]; ++i) {
+            double r[3];
+            sub3(s->xyz + 3 * n, s->cen + 3 * (int64_t)s->inc_cell[i], r);
+            s->inc_w[i] = 1.0 / norm3(r);
+            sum += s->inc_w[i];
+        }
+        for (int64_t i = s->inc_off[n]; i < s->inc_off[n + 1]; ++i) s->inc_w[i] /= sum;
+    }
+}
+
+/* conductivity tensor of a cell: scale * (s_t I + (s_l - s_t) f f^T) */
+static void cell_tensor(const orc_sim *s, int64_t c, double M[3][3])
+{
+    const double *f = s->fib + 3 * c;
+    const double sc = s->scale ? s->scale[c] : 1.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            M[a][b] = sc * ((a == b ? s->sigma_t : 0.0) +
+                            (s->sigma_l - s->sigma_t) * f[a] * f[b]);
+}
+
+/* ------------------------------------------------------------ operator -- */
+void orc_node_values(const orc_sim *s, const double *v, double *vn)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < s->nn; ++n) {
+        double acc = 0.0;
+        for (int64_t i = s->inc_off[n]; i < s->inc_off[n + 1]; ++i)
+            acc += s->inc_w[i] * v[s->inc_cell[i]];
+        vn[n] = acc;
+    }
+}
+
+static void gradients_from_nodes(const orc_sim *s, const double *vn, double *g)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < s->nc; ++c) {
+        const int32_t *t = s->tet + 4 * c;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; ++j) {
+            double vf = 0.0;
+            for (int k = 0; k < 4; ++k) if (k != j) vf += vn[t[k]];
+            vf /= 3.0;
+            for (int a = 0; a < 3; ++a) acc[a] += vf * s->S[(c * 4 + j) * 3 + a];
+        }
+        for (int a = 0; a < 3; ++a) g[3 * c + a] = acc[a] / s->vol[c];
+    }
+}
+
+void orc_cell_gradients(const orc_sim *s, const double *v, double *g)
+{
+    double *vn = malloc(sizeof(double) * (size_t)s->nn);
+    orc_node_values(s, v, vn);
+    gradients_from_nodes(s, vn, g);
+    free(vn);
+}
+
+/* the face-flux sum of one cell, divided by chi Cm V_c (mV/ms) */
+static double cell_flux_sum(const orc_sim *s, int64_t c, const double *v,
+                            const double *g)
+{
+    double Mc[3][3];
+    cell_tensor(s, c, Mc);
+    const int32_t *t = s->tet + 4 * c;
+    double total = 0.0;
+    for (int j = 0; j < 4; ++j) {
+        const int32_t c2 = s->nbr[4 * c + j];
+        if (c2 < 0) continue;                      /* no-flux boundary */
+        /* face centroid */
+        double xf[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 4; ++k)
+            if (k != j)
+                for (int a = 0; a < 3; ++a) xf[a] += s->xyz[3 * (int64_t)t[k] + a] / 3.0;
+        const double *x1 = s->cen + 3 * c, *x2 = s->cen + 3 * (int64_t)c2;
+        double r1[3], r2[3], dd[3];
+        sub3(x1, xf, r1); sub3(x2, xf, r2); sub3(x2, x1, dd);
+        const double alpha = norm3(r2) / (norm3(r1) + norm3(r2));
+        const double dist = norm3(dd);
+        double e[3] = {dd[0] / dist, dd[1] / dist, dd[2] / dist};
+        /* interpolated face gradient */
+        double gb[3];
+        for (int a = 0; a < 3; ++a)
+            gb[a] = alpha * g[3 * c + a] + (1.0 - alpha) * g[3 * (int64_t)c2 + a];
+        /* stabilised face gradient (eq. gra2bis) */
+        const double corr = (v[c2] - v[c]) / dist - dot3(gb, e);
+        double gf[3];
+        for (int a = 0; a < 3; ++a) gf[a] = gb[a] + corr * e[a];
+        /* face tensor and flux */
+        double M2[3][3];
+        cell_tensor(s, c2, M2);
+        const double *Sf = s->S + (c * 4 + j) * 3;
+        double flux = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double Mg = 0.0;
+            for (int b = 0; b < 3; ++b)
+                Mg += (alpha * Mc[a][b] + (1.0 - alpha) * M2[a][b]) * gf[b];
+            flux += Mg * Sf[a];
+        }
+        total += flux;
+    }
+    return total / (s->chi * s->cm * s->vol[c]);
+}
+
+void orc_apply_diffusion(const orc_sim *s, const double *v, double *L)
+{
+    double *vn = malloc(sizeof(double) * (size_t)s->nn);
+    double *g = malloc(sizeof(double) * (size_t)s->nc * 3);
+    orc_node_values(s, v, vn);
+    gradients_from_nodes(s, vn, g);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < s->nc; ++c) L[c] = cell_flux_sum(s, c, v, g);
+    free(vn);
+    free(g);
+}
+
+void orc_geometry(const orc_sim *s, double *vol, double *area_vec, int32_t *nbr)
+{
+    if (vol) memcpy(vol, s->vol, sizeof(double) * (size_t)s->nc);
+    if (area_vec) memcpy(area_vec, s->S, sizeof(double) * (size_t)s->nc * 12);
+    if (nbr) memcpy(nbr, s->nbr, sizeof(int32_t) * (size_t)s->nc * 4);
+}
+
+/* ---------------------------------------------------------- lifecycle -- */
+orc_sim *orc_create(int64_t n_nodes, const double *xyz, int64_t n_tets,
+                    const int32_t *tets, const double *fibre, double sigma_l,
+                    double sigma_t, const double *scale, const uint8_t *model,
+                    double dt, double chi, double cm)
+{
+    orc_sim *s = calloc(1, sizeof(orc_sim));
+    s->nn = n_nodes; s->nc = n_tets;
+    s->xyz = malloc(sizeof(double) * (size_t)n_nodes * 3);
+    memcpy(s->xyz, xyz, sizeof(double) * (size_t)n_nodes * 3);
+    s->tet = malloc(sizeof(int32_t) * (size_t)n_tets * 4);
+    memcpy(s->tet, tets, sizeof(int32_t) * (size_t)n_tets * 4);
+    s->fib = malloc(sizeof(double) * (size_t)n_tets * 3);
+    memcpy(s->fib, fibre, sizeof(double) * (size_t)n_tets * 3);
+    if (scale) {
+        s->scale = malloc(sizeof(double) * (size_t)n_tets);
+        memcpy(s->scale, scale, sizeof(double) * (size_t)n_tets);
+    }
+    s->model = malloc((size_t)n_tets);
+    memcpy(s->model, model, (size_t)n_tets);
+    s->sigma_l = sigma_l; s->sigma_t = sigma_t;
+    s->dt = dt; s->chi = chi; s->cm = cm;
+    s->thr = 0.0; s->repol = 0.9;
+    for (int i = 0; i < 4; ++i) s->gscale[i] = 1.0;
+    build_geometry(s);
+
+    s->y = malloc(sizeof(double) * (size_t)n_tets * ORC_MAX_SLOTS);
+    s->vn = malloc(sizeof(double) * (size_t)n_nodes);
+    s->g = malloc(sizeof(double) * (size_t)n_tets * 3);
+    s->L = malloc(sizeof(double) * (size_t)n_tets);
+    s->istim = malloc(sizeof(double) * (size_t)n_tets);
+    s->status = calloc((size_t)n_tets, 1);
+    s->t_act = malloc(sizeof(double) * (size_t)n_tets);
+    s->v_max = malloc(sizeof(double) * (size_t)n_tets);
+    s->t_rep = malloc(sizeof(double) * (size_t)n_tets);
+    s->v_rest = malloc(sizeof(double) * (size_t)n_tets);
+    for (int64_t c = 0; c < n_tets; ++c) {
+        orc_model_init(model[c], s->y + c * ORC_MAX_SLOTS);
+        s->v_rest[c] = s->y[c * ORC_MAX_SLOTS];
+        s->t_act[c] = NAN; s->t_rep[c] = NAN; s->v_max[c] = NAN;
+    }
+    return s;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    free(s->xyz); free(s->tet); free(s->fib); free(s->scale); free(s->model);
+    free(s->vol); free(s->cen); free(s->S); free(s->nbr);
+    free(s->inc_off); free(s->inc_cell); free(s->inc_w);
+    free(s->y); free(s->vn); free(s->g); free(s->L); free(s->istim);
+    free(s->status); free(s->t_act); free(s->v_max); free(s->t_rep);
+    free(s->v_rest);
+    for (int i = 0; i < s->n_stims; ++i) free(s->stims[i].ids);
+    free(s->stims);
+    free(s);
+}
+
+void orc_set_ionic_scale(orc_sim *s, const double gscale[4])
+{
+    for (int i = 0; i < 4; ++i) s->gscale[i] = gscale[i];
+}
+
+void orc_set_detection(orc_sim *s, double threshold, double repol_frac)
+{
+    s->thr = threshold;
+    s->repol = repol_frac;
+}
+
+int orc_add_stimulus(orc_sim *s, int64_t n_ids, const int32_t *ids, double t0,
+                     double dur, double amp, double period, int32_t count)
+{
+    s->stims = realloc(s->stims, sizeof(orc_stim) * (size_t)(s->n_stims + 1));
+    orc_stim *st = &s->stims[s->n_stims++];
+    st->ids = malloc(sizeof(int32_t) * (size_t)(n_ids > 0 ? n_ids : 1));
+    memcpy(st->ids, ids, sizeof(int32_t) * (size_t)n_ids);
+    st->n = n_ids;
+    /* the Heaviside window of eq. stimulus, on whole steps */
+    st->n0 = llround(t0 / s->dt);
+    st->ndur = llround(dur / s->dt);
+    st->nper = period > 0.0 ? llround(period / s->dt) : 0;
+    st->count = count < 1 ? 1 : count;
+    st->amp = amp;
+    return s->n_stims - 1;
+}
+
+static int stim_active(const orc_stim *st, int64_t n)
+{
+    const int64_t k = n - st->n0;
+    if (k < 0) return 0;
+    if (st->nper <= 0) return k < st->ndur;
+    return (k / st->nper) < st->count && (k % st->nper) < st->ndur;
+}
+
+/* ---------------------------------------------------------- time step -- */
+static void one_step(orc_sim *s)
+{
+    const int64_t nc = s->nc, n = s->step;
+    const double dt = s->dt;
+    double *v = malloc(sizeof(double) * (size_t)nc);
+    for (int64_t c = 0; c < nc; ++c) v[c] = s->y[c * ORC_MAX_SLOTS];
+
+    /* stimulus currents at level n */
+    memset(s->istim, 0, sizeof(double) * (size_t)nc);
+    for (int i = 0; i < s->n_stims; ++i) {
+        const orc_stim *st = &s->stims[i];
+        if (!stim_active(st, n)) continue;
+        for (int64_t q = 0; q < st->n; ++q) s->istim[st->ids[q]] += st->amp;
+    }
+
+    /* diffusion at level n */
+    orc_node_values(s, v, s->vn);
+    gradients_from_nodes(s, s->vn, s->g);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) s->L[c] = cell_flux_sum(s, c, v, s->g);
+
+    /* cells: ionic update, v update, detection */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        double *y = s->y + c * ORC_MAX_SLOTS;
+        const double vold = v[c];
+        const double iion = orc_model_step(s->model[c], y, dt, s->istim[c], s->gscale);
+        const double vnew = vold + dt * (s->L[c] - iion - s->istim[c]);
+        y[0] = vnew;
+        /* activation: first upward crossing of the threshold */
+        if (s->status[c] == 0) {
+            if (vold <= s->thr && vnew > s->thr) {
+                s->t_act[c] = ((double)n + (s->thr - vold) / (vnew - vold)) * dt;
+                s->v_max[c] = vnew;
+                s->status[c] = 1;
+            }
+        } else if (s->status[c] == 1) {
+            if (vnew > s->v_max[c]) s->v_max[c] = vnew;
+            const double v90 = s->v_max[c] - s->repol * (s->v_max[c] - s->v_rest[c]);
+            if (vold >= v90 && vnew < v90) {
+                s->t_rep[c] = ((double)n + (vold - v90) / (vold - vnew)) * dt;
+                s->status[c] = 2;
+            }
+        }
+    }
+    free(v);
+    s->step++;
+}
+
+void orc_step(orc_sim *s, int64_t n_steps)
+{
+    for (int64_t i = 0; i < n_steps; ++i) one_step(s);
+}
+
+int64_t orc_get_step(const orc_sim *s) { return s->step; }
+void orc_set_step(orc_sim *s, int64_t step) { s->step = step; }
+
+void orc_get_vm(const orc_sim *s, double *out)
+{
+    for (int64_t c = 0; c < s->nc; ++c) out[c] = s->y[c * ORC_MAX_SLOTS];
+}
+
+void orc_get_activation(const orc_sim *s, double *out)
+{
+    for (int64_t c = 0; c < s->nc; ++c) out[c] = s->status[c] ? s->t_act[c] : NAN;
+}
+
+void orc_get_apd90(const orc_sim *s, double *out)
+{
+    for (int64_t c = 0; c < s->nc; ++c)
+        out[c] = s->status[c] == 2 ? s->t_rep[c] - s->t_act[c] : NAN;
+}
+
+double orc_mean_vm(const orc_sim *s)
+{
+    double num = 0.0, den = 0.0;
+    for (int64_t c = 0; c < s->nc; ++c) {
+        num += s->vol[c] * s->y[c * ORC_MAX_SLOTS];
+        den += s->vol[c];
+    }
+    return num / den;
+}
+
+void orc_get_states(const orc_sim *s, double *out)
+{
+    for (int slot = 0; slot < ORC_MAX_SLOTS; ++slot)
+        for (int64_t c = 0; c < s->nc; ++c)
+            out[slot * s->nc + c] = slot < orc_model_n_slots(s->model[c])
+                                        ? s->y[c * ORC_MAX_SLOTS + slot] : NAN;
+}
+
+void orc_set_states(orc_sim *s, const double *in)
+{
+    for (int slot = 0; slot < ORC_MAX_SLOTS; ++slot)
+        for (int64_t c = 0; c < s->nc; ++c)
+            if (slot < orc_model_n_slots(s->model[c]))
+                s->y[c * ORC_MAX_SLOTS + slot] = in[slot * s->nc + c];
+}
+
+/* ---------------------------------------------------------- detection -- */
+void orc_detect_waveform(const double *v, int64_t n, double dt,
+                         double threshold, double repol_frac, double *t_act,
+                         double *apd90)
+{
+    int status = 0;
+    double ta = NAN, vmax = NAN, tr = NAN;
+    const double vrest = n > 0 ? v[0] : NAN;
+    for (int64_t i = 0; i + 1 < n; ++i) {
+        const double a = v[i], b = v[i + 1];
+        if (status == 0) {
+            if (a <= threshold && b > threshold) {
+                ta = ((double)i + (threshold - a) / (b - a)) * dt;
+                vmax = b;
+                status = 1;
+            }
+        } else if (status == 1) {
+            if (b > vmax) vmax = b;
+            const double v90 = vmax - repol_frac * (vmax - vrest);
+            if (a >= v90 && b < v90) {
+                tr = ((double)i + (a - v90) / (a - b)) * dt;
+                status = 2;
+            }
+        }
+    }
+    *t_act = status ? ta : NAN;
+    *apd90 = status == 2 ? tr - ta : NAN;
+}

@@ -1,0 +1,290 @@
+"""Seeded synthetic workloads for the monodomain step.
+
+This module only *defines inputs*: node coordinates, tetrahedra, fibre
+directions, per-cell model labels, stimulus cell sets and sweep parameters.
+It holds none of the method's arithmetic (no volumes, normals, weights,
+fluxes or ionic currents) so that the CPU oracle and the HIP library can both
+be fed from it without sharing any part of the computation.
+
+Units: mm, ms, mV, mS/mm, 1/mm, uF/mm^2, pA/pF (the cell models' current unit).
+
+Geometry recipe (the paper's Cartesian test boxes, Sec. 4, and its
+tetrahedral cell-centred FV setting, Sec. 3.2): a box of nx*ny*nz hexahedra of
+side h; nodes numbered i-major, id = (i*(ny+1) + j)*(nz+1) + k.  Each hex is
+split into five tetrahedra: a central tetrahedron on the four hex corners of
+even global parity (i+j+k even) and four corner tetrahedra, each cutting off
+one odd-parity corner together with its three edge neighbours.  Because the
+central tetrahedron always uses the globally even corners, every square face
+is cut along the same diagonal from both sides, so the mesh is conforming.
+Tetrahedra are emitted hex by hex (hexes i-major), central one first.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Cell-model labels (same values as the ep_model enum of the C-ABI).
+TP06_ENDO, TP06_MID, TP06_EPI, CRN, STEWART, PASSIVE = 0, 1, 2, 3, 4, 5
+
+# Parameter set of the paper (Sec. 3.1 and the conductivity table of Sec. 5).
+CHI = 140.0          # 1/mm
+CM = 0.01            # uF/mm^2
+SIGMA_L = 0.17       # mS/mm, along the fibre
+SIGMA_T = 0.019      # mS/mm, across the fibre
+
+
+@dataclass
+class Stimulus:
+    """A stimulus on a set of cells: amplitude amp (pA/pF, negative depolarises)
+    applied from t0 for dur ms, optionally repeated every `period` ms `count`
+    times (period 0 = once)."""
+    ids: np.ndarray
+    t0: float
+    dur: float
+    amp: float
+    period: float = 0.0
+    count: int = 1
+    domain: int = 0          # 0 tissue, 1 Purkinje graph
+
+
+@dataclass
+class Workload:
+    name: str
+    xyz: np.ndarray                  # [n_nodes, 3] float64
+    tets: np.ndarray                 # [n_tets, 4] int32
+    fibre: np.ndarray                # [n_tets, 3] float64, unit vectors
+    model: np.ndarray                # [n_tets] uint8
+    sigma_l: float = SIGMA_L
+    sigma_t: float = SIGMA_T
+    scale: np.ndarray | None = None  # [n_tets] conductivity scale or None
+    stimuli: list = field(default_factory=list)
+    dt: float = 0.02
+    n_steps: int = 2500
+    chi: float = CHI
+    cm: float = CM
+    ionic_scale: dict = field(default_factory=dict)  # "GKr","GKs","GCaL","GNa"
+    hex_ijk: np.ndarray | None = None  # [n_tets, 3] hex index of each tet
+    dims: tuple = ()                   # (nx, ny, nz, h)
+
+    @property
+    def n_tets(self) -> int:
+        return int(self.tets.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+
+def slab(nx: int, ny: int, nz: int, h: float):
+    """Box [0, nx h] x [0, ny h] x [0, nz h] of 5-tet-split hexes.
+
+    Returns (xyz [N_n,3] f64, tets [N_c,4] i32, hex_ijk [N_c,3] i32)."""
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1),
+                             np.arange(nz + 1), indexing="ij")
+    xyz = np.stack([ii.ravel() * h, jj.ravel() * h, kk.ravel() * h],
+                   axis=1).astype(np.float64)
+
+    def nid(i, j, k):
+        return (i * (ny + 1) + j) * (nz + 1) + k
+
+    hi, hj, hk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz),
+                             indexing="ij")
+    hi, hj, hk = hi.ravel(), hj.ravel(), hk.ravel()
+    nhex = hi.size
+    # corner ids of every hex, indexed by local (a, b, c)
+    corner = {}
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                corner[(a, b, c)] = nid(hi + a, hj + b, hk + c)
+    hexpar = (hi + hj + hk) & 1
+    tets = np.empty((nhex, 5, 4), dtype=np.int64)
+    # local even corners are globally even when the hex parity is even;
+    # otherwise the local odd corners are the globally even ones.
+    even_local = [(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+    odd_local = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)]
+    for hp in (0, 1):
+        sel = hexpar == hp
+        cen = even_local if hp == 0 else odd_local
+        cut = odd_local if hp == 0 else even_local
+        tets[sel, 0, :] = np.stack([corner[q][sel] for q in cen], axis=1)
+        for t, (a, b, c) in enumerate(cut):
+            nb = [(1 - a, b, c), (a, 1 - b, c), (a, b, 1 - c)]
+            tets[sel, 1 + t, 0] = corner[(a, b, c)][sel]
+            for m, q in enumerate(nb):
+                tets[sel, 1 + t, 1 + m] = corner[q][sel]
+    tets = tets.reshape(-1, 4).astype(np.int32)
+    hex_ijk = np.repeat(np.stack([hi, hj, hk], axis=1), 5, axis=0).astype(np.int32)
+    return xyz, tets, hex_ijk
+
+
+def hex_box_ids(hex_ijk: np.ndarray, lo, hi) -> np.ndarray:
+    """Ids of the tets whose hex index lies in [lo, hi) per axis (None = open)."""
+    sel = np.ones(hex_ijk.shape[0], dtype=bool)
+    for ax in range(3):
+        if lo[ax] is not None:
+            sel &= hex_ijk[:, ax] >= lo[ax]
+        if hi[ax] is not None:
+            sel &= hex_ijk[:, ax] < hi[ax]
+    return np.nonzero(sel)[0].astype(np.int32)
+
+
+def _uniform_fibre(n: int) -> np.ndarray:
+    f = np.zeros((n, 3), dtype=np.float64)
+    f[:, 0] = 1.0
+    return f
+
+
+def config1(n_steps: int = 2500, nx: int = 20, ny: int = 20, nz: int = 4,
+            h: float = 0.5) -> Workload:
+    """10 x 10 x 2 mm ventricular slab at h = 0.5 mm (8,000 tets), all
+    TP06-endocardial cells in the standard initial state, fibres along x,
+    no-flux boundaries, -52 pA/pF for 1 ms on the cells of the hexes with
+    x < 1 mm (800 tets), dt = 0.02 ms, 2,500 steps (50 ms)."""
+    xyz, tets, hijk = slab(nx, ny, nz, h)
+    n = tets.shape[0]
+    nstim = int(round(1.0 / h))
+    stim = Stimulus(ids=hex_box_ids(hijk, (0, None, None), (nstim, None, None)),
+                    t0=0.0, dur=1.0, amp=-52.0)
+    return Workload("slab-10x10x2mm-h0.5-tp06endo", xyz, tets, _uniform_fibre(n),
+                    np.full(n, TP06_ENDO, np.uint8), stimuli=[stim], dt=0.02,
+                    n_steps=n_steps, hex_ijk=hijk, dims=(nx, ny, nz, h))
+
+
+def transmural_fibres_layers(hex_ijk: np.ndarray, nz: int, seed: int,
+                             jitter_deg: float = 5.0):
+    """Fibre field and TP06 layer labels of the rotating-fibre slab.
+
+    Depth d of a tet = (k + 0.5) / nz from the z = 0 (endocardial) face, with
+    k its hex layer.  Fibre angle alpha(d) = -60 deg + 120 deg * d plus a
+    per-cell Gaussian jitter (sigma = jitter_deg, numpy PCG64 stream of
+    `seed`, one draw per cell in cell order); f = (cos a, sin a, 0).
+    Layers: d < 0.3 endo, 0.3 <= d < 0.7 mid, d >= 0.7 epi."""
+    n = hex_ijk.shape[0]
+    d = (hex_ijk[:, 2].astype(np.float64) + 0.5) / nz
+    rng = np.random.default_rng(seed)
+    jit = rng.normal(0.0, jitter_deg, n)
+    a = np.deg2rad(-60.0 + 120.0 * d + jit)
+    fibre = np.stack([np.cos(a), np.sin(a), np.zeros(n)], axis=1)
+    model = np.where(d < 0.3, TP06_ENDO, np.where(d < 0.7, TP06_MID, TP06_EPI))
+    return fibre, model.astype(np.uint8)
+
+
+def config2(n_steps: int = 20000, nx: int = 160, ny: int = 160, nz: int = 40,
+            h: float = 0.25, seed: int = 2) -> Workload:
+    """40 x 40 x 10 mm slab at h = 0.25 mm (5.12M tets), fibres rotating
+    transmurally -60 -> +60 deg with 5 deg Gaussian jitter, TP06 endo/mid/epi
+    layers at 30/40/30 % depth, corner stimulus (hexes inside [0, 1.5]^3 mm,
+    1,080 tets) of -52 pA/pF for 1 ms, dt = 0.02 ms, 20,000 steps (400 ms)."""
+    xyz, tets, hijk = slab(nx, ny, nz, h)
+    fibre, model = transmural_fibres_layers(hijk, nz, seed)
+    m = int(round(1.5 / h))
+    stim = Stimulus(ids=hex_box_ids(hijk, (0, 0, 0), (m, m, m)), t0=0.0,
+                    dur=1.0, amp=-52.0)
+    return Workload(f"slab-40x40x10mm-h{h}-tp06-layers-rotfibre", xyz, tets,
+                    fibre, model, stimuli=[stim], dt=0.02, n_steps=n_steps,
+                    hex_ijk=hijk, dims=(nx, ny, nz, h))
+
+
+def scaled_config2(nx: int, ny: int, nz: int, h: float = 0.25, seed: int = 2,
+                   n_steps: int = 100) -> Workload:
+    """A config-2-style slab of another size (same fibre, layer and corner
+    stimulus recipe), for parity runs the oracle finishes in seconds."""
+    return config2(n_steps=n_steps, nx=nx, ny=ny, nz=nz, h=h, seed=seed)
+
+
+def niederer_box(h: float, dt: float, n_steps: int, lx=20.0, ly=7.0, lz=3.0,
+                 stim_side: float = 1.5) -> Workload:
+    """The paper's convergence box (Sec. 4): 20 x 7 x 3 mm, fibres along the
+    long (x) axis, TP06 (endocardial parameters), stimulus on a corner cube of
+    side 1.5 mm at the origin (-52 pA/pF for 2 ms)."""
+    nx, ny, nz = int(round(lx / h)), int(round(ly / h)), int(round(lz / h))
+    xyz, tets, hijk = slab(nx, ny, nz, h)
+    n = tets.shape[0]
+    m = int(round(stim_side / h))
+    stim = Stimulus(ids=hex_box_ids(hijk, (0, 0, 0), (m, m, m)), t0=0.0,
+                    dur=2.0, amp=-52.0)
+    return Workload(f"box-20x7x3mm-h{h}", xyz, tets, _uniform_fibre(n),
+                    np.full(n, TP06_ENDO, np.uint8), stimuli=[stim], dt=dt,
+                    n_steps=n_steps, hex_ijk=hijk, dims=(nx, ny, nz, h))
+
+
+def cable(n_hex: int, h: float, model: int, sigma: float, dt: float,
+          n_steps: int, width: int = 1) -> Workload:
+    """A thin bar of n_hex x width x width hexes with isotropic conductivity
+    sigma, stimulated on its first 1 mm, for conduction-velocity checks."""
+    xyz, tets, hijk = slab(n_hex, width, width, h)
+    n = tets.shape[0]
+    m = max(1, int(round(1.0 / h)))
+    stim = Stimulus(ids=hex_box_ids(hijk, (0, None, None), (m, None, None)),
+                    t0=0.0, dur=2.0, amp=-52.0 if model != CRN else -40.0)
+    return Workload(f"cable-{model}", xyz, tets, _uniform_fibre(n),
+                    np.full(n, model, np.uint8), sigma_l=sigma, sigma_t=sigma,
+                    stimuli=[stim], dt=dt, n_steps=n_steps, hex_ijk=hijk,
+                    dims=(n_hex, width, width, h))
+
+
+# ---------------------------------------------------------------- sweeps --
+
+def uq_instances(n: int = 1024, seed: int = 5, h: float = 0.5,
+                 nx_range=(20, 80), ny_range=(20, 40), nz: int = 4):
+    """UQ batch recipe: n slabs with nx ~ U{20..80}, ny ~ U{20..40}, nz = 4 at
+    h = 0.5 mm (8k-64k tets), per-instance G_Kr, G_Ks, G_CaL, G_Na scales
+    drawn independently from U[0.7, 1.3].  Returns a list of dicts with
+    nx, ny, nz, h and the four scales (the meshes are built on demand)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        ny = int(rng.integers(ny_range[0], ny_range[1] + 1))
+        sc = rng.uniform(0.7, 1.3, 4)
+        out.append(dict(nx=nx, ny=ny, nz=nz, h=h, GKr=float(sc[0]),
+                        GKs=float(sc[1]), GCaL=float(sc[2]), GNa=float(sc[3])))
+    return out
+
+
+def uq_workload(spec: dict, n_steps: int, dt: float = 0.02) -> Workload:
+    w = config1(n_steps=n_steps, nx=spec["nx"], ny=spec["ny"], nz=spec["nz"],
+                h=spec["h"])
+    w.dt = dt
+    w.name = f"uq-{spec['nx']}x{spec['ny']}x{spec['nz']}"
+    w.ionic_scale = {k: spec[k] for k in ("GKr", "GKs", "GCaL", "GNa")}
+    return w
+
+
+def serving_requests(n: int = 256, seed: int = 4, h: float = 0.5,
+                     n_lo: float = 1e4, n_hi: float = 1e6, nz: int = 4):
+    """Serving recipe: n slab requests, target tet count log-uniform in
+    [n_lo, n_hi], nx = ny = round(sqrt(N / 20)) at nz = 4, conductivity scale
+    U[0.5, 2], stimulus on the cells within 1 mm of one of the six faces
+    (uniform), -52 pA/pF for 1 ms."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nt = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
+        side = max(2, int(round(math.sqrt(nt / (5 * nz)))))
+        out.append(dict(nx=side, ny=side, nz=nz, h=h,
+                        sigma_scale=float(rng.uniform(0.5, 2.0)),
+                        face=int(rng.integers(0, 6))))
+    return out
+
+
+def serving_workload(spec: dict, n_steps: int, dt: float = 0.02) -> Workload:
+    nx, ny, nz, h = spec["nx"], spec["ny"], spec["nz"], spec["h"]
+    xyz, tets, hijk = slab(nx, ny, nz, h)
+    n = tets.shape[0]
+    m = max(1, int(round(1.0 / h)))
+    dims = (nx, ny, nz)
+    ax, side = divmod(spec["face"], 2)
+    lo, hi = [None] * 3, [None] * 3
+    if side == 0:
+        hi[ax] = min(m, dims[ax])
+    else:
+        lo[ax] = max(0, dims[ax] - m)
+    stim = Stimulus(ids=hex_box_ids(hijk, lo, hi), t0=0.0, dur=1.0, amp=-52.0)
+    return Workload(f"req-{nx}x{ny}x{nz}", xyz, tets, _uniform_fibre(n),
+                    np.full(n, TP06_ENDO, np.uint8),
+                    scale=np.full(n, spec["sigma_scale"]), stimuli=[stim],
+                    dt=dt, n_steps=n_steps, hex_ijk=hijk, dims=(nx, ny, nz, h))

@@ -1,0 +1,99 @@
+"""Pins of activation-time / APD90 detection (P13) and of the integer-step
+stimulus window (eq. stimulus) on synthetic inputs with closed-form answers."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2112_12854_amd import meshgen as M
+
+
+def piecewise(knots, dt, t_end):
+    t = np.arange(int(round(t_end / dt)) + 1) * dt
+    kt, kv = zip(*knots)
+    return np.interp(t, kt, kv)
+
+
+@pytest.mark.parametrize("dt", [0.02, 0.1, 0.37])
+def test_activation_and_apd90_closed_form(oracle_lib, dt):
+    # rest -85, linear upstroke to +40 between t=10 and t=12, plateau,
+    # linear repolarisation from +20 at t=200 to -85 at t=300
+    knots = [(0, -85.0), (10, -85.0), (12, 40.0), (150, 20.0), (200, 20.0),
+             (300, -85.0), (500, -85.0)]
+    v = piecewise(knots, dt, 500.0)
+    ta, apd = oracle_lib.detect_waveform(v, dt)
+    # 0 mV crossing on the upstroke (linear, so exact under interpolation)
+    ta_exact = 10 + 2 * 85.0 / 125.0
+    assert abs(ta - ta_exact) < 1e-9
+    # v_max is the largest sample; V90 = vmax - 0.9 (vmax - vrest)
+    vmax = v.max()
+    v90 = vmax - 0.9 * (vmax + 85.0)
+    tr_exact = 200 + 100 * (20.0 - v90) / 105.0
+    assert abs(apd - (tr_exact - ta_exact)) < 1e-9
+
+
+def test_never_activated_is_nan(oracle_lib):
+    v = np.full(1000, -85.0)
+    v[100:200] = -1e-9          # touches but never exceeds 0 mV
+    ta, apd = oracle_lib.detect_waveform(v, 0.02)
+    assert math.isnan(ta) and math.isnan(apd)
+
+
+def test_unrepolarised_apd_is_nan(oracle_lib):
+    v = piecewise([(0, -85), (1, 30), (100, 25)], 0.02, 100.0)
+    ta, apd = oracle_lib.detect_waveform(v, 0.02)
+    assert ta > 0 and math.isnan(apd)
+
+
+def test_first_crossing_only(oracle_lib):
+    v = piecewise([(0, -85), (2, 30), (50, -85), (100, -85), (102, 30),
+                   (150, -85), (200, -85)], 0.02, 200.0)
+    ta, apd = oracle_lib.detect_waveform(v, 0.02)
+    assert abs(ta - 2 * 85 / 115) < 1e-9
+    assert apd < 50
+
+
+def test_tissue_stimulus_window_steps(oracle_lib):
+    """Eq. stimulus as whole steps: a stimulus from t0 for dur ms is on for
+    round(dur/dt) steps starting at step round(t0/dt); with a passive cell
+    and no diffusion partner the voltage change is exactly amp*dt per
+    active step."""
+    xyz, tets, hijk = M.slab(1, 1, 1, 0.5)
+    n = tets.shape[0]
+    f = np.zeros((n, 3)); f[:, 0] = 1
+    dt = 0.02
+    w = M.Workload("win", xyz, tets, f, np.full(n, M.PASSIVE, np.uint8), dt=dt,
+                   stimuli=[M.Stimulus(ids=np.arange(n, dtype=np.int32), t0=0.1,
+                                       dur=0.26, amp=-10.0, period=1.0, count=3)])
+    s = oracle_lib.Sim(w)
+    v0 = s.vm().copy()
+    trace = []
+    for _ in range(300):
+        s.step(1)
+        trace.append(s.vm()[0])
+    dv = -np.diff(np.concatenate([[v0[0]], trace]))
+    # steps 5..17 (0.1/0.02 = 5, round(0.26/0.02) = 13 steps), then +50, +100
+    expect = np.concatenate([np.arange(5, 18), np.arange(55, 68), np.arange(105, 118)])
+    # dv = amp*dt*(-1): active steps raise v by 10*0.02
+    assert np.array_equal(np.nonzero(np.abs(dv - (-0.2)) < 1e-12)[0], expect)
+
+
+def test_thread_count_invariance(oracle_lib):
+    """Each cell sums in a fixed order, so results are bitwise identical for
+    any OpenMP thread count."""
+    import subprocess, sys, os, json
+    code = (
+        "import sys, json; sys.path.insert(0, %r)\n"
+        "import numpy as np, oracle as O\n"
+        "from paper_2112_12854_amd import meshgen as M\n"
+        "w = M.config1(nx=8, ny=6, nz=2)\n"
+        "s = O.Sim(w); s.step(200)\n"
+        "print(json.dumps(s.vm().tolist()))\n") % os.path.dirname(os.path.dirname(
+            os.path.abspath(__file__)))
+    outs = []
+    for nt in ("1", "5"):
+        env = dict(os.environ, OMP_NUM_THREADS=nt)
+        r = subprocess.run([sys.executable, "-c", code], env=env, check=True,
+                           capture_output=True, text=True)
+        outs.append(np.array(json.loads(r.stdout)))
+    assert np.array_equal(outs[0], outs[1])
