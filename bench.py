@@ -1,0 +1,170 @@
+"""Benchmark of the monodomain step on one MI355X.
+
+Workload: the 40 x 40 x 10 mm ventricular slab at h = 0.25 mm (5,120,000
+tets), fibres rotating -60 -> +60 deg through the wall with 5 deg jitter,
+TP06 endo/mid/epi layers, corner stimulus, dt = 0.02 ms (synthetic, seeded).
+A step is the whole explicit step: node gather + fused flux / cell model /
+update / detection kernel (+ the vbar trace every 50 steps).
+
+Prints one JSON line: cell-steps/s of the FP32-mixed path (the `value`),
+the FP64 path beside it, p50/p99 step latency, the roofline of the dominant
+(cell) kernel and the CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_precision(ep, w, prec, steps, warmup, chunk, profile_steps):
+    import torch
+    t0 = time.time()
+    sim = ep.Sim(w, prec=prec, allocator="torch", trace_every=50)
+    log(f"prec={prec}: init {time.time() - t0:.1f}s, footprint {sim.footprint() / 2**30:.2f} GiB")
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    lat = []
+    done = 0
+    t_start = time.perf_counter()
+    while done < steps:
+        k = min(chunk, steps - done)
+        t1 = time.perf_counter()
+        sim.step(k)
+        sim.sync()
+        lat.append((time.perf_counter() - t1) / k)
+        done += k
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    log(f"prec={prec}: {steps} steps in {elapsed:.3f}s")
+    cell_ms, node_ms = sim.profile_steps(profile_steps)
+    node_b, cell_b = sim.algorithmic_bytes()
+    at = sim.activation()
+    res = dict(ms_per_step=1e3 * elapsed / steps,
+               cell_steps_per_s=w.n_tets * steps / elapsed,
+               p50_ms=1e3 * float(np.percentile(lat, 50)),
+               p99_ms=1e3 * float(np.percentile(lat, 99)),
+               cell_kernel_ms=cell_ms, node_kernel_ms=node_ms,
+               cell_bytes=cell_b, node_bytes=node_b,
+               activated=int(np.isfinite(at).sum()))
+    sim.close()
+    return res
+
+
+def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
+    """The oracle (as it stands) on a sub-slab of the same recipe."""
+    import oracle
+    from paper_2112_12854_amd import meshgen
+    w = meshgen.scaled_config2(nx, ny, nz, n_steps=steps)
+    ref = oracle.Sim(w)
+    ref.step(2)
+    t0 = time.perf_counter()
+    ref.step(steps)
+    el = time.perf_counter() - t0
+    return dict(value=w.n_tets * steps / el, unit="cell-steps/s",
+                cores=oracle.num_threads(), kind="oracle",
+                sample=f"{w.n_tets} tets ({nx}x{ny}x{nz} hexes of the same slab recipe, "
+                       f"h=0.25 mm), {steps} FP64 steps after 2 untimed, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--chunk", type=int, default=10)
+    ap.add_argument("--nx", type=int, default=160)
+    ap.add_argument("--ny", type=int, default=160)
+    ap.add_argument("--nz", type=int, default=40)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--only-fp32", action="store_true",
+                    help="FP32-mixed only (short profiling runs)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times "
+                         "(calibrates the HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        x = torch.ones(args.copy_calib * 2**20 // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calib} MiB x 10")
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path of this build is "
+              "a design (instances or mesh partitions per GPU), not an implementation",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2112_12854_amd import ep, meshgen
+    ep.lib()
+    torch.cuda.init()
+    t0 = time.time()
+    w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
+    log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")
+
+    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, 20)
+    f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
+                                                  args.warmup, args.chunk, 20)
+    cpu = None
+    if not (args.no_cpu or args.only_fp32):
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(args.cpu_steps, 80, 80, 40)
+        log(f"cpu baseline {cpu['value']:.3e} cell-steps/s on {cpu['cores']} threads")
+
+    achieved = f32["cell_bytes"] / (f32["cell_kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "cell-steps/s (ionic+FV step) FP32 vs FP64; p50/p99 solve latency",
+        "value": f32["cell_steps_per_s"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64conc",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_tets": w.n_tets, "n_nodes": w.n_nodes,
+                   "dt_ms": w.dt, "cells": "TP06 endo/mid/epi 30/40/30%",
+                   "fibres": "-60..+60 deg transmural + 5 deg jitter"},
+        "latency_ms": {"p50": f32["p50_ms"], "p99": f32["p99_ms"],
+                       "per": f"step (timed in chunks of {args.chunk} steps)"},
+        "fp64": None if f64 is None else {
+            "value": f64["cell_steps_per_s"], "ms_per_step": f64["ms_per_step"],
+            "p50_ms": f64["p50_ms"], "p99_ms": f64["p99_ms"],
+            "cell_kernel_ms": f64["cell_kernel_ms"], "node_kernel_ms": f64["node_kernel_ms"],
+            "cell_kernel_GBps": f64["cell_bytes"] / (f64["cell_kernel_ms"] * 1e-3) / 1e9},
+        "kernels_fp32": {"cell_kernel_ms": f32["cell_kernel_ms"],
+                         "node_kernel_ms": f32["node_kernel_ms"],
+                         "node_kernel_GBps": f32["node_bytes"] / (f32["node_kernel_ms"] * 1e-3) / 1e9},
+        "roofline": {"bound": "hbm", "kernel": "k_cell<float> (fused flux+ionic+update)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

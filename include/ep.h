@@ -1,0 +1,195 @@
+/* ep.h -- C ABI of the MI355X monodomain library (libep.so).
+ *
+ * One explicit monodomain time step of Del Corso, Verzicco & Viola, "A fast
+ * computational model for the electrophysiology of the whole human heart":
+ *   - cell-centred finite volumes on tetrahedra (Sec. 3.2, eqs. electro5 and
+ *     electro2_3dmono): node values by inverse-distance weighting of the
+ *     surrounding cell values, face values as the mean of the three node
+ *     values, Gauss-Green cell gradients, face gradients interpolated
+ *     between the two cells and corrected along the centre-to-centre
+ *     direction (eq. gra2bis), flux A_f (M_f grad v_f).n_f, no-flux outer
+ *     boundary;
+ *   - the fibre conductivity tensor M = A diag(m_l, m_t, m_t) A^T (Sec. 3.1,
+ *     eq. tensor), optionally scaled per cell;
+ *   - cell models (Sec. 3.1-3.2): ten Tusscher-Panfilov (endo/mid/epi),
+ *     Courtemanche, Stewart; Rush-Larsen for gating variables, forward
+ *     Euler for the other states and for v, every right-hand side at t^n;
+ *   - the stimulus of eq. stimulus (amplitude, onset, duration, optional
+ *     period and count) on a set of cells, as a whole-step window;
+ *   - activation time = first upward crossing of at_threshold (0 mV, Sec. 4),
+ *     linearly interpolated within the step; APD90 = time from activation
+ *     to the downward crossing of v_max - repol_frac (v_max - v_rest);
+ *   - the volume-averaged potential vbar(t) = int v dV / V (Sec. 4).
+ *
+ * Units: mm, ms, mV, mS/mm, 1/mm, uF/mm^2, pA/pF (= mV/ms).
+ * Indices are 0-based in the caller's numbering; the library reorders
+ * internally and every readout is returned in the caller's numbering.
+ *
+ * Ownership: every input array is owned by the caller, copied during the
+ * call and never retained.  Output arrays are allocated by the caller, their
+ * length is passed and checked.  Host pointers unless stated otherwise.
+ *
+ * Errors: every call returns an ep_status; on failure the object is left in
+ * its previous valid state and ep_last_error() describes the failure.  Calls
+ * that need an initialised simulation return EP_ESTATE before ep_init().  A
+ * non-finite membrane potential surfaces as EP_ENUMERIC at the next ep_sync()
+ * or readout.  Nothing throws across this interface.  A simulation object is
+ * not thread-safe; distinct objects are independent.
+ *
+ * Device work runs on the stream given in ep_options (or on a stream the
+ * library creates); ep_step() only enqueues.  There is no CPU fallback: if no
+ * HIP device is usable, ep_create() fails with EP_EDEVICE.
+ */
+#ifndef EP_H
+#define EP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EP_OK = 0,
+    EP_EINVAL = -1,   /* bad argument (null pointer, size, range, degenerate mesh) */
+    EP_ENOMEM = -2,   /* device or host allocation failed / over budget       */
+    EP_EDEVICE = -3,  /* HIP runtime error                                     */
+    EP_ESTATE = -4,   /* call not valid in the current state                   */
+    EP_ENUMERIC = -5, /* non-finite membrane potential detected                */
+    EP_EBUSY = -6     /* (server) request still running                        */
+} ep_status;
+
+typedef enum { EP_FP64 = 0, EP_FP32_MIXED = 1 } ep_precision;
+
+/* Cell models.  EP_PASSIVE has I_ion = 0 (diffusion only, for tests). */
+typedef enum {
+    EP_TP06_ENDO = 0, EP_TP06_MID = 1, EP_TP06_EPI = 2,
+    EP_CRN = 3, EP_STEWART = 4, EP_PASSIVE = 5
+} ep_model;
+
+#define EP_MAX_SLOTS 21     /* state slots per cell in ep_get_states()        */
+#define EP_MAX_STIMULI 32   /* stimuli per simulation                         */
+
+typedef struct {
+    ep_precision prec;  /* EP_FP64 or EP_FP32_MIXED (FP32 gates/currents/flux,
+                           FP64 Na/K/Ca concentrations and buffering)         */
+    int device;         /* HIP device ordinal                                  */
+    void *stream;       /* hipStream_t to run on, or NULL for a library stream */
+    double dt;          /* time step, ms                                       */
+    double chi;         /* surface-to-volume ratio, 1/mm (paper: 140)          */
+    double cm;          /* membrane capacitance, uF/mm^2 (paper: 0.01)         */
+    double at_threshold;/* activation threshold, mV (paper: 0)                 */
+    double repol_frac;  /* APD repolarisation fraction (0.9 = APD90)           */
+    int32_t trace_every;/* record vbar every this many steps (0 = never)       */
+    /* optional device allocator (e.g. a framework's caching allocator);
+       both NULL = hipMalloc/hipFree */
+    void *(*dev_alloc)(size_t bytes, void *ctx);
+    void (*dev_free)(void *ptr, void *ctx);
+    void *alloc_ctx;
+} ep_options;
+
+typedef struct ep_sim ep_sim;
+
+/* Fill *o with the paper's parameters (chi 140, cm 0.01, dt 0.02, 0 mV,
+ * 0.9, FP64, device 0, library stream, trace every 50 steps). */
+void ep_default_options(ep_options *o);
+
+/* Create an empty simulation bound to o->device.  EP_EDEVICE if HIP has no
+ * usable device. */
+ep_status ep_create(const ep_options *o, ep_sim **out);
+void ep_destroy(ep_sim *s);                 /* frees host and device memory */
+
+/* Mesh: n_nodes coordinates xyz[3*i+k] (mm) and n_tets tetrahedra
+ * tet_nodes[4*c+k] (node ids, any orientation).  EP_EINVAL on an index out of
+ * range or a zero-volume tetrahedron. */
+ep_status ep_set_mesh(ep_sim *s, int64_t n_nodes, const double *xyz,
+                      int64_t n_tets, const int32_t *tet_nodes);
+
+/* Conductivity (Sec. 3.1): per-tet unit fibre vectors fibre[3*c+k],
+ * longitudinal / transverse conductivities (mS/mm), optional per-tet scale
+ * (NULL = 1).  M_c = scale_c (sigma_t I + (sigma_l - sigma_t) f f^T). */
+ep_status ep_set_conductivity(ep_sim *s, const double *fibre, double sigma_l,
+                              double sigma_t, const double *scale);
+
+/* Cell model of every tet (ep_model values); default EP_TP06_ENDO. */
+ep_status ep_set_models(ep_sim *s, const uint8_t *model);
+
+/* Multiply a maximal conductance of every cell model by s (> 0):
+ * param = "GKr", "GKs", "GCaL" or "GNa". */
+ep_status ep_set_ionic_scale(ep_sim *s, const char *param, double scale);
+
+/* Stimulus (eq. stimulus) on n_ids tets: amp pA/pF (negative depolarises)
+ * from t0 for dur ms, on whole steps [round(t0/dt), round(t0/dt) +
+ * round(dur/dt)); repeated every period ms count times if period > 0.
+ * domain must be 0 (tissue).  At most EP_MAX_STIMULI. */
+ep_status ep_add_stimulus(ep_sim *s, int domain, int64_t n_ids,
+                          const int32_t *ids, double t0, double dur,
+                          double amp, double period, int32_t count);
+
+/* Precompute geometry and flux coefficients (FP64, host), reorder the mesh,
+ * upload to the device and set the standard initial state of every model.
+ * After this the mesh, conductivity and models are frozen. */
+ep_status ep_init(ep_sim *s);
+
+/* Device bytes the initialised simulation holds. */
+ep_status ep_footprint(const ep_sim *s, size_t *bytes);
+
+/* Enqueue n time steps (n >= 0) on the simulation's stream; returns at once. */
+ep_status ep_step(ep_sim *s, int64_t n);
+
+/* Wait for queued work; EP_ENUMERIC if a non-finite v appeared. */
+ep_status ep_sync(ep_sim *s);
+
+/* Readouts (synchronise first), caller numbering, length n == n_tets. */
+ep_status ep_get_vm(ep_sim *s, double *out, int64_t n);
+ep_status ep_get_activation(ep_sim *s, double *t_act, int64_t n); /* NaN = never */
+ep_status ep_get_apd90(ep_sim *s, double *apd, int64_t n);        /* NaN = undefined */
+
+/* The vbar(t) samples recorded so far (every trace_every steps, starting
+ * with step 0): up to cap pairs (t ms, vbar mV); *n_out = number written. */
+ep_status ep_get_mean_vm_trace(ep_sim *s, double *t, double *vbar,
+                               int64_t cap, int64_t *n_out);
+
+/* Current step index and time t = step * dt. */
+ep_status ep_get_time(ep_sim *s, int64_t *step, double *t);
+
+/* Per-cell states as FP64, layout out[slot * n + cell] with n == n_tets,
+ * n_slots == EP_MAX_SLOTS.  Slot 0 is V; the model's states follow in the
+ * order of ep_model_slot_name(); unused slots read NaN and are ignored on
+ * write.  In EP_FP32_MIXED the FP32 slots are rounded on write. */
+ep_status ep_get_states(ep_sim *s, double *out, int64_t n, int32_t n_slots);
+ep_status ep_set_states(ep_sim *s, const double *in, int64_t n, int32_t n_slots);
+int ep_model_n_slots(int model);                         /* incl. V, 0 if bad */
+const char *ep_model_slot_name(int model, int slot);     /* NULL if bad       */
+
+/* Checkpoint: an opaque byte image of every state array, the detection
+ * state, the step counter and the trace.  Restoring it into a simulation
+ * built from the same inputs continues bitwise identically. */
+ep_status ep_state_size(ep_sim *s, size_t *bytes);
+ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes);
+ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);
+
+/* Launch-shape controls used by the autotuner: block size (64..1024, a
+ * multiple of 64), number of steps captured per graph launch (0 = no
+ * graphs) and whether blocks are remapped so each XCD gets a contiguous
+ * range of tiles.  May be called any time after ep_create(). */
+ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
+                        int32_t xcd_remap);
+
+/* Average device duration (ms) of the fused cell kernel and of the node
+ * gather kernel over the last ep_profile_steps() call, from HIP events on
+ * the simulation's stream. */
+ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms,
+                           double *node_ms);
+
+/* Algorithmic bytes moved per step by the node gather and by the cell
+ * kernel for this mesh and precision (the roofline numerators). */
+ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes,
+                               double *cell_bytes);
+
+const char *ep_last_error(const ep_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,269 @@
+"""Python binding of libep.so (include/ep.h): argument marshalling only.
+
+Every step of the monodomain path runs in the HIP library; this module only
+converts arrays and forwards calls under the C names.  PyTorch, when used,
+only supplies device memory (its caching allocator, through the library's
+allocator callbacks) and the stream the library runs on.  There is no CPU
+fallback: if the library or a HIP device is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libep.so")
+
+EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ESTATE, EP_ENUMERIC, EP_EBUSY = 0, -1, -2, -3, -4, -5, -6
+EP_FP64, EP_FP32_MIXED = 0, 1
+EP_TP06_ENDO, EP_TP06_MID, EP_TP06_EPI, EP_CRN, EP_STEWART, EP_PASSIVE = range(6)
+EP_MAX_SLOTS = 21
+STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EDEVICE",
+                -4: "EP_ESTATE", -5: "EP_ENUMERIC", -6: "EP_EBUSY"}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class ep_options(C.Structure):
+    _fields_ = [("prec", C.c_int), ("device", C.c_int), ("stream", C.c_void_p),
+                ("dt", C.c_double), ("chi", C.c_double), ("cm", C.c_double),
+                ("at_threshold", C.c_double), ("repol_frac", C.c_double),
+                ("trace_every", C.c_int32), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class EPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "ep_default_options": (None, [C.POINTER(ep_options)]),
+    "ep_create": (C.c_int, [C.POINTER(ep_options), C.POINTER(C.c_void_p)]),
+    "ep_destroy": (None, [C.c_void_p]),
+    "ep_set_mesh": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip]),
+    "ep_set_conductivity": (C.c_int, [C.c_void_p, _dp, C.c_double, C.c_double, _dp]),
+    "ep_set_models": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
+    "ep_set_ionic_scale": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
+    "ep_add_stimulus": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _ip, C.c_double,
+                                  C.c_double, C.c_double, C.c_double, C.c_int32]),
+    "ep_init": (C.c_int, [C.c_void_p]),
+    "ep_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "ep_step": (C.c_int, [C.c_void_p, C.c_int64]),
+    "ep_sync": (C.c_int, [C.c_void_p]),
+    "ep_get_vm": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    "ep_get_activation": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    "ep_get_apd90": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    "ep_get_mean_vm_trace": (C.c_int, [C.c_void_p, _dp, _dp, C.c_int64,
+                                       C.POINTER(C.c_int64)]),
+    "ep_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), _dp]),
+    "ep_get_states": (C.c_int, [C.c_void_p, _dp, C.c_int64, C.c_int32]),
+    "ep_set_states": (C.c_int, [C.c_void_p, _dp, C.c_int64, C.c_int32]),
+    "ep_model_n_slots": (C.c_int, [C.c_int]),
+    "ep_model_slot_name": (C.c_char_p, [C.c_int, C.c_int]),
+    "ep_state_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "ep_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ep_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ep_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp]),
+    "ep_algorithmic_bytes": (C.c_int, [C.c_void_p, _dp, _dp]),
+    "ep_last_error": (C.c_char_p, [C.c_void_p]),
+}
+
+
+def lib():
+    """Load libep.so; raises if it was not built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "paper_2112_12854_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(st, h=None):
+    if st != EP_OK:
+        msg = lib().ep_last_error(h).decode() if h else ""
+        raise EPError(st, msg)
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+class _TorchAllocator:
+    """Device memory from PyTorch's caching allocator."""
+
+    def __init__(self, device: int):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device))
+        except Exception:
+            return None
+
+    def _free(self, ptr, ctx):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Sim:
+    """One simulation object: create, upload a workload, init, step, read.
+
+    `w` is a paper_2112_12854_amd.meshgen.Workload.  `allocator` is "torch"
+    (PyTorch caching allocator and a PyTorch side stream) or "hip" (the
+    library's hipMalloc and its own stream)."""
+
+    def __init__(self, w, prec: int = EP_FP64, device: int = 0,
+                 allocator: str = "hip", trace_every: int = 50,
+                 launch=None):
+        L = lib()
+        o = ep_options()
+        L.ep_default_options(C.byref(o))
+        o.prec, o.device = prec, device
+        o.dt, o.chi, o.cm = w.dt, w.chi, w.cm
+        o.trace_every = trace_every
+        self._alloc = None
+        self._stream = None
+        if allocator == "torch":
+            import torch
+            self._alloc = _TorchAllocator(device)
+            o.dev_alloc, o.dev_free = self._alloc.alloc_cb, self._alloc.free_cb
+            self._stream = torch.cuda.Stream(device=device)
+            o.stream = C.c_void_p(self._stream.cuda_stream)
+        h = C.c_void_p()
+        _check(L.ep_create(C.byref(o), C.byref(h)))
+        self.h = h
+        self.n = w.n_tets
+        self.prec = prec
+        xyz = np.ascontiguousarray(w.xyz, np.float64)
+        tets = np.ascontiguousarray(w.tets, np.int32)
+        _check(L.ep_set_mesh(h, w.n_nodes, _d(xyz), w.n_tets, tets.ctypes.data_as(_ip)), h)
+        fib = np.ascontiguousarray(w.fibre, np.float64)
+        sc = None if w.scale is None else np.ascontiguousarray(w.scale, np.float64)
+        _check(L.ep_set_conductivity(h, _d(fib), w.sigma_l, w.sigma_t,
+                                     None if sc is None else _d(sc)), h)
+        mdl = np.ascontiguousarray(w.model, np.uint8)
+        _check(L.ep_set_models(h, mdl.ctypes.data_as(C.POINTER(C.c_uint8))), h)
+        for k, v in (w.ionic_scale or {}).items():
+            _check(L.ep_set_ionic_scale(h, k.encode(), float(v)), h)
+        for st in w.stimuli:
+            ids = np.ascontiguousarray(st.ids, np.int32)
+            _check(L.ep_add_stimulus(h, st.domain, ids.size, ids.ctypes.data_as(_ip),
+                                     st.t0, st.dur, st.amp, st.period, st.count), h)
+        if launch is not None:
+            self.set_launch(*launch)
+        _check(L.ep_init(h), h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ep_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- stepping
+    def step(self, n: int):
+        _check(lib().ep_step(self.h, int(n)), self.h)
+
+    def sync(self):
+        _check(lib().ep_sync(self.h), self.h)
+
+    def set_launch(self, block=256, steps_per_graph=50, xcd_remap=1):
+        _check(lib().ep_set_launch(self.h, block, steps_per_graph, xcd_remap), self.h)
+
+    # ---- readouts
+    def _vec(self, fn):
+        out = np.empty(self.n)
+        _check(fn(self.h, _d(out), self.n), self.h)
+        return out
+
+    def vm(self):
+        return self._vec(lib().ep_get_vm)
+
+    def activation(self):
+        return self._vec(lib().ep_get_activation)
+
+    def apd90(self):
+        return self._vec(lib().ep_get_apd90)
+
+    def mean_vm_trace(self, cap: int = 1 << 16):
+        t, v = np.empty(cap), np.empty(cap)
+        n = C.c_int64()
+        _check(lib().ep_get_mean_vm_trace(self.h, _d(t), _d(v), cap, C.byref(n)), self.h)
+        return t[:n.value].copy(), v[:n.value].copy()
+
+    def time(self):
+        s, t = C.c_int64(), C.c_double()
+        _check(lib().ep_get_time(self.h, C.byref(s), C.byref(t)), self.h)
+        return s.value, t.value
+
+    def states(self):
+        out = np.empty((EP_MAX_SLOTS, self.n))
+        _check(lib().ep_get_states(self.h, _d(out), self.n, EP_MAX_SLOTS), self.h)
+        return out
+
+    def set_states(self, st):
+        st = np.ascontiguousarray(st, np.float64)
+        _check(lib().ep_set_states(self.h, _d(st), self.n, EP_MAX_SLOTS), self.h)
+
+    def footprint(self) -> int:
+        b = C.c_size_t()
+        _check(lib().ep_footprint(self.h, C.byref(b)), self.h)
+        return b.value
+
+    def checkpoint(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().ep_state_size(self.h, C.byref(n)), self.h)
+        buf = C.create_string_buffer(n.value)
+        _check(lib().ep_get_state(self.h, buf, n.value), self.h)
+        return buf.raw
+
+    def restore(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().ep_set_state(self.h, buf, len(blob)), self.h)
+
+    def profile_steps(self, n: int):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().ep_profile_steps(self.h, int(n), C.byref(a), C.byref(b)), self.h)
+        return a.value, b.value
+
+    def algorithmic_bytes(self):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().ep_algorithmic_bytes(self.h, C.byref(a), C.byref(b)), self.h)
+        return a.value, b.value
+
+
+def model_n_slots(model: int) -> int:
+    return lib().ep_model_n_slots(model)
+
+
+def model_slot_names(model: int):
+    return [lib().ep_model_slot_name(model, i).decode() for i in range(model_n_slots(model))]
