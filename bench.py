@@ -65,6 +65,28 @@ def run_precision(ep, w, prec, steps, warmup, chunk, profile_steps):
     return res
 
 
+def measure_hbm(mib: int = 2048, reps: int = 20):
+    """Achievable HBM bandwidth on this device for reference: a device copy
+    (read + write) and a read-only reduction of a 2 GiB buffer."""
+    import torch
+    x = torch.ones(mib * 2**20 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 2 * x.nbytes),
+                             ("read", lambda: x.sum(), x.nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    return out
+
+
 def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
     """The oracle (as it stands) on a sub-slab of the same recipe."""
     import oracle
@@ -86,7 +108,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--chunk", type=int, default=10)
+    ap.add_argument("--chunk", type=int, default=50,
+                    help="steps per timed launch (one HIP graph of 50 steps)")
     ap.add_argument("--nx", type=int, default=160)
     ap.add_argument("--ny", type=int, default=160)
     ap.add_argument("--nz", type=int, default=40)
@@ -95,6 +118,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--only-fp32", action="store_true",
                     help="FP32-mixed only (short profiling runs)")
+    ap.add_argument("--only-fp64", action="store_true",
+                    help="FP64 only (short profiling runs)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times "
                          "(calibrates the HBM byte counters) and exit")
@@ -122,9 +147,13 @@ def main():
     w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
     log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")
 
+    if args.only_fp64:
+        run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, 5)
+        return
     f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, 20)
     f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
                                                   args.warmup, args.chunk, 20)
+    hbm = None if args.only_fp32 else measure_hbm()
     cpu = None
     if not (args.no_cpu or args.only_fp32):
         log("cpu baseline (oracle) ...")
@@ -162,6 +191,7 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
+        "hbm_measured_GBps": hbm,
     }
     print(json.dumps(out), flush=True)
 

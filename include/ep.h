@@ -169,10 +169,11 @@ ep_status ep_state_size(ep_sim *s, size_t *bytes);
 ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes);
 ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);
 
-/* Launch-shape controls used by the autotuner: block size (64..1024, a
- * multiple of 64), number of steps captured per graph launch (0 = no
- * graphs) and whether blocks are remapped so each XCD gets a contiguous
- * range of tiles.  May be called any time after ep_create(). */
+/* Launch controls used by the autotuner: block is 0 or 256 (one block per
+ * tile of 256 cells or nodes), steps_per_graph is the number of steps
+ * captured per HIP graph launch (0 = direct launches only), xcd_remap
+ * remaps blocks so that each XCD gets a contiguous range of tiles.  May be
+ * called any time after ep_create(). */
 ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
                         int32_t xcd_remap);
 
@@ -188,6 +189,80 @@ ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes,
                                double *cell_bytes);
 
 const char *ep_last_error(const ep_sim *s);
+
+/* ------------------------------------------------------------- serving
+ * A single-GPU server for the parametric and uncertainty-quantification
+ * sweeps the paper motivates (Sec. 6): independent simulations arrive as
+ * requests, are precomputed on host worker threads, admitted while their
+ * device footprint fits the HBM budget and a slot is free (first come first
+ * served; a request that does not fit lets smaller later ones pass), and
+ * stepped together in batched kernels replayed as HIP graphs.  Requests
+ * that arrive while others run join at the next graph boundary (continuous
+ * batching).  Each result is bitwise the one the same request gives alone.
+ * All server calls are thread-safe. */
+
+typedef struct {
+    int64_t n_ids;        /* tets of the stimulus region (caller numbering) */
+    const int32_t *ids;
+    double t0, dur, amp;  /* ms, ms, pA/pF                                   */
+    double period;        /* 0 = single pulse                               */
+    int32_t count;
+} ep_stimulus;
+
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;            /* [3*n_nodes]                             */
+    int64_t n_tets;
+    const int32_t *tet_nodes;     /* [4*n_tets]                              */
+    const double *fibre;          /* [3*n_tets] unit vectors                 */
+    double sigma_l, sigma_t;      /* mS/mm                                   */
+    const double *scale;          /* [n_tets] or NULL                        */
+    const uint8_t *model;         /* [n_tets] ep_model, NULL = TP06 endo     */
+    int32_t n_stimuli;            /* <= EP_MAX_STIMULI                       */
+    const ep_stimulus *stimuli;
+    double ionic_scale[4];        /* GKr, GKs, GCaL, GNa multipliers (0 = 1) */
+    int64_t n_steps;              /* steps to run (> 0)                      */
+} ep_request;
+
+typedef struct {
+    int64_t id;
+    ep_status status;             /* EP_OK, EP_ENUMERIC (non-finite v), or an
+                                     admission / device error                */
+    int64_t n_tets, steps;
+    size_t footprint;             /* device bytes while resident             */
+    double t_submit, t_admit, t_done;   /* seconds since server creation     */
+} ep_result;
+
+typedef struct {
+    int64_t submitted, completed, running, queued;
+    double cell_steps;            /* tet-steps completed so far              */
+    size_t bytes_in_use, bytes_budget;
+    int64_t graph_launches, table_updates;
+} ep_server_stats;
+
+typedef struct ep_server ep_server;
+
+/* o->prec, device, dt, chi, cm, thresholds and allocator apply to every
+ * request.  hbm_budget: device bytes for resident requests (0 = 90 % of the
+ * free device memory); max_slots: resident requests at most (> 0). */
+ep_status ep_server_create(const ep_options *o, size_t hbm_budget, int32_t max_slots,
+                           ep_server **out);
+/* Copies the request; returns its id.  EP_EINVAL for malformed requests and
+ * EP_ENOMEM if it could never fit the budget. */
+ep_status ep_server_submit(ep_server *sv, const ep_request *rq, int64_t *id);
+/* EP_EBUSY while queued or running, else fills *res (EP_EINVAL: unknown id). */
+ep_status ep_server_poll(ep_server *sv, int64_t id, ep_result *res);
+ep_status ep_server_wait(ep_server *sv, int64_t id, ep_result *res);
+/* Results of a finished request, caller numbering, n == its n_tets. */
+ep_status ep_server_get_vm(ep_server *sv, int64_t id, double *out, int64_t n);
+ep_status ep_server_get_activation(ep_server *sv, int64_t id, double *out, int64_t n);
+ep_status ep_server_get_apd90(ep_server *sv, int64_t id, double *out, int64_t n);
+ep_status ep_server_release(ep_server *sv, int64_t id);   /* drop stored results */
+ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st);
+/* Graph length in steps (> 0) and XCD remap, as ep_set_launch. */
+ep_status ep_server_set_launch(ep_server *sv, int32_t steps_per_graph, int32_t xcd_remap);
+void ep_server_destroy(ep_server *sv);    /* waits for running requests */
+const char *ep_server_last_error(ep_server *sv);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,18 @@ def lib():
         L.orc_detect_waveform.argtypes = [_dp, C.c_int64, C.c_double, C.c_double,
                                           C.c_double, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_purkinje.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip,
+                                       C.c_double, C.c_int, C.c_int32]
+        L.orc_add_pmj.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
+                                  C.c_double, C.c_int, C.c_double, C.c_double]
+        L.orc_add_purkinje_stimulus.argtypes = [C.c_void_p, C.c_int64, _ip, C.c_double,
+                                                C.c_double, C.c_double, C.c_double, C.c_int32]
+        L.orc_purkinje_n_sub.argtypes = [C.c_void_p]
+        L.orc_purkinje_n_sub.restype = C.c_int32
+        L.orc_get_purkinje_vm.argtypes = [C.c_void_p, _dp]
+        L.orc_get_purkinje_activation.argtypes = [C.c_void_p, _dp]
+        L.orc_get_pmj_region.argtypes = [C.c_void_p, C.c_int, _ip, C.c_int64]
+        L.orc_get_pmj_region.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -135,12 +147,23 @@ class Sim:
                               w.sigma_l, w.sigma_t,
                               None if self._scale is None else _d(self._scale),
                               self._model.ctypes.data_as(_up), w.dt, w.chi, w.cm)
+        pk = getattr(w, "purkinje", None)
+        self.np = 0
+        if pk is not None:
+            pxyz = np.ascontiguousarray(pk.xyz, np.float64)
+            pe = np.ascontiguousarray(pk.edges, np.int32)
+            r = L.orc_set_purkinje(self.h, pxyz.shape[0], _d(pxyz), pe.shape[0],
+                                   pe.ctypes.data_as(_ip), pk.sigma, pk.model, pk.n_sub)
+            assert r == 0
+            self.np = pxyz.shape[0]
+            for node in pk.pmj_nodes:
+                L.orc_add_pmj(self.h, int(node), pk.pmj_radius, pk.delay_ortho,
+                              pk.delay_anti, int(pk.two_way), pk.pmj_amp, pk.pmj_dur)
         for st in w.stimuli:
-            if st.domain != 0:
-                continue
             ids = np.ascontiguousarray(st.ids, dtype=np.int32)
-            L.orc_add_stimulus(self.h, ids.size, ids.ctypes.data_as(_ip), st.t0,
-                               st.dur, st.amp, st.period, st.count)
+            fn = L.orc_add_stimulus if st.domain == 0 else L.orc_add_purkinje_stimulus
+            fn(self.h, ids.size, ids.ctypes.data_as(_ip), st.t0, st.dur, st.amp,
+               st.period, st.count)
         if w.ionic_scale:
             gs = np.array([w.ionic_scale.get(k, 1.0) for k in ("GKr", "GKs", "GCaL", "GNa")])
             L.orc_set_ionic_scale(self.h, _d(gs))
@@ -173,6 +196,24 @@ class Sim:
 
     def apd90(self):
         return self._vec(lib().orc_get_apd90)
+
+    def purkinje_vm(self):
+        out = np.empty(self.np)
+        lib().orc_get_purkinje_vm(self.h, _d(out))
+        return out
+
+    def purkinje_activation(self):
+        out = np.empty(self.np)
+        lib().orc_get_purkinje_activation(self.h, _d(out))
+        return out
+
+    def purkinje_n_sub(self) -> int:
+        return lib().orc_purkinje_n_sub(self.h)
+
+    def pmj_region(self, k: int):
+        out = np.empty(self.nc, np.int32)
+        n = lib().orc_get_pmj_region(self.h, k, out.ctypes.data_as(_ip), out.size)
+        return out[:n].copy()
 
     def mean_vm(self) -> float:
         return lib().orc_mean_vm(self.h)

@@ -68,6 +68,33 @@ void orc_get_states(const orc_sim *s, double *out);
 void orc_set_states(orc_sim *s, const double *in);
 void orc_set_step(orc_sim *s, int64_t step);
 
+/* ------------------------------------------------- Purkinje graph, PMJs */
+/* A 1D Purkinje graph discretised with vertex-centred finite volumes (the
+ * paper's choice for branching 1D media, Sec. 3.2): node i owns half of every
+ * incident segment, l_i = sum_j L_ij / 2, and
+ *   dv_i/dt = sigma / (chi Cm l_i) sum_j (v_j - v_i) / L_ij - I_ion - I_stim.
+ * It advances in n_sub explicit substeps per tissue step (n_sub <= 0: the
+ * smallest n_sub with dt/n_sub <= 0.9 min_i chi Cm l_i / (sigma sum_j 1/L_ij)).
+ * Junctions (Sec. 3.3): an upward crossing of the threshold at the junction
+ * node during tissue step n stimulates its muscle region (cells whose
+ * centroid lies within `radius`, else the cells sharing a node with the cell
+ * of nearest centroid) with amp for dur ms from step n + 1 + round(delay/dt);
+ * with two_way the upward crossing of the region's mean potential stimulates
+ * the node after delay_anti.  Each step: tissue, then Purkinje substeps, then
+ * junction events. */
+int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
+                     const int32_t *edges, double sigma, int model, int32_t n_sub);
+int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
+                double delay_anti, int two_way, double amp, double dur);
+int orc_add_purkinje_stimulus(orc_sim *s, int64_t n_ids, const int32_t *ids,
+                              double t0, double dur, double amp, double period,
+                              int32_t count);
+int32_t orc_purkinje_n_sub(const orc_sim *s);
+void orc_get_purkinje_vm(const orc_sim *s, double *out);
+void orc_get_purkinje_activation(const orc_sim *s, double *out);
+/* muscle region of junction k (at most cap ids); returns its size */
+int64_t orc_get_pmj_region(const orc_sim *s, int k, int32_t *out, int64_t cap);
+
 /* ---------------------------------------- operator probes (for pinning) */
 /* Per tet: volume, 4 outward area vectors S_j (face opposite local node j),
  * 4 face neighbours (-1 = boundary face). */

@@ -60,6 +60,35 @@ struct orc_sim {
     int n_stims;
     double gscale[4];
     int64_t step;
+    /* Purkinje graph */
+    int64_t np;
+    double *pxyz;
+    int64_t *padj_off;          /* node -> incident (neighbour, length) */
+    int32_t *padj_nbr;
+    double *padj_len;
+    double *pell;               /* control length l_i */
+    double psigma;
+    int pmodel;
+    int32_t n_sub;
+    double *py;                 /* py[i*ORC_MAX_SLOTS + slot] */
+    double *pistim;
+    uint8_t *pstatus;
+    double *pt_act;
+    orc_stim *pstims;
+    int n_pstims;
+    /* junctions */
+    int n_pmj;
+    struct orc_pmj *pmj;
+};
+
+struct orc_pmj {
+    int32_t node;
+    int32_t *cells;
+    int64_t n_cells;
+    int64_t delay_o, delay_a, ndur;
+    int two_way;
+    double amp;
+    int64_t fire_o, fire_a;     /* first step of the pending stimuli */
 };
 
 /* ------------------------------------------------------------- models -- */
@@ -379,6 +408,12 @@ void orc_destroy(orc_sim *s)
     free(s->v_rest);
     for (int i = 0; i < s->n_stims; ++i) free(s->stims[i].ids);
     free(s->stims);
+    free(s->pxyz); free(s->padj_off); free(s->padj_nbr); free(s->padj_len);
+    free(s->pell); free(s->py); free(s->pistim); free(s->pstatus); free(s->pt_act);
+    for (int i = 0; i < s->n_pstims; ++i) free(s->pstims[i].ids);
+    free(s->pstims);
+    for (int k = 0; k < s->n_pmj; ++k) free(s->pmj[k].cells);
+    free(s->pmj);
     free(s);
 }
 
@@ -418,6 +453,212 @@ static int stim_active(const orc_stim *st, int64_t n)
     return (k / st->nper) < st->count && (k % st->nper) < st->ndur;
 }
 
+/* ------------------------------------------------------------ Purkinje -- */
+static double region_mean(const struct orc_pmj *J, const double *v)
+{
+    double acc = 0.0;
+    for (int64_t q = 0; q < J->n_cells; ++q) acc += v[J->cells[q]];
+    return acc / (double)J->n_cells;
+}
+
+/* n_sub substeps of the graph over tissue step n, then junction events;
+ * v_old is the tissue potential at level n (the cells hold level n+1). */
+static void purkinje_step(orc_sim *s, const double *v_old)
+{
+    const int64_t n = s->step, np = s->np;
+    const double dtp = s->dt / s->n_sub;
+    double *vp = malloc(sizeof(double) * (size_t)np);
+    double *vp0 = malloc(sizeof(double) * (size_t)np);
+    for (int64_t i = 0; i < np; ++i) vp0[i] = s->py[i * ORC_MAX_SLOTS];
+    /* stimuli of the graph during this tissue step */
+    memset(s->pistim, 0, sizeof(double) * (size_t)np);
+    for (int i = 0; i < s->n_pstims; ++i) {
+        const orc_stim *st = &s->pstims[i];
+        if (!stim_active(st, n)) continue;
+        for (int64_t q = 0; q < st->n; ++q) s->pistim[st->ids[q]] += st->amp;
+    }
+    for (int k = 0; k < s->n_pmj; ++k) {
+        const struct orc_pmj *J = &s->pmj[k];
+        if (J->two_way && n >= J->fire_a && n < J->fire_a + J->ndur) s->pistim[J->node] += J->amp;
+    }
+    for (int sub = 0; sub < s->n_sub; ++sub) {
+        for (int64_t i = 0; i < np; ++i) vp[i] = s->py[i * ORC_MAX_SLOTS];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < np; ++i) {
+            double *y = s->py + i * ORC_MAX_SLOTS;
+            double flux = 0.0;
+            for (int64_t e = s->padj_off[i]; e < s->padj_off[i + 1]; ++e)
+                flux += (vp[s->padj_nbr[e]] - vp[i]) / s->padj_len[e];
+            const double L = s->psigma * flux / (s->chi * s->cm * s->pell[i]);
+            const double iion = orc_model_step(s->pmodel, y, dtp, s->pistim[i], s->gscale);
+            const double vnew = vp[i] + dtp * (L - iion - s->pistim[i]);
+            y[0] = vnew;
+            if (!s->pstatus[i] && vp[i] <= s->thr && vnew > s->thr) {
+                s->pt_act[i] = ((double)(n * s->n_sub + sub) +
+                                (s->thr - vp[i]) / (vnew - vp[i])) * dtp;
+                s->pstatus[i] = 1;
+            }
+        }
+    }
+    /* junction events: upward crossings during this step fire later */
+    for (int k = 0; k < s->n_pmj; ++k) {
+        struct orc_pmj *J = &s->pmj[k];
+        const double a = vp0[J->node], b = s->py[(int64_t)J->node * ORC_MAX_SLOTS];
+        if (a <= s->thr && b > s->thr) J->fire_o = n + 1 + J->delay_o;
+        if (J->two_way) {
+            const double m0 = region_mean(J, v_old);
+            double m1 = 0.0;
+            for (int64_t q = 0; q < J->n_cells; ++q) m1 += s->y[(int64_t)J->cells[q] * ORC_MAX_SLOTS];
+            m1 /= (double)J->n_cells;
+            if (m0 <= s->thr && m1 > s->thr) J->fire_a = n + 1 + J->delay_a;
+        }
+    }
+    free(vp);
+    free(vp0);
+}
+
+int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
+                     const int32_t *edges, double sigma, int model, int32_t n_sub)
+{
+    if (n <= 0 || n_edges < 0 || !(sigma > 0)) return -1;
+    for (int64_t e = 0; e < 2 * n_edges; ++e)
+        if (edges[e] < 0 || edges[e] >= n) return -1;
+    s->np = n;
+    s->pxyz = malloc(sizeof(double) * (size_t)n * 3);
+    memcpy(s->pxyz, xyz, sizeof(double) * (size_t)n * 3);
+    s->psigma = sigma;
+    s->pmodel = model;
+    s->padj_off = calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < n_edges; ++e) {
+        s->padj_off[edges[2 * e] + 1]++;
+        s->padj_off[edges[2 * e + 1] + 1]++;
+    }
+    for (int64_t i = 0; i < n; ++i) s->padj_off[i + 1] += s->padj_off[i];
+    s->padj_nbr = malloc(sizeof(int32_t) * (size_t)(2 * n_edges + 1));
+    s->padj_len = malloc(sizeof(double) * (size_t)(2 * n_edges + 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)n);
+    memcpy(fill, s->padj_off, sizeof(int64_t) * (size_t)n);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const int32_t a = edges[2 * e], b = edges[2 * e + 1];
+        double d[3];
+        sub3(xyz + 3 * (int64_t)a, xyz + 3 * (int64_t)b, d);
+        const double len = norm3(d);
+        s->padj_nbr[fill[a]] = b; s->padj_len[fill[a]++] = len;
+        s->padj_nbr[fill[b]] = a; s->padj_len[fill[b]++] = len;
+    }
+    free(fill);
+    s->pell = calloc((size_t)n, sizeof(double));
+    double dtmax = 1e300;
+    for (int64_t i = 0; i < n; ++i) {
+        double inv = 0.0;
+        for (int64_t e = s->padj_off[i]; e < s->padj_off[i + 1]; ++e) {
+            s->pell[i] += 0.5 * s->padj_len[e];
+            inv += 1.0 / s->padj_len[e];
+        }
+        if (inv > 0.0) {
+            const double lim = s->chi * s->cm * s->pell[i] / (sigma * inv);
+            if (lim < dtmax) dtmax = lim;
+        }
+    }
+    if (n_sub <= 0) {
+        n_sub = 1;
+        while (s->dt / n_sub > 0.9 * dtmax) ++n_sub;
+    }
+    s->n_sub = n_sub;
+    s->py = malloc(sizeof(double) * (size_t)n * ORC_MAX_SLOTS);
+    s->pistim = calloc((size_t)n, sizeof(double));
+    s->pstatus = calloc((size_t)n, 1);
+    s->pt_act = malloc(sizeof(double) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        orc_model_init(model, s->py + i * ORC_MAX_SLOTS);
+        s->pt_act[i] = NAN;
+    }
+    return 0;
+}
+
+int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
+                double delay_anti, int two_way, double amp, double dur)
+{
+    if (node < 0 || node >= s->np) return -1;
+    s->pmj = realloc(s->pmj, sizeof(struct orc_pmj) * (size_t)(s->n_pmj + 1));
+    struct orc_pmj *J = &s->pmj[s->n_pmj++];
+    memset(J, 0, sizeof(*J));
+    J->node = node;
+    const double *x = s->pxyz + 3 * (int64_t)node;
+    /* region: centroids within the radius */
+    int64_t cnt = 0, best = -1;
+    double bestd = 1e300;
+    for (int64_t c = 0; c < s->nc; ++c) {
+        double r[3];
+        sub3(s->cen + 3 * c, x, r);
+        const double d = norm3(r);
+        if (d <= radius) cnt++;
+        if (d < bestd) { bestd = d; best = c; }
+    }
+    if (cnt > 0) {
+        J->cells = malloc(sizeof(int32_t) * (size_t)cnt);
+        for (int64_t c = 0; c < s->nc; ++c) {
+            double r[3];
+            sub3(s->cen + 3 * c, x, r);
+            if (norm3(r) <= radius) J->cells[J->n_cells++] = (int32_t)c;
+        }
+    } else {
+        /* the cells sharing a node with the cell of nearest centroid */
+        const int32_t *t = s->tet + 4 * best;
+        J->cells = malloc(sizeof(int32_t) * (size_t)s->nc);
+        for (int64_t c = 0; c < s->nc; ++c) {
+            const int32_t *u = s->tet + 4 * c;
+            int share = 0;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) share |= (t[a] == u[b]);
+            if (share) J->cells[J->n_cells++] = (int32_t)c;
+        }
+    }
+    J->delay_o = llround(delay_ortho / s->dt);
+    J->delay_a = llround(delay_anti / s->dt);
+    J->ndur = llround(dur / s->dt);
+    J->two_way = two_way;
+    J->amp = amp;
+    J->fire_o = J->fire_a = INT64_MIN / 2;
+    return s->n_pmj - 1;
+}
+
+int orc_add_purkinje_stimulus(orc_sim *s, int64_t n_ids, const int32_t *ids, double t0,
+                              double dur, double amp, double period, int32_t count)
+{
+    s->pstims = realloc(s->pstims, sizeof(orc_stim) * (size_t)(s->n_pstims + 1));
+    orc_stim *st = &s->pstims[s->n_pstims++];
+    st->ids = malloc(sizeof(int32_t) * (size_t)(n_ids > 0 ? n_ids : 1));
+    memcpy(st->ids, ids, sizeof(int32_t) * (size_t)n_ids);
+    st->n = n_ids;
+    st->n0 = llround(t0 / s->dt);
+    st->ndur = llround(dur / s->dt);
+    st->nper = period > 0.0 ? llround(period / s->dt) : 0;
+    st->count = count < 1 ? 1 : count;
+    st->amp = amp;
+    return s->n_pstims - 1;
+}
+
+int32_t orc_purkinje_n_sub(const orc_sim *s) { return s->n_sub; }
+
+void orc_get_purkinje_vm(const orc_sim *s, double *out)
+{
+    for (int64_t i = 0; i < s->np; ++i) out[i] = s->py[i * ORC_MAX_SLOTS];
+}
+
+void orc_get_purkinje_activation(const orc_sim *s, double *out)
+{
+    for (int64_t i = 0; i < s->np; ++i) out[i] = s->pstatus[i] ? s->pt_act[i] : NAN;
+}
+
+int64_t orc_get_pmj_region(const orc_sim *s, int k, int32_t *out, int64_t cap)
+{
+    if (k < 0 || k >= s->n_pmj) return -1;
+    const struct orc_pmj *J = &s->pmj[k];
+    for (int64_t q = 0; q < J->n_cells && q < cap; ++q) out[q] = J->cells[q];
+    return J->n_cells;
+}
+
 /* ---------------------------------------------------------- time step -- */
 static void one_step(orc_sim *s)
 {
@@ -426,12 +667,17 @@ static void one_step(orc_sim *s)
     double *v = malloc(sizeof(double) * (size_t)nc);
     for (int64_t c = 0; c < nc; ++c) v[c] = s->y[c * ORC_MAX_SLOTS];
 
-    /* stimulus currents at level n */
+    /* stimulus currents at level n (protocol stimuli, then junctions) */
     memset(s->istim, 0, sizeof(double) * (size_t)nc);
     for (int i = 0; i < s->n_stims; ++i) {
         const orc_stim *st = &s->stims[i];
         if (!stim_active(st, n)) continue;
         for (int64_t q = 0; q < st->n; ++q) s->istim[st->ids[q]] += st->amp;
+    }
+    for (int k = 0; k < s->n_pmj; ++k) {
+        const struct orc_pmj *J = &s->pmj[k];
+        if (n >= J->fire_o && n < J->fire_o + J->ndur)
+            for (int64_t q = 0; q < J->n_cells; ++q) s->istim[J->cells[q]] += J->amp;
     }
 
     /* diffusion at level n */
@@ -464,6 +710,7 @@ static void one_step(orc_sim *s)
             }
         }
     }
+    if (s->np > 0) purkinje_step(s, v);
     free(v);
     s->step++;
 }

@@ -1,0 +1,465 @@
+// Building instances on the device and stepping sets of them.
+#include "instance.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace ep {
+
+using namespace epdev;
+
+int model_ng(int m) {
+    if (m <= 2) return tp06::NG;
+    if (m == 3) return crn::NG;
+    if (m == 4) return stewart::NG;
+    return 0;
+}
+int model_nc(int m) {
+    if (m <= 2) return tp06::NC;
+    if (m == 3) return crn::NC;
+    if (m == 4) return stewart::NC;
+    return 0;
+}
+void model_init(int m, double *y) {
+    for (int i = 0; i < EP_MAX_SLOTS; ++i) y[i] = 0.0;
+    if (m <= 2) tp06::init(y);
+    else if (m == 3) crn::init(y);
+    else if (m == 4) stewart::init(y);
+    else y[0] = -86.2;
+}
+
+namespace {
+
+void *dalloc(Inst &in, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    void *p = nullptr;
+    if (in.al.alloc) p = in.al.alloc(bytes, in.al.ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) {
+        in.allocs.push_back({p, bytes});
+        in.footprint += bytes;
+    }
+    return p;
+}
+
+template <typename T>
+bool up(Inst &in, void **dst, const std::vector<T> &src) {
+    *dst = dalloc(in, src.size() * sizeof(T));
+    if (!*dst) return false;
+    // synchronous: sources are often temporaries
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+template <typename R>
+std::vector<R> conv(const std::vector<double> &v) {
+    return std::vector<R>(v.begin(), v.end());
+}
+
+size_t round256(size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
+    (void)max_degree_hint;
+    const size_t c = (size_t)nc, n = (size_t)nn, r = (size_t)rs;
+    const size_t ent = (size_t)(4.4 * c) + 64 * 8;   // incidences incl. slice padding
+    size_t b = 0;
+    b += round256(((n + 63) / 64 + 1) * 8) + round256(ent * 4) + round256(ent * r);
+    b += round256(8 * c * 4) + round256(8 * c * r) + round256(4 * c * 4) + round256(4 * c * r);
+    b += round256(c) + round256(c * 8);                       // model, volume
+    b += round256(c * 4);                                     // stimulus mask
+    b += round256(NC_MAX * c * 8) + round256(NG_MAX * c * r); // states
+    b += 2 * round256(c * r) + 3 * round256(c * r) + round256(n * r);   // v0 v1 vrest vmax, vn
+    b += round256(c) + 2 * round256(c * 8);                   // detection
+    b += round256(((c + TILE - 1) / TILE) * 8) + round256(8 * 4096) + round256(sizeof(Ctrl));
+    return b;
+}
+
+std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
+    st = EP_OK;
+    PrepIn in;
+    in.n_nodes = sp.n_nodes;
+    in.n_tets = sp.n_tets;
+    in.xyz = sp.xyz.data();
+    in.tets = sp.tets.data();
+    in.fibre = sp.fibre.data();
+    in.scale = sp.has_scale ? sp.scale.data() : nullptr;
+    in.model = sp.model.data();
+    in.sigma_l = sp.sigma_l;
+    in.sigma_t = sp.sigma_t;
+    in.chi = sp.chi;
+    in.cm = sp.cm;
+    in.ordering = sp.ordering;
+    std::string e = prepare(in, I.prep);
+    if (!e.empty()) { st = EP_EINVAL; return e; }
+    return "";
+}
+
+size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
+    const PrepOut &P = I.prep;
+    const size_t c = (size_t)P.n_tets, n = (size_t)P.n_nodes, r = (size_t)rs;
+    const size_t ent = P.sell_cell.size();
+    int64_t cap = 4096;
+    if (sp.trace_every > 0 && sp.target != INT64_MAX) cap = std::max<int64_t>(2, sp.target / sp.trace_every + 2);
+    else if (sp.trace_every > 0) cap = 1 << 16;
+    size_t b = 0;
+    b += round256(P.sell_off.size() * 8) + round256(ent * 4) + round256(ent * r);
+    b += round256(8 * c * 4) + round256(8 * c * r) + round256(4 * c * 4) + round256(4 * c * r);
+    b += round256(c) + round256(c * 8) + round256(c * 4);
+    b += round256(NC_MAX * c * 8) + round256(NG_MAX * c * r);
+    b += 4 * round256(c * r) + round256(n * r);
+    b += round256(c) + 2 * round256(c * 8);
+    b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE) * 8) + round256(sizeof(Ctrl));
+    return b;
+}
+
+std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Inst &I,
+                            ep_status &st) {
+    st = EP_OK;
+    I.rs = rs;
+    I.al = al;
+    PrepOut &P = I.prep;
+    const int64_t nc = sp.n_tets, nn = sp.n_nodes;
+    I.n_slices = (int64_t)P.sell_off.size() - 1;
+    I.dt = sp.dt;
+    I.trace_every = sp.trace_every;
+    I.target = sp.target;
+    int present = 0;
+    for (uint8_t m : P.model) present |= m <= 2 ? 1 : (m == 3 ? 2 : (m == 4 ? 4 : 8));
+    I.mset = present;
+
+    InstDesc &D = I.desc;
+    std::memset(&D, 0, sizeof(D));
+    D.nc = nc;
+    D.nn = nn;
+    auto fail_mem = [&]() { st = EP_ENOMEM; free_instance(I); return std::string("device allocation failed"); };
+    if (!up(I, (void **)&D.sell_off, P.sell_off) || !up(I, (void **)&D.sell_cell, P.sell_cell) ||
+        !up(I, (void **)&D.cnode, P.cnode) || !up(I, (void **)&D.cnbr, P.cnbr) ||
+        !up(I, (void **)&D.model, P.model) || !up(I, (void **)&D.vol, P.vol))
+        return fail_mem();
+    bool ok = rs == 8 ? (up(I, (void **)&D.sell_w, P.sell_w) && up(I, (void **)&D.cbeta, P.cbeta) &&
+                         up(I, (void **)&D.cb, P.cb))
+                      : (up(I, (void **)&D.sell_w, conv<float>(P.sell_w)) &&
+                         up(I, (void **)&D.cbeta, conv<float>(P.cbeta)) &&
+                         up(I, (void **)&D.cb, conv<float>(P.cb)));
+    if (!ok) return fail_mem();
+
+    // initial state (structure of arrays, internal order)
+    std::vector<double> v0(nc), gate((size_t)NG_MAX * nc, 0.0), conc((size_t)NC_MAX * nc, 0.0);
+    for (int64_t i = 0; i < nc; ++i) {
+        double y[EP_MAX_SLOTS];
+        const int m = P.model[i];
+        model_init(m, y);
+        v0[i] = y[0];
+        const int ng = model_ng(m), ncc = model_nc(m);
+        for (int k = 0; k < ng; ++k) gate[(size_t)k * nc + i] = y[1 + k];
+        for (int k = 0; k < ncc; ++k) conc[(size_t)k * nc + i] = y[1 + ng + k];
+    }
+    std::vector<uint32_t> smask(nc, 0);
+    for (size_t k = 0; k < sp.stims.size(); ++k)
+        for (int32_t id : sp.stims[k].ids) smask[P.iperm[id]] |= 1u << k;
+    if (!up(I, (void **)&D.smask, smask) || !up(I, (void **)&D.conc, conc)) return fail_mem();
+    if (rs == 8) {
+        ok = up(I, (void **)&D.gate, gate) && up(I, &D.v[0], v0) && up(I, &D.v[1], v0) &&
+             up(I, (void **)&D.vrest, v0) && up(I, &D.vmax, v0) &&
+             up(I, &D.vn, std::vector<double>(nn, 0.0));
+    } else {
+        ok = up(I, (void **)&D.gate, conv<float>(gate)) && up(I, &D.v[0], conv<float>(v0)) &&
+             up(I, &D.v[1], conv<float>(v0)) && up(I, (void **)&D.vrest, conv<float>(v0)) &&
+             up(I, &D.vmax, conv<float>(v0)) && up(I, &D.vn, std::vector<float>(nn, 0.0f));
+    }
+    if (!ok) return fail_mem();
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    if (!up(I, (void **)&D.dstat, std::vector<uint8_t>(nc, 0)) ||
+        !up(I, (void **)&D.t_act, std::vector<double>(nc, nan)) ||
+        !up(I, (void **)&D.t_rep, std::vector<double>(nc, nan)))
+        return fail_mem();
+
+    // vbar trace: sample 0 now, then one every trace_every steps
+    D.n_cell_tiles = (int32_t)((nc + TILE - 1) / TILE);
+    I.trace_cap = 4096;
+    if (sp.trace_every > 0 && sp.target != INT64_MAX)
+        I.trace_cap = std::max<int64_t>(2, sp.target / sp.trace_every + 2);
+    else if (sp.trace_every > 0)
+        I.trace_cap = 1 << 16;
+    double tv = 0.0, vt = 0.0;
+    for (int64_t i = 0; i < nc; ++i) { tv += P.vol[i]; vt += P.vol[i] * v0[i]; }
+    std::vector<double> trace(I.trace_cap, nan);
+    trace[0] = vt / tv;
+    if (!up(I, (void **)&D.trace, trace) ||
+        !up(I, (void **)&D.part, std::vector<double>(D.n_cell_tiles, 0.0)))
+        return fail_mem();
+    D.dt = sp.dt;
+    D.thr = sp.thr;
+    D.repol = sp.repol;
+    D.inv_total_vol = 1.0 / tv;
+    D.gs = GScale{sp.gscale[0], sp.gscale[1], sp.gscale[2], sp.gscale[3]};
+    D.trace_cap = I.trace_cap;
+    D.trace_every = sp.trace_every;
+
+    Ctrl ctrl;
+    std::memset(&ctrl, 0, sizeof(ctrl));
+    ctrl.step = 0;
+    ctrl.target = sp.target;
+    ctrl.n_stim = (int32_t)sp.stims.size();
+    for (size_t k = 0; k < sp.stims.size(); ++k) {
+        const StimSpec &q = sp.stims[k];
+        ctrl.st_n0[k] = std::llround(q.t0 / sp.dt);
+        ctrl.st_ndur[k] = std::llround(q.dur / sp.dt);
+        ctrl.st_nper[k] = q.period > 0 ? std::llround(q.period / sp.dt) : 0;
+        ctrl.st_count[k] = q.count;
+        ctrl.st_amp[k] = q.amp;
+    }
+    I.d_ctrl = (Ctrl *)dalloc(I, sizeof(Ctrl));
+    if (!I.d_ctrl) return fail_mem();
+    if (hipMemcpy(I.d_ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice) != hipSuccess) {
+        st = EP_EDEVICE;
+        free_instance(I);
+        return "hipMemcpy of the control block failed";
+    }
+    D.ctrl = I.d_ctrl;
+    I.host_step = 0;
+    return "";
+}
+
+std::string build_instance(const InstSpec &sp, int rs, const Allocator &al, Inst &I,
+                           ep_status &st) {
+    std::string e = prep_instance(sp, I, st);
+    if (!e.empty()) return e;
+    return upload_instance(sp, rs, al, I, st);
+}
+
+void free_instance(Inst &I) {
+    for (auto &a : I.allocs) {
+        if (I.al.free) I.al.free(a.first, I.al.ctx);
+        else (void)hipFree(a.first);
+    }
+    I.allocs.clear();
+    I.footprint = 0;
+    I.d_ctrl = nullptr;
+}
+
+// ================================================================ stepper
+namespace {
+
+void drop_graph(Stepper &s) {
+    if (s.graph) { (void)hipGraphExecDestroy(s.graph); s.graph = nullptr; }
+}
+
+Tables tables(const Stepper &s) {
+    return Tables{s.d_desc, s.d_ctiles, s.d_ntiles, s.d_counts};
+}
+
+int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
+
+template <typename R>
+void launch_step(Stepper &s, int32_t off) {
+    const Tables tb = tables(s);
+    k_node_gather<R><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap);
+    switch (s.mset) {
+    case 1: k_cell<R, 1><<<s.grid_cell, TILE, 0, s.stream>>>(tb, off, s.remap); break;
+    case 8: k_cell<R, 8><<<s.grid_cell, TILE, 0, s.stream>>>(tb, off, s.remap); break;
+    default: k_cell<R, 15><<<s.grid_cell, TILE, 0, s.stream>>>(tb, off, s.remap); break;
+    }
+}
+
+void enqueue(Stepper &s, int64_t k) {
+    for (int64_t i = 0; i < k; ++i) {
+        if (s.rs == 8) launch_step<double>(s, (int32_t)i);
+        else launch_step<float>(s, (int32_t)i);
+    }
+    k_advance<<<1, 256, 0, s.stream>>>(tables(s), k);
+}
+
+std::string hip_err(const char *what, hipError_t e) {
+    return std::string(what) + ": " + hipGetErrorString(e);
+}
+
+}  // namespace
+
+std::string stepper_init(Stepper &s, int device, hipStream_t stream, int rs) {
+    s.device = device;
+    s.stream = stream;
+    s.rs = rs;
+    hipError_t e = hipEventCreateWithFlags(&s.stage_done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_err("hipEventCreate", e);
+    e = hipMalloc((void **)&s.d_counts, 4 * sizeof(int32_t));
+    if (e != hipSuccess) return hip_err("hipMalloc", e);
+    return "";
+}
+
+void stepper_free(Stepper &s) {
+    drop_graph(s);
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    if (s.d_desc) (void)hipFree(s.d_desc);
+    if (s.d_ctiles) (void)hipFree(s.d_ctiles);
+    if (s.d_ntiles) (void)hipFree(s.d_ntiles);
+    if (s.d_counts) (void)hipFree(s.d_counts);
+    if (s.h_stage) (void)hipHostFree(s.h_stage);
+    if (s.stage_done) (void)hipEventDestroy(s.stage_done);
+    s.d_desc = nullptr; s.d_ctiles = s.d_ntiles = nullptr; s.d_counts = nullptr;
+    s.h_stage = nullptr; s.stage_done = nullptr;
+}
+
+std::string stepper_sync_tables(Stepper &s) {
+    std::vector<InstDesc> desc;
+    std::vector<Tile> ct, nt;
+    int mset = 0;
+    for (size_t i = 0; i < s.insts.size(); ++i) {
+        const Inst &I = *s.insts[i];
+        desc.push_back(I.desc);
+        mset |= I.mset;
+        for (int64_t b = 0, t = 0; b < I.desc.nc; b += TILE, ++t)
+            ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nc - b), (int32_t)t});
+        for (int64_t b = 0, t = 0; b < I.desc.nn; b += TILE, ++t)
+            nt.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nn - b), (int32_t)t});
+    }
+    s.mset = (mset == 1 || mset == 8) ? mset : (mset ? 15 : 1);
+    // grow device tables geometrically; growth invalidates the graph
+    auto grow = [&](void **p, size_t &cap, size_t need, size_t elem) -> hipError_t {
+        if (need <= cap && *p) return hipSuccess;
+        size_t nc = std::max<size_t>(need, cap * 2);
+        nc = std::max<size_t>(nc, 16);
+        if (*p) { (void)hipStreamSynchronize(s.stream); (void)hipFree(*p); *p = nullptr; }
+        drop_graph(s);
+        cap = nc;
+        return hipMalloc(p, nc * elem);
+    };
+    hipError_t e;
+    if ((e = grow((void **)&s.d_desc, s.cap_inst, desc.size(), sizeof(InstDesc))) != hipSuccess ||
+        (e = grow((void **)&s.d_ctiles, s.cap_ct, ct.size(), sizeof(Tile))) != hipSuccess ||
+        (e = grow((void **)&s.d_ntiles, s.cap_nt, nt.size(), sizeof(Tile))) != hipSuccess)
+        return hip_err("hipMalloc(tables)", e);
+    // pinned staging: wait until the previous upload has left it
+    const size_t need = desc.size() * sizeof(InstDesc) + (ct.size() + nt.size()) * sizeof(Tile) + 64;
+    if (s.h_stage) (void)hipEventSynchronize(s.stage_done);
+    if (need > s.stage_bytes) {
+        if (s.h_stage) (void)hipHostFree(s.h_stage);
+        s.stage_bytes = need * 2;
+        if ((e = hipHostMalloc(&s.h_stage, s.stage_bytes)) != hipSuccess) {
+            s.h_stage = nullptr;
+            s.stage_bytes = 0;
+            return hip_err("hipHostMalloc", e);
+        }
+    }
+    char *p = (char *)s.h_stage;
+    int32_t counts[4] = {(int32_t)ct.size(), (int32_t)nt.size(), (int32_t)desc.size(), 0};
+    std::memcpy(p, counts, sizeof(counts));
+    char *pd = p + 64;
+    std::memcpy(pd, desc.data(), desc.size() * sizeof(InstDesc));
+    char *pc = pd + desc.size() * sizeof(InstDesc);
+    std::memcpy(pc, ct.data(), ct.size() * sizeof(Tile));
+    char *pn = pc + ct.size() * sizeof(Tile);
+    std::memcpy(pn, nt.data(), nt.size() * sizeof(Tile));
+    if ((e = hipMemcpyAsync(s.d_counts, p, sizeof(counts), hipMemcpyHostToDevice, s.stream)) != hipSuccess ||
+        (!desc.empty() && (e = hipMemcpyAsync(s.d_desc, pd, desc.size() * sizeof(InstDesc),
+                                              hipMemcpyHostToDevice, s.stream)) != hipSuccess) ||
+        (!ct.empty() && (e = hipMemcpyAsync(s.d_ctiles, pc, ct.size() * sizeof(Tile),
+                                            hipMemcpyHostToDevice, s.stream)) != hipSuccess) ||
+        (!nt.empty() && (e = hipMemcpyAsync(s.d_ntiles, pn, nt.size() * sizeof(Tile),
+                                            hipMemcpyHostToDevice, s.stream)) != hipSuccess))
+        return hip_err("hipMemcpyAsync(tables)", e);
+    (void)hipEventRecord(s.stage_done, s.stream);
+    s.n_ct = (int64_t)ct.size();
+    s.n_nt = (int64_t)nt.size();
+    s.dirty = false;
+    return "";
+}
+
+std::string stepper_run(Stepper &s, int64_t k) {
+    if (k <= 0) return "";
+    if (s.dirty) {
+        std::string e = stepper_sync_tables(s);
+        if (!e.empty()) return e;
+    }
+    if (s.insts.empty()) return "";
+    // one block per tile; a graph is reused until the tile counts change
+    s.grid_cell = grid_for(s.n_ct);
+    s.grid_node = grid_for(s.n_nt);
+    const int64_t glen = s.steps_per_graph > 0 ? s.steps_per_graph : 0;
+    int64_t left = k;
+    if (glen > 0 && left >= glen) {
+        if (s.graph && (s.graph_k != glen || s.graph_mset != s.mset || s.graph_gc != s.grid_cell ||
+                        s.graph_gn != s.grid_node || s.graph_remap != s.remap))
+            drop_graph(s);
+        if (!s.graph) {
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_err("hipStreamBeginCapture", e);
+            enqueue(s, glen);
+            e = hipStreamEndCapture(s.stream, &g);
+            if (e != hipSuccess) return hip_err("hipStreamEndCapture", e);
+            e = hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) { s.graph = nullptr; return hip_err("hipGraphInstantiate", e); }
+            s.graph_k = (int)glen;
+            s.graph_mset = s.mset;
+            s.graph_gc = s.grid_cell;
+            s.graph_gn = s.grid_node;
+            s.graph_remap = s.remap;
+        }
+        while (left >= glen) {
+            hipError_t e = hipGraphLaunch(s.graph, s.stream);
+            if (e != hipSuccess) return hip_err("hipGraphLaunch", e);
+            left -= glen;
+        }
+    }
+    if (left > 0) enqueue(s, left);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_err("kernel launch", e);
+    for (Inst *I : s.insts) I->host_step = std::min(I->host_step + k, std::max(I->host_step, I->target));
+    return "";
+}
+
+std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms) {
+    if (s.dirty) {
+        std::string e = stepper_sync_tables(s);
+        if (!e.empty()) return e;
+    }
+    const int gc = grid_for(s.n_ct);
+    const int gn = grid_for(s.n_nt);
+    s.grid_cell = gc;
+    s.grid_node = gn;
+    hipEvent_t ev[3];
+    for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) return "hipEventCreate failed";
+    double tc = 0, tn = 0;
+    const Tables tb = tables(s);
+    for (int64_t i = 0; i < n; ++i) {
+        (void)hipEventRecord(ev[0], s.stream);
+        if (s.rs == 8) k_node_gather<double><<<gn, TILE, 0, s.stream>>>(tb, 0, s.remap);
+        else k_node_gather<float><<<gn, TILE, 0, s.stream>>>(tb, 0, s.remap);
+        (void)hipEventRecord(ev[1], s.stream);
+        if (s.rs == 8) {
+            switch (s.mset) {
+            case 1: k_cell<double, 1><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
+            case 8: k_cell<double, 8><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
+            default: k_cell<double, 15><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
+            }
+        } else {
+            switch (s.mset) {
+            case 1: k_cell<float, 1><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
+            case 8: k_cell<float, 8><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
+            default: k_cell<float, 15><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
+            }
+        }
+        (void)hipEventRecord(ev[2], s.stream);
+        k_advance<<<1, 256, 0, s.stream>>>(tb, 1);
+        (void)hipEventSynchronize(ev[2]);
+        float a = 0, b = 0;
+        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+        (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+        tn += a;
+        tc += b;
+    }
+    for (Inst *I : s.insts) I->host_step = std::min(I->host_step + n, std::max(I->host_step, I->target));
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    cell_ms = tc / n;
+    node_ms = tn / n;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? "" : hip_err("kernel launch", e);
+}
+
+}  // namespace ep

@@ -1,0 +1,116 @@
+// Host-side objects behind the C ABI: one simulation instance on the device
+// and a stepper that advances a set of instances with batched kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ep.h"
+#include "kernels.hpp"
+#include "prep.hpp"
+
+namespace ep {
+
+struct StimSpec {
+    std::vector<int32_t> ids;   // caller numbering
+    double t0 = 0, dur = 0, amp = 0, period = 0;
+    int32_t count = 1;
+};
+
+// Everything needed to build an instance (copied from the caller).
+struct InstSpec {
+    std::vector<double> xyz, fibre, scale;
+    std::vector<int32_t> tets;
+    std::vector<uint8_t> model;
+    int64_t n_nodes = 0, n_tets = 0;
+    double sigma_l = 0.17, sigma_t = 0.019;
+    bool has_scale = false;
+    double gscale[4] = {1, 1, 1, 1};   // GKr, GKs, GCaL, GNa
+    std::vector<StimSpec> stims;
+    int ordering = ORDER_RCM;
+    double dt = 0.02, chi = 140.0, cm = 0.01, thr = 0.0, repol = 0.9;
+    int32_t trace_every = 50;
+    int64_t target = INT64_MAX;        // stop stepping at this step index
+};
+
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+
+// Device state of one simulation.
+struct Inst {
+    int rs = 8;                        // sizeof(R): 8 FP64, 4 mixed
+    PrepOut prep;
+    int mset = 0;                      // model-set bits present
+    Allocator al;
+    std::vector<std::pair<void *, size_t>> allocs;
+    size_t footprint = 0;
+    epdev::InstDesc desc{};            // device pointers and parameters
+    epdev::Ctrl *d_ctrl = nullptr;
+    int64_t host_step = 0;             // step index once queued work is done
+    int64_t target = INT64_MAX;
+    int64_t trace_cap = 0;
+    int32_t trace_every = 50;
+    double dt = 0.02;
+    int64_t n_slices = 0;
+};
+
+// Host precompute only (thread-safe, no HIP calls).
+std::string prep_instance(const InstSpec &spec, Inst &out, ep_status &st);
+// Device bytes upload_instance will allocate for a prepared instance.
+size_t instance_footprint(const Inst &inst, int rs, const InstSpec &spec);
+// Allocate and upload a prepared instance.
+std::string upload_instance(const InstSpec &spec, int rs, const Allocator &al, Inst &out,
+                            ep_status &st);
+// prep_instance + upload_instance; returns "" or the reason (st set).
+std::string build_instance(const InstSpec &spec, int rs, const Allocator &al, Inst &out,
+                           ep_status &st);
+void free_instance(Inst &inst);
+// Exact device bytes build_instance would allocate for a mesh of this size
+// and precision (used for admission by footprint).
+size_t estimate_footprint(int64_t n_tets, int64_t n_nodes, int rs, int max_degree_hint = 32);
+
+// A set of instances stepped together on one stream.
+struct Stepper {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int rs = 8;
+    int mset = 0;
+    int grid_cell = 0, grid_node = 0;  // one block per tile (set when launching)
+    int remap = 1;
+    int steps_per_graph = 50;
+    std::vector<Inst *> insts;
+    // device tables
+    epdev::InstDesc *d_desc = nullptr;
+    epdev::Tile *d_ctiles = nullptr, *d_ntiles = nullptr;
+    int32_t *d_counts = nullptr;
+    size_t cap_inst = 0, cap_ct = 0, cap_nt = 0;
+    int64_t n_ct = 0, n_nt = 0;
+    // pinned staging of the tables
+    void *h_stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_k = 0, graph_mset = -1, graph_gc = -1, graph_gn = -1, graph_remap = -1;
+    bool dirty = true;
+};
+
+std::string stepper_init(Stepper &s, int device, hipStream_t stream, int rs);
+void stepper_free(Stepper &s);
+// Rebuild and upload the tables from s.insts (call after membership changes).
+std::string stepper_sync_tables(Stepper &s);
+// Enqueue k steps of every live instance (graphs for whole multiples of the
+// graph length, direct launches for the rest).  Updates host_step.
+std::string stepper_run(Stepper &s, int64_t k);
+// Time one node-gather and one cell launch with events (ms).
+std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms);
+
+int model_ng(int m);
+int model_nc(int m);
+void model_init(int m, double *y);
+
+}  // namespace ep

@@ -1,13 +1,16 @@
-// Device kernels of the monodomain step.
+// Device kernels of the monodomain step, batched over simulation instances.
 //
-// Per step two kernels run: the node gather (the inverse-distance node
-// values of Sec. 3.2) and the fused cell kernel, which evaluates the face
-// fluxes from the node values and neighbour potentials, the stimulus, the
-// cell model, v^{n+1} = v^n + dt (L - I_ion - I_stim) and the activation /
-// APD90 detection, all with level-n inputs.  Cells and nodes are
-// renumbered on the host so that a block's gathers are local; both kernels
-// read structure-of-arrays data with consecutive lanes on consecutive
-// entries.
+// Per step two kernels run over every live instance: the node gather (the
+// inverse-distance node values of Sec. 3.2) and the fused cell kernel, which
+// evaluates the face fluxes from the node values and neighbour potentials,
+// the stimulus, the cell model, v^{n+1} = v^n + dt (L - I_ion - I_stim) and
+// the activation / APD90 detection, all with level-n inputs.
+//
+// Work is described by tables in device memory: one descriptor per instance
+// (its arrays, parameters and step counter) and lists of tiles of at most
+// 256 cells or nodes, each inside one instance; one block per tile.  A
+// captured graph is reused until the set of instances changes.  Every
+// instance keeps its own step counter; v^n lives in buffer n & 1.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -19,13 +22,16 @@ namespace epdev {
 constexpr int MAX_STIM = 32;
 constexpr int NG_MAX = 15;   // gate slots (CRN)
 constexpr int NC_MAX = 6;    // FP64 slots (Stewart)
+constexpr int TILE = 256;    // cells or nodes per tile (= block size)
 
-// Device-resident control block: read by every kernel of a step, so a
-// captured graph can be replayed at any step index.
+// Per-instance control block, device resident.
 struct Ctrl {
-    int64_t step;                 // index n of the next step
+    int64_t step;                 // index n of the next step of this instance
+    int64_t target;               // the instance stops stepping at this index
     int32_t nan_flag;             // set when a non-finite v^{n+1} appears
     int32_t n_stim;
+    uint32_t tiles_done;          // trace reduction: tiles finished this step
+    int32_t pad;
     int64_t st_n0[MAX_STIM];      // first active step
     int64_t st_ndur[MAX_STIM];    // active steps per pulse
     int64_t st_nper[MAX_STIM];    // steps between pulses (0 = single pulse)
@@ -33,206 +39,327 @@ struct Ctrl {
     double st_amp[MAX_STIM];      // pA/pF
 };
 
-// Map block b of nb so that each of the 8 XCDs (blocks are dealt round-robin
-// to XCDs) works on one contiguous range of tiles and its L2 sees the
-// neighbour data of its own range.
+// Everything a block needs to work on one instance (R = double or float
+// arrays are passed as void and typed inside the kernels).
+struct InstDesc {
+    int64_t nc, nn;
+    const int64_t *sell_off;
+    const int32_t *sell_cell;
+    const void *sell_w;
+    const int32_t *cnode;         // [8][nc]
+    const void *cbeta;            // [8][nc]
+    const int32_t *cnbr;          // [4][nc]
+    const void *cb;               // [4][nc]
+    void *vn;                     // [nn]
+    void *v[2];                   // v^n in v[n & 1]
+    void *gate;                   // [NG_MAX][nc]
+    double *conc;                 // [NC_MAX][nc]
+    const uint8_t *model;
+    const uint32_t *smask;
+    uint8_t *dstat;
+    double *t_act, *t_rep;
+    void *vmax;
+    const void *vrest;
+    const double *vol;
+    double *part;                 // one partial sum per cell tile
+    double *trace;                // vbar samples
+    Ctrl *ctrl;
+    double dt, thr, repol, inv_total_vol;
+    GScale gs;
+    int64_t trace_cap;
+    int32_t trace_every;
+    int32_t n_cell_tiles;
+};
+
+// A tile carries a copy of its instance's descriptor, so a block reaches
+// all it needs with one scalar load chain.
+struct Tile {
+    InstDesc d;
+    int64_t begin;                // first cell / node of the tile
+    int32_t count;                // cells / nodes in the tile (<= TILE)
+    int32_t local;                // tile index inside its instance
+};
+
+// The launch grids always equal the tile counts (graphs are re-captured when
+// the counts change), so kernels index the tables without a bound check.
+struct Tables {
+    const InstDesc *desc;         // one per instance (for the step counters)
+    const Tile *cell_tiles;
+    const Tile *node_tiles;
+    const int32_t *counts;        // [0] cell tiles, [1] node tiles, [2] instances
+};
+
+// Blocks are dealt round-robin to the 8 XCDs; remap block b so that each XCD
+// works on one contiguous range of tiles and its L2 holds the neighbour data
+// of that range.  A bijection of [0, nb).
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
     const int64_t x = b & 7, i = b >> 3;
     const int64_t q = nb >> 3, r = nb & 7;
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+__device__ __forceinline__ int64_t my_tile(int remap) {
+    return remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+}
+
+__device__ __forceinline__ bool stepping(const Ctrl *ctrl, int32_t off, int64_t &n) {
+    n = ctrl->step + off;
+    return n < ctrl->target;
+}
+
+// ------------------------------------------------------------ node gather
 template <typename R>
-__global__ void k_node_gather(int64_t nn, const int64_t *__restrict__ off,
-                              const int32_t *__restrict__ cell,
-                              const R *__restrict__ w, const R *__restrict__ v,
-                              R *__restrict__ vn, int remap) {
-    const int64_t b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t n = b * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
-    const int64_t lane = n & 63;
-    const int64_t e0 = off[n >> 6] + lane, e1 = off[(n >> 6) + 1];
-    // four independent gathers in flight per lane; the sum order is fixed
+__global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_off, int remap) {
+    const Tile &T = tb.node_tiles[my_tile(remap)];
+    const InstDesc &D = T.d;
+    int64_t n;
+    if (!stepping(D.ctrl, step_off, n)) return;
+    if ((int32_t)threadIdx.x >= T.count) return;
+    const int64_t node = T.begin + threadIdx.x;
+    const R *__restrict__ v = (const R *)D.v[n & 1];
+    const R *__restrict__ w8 = (const R *)D.sell_w;
+    const int32_t *__restrict__ cell = D.sell_cell;
+    const int64_t e0 = D.sell_off[node >> 6] + (node & 63), e1 = D.sell_off[(node >> 6) + 1];
+    // four independent gathers in flight per lane; fixed summation order
     R a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
     int64_t e = e0;
     for (; e + 192 < e1; e += 256) {
         const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
-        const R w0 = w[e], w1 = w[e + 64], w2 = w[e + 128], w3 = w[e + 192];
-        a0 += w0 * v[c0];
-        a1 += w1 * v[c1];
-        a2 += w2 * v[c2];
-        a3 += w3 * v[c3];
+        const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
+        a0 += x0 * v[c0];
+        a1 += x1 * v[c1];
+        a2 += x2 * v[c2];
+        a3 += x3 * v[c3];
     }
-    for (; e < e1; e += 64) a0 += w[e] * v[cell[e]];
-    vn[n] = (a0 + a1) + (a2 + a3);
+    for (; e < e1; e += 64) a0 += w8[e] * v[cell[e]];
+    ((R *)D.vn)[node] = (a0 + a1) + (a2 + a3);
 }
 
-template <typename R>
-struct CellArgs {
-    int64_t n;                               // cells
-    const int32_t *__restrict__ cnode;       // [8][n]
-    const R *__restrict__ cbeta;             // [8][n]
-    const int32_t *__restrict__ cnbr;        // [4][n]
-    const R *__restrict__ cb;                // [4][n]
-    const R *__restrict__ vn;                // node values
-    const R *__restrict__ vin;               // v^n
-    R *__restrict__ vout;                    // v^{n+1}
-    R *__restrict__ gate;                    // [NG_MAX][n]
-    double *__restrict__ conc;               // [NC_MAX][n]
-    const uint8_t *__restrict__ model;       // [n]
-    const uint32_t *__restrict__ smask;      // [n] stimulus membership bits
-    uint8_t *__restrict__ dstat;             // 0 resting, 1 activated, 2 repolarised
-    double *__restrict__ t_act;
-    double *__restrict__ t_rep;
-    R *__restrict__ vmax;
-    const R *__restrict__ vrest;
-    Ctrl *ctrl;
-    R dt;
-    double dtd;
-    R thr, repol;
-    GScale gs;
+// ------------------------------------------------------------- cell step
+// Per-cell arrays are addressed as a uniform base plus a 32-bit byte offset
+// (scalar-base + vector-offset loads: one offset register serves every array
+// instead of a 64-bit address pair per array).  Instances stay below 2^29
+// cells, so the byte offsets of 8-byte elements fit.
+template <typename T>
+__device__ __forceinline__ T *slot(T *p, int s, int64_t n) { return p + (int64_t)s * n; }
+template <typename T>
+__device__ __forceinline__ T &at(T *p, uint32_t c) {
+    return *(T *)((char *)p + c * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T &at(const T *p, uint32_t c) {
+    return *(const T *)((const char *)p + c * (uint32_t)sizeof(T));
+}
+
+// Slot-major arrays ([slot][n]) go through buffer resources: one resource and
+// one lane offset serve every slot, the slot is a scalar offset.  Offsets are
+// 32-bit, so an instance holds fewer than 2^25 cells (checked on the host).
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, -1, 0x00020000);
+}
+template <typename T> struct BufIO;
+template <> struct BufIO<float> {
+    static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float x, uint32_t v, uint32_t s) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+    }
 };
+template <> struct BufIO<int32_t> {
+    static __device__ __forceinline__ int32_t ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+        return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+    }
+};
+template <> struct BufIO<double> {
+    static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    }
+    static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, double x, uint32_t v, uint32_t s) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, v, s, 0);
+    }
+};
+// element `c` of slot `s` of a slot-major array with n entries per slot
+template <typename T>
+__device__ __forceinline__ T sld(__amdgpu_buffer_rsrc_t r, int s, int64_t n, uint32_t c) {
+    return BufIO<T>::ld(r, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, int64_t n, uint32_t c, T x) {
+    BufIO<T>::st(r, x, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
+}
 
 // MSET: bit 0 TP06 (any layer), 1 CRN, 2 Stewart, 3 passive.
 template <typename R, int MSET>
-__global__ void __launch_bounds__(256) k_cell(CellArgs<R> a, int32_t step_off, int remap) {
-    const int64_t b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t c = b * blockDim.x + threadIdx.x;
-    const int64_t N = a.n;
-    const int64_t n = a.ctrl->step + step_off;
-    const int ns = a.ctrl->n_stim;
-    uint32_t active = 0;
-    for (int i = 0; i < ns; ++i) {
-        const int64_t k = n - a.ctrl->st_n0[i];
-        const int64_t per = a.ctrl->st_nper[i];
-        bool on = k >= 0 && (per <= 0 ? k < a.ctrl->st_ndur[i]
-                                      : (k / per) < a.ctrl->st_count[i] &&
-                                            (k % per) < a.ctrl->st_ndur[i]);
-        active |= (on ? 1u : 0u) << i;
-    }
-    if (c >= N) return;
+__device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
+                                          uint32_t active, bool sample, double &vol_v) {
+    const int64_t N = D.nc;
+    const R *__restrict__ vin = (const R *)D.v[n & 1];
+    R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
+    const R *__restrict__ vn = (const R *)D.vn;
+    const __amdgpu_buffer_rsrc_t rbeta = rsrc(D.cbeta), rb = rsrc(D.cb);
+    const __amdgpu_buffer_rsrc_t rnode = rsrc(D.cnode), rnbr = rsrc(D.cnbr);
 
     // ---- diffusion: fused node-coefficient stencil plus two-point terms
-    const R v = a.vin[c];
+    const R v = at(vin, c);
     R L = R(0);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) L += a.cbeta[s * N + c] * a.vn[a.cnode[s * N + c]];
+    for (int s = 0; s < 8; ++s)
+        L += sld<R>(rbeta, s, N, c) * at(vn, (uint32_t)sld<int32_t>(rnode, s, N, c));
 #pragma unroll
-    for (int f = 0; f < 4; ++f) L += a.cb[f * N + c] * (a.vin[a.cnbr[f * N + c]] - v);
+    for (int f = 0; f < 4; ++f)
+        L += sld<R>(rb, f, N, c) * (at(vin, (uint32_t)sld<int32_t>(rnbr, f, N, c)) - v);
 
     // ---- stimulus
     R istim = R(0);
     if (active) {
-        uint32_t m = a.smask[c] & active;
+        uint32_t m = at(D.smask, c) & active;
         while (m) {
             const int i = __ffs(m) - 1;
-            istim += R(a.ctrl->st_amp[i]);
+            istim += R(D.ctrl->st_amp[i]);
             m &= m - 1;
         }
     }
 
     // ---- cell model
     R iion = R(0);
-    const int md = (MSET == 8) ? 5 : a.model[c];   // TP06 layer or model id
+    const int md = (MSET == 8) ? 5 : at(D.model, c);   // TP06 layer or model id
+    const __amdgpu_buffer_rsrc_t rgate = rsrc(D.gate), rconc = rsrc(D.conc);
+    const R dt = R(D.dt);
     R g[NG_MAX];
     double cc[NC_MAX];
     if ((MSET & 1) && md <= 2) {
 #pragma unroll
-        for (int s = 0; s < tp06::NG; ++s) g[s] = a.gate[s * N + c];
+        for (int s = 0; s < tp06::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
 #pragma unroll
-        for (int s = 0; s < tp06::NC; ++s) cc[s] = a.conc[s * N + c];
-        iion = tp06::step<R>(md, v, g, cc, a.dt, a.dtd, istim, a.gs);
+        for (int s = 0; s < tp06::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+        iion = tp06::step<R>(md, v, g, cc, dt, D.dt, istim, D.gs);
 #pragma unroll
-        for (int s = 0; s < tp06::NG; ++s) a.gate[s * N + c] = g[s];
+        for (int s = 0; s < tp06::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
 #pragma unroll
-        for (int s = 0; s < tp06::NC; ++s) a.conc[s * N + c] = cc[s];
+        for (int s = 0; s < tp06::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
     } else if ((MSET & 2) && md == 3) {
 #pragma unroll
-        for (int s = 0; s < crn::NG; ++s) g[s] = a.gate[s * N + c];
+        for (int s = 0; s < crn::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
 #pragma unroll
-        for (int s = 0; s < crn::NC; ++s) cc[s] = a.conc[s * N + c];
-        iion = crn::step<R>(v, g, cc, a.dt, a.dtd, a.gs);
+        for (int s = 0; s < crn::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+        iion = crn::step<R>(v, g, cc, dt, D.dt, D.gs);
 #pragma unroll
-        for (int s = 0; s < crn::NG; ++s) a.gate[s * N + c] = g[s];
+        for (int s = 0; s < crn::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
 #pragma unroll
-        for (int s = 0; s < crn::NC; ++s) a.conc[s * N + c] = cc[s];
+        for (int s = 0; s < crn::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
     } else if ((MSET & 4) && md == 4) {
 #pragma unroll
-        for (int s = 0; s < stewart::NG; ++s) g[s] = a.gate[s * N + c];
+        for (int s = 0; s < stewart::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
 #pragma unroll
-        for (int s = 0; s < stewart::NC; ++s) cc[s] = a.conc[s * N + c];
-        iion = stewart::step<R>(v, g, cc, a.dt, a.dtd, istim, a.gs);
+        for (int s = 0; s < stewart::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+        iion = stewart::step<R>(v, g, cc, dt, D.dt, istim, D.gs);
 #pragma unroll
-        for (int s = 0; s < stewart::NG; ++s) a.gate[s * N + c] = g[s];
+        for (int s = 0; s < stewart::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
 #pragma unroll
-        for (int s = 0; s < stewart::NC; ++s) a.conc[s * N + c] = cc[s];
+        for (int s = 0; s < stewart::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
     }
 
     // ---- explicit update of v
-    const R vnew = v + a.dt * (L - iion - istim);
-    a.vout[c] = vnew;
-    if (!(fabs(vnew) < R(1e30))) atomicOr(&a.ctrl->nan_flag, 1);
+    const R vnew = v + dt * (L - iion - istim);
+    at(vout, c) = vnew;
+    if (!(fabs(vnew) < R(1e30))) atomicOr(&D.ctrl->nan_flag, 1);
+    if (sample) vol_v = at(D.vol, c) * double(vnew);
 
     // ---- activation time and APD90
-    const uint8_t st = a.dstat[c];
+    const uint8_t st = at(D.dstat, c);
     if (st == 0) {
-        if (v <= a.thr && vnew > a.thr) {
-            a.t_act[c] = (double(n) + double((a.thr - v) / (vnew - v))) * a.dtd;
-            a.vmax[c] = vnew;
-            a.dstat[c] = 1;
+        const R thr = R(D.thr);
+        if (v <= thr && vnew > thr) {
+            at(D.t_act, c) = (double(n) + double((thr - v) / (vnew - v))) * D.dt;
+            at((R *)D.vmax, c) = vnew;
+            at(D.dstat, c) = 1;
         }
     } else if (st == 1) {
-        R vm = a.vmax[c];
+        R vm = at((const R *)D.vmax, c);
         if (vnew > vm) {
             vm = vnew;
-            a.vmax[c] = vm;
+            at((R *)D.vmax, c) = vm;
         }
-        const R v90 = vm - a.repol * (vm - a.vrest[c]);
+        const R v90 = vm - R(D.repol) * (vm - at((const R *)D.vrest, c));
         if (v >= v90 && vnew < v90) {
-            a.t_rep[c] = (double(n) + double((v - v90) / (v - vnew))) * a.dtd;
-            a.dstat[c] = 2;
+            at(D.t_rep, c) = (double(n) + double((v - v90) / (v - vnew))) * D.dt;
+            at(D.dstat, c) = 2;
         }
     }
 }
 
-__global__ void k_advance(Ctrl *ctrl, int64_t k) { ctrl->step += k; }
-
-// Volume-weighted sum of v, stage 1: one partial per block.
-template <typename R>
-__global__ void __launch_bounds__(256) k_vsum_partial(int64_t n, const R *__restrict__ v,
-                                                      const double *__restrict__ vol,
-                                                      double *__restrict__ part) {
-    __shared__ double red[256];
-    double acc = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256)
-        acc += vol[c] * double(v[c]);
-    red[threadIdx.x] = acc;
+// Trace of vbar: each tile of an instance that just produced a sample step
+// stores its partial sum; the last tile to finish (atomic ticket) adds the
+// partials in tile order, so the result does not depend on scheduling.
+__device__ __forceinline__ void trace_tile(const InstDesc &D, const Tile &T, int64_t n,
+                                           double x, double *red) {
+    red[threadIdx.x] = x;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = TILE / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        D.part[T.local] = red[0];
+        __threadfence();
+        const uint32_t k = atomicAdd(&D.ctrl->tiles_done, 1u);
+        last = (k + 1 == (uint32_t)D.n_cell_tiles);
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < D.n_cell_tiles; i += TILE)
+            acc += ((volatile double *)D.part)[i];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = TILE / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int64_t idx = (n + 1) / D.trace_every;
+            if (idx < D.trace_cap) D.trace[idx] = red[0] * D.inv_total_vol;
+            D.ctrl->tiles_done = 0u;
+        }
+    }
+    __syncthreads();
 }
 
-// Stage 2 (one block): fixed-order sum of the partials, stored as the trace
-// sample of step ctrl->step + step_off.
-__global__ void __launch_bounds__(256) k_vsum_final(int nparts, const double *__restrict__ part,
-                                                    double inv_vol, const Ctrl *ctrl, int32_t step_off,
-                                                    int32_t every, int64_t cap,
-                                                    double *__restrict__ trace) {
-    __shared__ double red[256];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
+template <typename R, int MSET>
+__global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
+    __shared__ double red[TILE];
+    const Tile &T = tb.cell_tiles[my_tile(remap)];
+    const InstDesc &D = T.d;
+    int64_t n;
+    if (!stepping(D.ctrl, step_off, n)) return;
+    uint32_t active = 0;
+    const int ns = D.ctrl->n_stim;
+    for (int i = 0; i < ns; ++i) {
+        const int64_t k = n - D.ctrl->st_n0[i];
+        const int64_t per = D.ctrl->st_nper[i];
+        const bool on = k >= 0 && (per <= 0 ? k < D.ctrl->st_ndur[i]
+                                            : (k / per) < D.ctrl->st_count[i] &&
+                                                  (k % per) < D.ctrl->st_ndur[i]);
+        active |= (on ? 1u : 0u) << i;
     }
-    if (threadIdx.x == 0) {
-        const int64_t idx = (ctrl->step + step_off) / every;
-        if (idx >= 0 && idx < cap) trace[idx] = red[0] * inv_vol;
+    double x = 0.0;
+    const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
+    if ((int32_t)threadIdx.x < T.count)
+        cell_step<R, MSET>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
+    if (sample) trace_tile(D, T, n, x, red);
+}
+
+// Advance the step counter of every live instance by k (capped at target).
+static __global__ void k_advance(Tables tb, int64_t k) {
+    const int32_t ni = tb.counts[2];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += gridDim.x * blockDim.x) {
+        Ctrl *c = tb.desc[i].ctrl;
+        const int64_t s = c->step + k;
+        c->step = s < c->target ? s : (c->step < c->target ? c->target : c->step);
     }
 }
 

@@ -70,8 +70,9 @@ V3 node(const PrepIn &in, int32_t i) {
 
 std::string validate(const PrepIn &in) {
     if (in.n_nodes <= 0 || in.n_tets <= 0) return "empty mesh";
-    if (in.n_tets > (int64_t)INT32_MAX / 8 || in.n_nodes > (int64_t)INT32_MAX)
-        return "mesh too large for 32-bit indices";
+    // device arrays of one instance are addressed with 32-bit byte offsets
+    if (in.n_tets >= ((int64_t)1 << 25) || in.n_nodes >= ((int64_t)1 << 28))
+        return "mesh too large for one instance (limit 2^25 tets)";
     for (int64_t i = 0; i < 4 * in.n_tets; ++i)
         if (in.tets[i] < 0 || in.tets[i] >= in.n_nodes)
             return "tet " + std::to_string(i / 4) + " references node out of range";

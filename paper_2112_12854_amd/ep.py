@@ -35,6 +35,35 @@ class ep_options(C.Structure):
                 ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p)]
 
 
+class ep_stimulus(C.Structure):
+    _fields_ = [("n_ids", C.c_int64), ("ids", C.POINTER(C.c_int32)), ("t0", C.c_double),
+                ("dur", C.c_double), ("amp", C.c_double), ("period", C.c_double),
+                ("count", C.c_int32)]
+
+
+class ep_request(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.POINTER(C.c_double)),
+                ("n_tets", C.c_int64), ("tet_nodes", C.POINTER(C.c_int32)),
+                ("fibre", C.POINTER(C.c_double)), ("sigma_l", C.c_double),
+                ("sigma_t", C.c_double), ("scale", C.POINTER(C.c_double)),
+                ("model", C.POINTER(C.c_uint8)), ("n_stimuli", C.c_int32),
+                ("stimuli", C.POINTER(ep_stimulus)), ("ionic_scale", C.c_double * 4),
+                ("n_steps", C.c_int64)]
+
+
+class ep_result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("status", C.c_int), ("n_tets", C.c_int64),
+                ("steps", C.c_int64), ("footprint", C.c_size_t), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ep_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("running", C.c_int64),
+                ("queued", C.c_int64), ("cell_steps", C.c_double),
+                ("bytes_in_use", C.c_size_t), ("bytes_budget", C.c_size_t),
+                ("graph_launches", C.c_int64), ("table_updates", C.c_int64)]
+
+
 class EPError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -77,6 +106,19 @@ _SIGS = {
     "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp]),
     "ep_algorithmic_bytes": (C.c_int, [C.c_void_p, _dp, _dp]),
     "ep_last_error": (C.c_char_p, [C.c_void_p]),
+    "ep_server_create": (C.c_int, [C.POINTER(ep_options), C.c_size_t, C.c_int32,
+                                   C.POINTER(C.c_void_p)]),
+    "ep_server_submit": (C.c_int, [C.c_void_p, C.POINTER(ep_request), C.POINTER(C.c_int64)]),
+    "ep_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(ep_result)]),
+    "ep_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(ep_result)]),
+    "ep_server_get_vm": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
+    "ep_server_get_activation": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
+    "ep_server_get_apd90": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
+    "ep_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
+    "ep_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ep_server_stats)]),
+    "ep_server_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "ep_server_destroy": (None, [C.c_void_p]),
+    "ep_server_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
 
@@ -197,6 +239,7 @@ class Sim:
         _check(lib().ep_sync(self.h), self.h)
 
     def set_launch(self, block=256, steps_per_graph=50, xcd_remap=1):
+        """block: 0 or 256; steps_per_graph: 0 = no graphs."""
         _check(lib().ep_set_launch(self.h, block, steps_per_graph, xcd_remap), self.h)
 
     # ---- readouts
@@ -267,3 +310,117 @@ def model_n_slots(model: int) -> int:
 
 def model_slot_names(model: int):
     return [lib().ep_model_slot_name(model, i).decode() for i in range(model_n_slots(model))]
+
+
+def _result_dict(r: ep_result) -> dict:
+    return dict(id=r.id, status=r.status, n_tets=r.n_tets, steps=r.steps,
+                footprint=r.footprint, t_submit=r.t_submit, t_admit=r.t_admit,
+                t_done=r.t_done, latency=r.t_done - r.t_submit)
+
+
+class Server:
+    """Continuous-batching server (ep_server_*): submit workloads, wait, read."""
+
+    def __init__(self, prec: int = EP_FP32_MIXED, dt: float = 0.02, hbm_budget: int = 0,
+                 max_slots: int = 64, device: int = 0, trace_every: int = 50,
+                 allocator: str = "hip", steps_per_graph: int = 50, chi=140.0, cm=0.01):
+        L = lib()
+        o = ep_options()
+        L.ep_default_options(C.byref(o))
+        o.prec, o.device, o.dt, o.chi, o.cm = prec, device, dt, chi, cm
+        o.trace_every = trace_every
+        self._alloc = None
+        self._stream = None
+        if allocator == "torch":
+            import torch
+            self._alloc = _TorchAllocator(device)
+            o.dev_alloc, o.dev_free = self._alloc.alloc_cb, self._alloc.free_cb
+            self._stream = torch.cuda.Stream(device=device)
+            o.stream = C.c_void_p(self._stream.cuda_stream)
+        h = C.c_void_p()
+        _check(L.ep_server_create(C.byref(o), int(hbm_budget), int(max_slots), C.byref(h)))
+        self.h = h
+        self.n_of = {}
+        _check(L.ep_server_set_launch(h, steps_per_graph, 1))
+
+    def _err(self):
+        return lib().ep_server_last_error(self.h).decode()
+
+    def _chk(self, st):
+        if st != EP_OK:
+            raise EPError(st, self._err())
+
+    def submit(self, w, n_steps: int) -> int:
+        xyz = np.ascontiguousarray(w.xyz, np.float64)
+        tets = np.ascontiguousarray(w.tets, np.int32)
+        fib = np.ascontiguousarray(w.fibre, np.float64)
+        sc = None if w.scale is None else np.ascontiguousarray(w.scale, np.float64)
+        mdl = np.ascontiguousarray(w.model, np.uint8)
+        ids = [np.ascontiguousarray(st.ids, np.int32) for st in w.stimuli]
+        stims = (ep_stimulus * max(1, len(w.stimuli)))()
+        for k, st in enumerate(w.stimuli):
+            stims[k] = ep_stimulus(ids[k].size, ids[k].ctypes.data_as(_ip), st.t0, st.dur,
+                                   st.amp, st.period, st.count)
+        rq = ep_request()
+        rq.n_nodes, rq.xyz = w.n_nodes, _d(xyz)
+        rq.n_tets, rq.tet_nodes = w.n_tets, tets.ctypes.data_as(_ip)
+        rq.fibre, rq.sigma_l, rq.sigma_t = _d(fib), w.sigma_l, w.sigma_t
+        rq.scale = None if sc is None else _d(sc)
+        rq.model = mdl.ctypes.data_as(C.POINTER(C.c_uint8))
+        rq.n_stimuli, rq.stimuli = len(w.stimuli), stims
+        gs = w.ionic_scale or {}
+        for i, k in enumerate(("GKr", "GKs", "GCaL", "GNa")):
+            rq.ionic_scale[i] = float(gs.get(k, 1.0))
+        rq.n_steps = int(n_steps)
+        rid = C.c_int64()
+        self._chk(lib().ep_server_submit(self.h, C.byref(rq), C.byref(rid)))
+        self.n_of[rid.value] = w.n_tets
+        return rid.value
+
+    def poll(self, rid: int):
+        r = ep_result()
+        st = lib().ep_server_poll(self.h, rid, C.byref(r))
+        if st == EP_EBUSY:
+            return None
+        self._chk(st)
+        return _result_dict(r)
+
+    def wait(self, rid: int) -> dict:
+        r = ep_result()
+        self._chk(lib().ep_server_wait(self.h, rid, C.byref(r)))
+        return _result_dict(r)
+
+    def _vec(self, fn, rid):
+        out = np.empty(self.n_of[rid])
+        st = fn(self.h, rid, _d(out), out.size)
+        if st not in (EP_OK, EP_ENUMERIC):
+            self._chk(st)
+        return out
+
+    def vm(self, rid):
+        return self._vec(lib().ep_server_get_vm, rid)
+
+    def activation(self, rid):
+        return self._vec(lib().ep_server_get_activation, rid)
+
+    def apd90(self, rid):
+        return self._vec(lib().ep_server_get_apd90, rid)
+
+    def release(self, rid):
+        self._chk(lib().ep_server_release(self.h, rid))
+
+    def stats(self) -> dict:
+        s = ep_server_stats()
+        self._chk(lib().ep_server_get_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ep_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ep_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -67,6 +67,7 @@ class Workload:
     ionic_scale: dict = field(default_factory=dict)  # "GKr","GKs","GCaL","GNa"
     hex_ijk: np.ndarray | None = None  # [n_tets, 3] hex index of each tet
     dims: tuple = ()                   # (nx, ny, nz, h)
+    purkinje: object = None            # Purkinje graph (heart workloads)
 
     @property
     def n_tets(self) -> int:
@@ -288,3 +289,234 @@ def serving_workload(spec: dict, n_steps: int, dt: float = 0.02) -> Workload:
                     np.full(n, TP06_ENDO, np.uint8),
                     scale=np.full(n, spec["sigma_scale"]), stimuli=[stim],
                     dt=dt, n_steps=n_steps, hex_ijk=hijk, dims=(nx, ny, nz, h))
+
+
+# ------------------------------------------------------ three-media heart --
+
+@dataclass
+class Purkinje:
+    """A 1D Purkinje graph: node coordinates [n,3], edges [m,2], terminal
+    (junction) nodes, conductivity sigma (mS/mm) and the cell model."""
+    xyz: np.ndarray
+    edges: np.ndarray
+    pmj_nodes: np.ndarray
+    sigma: float = 3.95            # mS/mm, Sec. 5 table (4 m/s)
+    model: int = STEWART
+    n_sub: int = 0                 # substeps per tissue step (0 = from stability)
+    pmj_radius: float = 0.1        # mm, Sec. 3.3
+    delay_ortho: float = 5.0       # ms, Sec. 3.3
+    delay_anti: float = 3.0        # ms (antidromic, pathologic two-way coupling)
+    two_way: bool = False
+    pmj_amp: float = -200.0        # pA/pF
+    pmj_dur: float = 0.5           # ms, Sec. 3.3 (S_d of communication nodes)
+
+
+def _ellipsoid_depth(p, a_in, c_in, a_out, c_out, iters=30):
+    """Normalised wall depth s in [0, 1] (0 inner surface, 1 outer) of points
+    p [n,3] between two confocal-like prolate ellipsoids (axis z): the s with
+    (x^2+y^2)/a(s)^2 + z^2/c(s)^2 = 1, a(s), c(s) linear in s (bisection)."""
+    r2 = p[:, 0] ** 2 + p[:, 1] ** 2
+    z2 = p[:, 2] ** 2
+    lo = np.full(p.shape[0], -1.0)
+    hi = np.full(p.shape[0], 2.0)
+    for _ in range(iters):
+        s = 0.5 * (lo + hi)
+        a = a_in + s * (a_out - a_in)
+        c = c_in + s * (c_out - c_in)
+        f = r2 / a ** 2 + z2 / c ** 2 - 1.0
+        lo = np.where(f > 0, s, lo)
+        hi = np.where(f > 0, hi, s)
+    return 0.5 * (lo + hi)
+
+
+def heart(h: float = 0.5, seed: int = 3, scale: float = 1.0, purkinje_nodes: int = 60000,
+          n_pmj: int = 2000, seg: float = 0.1, with_atria: bool = True):
+    """Synthetic three-media heart (stand-in for the paper's anatomical
+    meshes, Sec. 2): a biventricle of two truncated prolate-ellipsoidal
+    shells (LV, and an RV shell fused to it through the septum) with TP06
+    layers and transmurally rotating fibres, an electrically insulated
+    atrial cap shell above the base (Courtemanche, conductivity x 1.05, Sec. 5
+    table), and a seeded fractal Purkinje tree grown on the endocardium with
+    Stewart cells whose leaves outside the septum are the junctions.
+    Voxelised on the 5-tet lattice at spacing h; `scale` shrinks every
+    length (scale 1: ~10M ventricular + ~2M atrial tets at h = 0.5)."""
+    L = scale
+    # LV: inner (a, c) = (22, 70), outer (32, 80) mm; RV shifted +x, thinner
+    lv = (22 * L, 70 * L, 32 * L, 80 * L)
+    rv_off = np.array([26 * L, 0.0, -4 * L])
+    rv = (28 * L, 62 * L, 33 * L, 66 * L)
+    z_base = 0.0
+    at_gap, at_thick = 4 * L, 3 * L
+    at_a, at_c = 30 * L, 22 * L
+    lo = np.array([-33 * L, -34 * L, -82 * L])
+    hi = np.array([60 * L, 34 * L, (at_gap + at_c + at_thick + 1) * L if with_atria else 1.0])
+    n = np.ceil((hi - lo) / h).astype(int)
+    ii, jj, kk = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    cen = lo + (np.stack([ii, jj, kk], axis=-1).reshape(-1, 3) + 0.5) * h
+
+    def shell(p, a_i, c_i, a_o, c_o):
+        r2 = p[:, 0] ** 2 + p[:, 1] ** 2
+        outer = r2 / a_o ** 2 + p[:, 2] ** 2 / c_o ** 2 <= 1.0
+        inner = r2 / a_i ** 2 + p[:, 2] ** 2 / c_i ** 2 <= 1.0
+        return outer & ~inner, inner
+
+    below = cen[:, 2] < z_base
+    lv_wall, lv_cav = shell(cen, *lv)
+    rv_wall, rv_cav = shell(cen - rv_off, *rv)
+    vent = below & ((lv_wall | rv_wall) & ~lv_cav & ~rv_cav)
+    region = np.zeros(cen.shape[0], np.int8)
+    region[vent] = 1
+    if with_atria:
+        pa = cen - np.array([8 * L, 0.0, at_gap])
+        r2 = pa[:, 0] ** 2 + pa[:, 1] ** 2
+        o = r2 / (at_a + at_thick) ** 2 + pa[:, 2] ** 2 / (at_c + at_thick) ** 2 <= 1
+        i_ = r2 / at_a ** 2 + pa[:, 2] ** 2 / at_c ** 2 <= 1
+        atria = o & ~i_ & (pa[:, 2] >= 0)
+        region[atria & ~vent] = 2
+    keep = np.nonzero(region > 0)[0]
+    hx = np.stack(np.unravel_index(keep, tuple(n)), axis=1)
+    # 5-tet split of the kept hexes on the global lattice (same rule as slab())
+    ny1, nz1 = n[1] + 1, n[2] + 1
+
+    def nid(a):
+        return (a[:, 0] * ny1 + a[:, 1]) * nz1 + a[:, 2]
+
+    even_local = [(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+    odd_local = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1)]
+    par = hx.sum(axis=1) & 1
+    tets = np.empty((keep.size, 5, 4), np.int64)
+    for hp in (0, 1):
+        sel = par == hp
+        base = hx[sel]
+        cen_c = even_local if hp == 0 else odd_local
+        cut = odd_local if hp == 0 else even_local
+        tets[sel, 0, :] = np.stack([nid(base + np.array(q)) for q in cen_c], axis=1)
+        for t, q in enumerate(cut):
+            a, b, c = q
+            tets[sel, 1 + t, 0] = nid(base + np.array(q))
+            for m, r in enumerate([(1 - a, b, c), (a, 1 - b, c), (a, b, 1 - c)]):
+                tets[sel, 1 + t, 1 + m] = nid(base + np.array(r))
+    tets = tets.reshape(-1, 4)
+    used, inv = np.unique(tets, return_inverse=True)
+    tets = inv.reshape(-1, 4).astype(np.int32)
+    gi = np.stack(np.unravel_index(used, (n[0] + 1, n[1] + 1, n[2] + 1)), axis=1)
+    xyz = lo + gi * h
+    reg = np.repeat(region[keep], 5)
+    hcen = np.repeat(cen[keep], 5, axis=0)
+    nt = tets.shape[0]
+    # depth, layers and fibres of the ventricles (LV depth; RV free wall by its own shell)
+    d_lv = _ellipsoid_depth(hcen, *lv)
+    d_rv = _ellipsoid_depth(hcen - rv_off, *rv)
+    in_rv = (hcen[:, 0] - rv_off[0]) ** 2 / rv[2] ** 2 + hcen[:, 1] ** 2 / rv[2] ** 2 + \
+        (hcen[:, 2] - rv_off[2]) ** 2 / rv[3] ** 2 <= 1.0
+    in_lv_wall = (hcen[:, 0] ** 2 + hcen[:, 1] ** 2) / lv[2] ** 2 + hcen[:, 2] ** 2 / lv[3] ** 2 <= 1.0
+    d = np.where(in_lv_wall, d_lv, d_rv)
+    d = np.clip(d, 0.0, 1.0)
+    model = np.where(d < 0.3, TP06_ENDO, np.where(d < 0.7, TP06_MID, TP06_EPI)).astype(np.uint8)
+    rng = np.random.default_rng(seed)
+    alpha = np.deg2rad(-60.0 + 120.0 * d + rng.normal(0.0, 5.0, nt))
+    # circumferential and meridional unit vectors of the local ellipsoid
+    q = np.where(in_rv[:, None] & ~in_lv_wall[:, None], hcen - rv_off, hcen)
+    rr = np.maximum(np.hypot(q[:, 0], q[:, 1]), 1e-9)
+    e_t = np.stack([-q[:, 1] / rr, q[:, 0] / rr, np.zeros(nt)], axis=1)
+    e_l = np.stack([q[:, 0] / rr * 0.3, q[:, 1] / rr * 0.3, np.ones(nt)], axis=1)
+    e_l -= (e_l * e_t).sum(axis=1, keepdims=True) * e_t
+    e_l /= np.linalg.norm(e_l, axis=1, keepdims=True)
+    fibre = np.cos(alpha)[:, None] * e_t + np.sin(alpha)[:, None] * e_l
+    scale_arr = np.ones(nt)
+    atr = reg == 2
+    if atr.any():
+        model[atr] = CRN
+        fibre[atr] = e_t[atr]                 # circumferential around the cap
+        scale_arr[atr] = 1.05
+    fibre /= np.linalg.norm(fibre, axis=1, keepdims=True)
+    stimuli = []
+    if atr.any():
+        # sino-atrial-like ball of 1.5 mm on the cap at t = 0
+        top = hcen[atr][np.argmax(hcen[atr][:, 0])]
+        ids = np.nonzero(atr & (np.linalg.norm(hcen - top, axis=1) < 1.5 * max(L, h)))[0]
+        stimuli.append(Stimulus(ids=ids.astype(np.int32), t0=0.0, dur=2.0, amp=-40.0))
+    w = Workload(f"heart-h{h}-s{scale}", xyz, tets, fibre, model, sigma_l=SIGMA_L,
+                 sigma_t=SIGMA_T, scale=scale_arr, stimuli=stimuli, dt=0.01,
+                 n_steps=80000, hex_ijk=None, dims=())
+    pk = purkinje_tree(lv, rv, rv_off, n_nodes=purkinje_nodes, n_pmj=n_pmj, seg=seg,
+                       seed=seed, z_base=z_base)
+    w.purkinje = pk
+    # the His-bundle root is stimulated at 130 ms (AV conduction, Sec. 1)
+    w.stimuli.append(Stimulus(ids=np.array([0], np.int32), t0=130.0, dur=2.0,
+                              amp=-100.0, domain=1))
+    return w
+
+
+def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_base=0.0):
+    """Seeded fractal tree on the LV and RV endocardium: from a root near the
+    base of the septum, branches of random length (2-12 mm, segments of
+    `seg` mm) split into two at +-20..50 deg, each point projected back onto
+    the endocardial ellipsoid, until n_nodes nodes exist.  Leaves become the
+    junctions, except those within 4 mm of the septal plane (the paper places
+    none in the septum); at most n_pmj are kept, evenly subsampled."""
+    rng = np.random.default_rng(seed)
+    a_i, c_i = lv[0], lv[1]
+
+    def project(p, side):
+        if side == 0:
+            q = p.copy()
+            a, c = a_i * 1.01, c_i * 1.01
+        else:
+            q = p - rv_off
+            a, c = rv[0] * 1.01, rv[1] * 1.01
+        s = np.sqrt((q[0] ** 2 + q[1] ** 2) / a ** 2 + q[2] ** 2 / c ** 2)
+        q = q / s
+        q[2] = min(q[2], z_base - 1.0)
+        return q if side == 0 else q + rv_off
+
+    pts = [np.array([a_i * 0.9, 0.0, z_base - 2.0])]
+    side_of = [0]
+    edges = []
+    leaves = []
+    # two bundle branches, one per ventricle
+    stack = []
+    for side, direc in ((0, np.array([0.0, 0.3, -1.0])), (1, np.array([0.3, -0.3, -1.0]))):
+        stack.append((0, side, direc / np.linalg.norm(direc), 0))
+    while stack and len(pts) < n_nodes:
+        start, side, direc, depth = stack.pop(0)
+        length = rng.uniform(2.0, 12.0) * (1.6 if depth < 2 else 1.0)
+        nseg = max(2, int(length / seg))
+        prev = start
+        for _ in range(nseg):
+            if len(pts) >= n_nodes:
+                break
+            p = project(pts[prev] + seg * direc, side)
+            step = p - pts[prev]
+            nrm = np.linalg.norm(step)
+            if nrm < 0.2 * seg:
+                break
+            direc = step / nrm
+            p = pts[prev] + seg * direc       # every segment is exactly `seg` long
+            pts.append(p)
+            side_of.append(side)
+            edges.append((prev, len(pts) - 1))
+            prev = len(pts) - 1
+        if len(pts) >= n_nodes or depth > 40:
+            leaves.append(prev)
+            continue
+        for sgn in (-1.0, 1.0):
+            ang = np.deg2rad(rng.uniform(20, 50)) * sgn
+            axis = pts[prev] - (np.zeros(3) if side == 0 else rv_off)
+            axis /= np.linalg.norm(axis)
+            # rotate direc about the surface normal by ang (Rodrigues)
+            nd = (direc * np.cos(ang) + np.cross(axis, direc) * np.sin(ang) +
+                  axis * np.dot(axis, direc) * (1 - np.cos(ang)))
+            stack.append((prev, side, nd / np.linalg.norm(nd), depth + 1))
+    for item in stack:
+        leaves.append(item[0])
+    xyz = np.array(pts)
+    edges = np.array(edges, np.int32).reshape(-1, 2)
+    leaves = np.unique(np.array(leaves, np.int64))
+    deg = np.bincount(edges.ravel(), minlength=xyz.shape[0])
+    leaves = leaves[deg[leaves] == 1]
+    septal = np.abs(xyz[leaves, 0] - 0.5 * (a_i + (rv_off[0] - rv[0]))) < 4.0
+    leaves = leaves[~septal]
+    if leaves.size > n_pmj:
+        leaves = leaves[np.linspace(0, leaves.size - 1, n_pmj).astype(int)]
+    return Purkinje(xyz=xyz, edges=edges, pmj_nodes=leaves.astype(np.int32))

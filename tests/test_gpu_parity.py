@@ -184,7 +184,7 @@ def test_single_tet_and_ordering_edge_cases(ep, oracle_lib):
 def test_graph_replay_equals_direct_launch(ep):
     w = M.config1(nx=8, ny=8, nz=2)
     a = ep.Sim(w, launch=(256, 50, 1))
-    b = ep.Sim(w, launch=(128, 0, 0))
+    b = ep.Sim(w, launch=(256, 0, 0))
     for n in (7, 100, 243, 50):
         a.step(n)
         b.step(n)

@@ -1,0 +1,121 @@
+"""Continuous batching on the GPU: requests of uneven size run together, join
+while others run, are admitted by HBM footprint, and each result is the same
+(bitwise) as the same request run alone.  A request that goes non-finite
+fails alone."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2112_12854_amd import meshgen as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ep():
+    from paper_2112_12854_amd import ep as _ep
+    _ep.lib()
+    return _ep
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def requests(n, seed=4, n_lo=2e3, n_hi=2e4, steps=600):
+    specs = M.serving_requests(n=n, seed=seed, n_lo=n_lo, n_hi=n_hi)
+    out = []
+    rng = np.random.default_rng(seed)
+    for sp in specs:
+        w = M.serving_workload(sp, n_steps=steps)
+        w.ionic_scale = {k: float(rng.uniform(0.7, 1.3)) for k in ("GKr", "GKs", "GCaL", "GNa")}
+        out.append(w)
+    return out
+
+
+def alone(ep, w, prec, steps):
+    s = ep.Sim(w, prec=prec)
+    s.step(steps)
+    return s.vm(), s.activation(), s.apd90()
+
+
+@pytest.mark.parametrize("prec_name", ["EP_FP32_MIXED", "EP_FP64"])
+def test_mix_equals_alone_bitwise(ep, prec_name):
+    prec = getattr(ep, prec_name)
+    steps = 600
+    ws = requests(5, steps=steps)
+    say(f"serving mix ({prec_name}): sizes {[w.n_tets for w in ws]}")
+    sv = ep.Server(prec=prec, max_slots=8, steps_per_graph=50)
+    ids = [sv.submit(ws[0], steps), sv.submit(ws[1], steps)]
+    time.sleep(0.05)                       # the rest joins while these run
+    ids += [sv.submit(w, steps) for w in ws[2:]]
+    res = [sv.wait(i) for i in ids]
+    assert all(r["status"] == ep.EP_OK for r in res)
+    for w, i in zip(ws, ids):
+        vm, at, apd = alone(ep, w, prec, steps)
+        assert np.array_equal(sv.vm(i), vm)
+        assert np.array_equal(sv.activation(i), at, equal_nan=True)
+        assert np.array_equal(sv.apd90(i), apd, equal_nan=True)
+    st = sv.stats()
+    assert st["completed"] == len(ws) and st["running"] == 0
+    assert st["cell_steps"] == sum(w.n_tets for w in ws) * steps
+    sv.close()
+
+
+def test_admission_by_footprint(ep):
+    """A budget that holds only about two requests: all still finish, never
+    more than the budget is resident, results unchanged."""
+    steps = 300
+    ws = requests(6, seed=7, steps=steps)
+    probe = ep.Sim(ws[0], prec=ep.EP_FP32_MIXED)
+    per_tet = probe.footprint() / ws[0].n_tets
+    probe.close()
+    budget = int(2.2 * per_tet * max(w.n_tets for w in ws))
+    say(f"admission: budget {budget / 2**20:.1f} MiB for sizes {[w.n_tets for w in ws]}")
+    sv = ep.Server(prec=ep.EP_FP32_MIXED, hbm_budget=budget, max_slots=16)
+    ids = [sv.submit(w, steps) for w in ws]
+    peak = 0
+    while any(sv.poll(i) is None for i in ids):
+        peak = max(peak, sv.stats()["bytes_in_use"])
+        time.sleep(0.002)
+    assert peak <= budget
+    res = [sv.wait(i) for i in ids]
+    assert all(r["status"] == ep.EP_OK for r in res)
+    # with this budget some requests had to queue behind others
+    assert max(r["t_admit"] for r in res) > min(r["t_done"] for r in res) - 1e-9
+    for w, i in zip(ws[:2], ids[:2]):
+        vm, at, _ = alone(ep, w, ep.EP_FP32_MIXED, steps)
+        assert np.array_equal(sv.vm(i), vm)
+    sv.close()
+
+
+def test_nonfinite_request_fails_alone(ep):
+    steps = 200
+    ws = requests(3, seed=9, steps=steps)
+    bad = requests(1, seed=10, steps=steps)[0]
+    bad.stimuli[0].amp = -1e35             # drives v out of range -> non-finite
+    sv = ep.Server(prec=ep.EP_FP32_MIXED, max_slots=8)
+    ids = [sv.submit(w, steps) for w in ws]
+    bid = sv.submit(bad, steps)
+    res = {i: sv.wait(i) for i in ids + [bid]}
+    assert res[bid]["status"] == ep.EP_ENUMERIC
+    for w, i in zip(ws, ids):
+        assert res[i]["status"] == ep.EP_OK
+        vm, _, _ = alone(ep, w, ep.EP_FP32_MIXED, steps)
+        assert np.array_equal(sv.vm(i), vm)
+    sv.close()
+
+
+def test_malformed_and_oversized_requests(ep):
+    sv = ep.Server(prec=ep.EP_FP32_MIXED, hbm_budget=1 << 20, max_slots=2)
+    w = requests(1, seed=3, n_lo=2e4, n_hi=3e4)[0]
+    with pytest.raises(ep.EPError):
+        sv.submit(w, 0)                    # no steps
+    try:                                   # cannot fit 1 MiB
+        rid = sv.submit(w, 10)
+    except ep.EPError as e:
+        assert e.status == ep.EP_ENOMEM
+    else:
+        assert sv.wait(rid)["status"] == ep.EP_ENOMEM
+    sv.close()
