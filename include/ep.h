@@ -121,10 +121,45 @@ ep_status ep_set_ionic_scale(ep_sim *s, const char *param, double scale);
 /* Stimulus (eq. stimulus) on n_ids tets: amp pA/pF (negative depolarises)
  * from t0 for dur ms, on whole steps [round(t0/dt), round(t0/dt) +
  * round(dur/dt)); repeated every period ms count times if period > 0.
- * domain must be 0 (tissue).  At most EP_MAX_STIMULI. */
+ * domain 0: ids are tets; domain 1: ids are Purkinje graph nodes (the window
+ * covers every graph substep of those tissue steps).  At most
+ * EP_MAX_STIMULI over both domains. */
 ep_status ep_add_stimulus(ep_sim *s, int domain, int64_t n_ids,
                           const int32_t *ids, double t0, double dur,
                           double amp, double period, int32_t count);
+
+/* Purkinje network (Sec. 2.2, 3.2; a 1D graph in place of the paper's 2D
+ * surface): n nodes xyz[3*i+k], n_edges segments edges[2*e], conductivity
+ * sigma (mS/mm; the paper's Purkinje value is 3.95), cell model (normally
+ * EP_STEWART).  Vertex-centred finite volumes: node i owns half of each
+ * incident segment, l_i = sum_j L_ij / 2, and
+ *   dv_i/dt = sigma / (chi Cm l_i) sum_j (v_j - v_i) / L_ij - I_ion - I_stim.
+ * The graph advances in n_sub explicit substeps per tissue step (n_sub <= 0:
+ * the smallest n_sub with dt / n_sub <= 0.9 min_i chi Cm l_i / (sigma
+ * sum_j 1/L_ij), a sufficient stability bound).  Stimuli on the graph use
+ * ep_add_stimulus with domain 1 and node ids.  Call before ep_init. */
+ep_status ep_set_purkinje(ep_sim *s, int64_t n, const double *xyz, int64_t n_edges,
+                          const int32_t *edges, double sigma, int32_t model,
+                          int32_t n_sub);
+
+/* Purkinje-muscle junction at graph node `node` (Sec. 3.3): when the node's
+ * potential crosses at_threshold upward during tissue step n, the tissue
+ * cells whose centroid lies within `radius` of the node (if none: the cells
+ * sharing a mesh node with the cell of nearest centroid) receive amp pA/pF
+ * for dur ms from step n + 1 + round(delay_ortho/dt).  With two_way, an
+ * upward crossing of the mean potential of that region stimulates the node
+ * from step n + 1 + round(delay_anti/dt) (antidromic conduction).  Each step
+ * runs the tissue, then the graph substeps, then these events.  Call before
+ * ep_init. */
+ep_status ep_add_pmj(ep_sim *s, int32_t node, double radius, double delay_ortho,
+                     double delay_anti, int32_t two_way, double amp, double dur);
+
+/* Graph readouts (caller numbering of graph nodes, n == graph size):
+ * potential and activation time (first upward threshold crossing, NaN if
+ * none); and the substep count in use. */
+ep_status ep_get_purkinje_vm(ep_sim *s, double *out, int64_t n);
+ep_status ep_get_purkinje_activation(ep_sim *s, double *out, int64_t n);
+ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub);
 
 /* Precompute geometry and flux coefficients (FP64, host), reorder the mesh,
  * upload to the device and set the standard initial state of every model.

@@ -19,7 +19,7 @@ using ep::model_ng;
 
 namespace {
 
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b32ULL;   // "EPSMCHK2"
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b33ULL;   // "EPSMCHK3"
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
@@ -146,6 +146,7 @@ ep_status ep_set_mesh(ep_sim *s, int64_t n_nodes, const double *xyz, int64_t n_t
     sp.model.assign(n_tets, EP_TP06_ENDO);
     sp.fibre.clear();
     sp.stims.clear();
+    sp.purk = ep::PurkSpec();
     s->has_cond = false;
     return EP_OK;
 }
@@ -196,19 +197,72 @@ ep_status ep_add_stimulus(ep_sim *s, int domain, int64_t n_ids, const int32_t *i
                           double dur, double amp, double period, int32_t count) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "stimuli are frozen after ep_init");
-    if (domain != 0) return fail(s, EP_EINVAL, "only the tissue domain (0) takes stimuli");
+    if (domain != 0 && domain != 1) return fail(s, EP_EINVAL, "domain must be 0 (tissue) or 1 (graph)");
     ep::InstSpec &sp = s->spec;
     if (sp.n_tets == 0) return fail(s, EP_ESTATE, "set the mesh first");
+    if (domain == 1 && sp.purk.n == 0) return fail(s, EP_ESTATE, "set the Purkinje graph first");
     if ((int)sp.stims.size() >= EP_MAX_STIMULI) return fail(s, EP_EINVAL, "too many stimuli");
     if (n_ids < 0 || (n_ids > 0 && !ids) || !(dur >= 0) || !std::isfinite(amp) || period < 0)
         return fail(s, EP_EINVAL, "bad stimulus");
+    const int64_t lim = domain == 0 ? sp.n_tets : sp.purk.n;
     for (int64_t i = 0; i < n_ids; ++i)
-        if (ids[i] < 0 || ids[i] >= sp.n_tets) return fail(s, EP_EINVAL, "stimulus id out of range");
+        if (ids[i] < 0 || ids[i] >= lim) return fail(s, EP_EINVAL, "stimulus id out of range");
     ep::StimSpec st;
+    st.domain = domain;
     st.ids.assign(ids, ids + n_ids);
     st.t0 = t0; st.dur = dur; st.amp = amp; st.period = period;
     st.count = count < 1 ? 1 : count;
     sp.stims.push_back(std::move(st));
+    return EP_OK;
+}
+
+ep_status ep_set_purkinje(ep_sim *s, int64_t n, const double *xyz, int64_t n_edges,
+                          const int32_t *edges, double sigma, int32_t model, int32_t n_sub) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "the graph is frozen after ep_init");
+    ep::InstSpec &sp = s->spec;
+    if (sp.n_tets == 0) return fail(s, EP_ESTATE, "set the mesh first");
+    if (n <= 0 || n >= ((int64_t)1 << 25) || !xyz || n_edges < 0 || (n_edges > 0 && !edges))
+        return fail(s, EP_EINVAL, "empty graph or null array");
+    if (!(sigma > 0) || !std::isfinite(sigma)) return fail(s, EP_EINVAL, "sigma must be > 0");
+    if (model < 0 || model > EP_PASSIVE) return fail(s, EP_EINVAL, "model id out of range");
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(xyz[i])) return fail(s, EP_EINVAL, "non-finite node coordinate");
+    for (int64_t e = 0; e < 2 * n_edges; ++e)
+        if (edges[e] < 0 || edges[e] >= n) return fail(s, EP_EINVAL, "edge node index out of range");
+    for (const ep::StimSpec &st : sp.stims)
+        if (st.domain == 1) return fail(s, EP_ESTATE, "graph stimuli refer to the previous graph");
+    sp.purk = ep::PurkSpec();
+    sp.purk.n = n;
+    sp.purk.xyz.assign(xyz, xyz + 3 * n);
+    sp.purk.edges.assign(edges, edges + 2 * n_edges);
+    sp.purk.sigma = sigma;
+    sp.purk.model = model;
+    sp.purk.n_sub = n_sub;
+    return EP_OK;
+}
+
+ep_status ep_add_pmj(ep_sim *s, int32_t node, double radius, double delay_ortho,
+                     double delay_anti, int32_t two_way, double amp, double dur) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "junctions are frozen after ep_init");
+    ep::PurkSpec &pk = s->spec.purk;
+    if (pk.n == 0) return fail(s, EP_ESTATE, "set the Purkinje graph first");
+    if (node < 0 || node >= pk.n) return fail(s, EP_EINVAL, "junction node out of range");
+    if (!(radius >= 0) || !std::isfinite(radius) || !(delay_ortho >= 0) || !(delay_anti >= 0) ||
+        !std::isfinite(delay_ortho) || !std::isfinite(delay_anti) || !std::isfinite(amp) ||
+        !(dur >= 0) || !std::isfinite(dur))
+        return fail(s, EP_EINVAL, "bad junction parameters");
+    if (pk.pmjs.size() >= (size_t)1 << 24) return fail(s, EP_EINVAL, "too many junctions");
+    ep::PmjIn q;
+    q.node = node;
+    q.radius = radius;
+    q.delay_ortho = delay_ortho;
+    q.delay_anti = delay_anti;
+    q.two_way = two_way ? 1 : 0;
+    q.amp = amp;
+    q.dur = dur;
+    pk.pmjs.push_back(q);
     return EP_OK;
 }
 
@@ -231,6 +285,8 @@ ep_status ep_init(ep_sim *s) {
     s->spec.xyz.clear(); s->spec.xyz.shrink_to_fit();
     s->spec.tets.clear(); s->spec.tets.shrink_to_fit();
     s->spec.fibre.clear(); s->spec.fibre.shrink_to_fit();
+    s->spec.purk.xyz.clear(); s->spec.purk.xyz.shrink_to_fit();
+    s->spec.purk.edges.clear(); s->spec.purk.edges.shrink_to_fit();
     return EP_OK;
 }
 
@@ -348,6 +404,44 @@ ep_status ep_get_time(ep_sim *s, int64_t *step, double *t) {
     return EP_OK;
 }
 
+static const void *cur_pv(ep_sim *s) {
+    return s->inst.pdesc.pv[(s->inst.host_step * s->inst.pdesc.n_sub) & 1];
+}
+
+static ep_status purkinje_readout(ep_sim *s, const void *dev, int bytes_per, double *out, int64_t n) {
+    if (!s) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    if (s->inst.pk.n == 0) return fail(s, EP_ESTATE, "no Purkinje graph");
+    if (!out || n != s->inst.pk.n) return fail(s, EP_EINVAL, "output length must equal the graph size");
+    ep_status st = ep_sync(s);
+    if (st != EP_OK && st != EP_ENUMERIC) return st;
+    if (bytes_per == 8) {
+        HIP_TRY(s, hipMemcpy(out, dev, n * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(n);
+        HIP_TRY(s, hipMemcpy(tmp.data(), dev, n * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) out[i] = tmp[i];
+    }
+    return st;
+}
+
+ep_status ep_get_purkinje_vm(ep_sim *s, double *out, int64_t n) {
+    if (!s) return EP_EINVAL;
+    return purkinje_readout(s, s->inited ? cur_pv(s) : nullptr, s->inst.rs, out, n);
+}
+
+ep_status ep_get_purkinje_activation(ep_sim *s, double *out, int64_t n) {
+    if (!s) return EP_EINVAL;
+    return purkinje_readout(s, s->inst.pdesc.pt_act, 8, out, n);
+}
+
+ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub) {
+    if (!s || !n_sub) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    *n_sub = s->inst.pk.n > 0 ? s->inst.pk.n_sub : 0;
+    return EP_OK;
+}
+
 int ep_model_n_slots(int model) {
     switch (model) {
     case EP_TP06_ENDO: case EP_TP06_MID: case EP_TP06_EPI: return 19;
@@ -433,17 +527,30 @@ ep_status ep_set_states(ep_sim *s, const double *in, int64_t n, int32_t n_slots)
 struct CkptHeader {
     uint64_t magic;
     int64_t n_tets, n_nodes, step;
-    int32_t rs, pad;
-    int64_t trace_cap;
+    int32_t rs, n_pmj;
+    int64_t trace_cap, n_purkinje;
 };
 
 static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
     const epdev::InstDesc &D = s->inst.desc;
     const size_t nc = D.nc, r = s->inst.rs;
-    return {{D.v[0], nc * r},           {D.v[1], nc * r},        {D.gate, NG_MAX * nc * r},
-            {D.conc, NC_MAX * nc * 8},  {D.dstat, nc},           {D.t_act, nc * 8},
-            {D.t_rep, nc * 8},          {D.vmax, nc * r},        {(void *)D.vrest, nc * r},
-            {D.trace, (size_t)s->inst.trace_cap * 8}, {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
+    std::vector<std::pair<void *, size_t>> a = {
+        {D.v[0], nc * r},           {D.v[1], nc * r},        {D.gate, NG_MAX * nc * r},
+        {D.conc, NC_MAX * nc * 8},  {D.dstat, nc},           {D.t_act, nc * 8},
+        {D.t_rep, nc * 8},          {D.vmax, nc * r},        {(void *)D.vrest, nc * r},
+        {D.trace, (size_t)s->inst.trace_cap * 8}, {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
+    if (s->inst.pk.n > 0) {
+        const epdev::PurkDesc &P = s->inst.pdesc;
+        const size_t np = P.np;
+        a.push_back({P.pv[0], np * r});
+        a.push_back({P.pv[1], np * r});
+        a.push_back({P.gate, NG_MAX * np * r});
+        a.push_back({P.conc, NC_MAX * np * 8});
+        a.push_back({P.pstat, np});
+        a.push_back({P.pt_act, np * 8});
+        a.push_back({P.pmj, std::max<size_t>(P.n_pmj, 1) * sizeof(epdev::Pmj)});
+    }
+    return a;
 }
 
 ep_status ep_state_size(ep_sim *s, size_t *bytes) {
@@ -461,8 +568,8 @@ ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes) {
     if (st != EP_OK) return st;
     if (!buf || bytes < need) return fail(s, EP_EINVAL, "checkpoint buffer too small");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
-    CkptHeader h{CKPT_MAGIC, s->inst.desc.nc, s->inst.desc.nn, s->inst.host_step, s->inst.rs, 0,
-                 s->inst.trace_cap};
+    CkptHeader h{CKPT_MAGIC, s->inst.desc.nc, s->inst.desc.nn, s->inst.host_step, s->inst.rs,
+                 (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n};
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
@@ -481,7 +588,8 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes) {
     CkptHeader h;
     std::memcpy(&h, buf, sizeof(h));
     if (h.magic != CKPT_MAGIC || h.n_tets != s->inst.desc.nc || h.n_nodes != s->inst.desc.nn ||
-        h.rs != s->inst.rs || h.trace_cap != s->inst.trace_cap)
+        h.rs != s->inst.rs || h.trace_cap != s->inst.trace_cap || h.n_purkinje != s->inst.pk.n ||
+        h.n_pmj != (int32_t)s->inst.n_pmj)
         return fail(s, EP_EINVAL, "checkpoint does not match this simulation");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const char *p = (const char *)buf + sizeof(h);

@@ -94,8 +94,43 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     in.ordering = sp.ordering;
     std::string e = prepare(in, I.prep);
     if (!e.empty()) { st = EP_EINVAL; return e; }
+    I.pk = PurkOut();
+    I.n_pmj = 0;
+    if (sp.purk.n > 0) {
+        PurkIn pin;
+        pin.n = sp.purk.n;
+        pin.n_edges = (int64_t)sp.purk.edges.size() / 2;
+        pin.xyz = sp.purk.xyz.data();
+        pin.edges = sp.purk.edges.data();
+        pin.sigma = sp.purk.sigma;
+        pin.dt = sp.dt;
+        pin.chi = sp.chi;
+        pin.cm = sp.cm;
+        pin.n_sub = sp.purk.n_sub;
+        pin.pmjs = sp.purk.pmjs;
+        e = prepare_purkinje(pin, in, I.prep, I.pk);
+        if (!e.empty()) { st = EP_EINVAL; return e; }
+        I.pmodel = sp.purk.model;
+        I.n_pmj = (int64_t)sp.purk.pmjs.size();
+    }
     return "";
 }
+
+namespace {
+
+size_t purkinje_bytes(const Inst &I, int rs) {
+    if (I.pk.n == 0) return 0;
+    const size_t np = (size_t)I.pk.n, E = I.pk.nbr.size(), r = (size_t)rs, c = (size_t)I.prep.n_tets;
+    size_t b = round256((np + 1) * 4) + round256(E * 4) + round256(E * r);
+    b += 2 * round256(np * r) + round256(NG_MAX * np * r) + round256(NC_MAX * np * 8);
+    b += round256(np * 4) + round256(np) + round256(np * 8) + round256(np * 4);
+    b += round256((np + (size_t)I.n_pmj + 1) * 4) + round256(std::max<size_t>(I.n_pmj, 1) * sizeof(Pmj));
+    b += round256(std::max<size_t>(I.pk.jcells.size(), 1) * 4);
+    b += round256(c * 4) + round256(I.pk.cpmj_list.size() * 4);
+    return b;
+}
+
+}  // namespace
 
 size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     const PrepOut &P = I.prep;
@@ -112,8 +147,95 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     b += 4 * round256(c * r) + round256(n * r);
     b += round256(c) + 2 * round256(c * 8);
     b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE) * 8) + round256(sizeof(Ctrl));
-    return b;
+    return b + purkinje_bytes(I, rs);
 }
+
+namespace {
+
+// Graph arrays, junction table and the muscle's junction lists.
+std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) {
+    const PurkOut &K = I.pk;
+    const int64_t np = K.n;
+    PurkDesc &P = I.pdesc;
+    std::memset(&P, 0, sizeof(P));
+    auto fail_mem = [&]() { st = EP_ENOMEM; free_instance(I); return std::string("device allocation failed"); };
+    std::vector<double> v0(np), gate((size_t)NG_MAX * np, 0.0), conc((size_t)NC_MAX * np, 0.0);
+    {
+        double y[EP_MAX_SLOTS];
+        model_init(I.pmodel, y);
+        const int ng = model_ng(I.pmodel), ncc = model_nc(I.pmodel);
+        for (int64_t i = 0; i < np; ++i) {
+            v0[i] = y[0];
+            for (int k = 0; k < ng; ++k) gate[(size_t)k * np + i] = y[1 + k];
+            for (int k = 0; k < ncc; ++k) conc[(size_t)k * np + i] = y[1 + ng + k];
+        }
+    }
+    std::vector<uint32_t> pmask(np, 0);
+    for (size_t k = 0; k < sp.stims.size(); ++k)
+        if (sp.stims[k].domain == 1)
+            for (int32_t id : sp.stims[k].ids) pmask[id] |= 1u << k;
+    // per node: its two-way junctions, in junction order
+    std::vector<int32_t> npmj(np, -1), nlist;
+    {
+        std::vector<std::vector<int32_t>> at(np);
+        for (size_t k = 0; k < sp.purk.pmjs.size(); ++k)
+            if (sp.purk.pmjs[k].two_way) at[sp.purk.pmjs[k].node].push_back((int32_t)k);
+        for (int64_t i = 0; i < np; ++i)
+            if (!at[i].empty()) {
+                npmj[i] = (int32_t)nlist.size();
+                for (int32_t k : at[i]) nlist.push_back(k);
+                nlist.push_back(-1);
+            }
+        if (nlist.empty()) nlist.push_back(-1);
+    }
+    std::vector<Pmj> pmj(std::max<size_t>(sp.purk.pmjs.size(), 1));
+    for (size_t k = 0; k < sp.purk.pmjs.size(); ++k) {
+        const PmjIn &q = sp.purk.pmjs[k];
+        Pmj &J = pmj[k];
+        J.fire_o = J.fire_a = INT64_MIN / 2;
+        J.delay_o = std::llround(q.delay_ortho / sp.dt);
+        J.delay_a = std::llround(q.delay_anti / sp.dt);
+        J.ndur = std::llround(q.dur / sp.dt);
+        J.amp = q.amp;
+        J.vprev = rs == 8 ? v0[q.node] : (double)(float)v0[q.node];
+        J.node = q.node;
+        J.two_way = q.two_way ? 1 : 0;
+        J.roff = K.jroff[k];
+        J.rcnt = K.jroff[k + 1] - K.jroff[k];
+    }
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    std::vector<int32_t> jc = K.jcells;
+    if (jc.empty()) jc.push_back(0);
+    bool ok = up(I, (void **)&P.off, K.off) && up(I, (void **)&P.nbr, K.nbr) &&
+              up(I, (void **)&P.conc, conc) && up(I, (void **)&P.pmask, pmask) &&
+              up(I, (void **)&P.pstat, std::vector<uint8_t>(np, 0)) &&
+              up(I, (void **)&P.pt_act, std::vector<double>(np, nan)) &&
+              up(I, (void **)&P.npmj, npmj) && up(I, (void **)&P.npmj_list, nlist) &&
+              up(I, (void **)&P.pmj, pmj) && up(I, (void **)&P.jcells, jc) &&
+              up(I, (void **)&I.desc.cpmj, K.cpmj) && up(I, (void **)&I.desc.cpmj_list, K.cpmj_list);
+    if (!ok) return fail_mem();
+    if (rs == 8)
+        ok = up(I, (void **)&P.g, K.g) && up(I, &P.pv[0], v0) && up(I, &P.pv[1], v0) &&
+             up(I, &P.gate, gate);
+    else
+        ok = up(I, (void **)&P.g, conv<float>(K.g)) && up(I, &P.pv[0], conv<float>(v0)) &&
+             up(I, &P.pv[1], conv<float>(v0)) && up(I, &P.gate, conv<float>(gate));
+    if (!ok) return fail_mem();
+    I.desc.pmj = P.pmj;
+    P.np = np;
+    P.n_sub = K.n_sub;
+    P.n_pmj = (int32_t)sp.purk.pmjs.size();
+    P.model = I.pmodel;
+    P.tv[0] = I.desc.v[0];
+    P.tv[1] = I.desc.v[1];
+    P.ctrl = I.d_ctrl;
+    P.dtp = sp.dt / K.n_sub;
+    P.thr = sp.thr;
+    P.gs = I.desc.gs;
+    return "";
+}
+
+}  // namespace
 
 std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Inst &I,
                             ep_status &st) {
@@ -159,7 +281,8 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     }
     std::vector<uint32_t> smask(nc, 0);
     for (size_t k = 0; k < sp.stims.size(); ++k)
-        for (int32_t id : sp.stims[k].ids) smask[P.iperm[id]] |= 1u << k;
+        if (sp.stims[k].domain == 0)
+            for (int32_t id : sp.stims[k].ids) smask[P.iperm[id]] |= 1u << k;
     if (!up(I, (void **)&D.smask, smask) || !up(I, (void **)&D.conc, conc)) return fail_mem();
     if (rs == 8) {
         ok = up(I, (void **)&D.gate, gate) && up(I, &D.v[0], v0) && up(I, &D.v[1], v0) &&
@@ -221,6 +344,10 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     }
     D.ctrl = I.d_ctrl;
     I.host_step = 0;
+    if (I.pk.n > 0) {
+        std::string e = upload_purkinje(sp, rs, I, st);
+        if (!e.empty()) return e;
+    }
     return "";
 }
 
@@ -249,7 +376,7 @@ void drop_graph(Stepper &s) {
 }
 
 Tables tables(const Stepper &s) {
-    return Tables{s.d_desc, s.d_ctiles, s.d_ntiles, s.d_counts};
+    return Tables{s.d_desc, s.d_ctiles, s.d_ntiles, s.d_ptiles, s.d_purk, s.d_counts};
 }
 
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
@@ -265,10 +392,23 @@ void launch_step(Stepper &s, int32_t off) {
     }
 }
 
+// Graph substeps and junction events of step offset `off` (after the tissue).
+template <typename R>
+void launch_purkinje(Stepper &s, int32_t off) {
+    const Tables tb = tables(s);
+    for (int32_t sub = 0; sub < s.n_sub_max; ++sub)
+        k_purkinje<R><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+    k_junctions<R><<<(int)s.n_pk, TILE, 0, s.stream>>>(tb, off);
+}
+
 void enqueue(Stepper &s, int64_t k) {
     for (int64_t i = 0; i < k; ++i) {
         if (s.rs == 8) launch_step<double>(s, (int32_t)i);
         else launch_step<float>(s, (int32_t)i);
+        if (s.n_pk > 0) {
+            if (s.rs == 8) launch_purkinje<double>(s, (int32_t)i);
+            else launch_purkinje<float>(s, (int32_t)i);
+        }
     }
     k_advance<<<1, 256, 0, s.stream>>>(tables(s), k);
 }
@@ -285,7 +425,7 @@ std::string stepper_init(Stepper &s, int device, hipStream_t stream, int rs) {
     s.rs = rs;
     hipError_t e = hipEventCreateWithFlags(&s.stage_done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_err("hipEventCreate", e);
-    e = hipMalloc((void **)&s.d_counts, 4 * sizeof(int32_t));
+    e = hipMalloc((void **)&s.d_counts, 8 * sizeof(int32_t));
     if (e != hipSuccess) return hip_err("hipMalloc", e);
     return "";
 }
@@ -297,6 +437,10 @@ void stepper_free(Stepper &s) {
     if (s.d_ctiles) (void)hipFree(s.d_ctiles);
     if (s.d_ntiles) (void)hipFree(s.d_ntiles);
     if (s.d_counts) (void)hipFree(s.d_counts);
+    if (s.d_ptiles) (void)hipFree(s.d_ptiles);
+    if (s.d_purk) (void)hipFree(s.d_purk);
+    s.d_ptiles = nullptr;
+    s.d_purk = nullptr;
     if (s.h_stage) (void)hipHostFree(s.h_stage);
     if (s.stage_done) (void)hipEventDestroy(s.stage_done);
     s.d_desc = nullptr; s.d_ctiles = s.d_ntiles = nullptr; s.d_counts = nullptr;
@@ -306,10 +450,19 @@ void stepper_free(Stepper &s) {
 std::string stepper_sync_tables(Stepper &s) {
     std::vector<InstDesc> desc;
     std::vector<Tile> ct, nt;
+    std::vector<PTile> pt;
+    std::vector<PurkDesc> pk;
     int mset = 0;
+    int32_t nsub = 0;
     for (size_t i = 0; i < s.insts.size(); ++i) {
         const Inst &I = *s.insts[i];
         desc.push_back(I.desc);
+        if (I.pk.n > 0) {
+            pk.push_back(I.pdesc);
+            nsub = std::max(nsub, I.pdesc.n_sub);
+            for (int64_t b = 0, t = 0; b < I.pdesc.np; b += TILE, ++t)
+                pt.push_back(PTile{I.pdesc, b, (int32_t)std::min<int64_t>(TILE, I.pdesc.np - b), (int32_t)t});
+        }
         mset |= I.mset;
         for (int64_t b = 0, t = 0; b < I.desc.nc; b += TILE, ++t)
             ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nc - b), (int32_t)t});
@@ -330,10 +483,13 @@ std::string stepper_sync_tables(Stepper &s) {
     hipError_t e;
     if ((e = grow((void **)&s.d_desc, s.cap_inst, desc.size(), sizeof(InstDesc))) != hipSuccess ||
         (e = grow((void **)&s.d_ctiles, s.cap_ct, ct.size(), sizeof(Tile))) != hipSuccess ||
-        (e = grow((void **)&s.d_ntiles, s.cap_nt, nt.size(), sizeof(Tile))) != hipSuccess)
+        (e = grow((void **)&s.d_ntiles, s.cap_nt, nt.size(), sizeof(Tile))) != hipSuccess ||
+        (e = grow((void **)&s.d_ptiles, s.cap_pt, pt.size(), sizeof(PTile))) != hipSuccess ||
+        (e = grow((void **)&s.d_purk, s.cap_pk, pk.size(), sizeof(PurkDesc))) != hipSuccess)
         return hip_err("hipMalloc(tables)", e);
     // pinned staging: wait until the previous upload has left it
-    const size_t need = desc.size() * sizeof(InstDesc) + (ct.size() + nt.size()) * sizeof(Tile) + 64;
+    const size_t need = desc.size() * sizeof(InstDesc) + (ct.size() + nt.size()) * sizeof(Tile) +
+                        pt.size() * sizeof(PTile) + pk.size() * sizeof(PurkDesc) + 64;
     if (s.h_stage) (void)hipEventSynchronize(s.stage_done);
     if (need > s.stage_bytes) {
         if (s.h_stage) (void)hipHostFree(s.h_stage);
@@ -345,7 +501,8 @@ std::string stepper_sync_tables(Stepper &s) {
         }
     }
     char *p = (char *)s.h_stage;
-    int32_t counts[4] = {(int32_t)ct.size(), (int32_t)nt.size(), (int32_t)desc.size(), 0};
+    int32_t counts[8] = {(int32_t)ct.size(), (int32_t)nt.size(), (int32_t)desc.size(),
+                         (int32_t)pt.size(), (int32_t)pk.size(), 0, 0, 0};
     std::memcpy(p, counts, sizeof(counts));
     char *pd = p + 64;
     std::memcpy(pd, desc.data(), desc.size() * sizeof(InstDesc));
@@ -353,17 +510,28 @@ std::string stepper_sync_tables(Stepper &s) {
     std::memcpy(pc, ct.data(), ct.size() * sizeof(Tile));
     char *pn = pc + ct.size() * sizeof(Tile);
     std::memcpy(pn, nt.data(), nt.size() * sizeof(Tile));
+    char *pp = pn + nt.size() * sizeof(Tile);
+    std::memcpy(pp, pt.data(), pt.size() * sizeof(PTile));
+    char *pq = pp + pt.size() * sizeof(PTile);
+    std::memcpy(pq, pk.data(), pk.size() * sizeof(PurkDesc));
     if ((e = hipMemcpyAsync(s.d_counts, p, sizeof(counts), hipMemcpyHostToDevice, s.stream)) != hipSuccess ||
         (!desc.empty() && (e = hipMemcpyAsync(s.d_desc, pd, desc.size() * sizeof(InstDesc),
                                               hipMemcpyHostToDevice, s.stream)) != hipSuccess) ||
         (!ct.empty() && (e = hipMemcpyAsync(s.d_ctiles, pc, ct.size() * sizeof(Tile),
                                             hipMemcpyHostToDevice, s.stream)) != hipSuccess) ||
         (!nt.empty() && (e = hipMemcpyAsync(s.d_ntiles, pn, nt.size() * sizeof(Tile),
+                                            hipMemcpyHostToDevice, s.stream)) != hipSuccess) ||
+        (!pt.empty() && (e = hipMemcpyAsync(s.d_ptiles, pp, pt.size() * sizeof(PTile),
+                                            hipMemcpyHostToDevice, s.stream)) != hipSuccess) ||
+        (!pk.empty() && (e = hipMemcpyAsync(s.d_purk, pq, pk.size() * sizeof(PurkDesc),
                                             hipMemcpyHostToDevice, s.stream)) != hipSuccess))
         return hip_err("hipMemcpyAsync(tables)", e);
     (void)hipEventRecord(s.stage_done, s.stream);
     s.n_ct = (int64_t)ct.size();
     s.n_nt = (int64_t)nt.size();
+    s.n_pt = (int64_t)pt.size();
+    s.n_pk = (int64_t)pk.size();
+    s.n_sub_max = nsub;
     s.dirty = false;
     return "";
 }
@@ -382,7 +550,8 @@ std::string stepper_run(Stepper &s, int64_t k) {
     int64_t left = k;
     if (glen > 0 && left >= glen) {
         if (s.graph && (s.graph_k != glen || s.graph_mset != s.mset || s.graph_gc != s.grid_cell ||
-                        s.graph_gn != s.grid_node || s.graph_remap != s.remap))
+                        s.graph_gn != s.grid_node || s.graph_remap != s.remap ||
+                        s.graph_pt != s.n_pt || s.graph_pk != s.n_pk || s.graph_nsub != s.n_sub_max))
             drop_graph(s);
         if (!s.graph) {
             hipGraph_t g = nullptr;
@@ -399,6 +568,9 @@ std::string stepper_run(Stepper &s, int64_t k) {
             s.graph_gc = s.grid_cell;
             s.graph_gn = s.grid_node;
             s.graph_remap = s.remap;
+            s.graph_pt = s.n_pt;
+            s.graph_pk = s.n_pk;
+            s.graph_nsub = s.n_sub_max;
         }
         while (left >= glen) {
             hipError_t e = hipGraphLaunch(s.graph, s.stream);
@@ -446,6 +618,10 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
             }
         }
         (void)hipEventRecord(ev[2], s.stream);
+        if (s.n_pk > 0) {
+            if (s.rs == 8) launch_purkinje<double>(s, 0);
+            else launch_purkinje<float>(s, 0);
+        }
         k_advance<<<1, 256, 0, s.stream>>>(tb, 1);
         (void)hipEventSynchronize(ev[2]);
         float a = 0, b = 0;

@@ -14,9 +14,21 @@
 namespace ep {
 
 struct StimSpec {
-    std::vector<int32_t> ids;   // caller numbering
+    std::vector<int32_t> ids;   // caller numbering (tets, or graph nodes for domain 1)
     double t0 = 0, dur = 0, amp = 0, period = 0;
     int32_t count = 1;
+    int32_t domain = 0;         // 0 tissue, 1 Purkinje graph
+};
+
+// Purkinje graph coupled to the tissue through junctions.
+struct PurkSpec {
+    int64_t n = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> edges;
+    double sigma = 3.95;
+    int32_t model = 4;
+    int32_t n_sub = 0;
+    std::vector<PmjIn> pmjs;
 };
 
 // Everything needed to build an instance (copied from the caller).
@@ -33,6 +45,7 @@ struct InstSpec {
     double dt = 0.02, chi = 140.0, cm = 0.01, thr = 0.0, repol = 0.9;
     int32_t trace_every = 50;
     int64_t target = INT64_MAX;        // stop stepping at this step index
+    PurkSpec purk;                     // n == 0: no graph
 };
 
 struct Allocator {
@@ -57,6 +70,11 @@ struct Inst {
     int32_t trace_every = 50;
     double dt = 0.02;
     int64_t n_slices = 0;
+    // Purkinje graph (pk.n == 0: none)
+    PurkOut pk;
+    int pmodel = 4;
+    int64_t n_pmj = 0;
+    epdev::PurkDesc pdesc{};
 };
 
 // Host precompute only (thread-safe, no HIP calls).
@@ -87,15 +105,20 @@ struct Stepper {
     // device tables
     epdev::InstDesc *d_desc = nullptr;
     epdev::Tile *d_ctiles = nullptr, *d_ntiles = nullptr;
+    epdev::PTile *d_ptiles = nullptr;
+    epdev::PurkDesc *d_purk = nullptr;
     int32_t *d_counts = nullptr;
-    size_t cap_inst = 0, cap_ct = 0, cap_nt = 0;
-    int64_t n_ct = 0, n_nt = 0;
+    size_t cap_inst = 0, cap_ct = 0, cap_nt = 0, cap_pt = 0, cap_pk = 0;
+    int64_t n_ct = 0, n_nt = 0, n_pt = 0, n_pk = 0;
+    int32_t n_sub_max = 0;             // graph substeps per step (max over instances)
     // pinned staging of the tables
     void *h_stage = nullptr;
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_k = 0, graph_mset = -1, graph_gc = -1, graph_gn = -1, graph_remap = -1;
+    int64_t graph_pt = -1, graph_pk = -1;
+    int32_t graph_nsub = -1;
     bool dirty = true;
 };
 

@@ -39,6 +39,17 @@ struct Ctrl {
     double st_amp[MAX_STIM];      // pA/pF
 };
 
+// A Purkinje-muscle junction.  fire_o / fire_a are the first steps of the
+// pending stimuli of its muscle region / of its graph node.
+struct Pmj {
+    int64_t fire_o, fire_a;
+    int64_t delay_o, delay_a, ndur;   // in steps
+    double amp;
+    double vprev;                     // junction node potential at the start of the step
+    int32_t node, two_way;
+    int32_t roff, rcnt;               // region: jcells[roff .. roff + rcnt)
+};
+
 // Everything a block needs to work on one instance (R = double or float
 // arrays are passed as void and typed inside the kernels).
 struct InstDesc {
@@ -69,6 +80,33 @@ struct InstDesc {
     int64_t trace_cap;
     int32_t trace_every;
     int32_t n_cell_tiles;
+    // junction stimuli of the muscle (null without a Purkinje graph)
+    const int32_t *cpmj;          // [nc]: -1 or start of a -1-terminated list
+    const int32_t *cpmj_list;
+    const Pmj *pmj;
+};
+
+// A Purkinje graph (vertex-centred finite volumes on a 1D graph) coupled to
+// an instance: CSR operator, states, detection and junctions.
+struct PurkDesc {
+    int64_t np;
+    int32_t n_sub, n_pmj, model, pad;
+    const int32_t *off, *nbr;
+    const void *g;                // [off[np]] coefficients of (v_j - v_i)
+    void *pv[2];                  // substep q reads pv[q & 1], writes pv[(q+1) & 1]
+    void *gate;                   // [NG_MAX][np]
+    double *conc;                 // [NC_MAX][np]
+    const uint32_t *pmask;        // graph stimuli holding the node
+    uint8_t *pstat;
+    double *pt_act;
+    const int32_t *npmj;          // [np]: -1 or start of a list of two-way junctions
+    const int32_t *npmj_list;
+    Pmj *pmj;
+    const int32_t *jcells;
+    const void *tv[2];            // the instance's tissue potential buffers
+    Ctrl *ctrl;
+    double dtp, thr;
+    GScale gs;
 };
 
 // A tile carries a copy of its instance's descriptor, so a block reaches
@@ -82,11 +120,20 @@ struct Tile {
 
 // The launch grids always equal the tile counts (graphs are re-captured when
 // the counts change), so kernels index the tables without a bound check.
+struct PTile {
+    PurkDesc p;
+    int64_t begin;
+    int32_t count, local;
+};
+
 struct Tables {
     const InstDesc *desc;         // one per instance (for the step counters)
     const Tile *cell_tiles;
     const Tile *node_tiles;
-    const int32_t *counts;        // [0] cell tiles, [1] node tiles, [2] instances
+    const PTile *purk_tiles;
+    const PurkDesc *purk;         // one per instance with a Purkinje graph
+    const int32_t *counts;        // [0] cell tiles, [1] node tiles, [2] instances,
+                                  // [3] graph tiles, [4] graphs
 };
 
 // Blocks are dealt round-robin to the 8 XCDs; remap block b so that each XCD
@@ -190,7 +237,51 @@ __device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, int64_t n, 
     BufIO<T>::st(r, x, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
 }
 
+// One cell-model update of cell c of a slot-major state set: gates by
+// Rush-Larsen, FP64 concentrations by forward Euler, all from level-n values.
+// Returns I_ion at level n (0 for passive cells).
 // MSET: bit 0 TP06 (any layer), 1 CRN, 2 Stewart, 3 passive.
+template <typename R, int MSET>
+__device__ __forceinline__ R ionic(int md, R v, __amdgpu_buffer_rsrc_t rgate,
+                                   __amdgpu_buffer_rsrc_t rconc, int64_t N, uint32_t c, R dt,
+                                   double dtd, R istim, const GScale &gs) {
+    R iion = R(0);
+    R g[NG_MAX];
+    double cc[NC_MAX];
+    if ((MSET & 1) && md <= 2) {
+#pragma unroll
+        for (int s = 0; s < tp06::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
+#pragma unroll
+        for (int s = 0; s < tp06::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+        iion = tp06::step<R>(md, v, g, cc, dt, dtd, istim, gs);
+#pragma unroll
+        for (int s = 0; s < tp06::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
+#pragma unroll
+        for (int s = 0; s < tp06::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+    } else if ((MSET & 2) && md == 3) {
+#pragma unroll
+        for (int s = 0; s < crn::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
+#pragma unroll
+        for (int s = 0; s < crn::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+        iion = crn::step<R>(v, g, cc, dt, dtd, gs);
+#pragma unroll
+        for (int s = 0; s < crn::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
+#pragma unroll
+        for (int s = 0; s < crn::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+    } else if ((MSET & 4) && md == 4) {
+#pragma unroll
+        for (int s = 0; s < stewart::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
+#pragma unroll
+        for (int s = 0; s < stewart::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+        iion = stewart::step<R>(v, g, cc, dt, dtd, istim, gs);
+#pragma unroll
+        for (int s = 0; s < stewart::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
+#pragma unroll
+        for (int s = 0; s < stewart::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+    }
+    return iion;
+}
+
 template <typename R, int MSET>
 __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
                                           uint32_t active, bool sample, double &vol_v) {
@@ -211,7 +302,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     for (int f = 0; f < 4; ++f)
         L += sld<R>(rb, f, N, c) * (at(vin, (uint32_t)sld<int32_t>(rnbr, f, N, c)) - v);
 
-    // ---- stimulus
+    // ---- stimulus: protocol pulses, then junction pulses (junction order)
     R istim = R(0);
     if (active) {
         uint32_t m = at(D.smask, c) & active;
@@ -221,45 +312,19 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
             m &= m - 1;
         }
     }
+    if (D.cpmj) {
+        int32_t q = at(D.cpmj, c);
+        if (q >= 0)
+            for (int32_t k; (k = D.cpmj_list[q]) >= 0; ++q) {
+                const Pmj &J = D.pmj[k];
+                if (n >= J.fire_o && n < J.fire_o + J.ndur) istim += R(J.amp);
+            }
+    }
 
     // ---- cell model
-    R iion = R(0);
     const int md = (MSET == 8) ? 5 : at(D.model, c);   // TP06 layer or model id
-    const __amdgpu_buffer_rsrc_t rgate = rsrc(D.gate), rconc = rsrc(D.conc);
     const R dt = R(D.dt);
-    R g[NG_MAX];
-    double cc[NC_MAX];
-    if ((MSET & 1) && md <= 2) {
-#pragma unroll
-        for (int s = 0; s < tp06::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
-#pragma unroll
-        for (int s = 0; s < tp06::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
-        iion = tp06::step<R>(md, v, g, cc, dt, D.dt, istim, D.gs);
-#pragma unroll
-        for (int s = 0; s < tp06::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
-#pragma unroll
-        for (int s = 0; s < tp06::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
-    } else if ((MSET & 2) && md == 3) {
-#pragma unroll
-        for (int s = 0; s < crn::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
-#pragma unroll
-        for (int s = 0; s < crn::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
-        iion = crn::step<R>(v, g, cc, dt, D.dt, D.gs);
-#pragma unroll
-        for (int s = 0; s < crn::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
-#pragma unroll
-        for (int s = 0; s < crn::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
-    } else if ((MSET & 4) && md == 4) {
-#pragma unroll
-        for (int s = 0; s < stewart::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
-#pragma unroll
-        for (int s = 0; s < stewart::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
-        iion = stewart::step<R>(v, g, cc, dt, D.dt, istim, D.gs);
-#pragma unroll
-        for (int s = 0; s < stewart::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
-#pragma unroll
-        for (int s = 0; s < stewart::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
-    }
+    const R iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim, D.gs);
 
     // ---- explicit update of v
     const R vnew = v + dt * (L - iion - istim);
@@ -329,6 +394,21 @@ __device__ __forceinline__ void trace_tile(const InstDesc &D, const Tile &T, int
     __syncthreads();
 }
 
+// Bit i set when stimulus i is on during step n (integer step windows).
+__device__ __forceinline__ uint32_t active_stimuli(const Ctrl *ctrl, int64_t n) {
+    uint32_t active = 0;
+    const int ns = ctrl->n_stim;
+    for (int i = 0; i < ns; ++i) {
+        const int64_t k = n - ctrl->st_n0[i];
+        const int64_t per = ctrl->st_nper[i];
+        const bool on = k >= 0 && (per <= 0 ? k < ctrl->st_ndur[i]
+                                            : (k / per) < ctrl->st_count[i] &&
+                                                  (k % per) < ctrl->st_ndur[i]);
+        active |= (on ? 1u : 0u) << i;
+    }
+    return active;
+}
+
 template <typename R, int MSET>
 __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
     __shared__ double red[TILE];
@@ -336,21 +416,86 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
     const InstDesc &D = T.d;
     int64_t n;
     if (!stepping(D.ctrl, step_off, n)) return;
-    uint32_t active = 0;
-    const int ns = D.ctrl->n_stim;
-    for (int i = 0; i < ns; ++i) {
-        const int64_t k = n - D.ctrl->st_n0[i];
-        const int64_t per = D.ctrl->st_nper[i];
-        const bool on = k >= 0 && (per <= 0 ? k < D.ctrl->st_ndur[i]
-                                            : (k / per) < D.ctrl->st_count[i] &&
-                                                  (k % per) < D.ctrl->st_ndur[i]);
-        active |= (on ? 1u : 0u) << i;
-    }
+    const uint32_t active = active_stimuli(D.ctrl, n);
     double x = 0.0;
     const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
     if ((int32_t)threadIdx.x < T.count)
         cell_step<R, MSET>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
     if (sample) trace_tile(D, T, n, x, red);
+}
+
+// ------------------------------------------------------- Purkinje graph
+// Substep `sub` of step n of every graph: explicit update of node i with the
+// graph flux, the stimuli of the graph and of its two-way junctions, and the
+// node's cell model over dt / n_sub; first upward threshold crossing.
+template <typename R>
+__global__ void __launch_bounds__(TILE) k_purkinje(Tables tb, int32_t step_off, int32_t sub) {
+    const PTile &T = tb.purk_tiles[blockIdx.x];
+    const PurkDesc &P = T.p;
+    int64_t n;
+    if (!stepping(P.ctrl, step_off, n) || sub >= P.n_sub) return;
+    const uint32_t active = active_stimuli(P.ctrl, n);
+    if ((int32_t)threadIdx.x >= T.count) return;
+    const uint32_t i = (uint32_t)(T.begin + threadIdx.x);
+    const int64_t q = n * P.n_sub + sub;
+    const R *__restrict__ vin = (const R *)P.pv[q & 1];
+    R *__restrict__ vout = (R *)P.pv[(q + 1) & 1];
+    const R *__restrict__ g = (const R *)P.g;
+    const R v = vin[i];
+    R L = R(0);
+    for (int32_t e = P.off[i]; e < P.off[i + 1]; ++e) L += g[e] * (vin[P.nbr[e]] - v);
+    R istim = R(0);
+    uint32_t m = P.pmask[i] & active;
+    while (m) {
+        const int k = __ffs(m) - 1;
+        istim += R(P.ctrl->st_amp[k]);
+        m &= m - 1;
+    }
+    int32_t l = P.npmj[i];
+    if (l >= 0)
+        for (int32_t k; (k = P.npmj_list[l]) >= 0; ++l) {
+            const Pmj &J = P.pmj[k];
+            if (n >= J.fire_a && n < J.fire_a + J.ndur) istim += R(J.amp);
+        }
+    const R dt = R(P.dtp);
+    const R iion = ionic<R, 15>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp, istim, P.gs);
+    const R vnew = v + dt * (L - iion - istim);
+    vout[i] = vnew;
+    if (!(fabs(vnew) < R(1e30))) atomicOr(&P.ctrl->nan_flag, 1);
+    const R thr = R(P.thr);
+    if (P.pstat[i] == 0 && v <= thr && vnew > thr) {
+        P.pt_act[i] = (double(q) + double((thr - v) / (vnew - v))) * P.dtp;
+        P.pstat[i] = 1;
+    }
+}
+
+// Junction events of step n, after the graph substeps: an upward crossing at
+// the junction node schedules the muscle pulse, an upward crossing of the
+// region's mean potential (two-way junctions) schedules the node pulse.
+// One block per graph; one thread per junction.
+template <typename R>
+__global__ void __launch_bounds__(TILE) k_junctions(Tables tb, int32_t step_off) {
+    const PurkDesc &P = tb.purk[blockIdx.x];
+    int64_t n;
+    if (!stepping(P.ctrl, step_off, n)) return;
+    const R *vp = (const R *)P.pv[((n + 1) * P.n_sub) & 1];
+    const R *v0 = (const R *)P.tv[n & 1];
+    const R *v1 = (const R *)P.tv[(n + 1) & 1];
+    const R thr = R(P.thr);
+    for (int32_t k = threadIdx.x; k < P.n_pmj; k += blockDim.x) {
+        Pmj &J = P.pmj[k];
+        const R a = R(J.vprev), b = vp[J.node];
+        if (a <= thr && b > thr) J.fire_o = n + 1 + J.delay_o;
+        J.vprev = double(b);
+        if (J.two_way) {
+            double m0 = 0.0, m1 = 0.0;
+            for (int32_t r = J.roff; r < J.roff + J.rcnt; ++r) m0 += double(v0[P.jcells[r]]);
+            for (int32_t r = J.roff; r < J.roff + J.rcnt; ++r) m1 += double(v1[P.jcells[r]]);
+            m0 /= double(J.rcnt);
+            m1 /= double(J.rcnt);
+            if (m0 <= P.thr && m1 > P.thr) J.fire_a = n + 1 + J.delay_a;
+        }
+    }
 }
 
 // Advance the step counter of every live instance by k (capped at target).

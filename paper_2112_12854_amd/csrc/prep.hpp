@@ -48,4 +48,37 @@ struct PrepOut {
 // Returns an empty string on success, else the reason for EP_EINVAL.
 std::string prepare(const PrepIn &in, PrepOut &out);
 
+// ---------------------------------------------- Purkinje graph, junctions
+struct PmjIn {
+    int32_t node = 0;                  // Purkinje node of the junction
+    double radius = 0.1, delay_ortho = 5.0, delay_anti = 3.0, amp = -200.0, dur = 0.5;
+    int32_t two_way = 0;
+};
+
+struct PurkIn {
+    int64_t n = 0, n_edges = 0;
+    const double *xyz = nullptr;       // [n*3]
+    const int32_t *edges = nullptr;    // [n_edges*2]
+    double sigma = 3.95, dt = 0.02, chi = 140.0, cm = 0.01;
+    int32_t n_sub = 0;                 // <= 0: derived from the stability bound
+    std::vector<PmjIn> pmjs;
+};
+
+// Vertex-centred graph operator in CSR (caller node numbering):
+//   dv_i/dt += sum_{e in [off[i], off[i+1])} g[e] (v[nbr[e]] - v_i).
+// Junction k stimulates the cells jcells[jroff[k] .. jroff[k+1]) (internal
+// ids, listed in increasing caller id).  cpmj[c] (internal cell) is -1 or the
+// start of a -1-terminated list in cpmj_list of the junctions holding c.
+struct PurkOut {
+    int64_t n = 0;
+    int32_t n_sub = 1;
+    std::vector<int32_t> off, nbr;
+    std::vector<double> g;
+    std::vector<int32_t> jroff, jcells;
+    std::vector<int32_t> cpmj, cpmj_list;
+};
+
+std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut &tout,
+                             PurkOut &out);
+
 }  // namespace ep

@@ -85,6 +85,13 @@ _SIGS = {
     "ep_set_ionic_scale": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
     "ep_add_stimulus": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, _ip, C.c_double,
                                   C.c_double, C.c_double, C.c_double, C.c_int32]),
+    "ep_set_purkinje": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip, C.c_double,
+                                  C.c_int32, C.c_int32]),
+    "ep_add_pmj": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
+                             C.c_int32, C.c_double, C.c_double]),
+    "ep_get_purkinje_vm": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    "ep_get_purkinje_activation": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    "ep_get_purkinje_substeps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "ep_init": (C.c_int, [C.c_void_p]),
     "ep_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "ep_step": (C.c_int, [C.c_void_p, C.c_int64]),
@@ -212,6 +219,17 @@ class Sim:
         _check(L.ep_set_models(h, mdl.ctypes.data_as(C.POINTER(C.c_uint8))), h)
         for k, v in (w.ionic_scale or {}).items():
             _check(L.ep_set_ionic_scale(h, k.encode(), float(v)), h)
+        pk = getattr(w, "purkinje", None)
+        self.n_purkinje = 0
+        if pk is not None:
+            pxyz = np.ascontiguousarray(pk.xyz, np.float64)
+            pe = np.ascontiguousarray(pk.edges, np.int32)
+            _check(L.ep_set_purkinje(h, pxyz.shape[0], _d(pxyz), pe.shape[0],
+                                     pe.ctypes.data_as(_ip), pk.sigma, pk.model, pk.n_sub), h)
+            self.n_purkinje = pxyz.shape[0]
+            for node in pk.pmj_nodes:
+                _check(L.ep_add_pmj(h, int(node), pk.pmj_radius, pk.delay_ortho, pk.delay_anti,
+                                    int(pk.two_way), pk.pmj_amp, pk.pmj_dur), h)
         for st in w.stimuli:
             ids = np.ascontiguousarray(st.ids, np.int32)
             _check(L.ep_add_stimulus(h, st.domain, ids.size, ids.ctypes.data_as(_ip),
@@ -256,6 +274,22 @@ class Sim:
 
     def apd90(self):
         return self._vec(lib().ep_get_apd90)
+
+    def _pvec(self, fn):
+        out = np.empty(self.n_purkinje)
+        _check(fn(self.h, _d(out), self.n_purkinje), self.h)
+        return out
+
+    def purkinje_vm(self):
+        return self._pvec(lib().ep_get_purkinje_vm)
+
+    def purkinje_activation(self):
+        return self._pvec(lib().ep_get_purkinje_activation)
+
+    def purkinje_n_sub(self) -> int:
+        n = C.c_int32()
+        _check(lib().ep_get_purkinje_substeps(self.h, C.byref(n)), self.h)
+        return n.value
 
     def mean_vm_trace(self, cap: int = 1 << 16):
         t, v = np.empty(cap), np.empty(cap)

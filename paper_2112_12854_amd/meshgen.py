@@ -520,3 +520,56 @@ def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_
     if leaves.size > n_pmj:
         leaves = leaves[np.linspace(0, leaves.size - 1, n_pmj).astype(int)]
     return Purkinje(xyz=xyz, edges=edges, pmj_nodes=leaves.astype(np.int32))
+
+
+def purkinje_slab(nx: int = 16, ny: int = 8, nz: int = 2, h: float = 0.5, seg: float = 0.1,
+                  two_way: bool = False, drive: str = "graph", n_steps: int = 750,
+                  dt: float = 0.02, pmj_amp: float | None = None) -> Workload:
+    """Slab of TP06-endocardial tissue (fibres along x) with a Y-shaped
+    Stewart Purkinje graph lying at mid-depth: a trunk from x = 0.25 mm along
+    +x to 40 % of the length, then two straight branches to leaves near the
+    far corners (segments of at most `seg` mm).  The two leaves are the
+    junctions (radius 0.6 mm, Sec. 3.3 delays and pulse).  drive="graph":
+    -100 pA/pF for 1 ms on the graph nodes within 0.5 mm of the root;
+    drive="tissue": -52 pA/pF for 1 ms on the cells within 1 mm of the first
+    leaf (for the antidromic path with two_way).  The junction pulse is
+    -200 pA/pF, or -1000 pA/pF with drive="tissue": a pulse into a single
+    graph node must charge the cable around it, whose load is far larger
+    than that of a tissue region."""
+    xyz, tets, hijk = slab(nx, ny, nz, h)
+    n = tets.shape[0]
+    lx, ly, zm = nx * h, ny * h, 0.5 * nz * h
+    root = np.array([0.25, 0.5 * ly, zm])
+    fork = np.array([0.4 * lx, 0.5 * ly, zm])
+    leaves = [np.array([lx - 0.5, 0.2 * ly, zm]), np.array([lx - 0.5, 0.8 * ly, zm])]
+    pts, edges = [root], []
+
+    def line(start_id, a, b):
+        m = max(1, int(math.ceil(np.linalg.norm(b - a) / seg - 1e-9)))
+        prev = start_id
+        for s in range(1, m + 1):
+            pts.append(a + (b - a) * (s / m))
+            edges.append((prev, len(pts) - 1))
+            prev = len(pts) - 1
+        return prev
+
+    f = line(0, root, fork)
+    leaf_ids = [line(f, fork, q) for q in leaves]
+    pxyz = np.array(pts)
+    if pmj_amp is None:
+        pmj_amp = -200.0 if drive == "graph" else -1000.0
+    pk = Purkinje(xyz=pxyz, edges=np.array(edges, np.int32), pmj_nodes=np.array(leaf_ids, np.int32),
+                  pmj_radius=0.6, two_way=two_way, pmj_amp=pmj_amp)
+    stimuli = []
+    if drive == "graph":
+        ids = np.nonzero(np.linalg.norm(pxyz - root, axis=1) <= 0.5)[0].astype(np.int32)
+        stimuli.append(Stimulus(ids=ids, t0=0.0, dur=1.0, amp=-100.0, domain=1))
+    else:
+        cen = xyz[tets].mean(axis=1)
+        ids = np.nonzero(np.linalg.norm(cen - pxyz[leaf_ids[0]], axis=1) <= 1.0)[0].astype(np.int32)
+        stimuli.append(Stimulus(ids=ids, t0=0.0, dur=1.0, amp=-52.0))
+    w = Workload(f"purkinje-slab-{nx}x{ny}x{nz}-h{h}", xyz, tets, _uniform_fibre(n),
+                 np.full(n, TP06_ENDO, np.uint8), stimuli=stimuli, dt=dt, n_steps=n_steps,
+                 hex_ijk=hijk, dims=(nx, ny, nz, h))
+    w.purkinje = pk
+    return w
