@@ -19,7 +19,7 @@ using ep::model_ng;
 
 namespace {
 
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b33ULL;   // "EPSMCHK3"
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b34ULL;   // "EPSMCHK4"
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
@@ -389,6 +389,24 @@ ep_status ep_get_mean_vm_trace(ep_sim *s, double *t, double *vbar, int64_t cap, 
     int64_t m = std::min(cap, avail);
     std::vector<double> tr(std::max<int64_t>(m, 1));
     if (m > 0) HIP_TRY(s, hipMemcpy(tr.data(), s->inst.desc.trace, m * 8, hipMemcpyDeviceToHost));
+    // the sample of the last step issued is still held as per-tile partials
+    // (the next step's node gather would add them): add them here, in the
+    // device's order
+    const int64_t hs = s->inst.host_step;
+    if (every > 0 && hs > 0 && hs % every == 0 && hs / every < m) {
+        const int nt = s->inst.desc.n_cell_tiles;
+        std::vector<double> part(nt);
+        HIP_TRY(s, hipMemcpy(part.data(), s->inst.desc.part, (size_t)nt * 8, hipMemcpyDeviceToHost));
+        double red[epdev::TILE];
+        for (int t = 0; t < epdev::TILE; ++t) {
+            double acc = 0.0;
+            for (int i = t; i < nt; i += epdev::TILE) acc += part[i];
+            red[t] = acc;
+        }
+        for (int w = epdev::TILE / 2; w > 0; w >>= 1)
+            for (int t = 0; t < w; ++t) red[t] += red[t + w];
+        tr[hs / every] = red[0] * s->inst.desc.inv_total_vol;
+    }
     for (int64_t i = 0; i < m; ++i) {
         t[i] = (double)(i * (int64_t)std::max(every, 1)) * s->inst.dt;
         vbar[i] = tr[i];
@@ -538,7 +556,8 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
         {D.v[0], nc * r},           {D.v[1], nc * r},        {D.gate, NG_MAX * nc * r},
         {D.conc, NC_MAX * nc * 8},  {D.dstat, nc},           {D.t_act, nc * 8},
         {D.t_rep, nc * 8},          {D.vmax, nc * r},        {(void *)D.vrest, nc * r},
-        {D.trace, (size_t)s->inst.trace_cap * 8}, {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
+        {D.trace, (size_t)s->inst.trace_cap * 8}, {D.part, (size_t)D.n_cell_tiles * 8},
+        {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
     if (s->inst.pk.n > 0) {
         const epdev::PurkDesc &P = s->inst.pdesc;
         const size_t np = P.np;

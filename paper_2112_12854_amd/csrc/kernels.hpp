@@ -30,8 +30,7 @@ struct Ctrl {
     int64_t target;               // the instance stops stepping at this index
     int32_t nan_flag;             // set when a non-finite v^{n+1} appears
     int32_t n_stim;
-    uint32_t tiles_done;          // trace reduction: tiles finished this step
-    int32_t pad;
+    int32_t pad[2];
     int64_t st_n0[MAX_STIM];      // first active step
     int64_t st_ndur[MAX_STIM];    // active steps per pulse
     int64_t st_nper[MAX_STIM];    // steps between pulses (0 = single pulse)
@@ -154,6 +153,50 @@ __device__ __forceinline__ bool stepping(const Ctrl *ctrl, int32_t off, int64_t 
     return n < ctrl->target;
 }
 
+// Trace of vbar.  On a sample step every cell tile stores the sum of
+// V_c v_c over its cells; the first node tile of the next step adds the
+// partials (the partials are complete by then: the two kernels are stream
+// ordered), so no tile waits on another and the order of the additions is
+// fixed: lane t adds partials t, t + TILE, ... in order, then a fixed tree.
+// A sample taken by the last step issued is reduced the same way on the host.
+__device__ __forceinline__ void tile_partial(const InstDesc &D, const Tile &T, double x,
+                                             double *red) {
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int s = TILE / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) D.part[T.local] = red[0];
+}
+
+__device__ __forceinline__ void reduce_trace(const InstDesc &D, int64_t idx, double *red) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < D.n_cell_tiles; i += TILE) acc += D.part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = TILE / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && idx < D.trace_cap) D.trace[idx] = red[0] * D.inv_total_vol;
+}
+
+// Bit i set when stimulus i is on during step n (integer step windows).
+__device__ __forceinline__ uint32_t active_stimuli(const Ctrl *ctrl, int64_t n) {
+    uint32_t active = 0;
+    const int ns = ctrl->n_stim;
+    for (int i = 0; i < ns; ++i) {
+        const int64_t k = n - ctrl->st_n0[i];
+        const int64_t per = ctrl->st_nper[i];
+        const bool on = k >= 0 && (per <= 0 ? k < ctrl->st_ndur[i]
+                                            : (k / per) < ctrl->st_count[i] &&
+                                                  (k % per) < ctrl->st_ndur[i]);
+        active |= (on ? 1u : 0u) << i;
+    }
+    return active;
+}
+
 // ------------------------------------------------------------ node gather
 template <typename R>
 __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_off, int remap) {
@@ -161,6 +204,10 @@ __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_of
     const InstDesc &D = T.d;
     int64_t n;
     if (!stepping(D.ctrl, step_off, n)) return;
+    if (T.local == 0 && D.trace_every > 0 && n > 0 && n % D.trace_every == 0) {
+        __shared__ double red[TILE];
+        reduce_trace(D, n / D.trace_every, red);
+    }
     if ((int32_t)threadIdx.x >= T.count) return;
     const int64_t node = T.begin + threadIdx.x;
     const R *__restrict__ v = (const R *)D.v[n & 1];
@@ -355,60 +402,6 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     }
 }
 
-// Trace of vbar: each tile of an instance that just produced a sample step
-// stores its partial sum; the last tile to finish (atomic ticket) adds the
-// partials in tile order, so the result does not depend on scheduling.
-__device__ __forceinline__ void trace_tile(const InstDesc &D, const Tile &T, int64_t n,
-                                           double x, double *red) {
-    red[threadIdx.x] = x;
-    __syncthreads();
-    for (int s = TILE / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        D.part[T.local] = red[0];
-        __threadfence();
-        const uint32_t k = atomicAdd(&D.ctrl->tiles_done, 1u);
-        last = (k + 1 == (uint32_t)D.n_cell_tiles);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < D.n_cell_tiles; i += TILE)
-            acc += ((volatile double *)D.part)[i];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = TILE / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            const int64_t idx = (n + 1) / D.trace_every;
-            if (idx < D.trace_cap) D.trace[idx] = red[0] * D.inv_total_vol;
-            D.ctrl->tiles_done = 0u;
-        }
-    }
-    __syncthreads();
-}
-
-// Bit i set when stimulus i is on during step n (integer step windows).
-__device__ __forceinline__ uint32_t active_stimuli(const Ctrl *ctrl, int64_t n) {
-    uint32_t active = 0;
-    const int ns = ctrl->n_stim;
-    for (int i = 0; i < ns; ++i) {
-        const int64_t k = n - ctrl->st_n0[i];
-        const int64_t per = ctrl->st_nper[i];
-        const bool on = k >= 0 && (per <= 0 ? k < ctrl->st_ndur[i]
-                                            : (k / per) < ctrl->st_count[i] &&
-                                                  (k % per) < ctrl->st_ndur[i]);
-        active |= (on ? 1u : 0u) << i;
-    }
-    return active;
-}
-
 template <typename R, int MSET>
 __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
     __shared__ double red[TILE];
@@ -421,7 +414,7 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
     const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
     if ((int32_t)threadIdx.x < T.count)
         cell_step<R, MSET>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
-    if (sample) trace_tile(D, T, n, x, red);
+    if (sample) tile_partial(D, T, x, red);
 }
 
 // ------------------------------------------------------- Purkinje graph

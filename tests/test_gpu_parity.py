@@ -195,6 +195,20 @@ def test_graph_replay_equals_direct_launch(ep):
     assert np.array_equal(va, vb)
 
 
+def test_trace_sample_same_from_host_and_device(ep):
+    """A vbar sample taken by the last step issued is added up on the host;
+    once the next step runs, the device adds the same partials: both give
+    the same bits."""
+    w = M.config1(nx=8, ny=8, nz=2)
+    a = ep.Sim(w, trace_every=25)
+    a.step(100)
+    _, v_host = a.mean_vm_trace()
+    assert v_host.size == 5 and np.isfinite(v_host).all()
+    a.step(10)
+    _, v_dev = a.mean_vm_trace()
+    assert v_dev[4] == v_host[4]
+
+
 def test_checkpoint_roundtrip_bitwise(ep):
     w = M.config1(nx=8, ny=6, nz=2)
     for prec in (ep.EP_FP64, ep.EP_FP32_MIXED):
