@@ -103,6 +103,81 @@ def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
                        f"h=0.25 mm), {steps} FP64 steps after 2 untimed, {el:.1f} s")
 
 
+def run_serving(ep, n_req, n_steps, capacity, load=0.7, seed=4, prec=None, one_at_a_time=False,
+                trial=20):
+    """Config-4 stream: slab requests log-uniform in [1e4, 1e6] tets with
+    Poisson arrivals at `load` x capacity (cell-steps/s) / mean request work;
+    continuous batching with the autotuned schedule (re-tuned as the batch
+    grows or shrinks), or one request at a time."""
+    from paper_2112_12854_amd import meshgen
+    specs = meshgen.serving_requests(n=n_req, seed=seed)
+    ws = [meshgen.serving_workload(sp, n_steps) for sp in specs]
+    work = np.array([w.n_tets * n_steps for w in ws], dtype=np.float64)
+    lam = load * capacity / work.mean()
+    rng = np.random.default_rng(seed + 1000)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+    sv = ep.Server(prec=prec, max_slots=1 if one_at_a_time else 256)
+    if not one_at_a_time:
+        sv.autotune(trial, retune=True)
+    t0 = time.perf_counter()
+    ids = []
+    for i, w in enumerate(ws):
+        wait = arrivals[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        ids.append(sv.submit(w, n_steps))
+    res = [sv.wait(r) for r in ids]
+    st = sv.stats()
+    sv.close()
+    bad = [r for r in res if r["status"] != ep.EP_OK]
+    if bad:
+        raise RuntimeError(f"{len(bad)} serving requests failed")
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                mean_s=float(lat.mean()), cell_steps_per_s=float(work.sum() / span),
+                span_s=span, arrival_rate_per_s=lam, n_requests=n_req, steps=n_steps,
+                mean_tets=float(np.mean([w.n_tets for w in ws])),
+                steps_per_graph=st["steps_per_graph"], xcd_remap=st["xcd_remap"],
+                autotune_runs=st["autotune_runs"])
+
+
+def run_uq(ep, n_inst, n_steps, prec, trial=25, seed=5):
+    """Config-5 batch: uneven slabs (8k-64k tets) with per-instance ionic
+    conductance scales, all resident together, autotuned once on the full
+    batch, then timed from the live progress counter."""
+    from paper_2112_12854_amd import meshgen
+    specs = meshgen.uq_instances(n=n_inst, seed=seed)
+    ws = [meshgen.uq_workload(sp, n_steps) for sp in specs]
+    total = sum(w.n_tets for w in ws)
+    sv = ep.Server(prec=prec, max_slots=n_inst)
+    sv.hold(True)
+    t0 = time.perf_counter()
+    ids = [sv.submit(w, n_steps) for w in ws]
+    while sv.stats()["running"] < n_inst:
+        if time.perf_counter() - t0 > 300:
+            raise RuntimeError("UQ batch did not become resident")
+        time.sleep(0.01)
+    t_res = time.perf_counter() - t0
+    sv.autotune(trial)
+    sv.hold(False)
+    while sv.stats()["autotune_runs"] < 1:
+        time.sleep(0.005)
+    st1, t1 = sv.stats(), time.perf_counter()
+    res = [sv.wait(r) for r in ids]
+    t2 = time.perf_counter()
+    st2 = sv.stats()
+    sv.close()
+    if any(r["status"] != ep.EP_OK for r in res):
+        raise RuntimeError("UQ instances failed")
+    return dict(n_instances=n_inst, total_tets=total, steps=n_steps,
+                cell_steps_per_s=(st2["cell_steps"] - st1["cell_steps"]) / (t2 - t1),
+                tuned_ms_per_step=st1["tuned_ms_per_step"],
+                tuned_cell_steps_per_s=total / (st1["tuned_ms_per_step"] * 1e-3),
+                steps_per_graph=st1["steps_per_graph"], xcd_remap=st1["xcd_remap"],
+                resident_after_s=t_res)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +195,12 @@ def main():
                     help="FP32-mixed only (short profiling runs)")
     ap.add_argument("--only-fp64", action="store_true",
                     help="FP64 only (short profiling runs)")
+    ap.add_argument("--serving", type=str, default="32x2500", metavar="NxSTEPS",
+                    help="serving stream sample (requests x steps each; '0' skips; "
+                         "the full stream is 256x15000)")
+    ap.add_argument("--uq", type=str, default="1024x2000", metavar="NxSTEPS",
+                    help="UQ batch sample (instances x steps; '0' skips; the full "
+                         "batch is 1024x25000)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times "
                          "(calibrates the HBM byte counters) and exit")
@@ -154,6 +235,28 @@ def main():
     f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
                                                   args.warmup, args.chunk, 20)
     hbm = None if args.only_fp32 else measure_hbm()
+    serving = uq = None
+    if not (args.only_fp32 or args.serving == "0"):
+        nreq, nst = (int(x) for x in args.serving.split("x"))
+        log(f"serving stream: {nreq} requests x {nst} steps (batched FP32-mixed) ...")
+        bat = run_serving(ep, nreq, nst, f32["cell_steps_per_s"], prec=ep.EP_FP32_MIXED)
+        log(f"  p50 {bat['p50_s']:.3f}s p99 {bat['p99_s']:.3f}s, {bat['cell_steps_per_s']:.3e} cell-steps/s")
+        log("serving stream: one at a time, FP64 ...")
+        one = run_serving(ep, nreq, nst, f32["cell_steps_per_s"], prec=ep.EP_FP64,
+                          one_at_a_time=True)
+        log(f"  p50 {one['p50_s']:.3f}s p99 {one['p99_s']:.3f}s, {one['cell_steps_per_s']:.3e} cell-steps/s")
+        serving = {"workload": f"{nreq} slab requests, 1e4-1e6 tets log-uniform, sigma scale "
+                               f"U[0.5,2], random stimulus face, {nst} steps each, Poisson "
+                               f"arrivals at 0.7 x the FP32 slab throughput",
+                   "batched_fp32": bat, "one_at_a_time_fp64": one}
+    if not (args.only_fp32 or args.uq == "0"):
+        ni, nst = (int(x) for x in args.uq.split("x"))
+        uq = {}
+        for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
+            log(f"UQ batch {name}: {ni} instances x {nst} steps ...")
+            uq[name] = run_uq(ep, ni, nst, prec)
+            log(f"  {uq[name]['cell_steps_per_s']:.3e} cell-steps/s "
+                f"(k={uq[name]['steps_per_graph']}, remap={uq[name]['xcd_remap']})")
     cpu = None
     if not (args.no_cpu or args.only_fp32):
         log("cpu baseline (oracle) ...")
@@ -192,6 +295,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
         "hbm_measured_GBps": hbm,
+        "serving": serving,
+        "uq_batch": uq,
     }
     print(json.dumps(out), flush=True)
 

@@ -212,6 +212,18 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);
 ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
                         int32_t xcd_remap);
 
+/* Launch-schedule autotuner (batched scheduling is this library's, not the
+ * paper's).  Tries every graph length in {0 (direct launches), 10, 25, 50,
+ * 100} steps, each with and without the XCD tile remap: one untimed launch
+ * (graph capture, warm caches), then trial_steps steps timed with HIP events
+ * on the simulation's stream.  Keeps the fastest (as ep_set_launch would)
+ * and reports it; any output pointer may be NULL.  The trials are ordinary
+ * steps: the simulation advances by 10 * trial_steps + 372 steps, with the
+ * same results as under any fixed schedule.  EP_ESTATE before ep_init,
+ * EP_EINVAL for trial_steps <= 0. */
+ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
+                      int32_t *xcd_remap, double *ms_per_step);
+
 /* Average device duration (ms) of the fused cell kernel and of the node
  * gather kernel over the last ep_profile_steps() call, from HIP events on
  * the simulation's stream. */
@@ -270,9 +282,13 @@ typedef struct {
 
 typedef struct {
     int64_t submitted, completed, running, queued;
-    double cell_steps;            /* tet-steps completed so far              */
+    double cell_steps;            /* tet-steps issued so far (finished
+                                     requests and the progress of running ones) */
     size_t bytes_in_use, bytes_budget;
     int64_t graph_launches, table_updates;
+    int32_t steps_per_graph, xcd_remap;   /* schedule in effect              */
+    int64_t autotune_runs;
+    double tuned_ms_per_step;     /* batch step time of the last tuning      */
 } ep_server_stats;
 
 typedef struct ep_server ep_server;
@@ -296,6 +312,15 @@ ep_status ep_server_release(ep_server *sv, int64_t id);   /* drop stored results
 ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st);
 /* Graph length in steps (> 0) and XCD remap, as ep_set_launch. */
 ep_status ep_server_set_launch(ep_server *sv, int32_t steps_per_graph, int32_t xcd_remap);
+/* hold != 0: keep admitting and uploading requests but step none, so that a
+ * batch can start together (a UQ sweep); hold == 0 resumes stepping. */
+ep_status ep_server_hold(ep_server *sv, int32_t hold);
+/* Autotune the schedule (as ep_autotune, trial_steps per candidate) on the
+ * batch that is live when the driver next steps; with retune != 0, tune again
+ * whenever at least 4 requests are live and their number has doubled or
+ * halved since the last tuning.  The trials are ordinary steps of the live
+ * requests. */
+ep_status ep_server_autotune(ep_server *sv, int64_t trial_steps, int32_t retune);
 void ep_server_destroy(ep_server *sv);    /* waits for running requests */
 const char *ep_server_last_error(ep_server *sv);
 

@@ -621,6 +621,21 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes) {
 }
 
 // ------------------------------------------------------------- profiling
+ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
+                      int32_t *xcd_remap, double *ms_per_step) {
+    if (!s) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    if (trial_steps <= 0) return fail(s, EP_EINVAL, "trial_steps must be positive");
+    HIP_TRY(s, hipSetDevice(s->opt.device));
+    ep::TuneResult r;
+    std::string e = ep::stepper_autotune(s->stepper, trial_steps, r);
+    if (!e.empty()) return fail(s, EP_EDEVICE, e);
+    if (steps_per_graph) *steps_per_graph = r.steps_per_graph;
+    if (xcd_remap) *xcd_remap = r.xcd_remap;
+    if (ms_per_step) *ms_per_step = r.ms_per_step;
+    return EP_OK;
+}
+
 ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms, double *node_ms) {
     if (!s) return EP_EINVAL;
     if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");

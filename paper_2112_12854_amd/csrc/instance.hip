@@ -585,6 +585,50 @@ std::string stepper_run(Stepper &s, int64_t k) {
     return "";
 }
 
+std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
+                             bool allow_direct) {
+    if (trial_steps <= 0) return "trial_steps must be positive";
+    static const int32_t kGraph[] = {0, 10, 25, 50, 100};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return "hipEventCreate failed";
+    }
+    out = TuneResult();
+    double best = HUGE_VAL;
+    std::string err;
+    for (int32_t remap = 0; remap <= 1 && err.empty(); ++remap)
+        for (int32_t k : kGraph) {
+            if (k == 0 && !allow_direct) continue;
+            s.steps_per_graph = k;
+            s.remap = remap;
+            const int64_t warm = k > 0 ? k : 1;
+            err = stepper_run(s, warm);
+            if (!err.empty()) break;
+            (void)hipEventRecord(e0, s.stream);
+            err = stepper_run(s, trial_steps);
+            if (!err.empty()) break;
+            (void)hipEventRecord(e1, s.stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            out.n_trials++;
+            out.steps_used += warm + trial_steps;
+            const double per = ms / trial_steps;
+            if (per < best) {
+                best = per;
+                out.steps_per_graph = k;
+                out.xcd_remap = remap;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s.steps_per_graph = out.steps_per_graph;
+    s.remap = out.xcd_remap;
+    out.ms_per_step = best;
+    return err;
+}
+
 std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms) {
     if (s.dirty) {
         std::string e = stepper_sync_tables(s);

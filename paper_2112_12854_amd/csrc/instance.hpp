@@ -132,6 +132,20 @@ std::string stepper_run(Stepper &s, int64_t k);
 // Time one node-gather and one cell launch with events (ms).
 std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms);
 
+// Launch-schedule autotuner.  Every candidate (steps per graph launch x XCD
+// tile remap) runs one untimed launch (graph capture, warm caches) and then
+// `trial_steps` timed steps of the live instances; the fastest per step is
+// kept in the stepper.  Results do not depend on the schedule, so the trial
+// steps are ordinary steps of the simulations.
+struct TuneResult {
+    int32_t steps_per_graph = 50, xcd_remap = 1;
+    double ms_per_step = 0;
+    int32_t n_trials = 0;
+    int64_t steps_used = 0;
+};
+std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
+                             bool allow_direct = true);
+
 int model_ng(int m);
 int model_nc(int m);
 void model_init(int m, double *y);

@@ -76,6 +76,11 @@ struct ep_server {
     std::string err;
     std::string driver_err;
     int32_t want_k = 50, want_remap = 1;   // launch settings, applied by the driver
+    // autotuning requests, served by the driver on the live batch
+    bool hold = false;                     // admit and upload, but do not step
+    bool tune_pending = false, tune_retune = false;
+    int64_t tune_trial = 0;
+    size_t tuned_live = 0;
 };
 
 namespace {
@@ -173,7 +178,6 @@ void finish(ep_server *sv, Req *r) {
         r->err = "non-finite membrane potential";
     }
     const size_t fp = r->footprint;
-    const double cell_steps = (double)nc * (double)r->spec.target;
     ep::free_instance(r->inst);
     r->inst.prep = ep::PrepOut();
     std::lock_guard<std::mutex> g(sv->mu);
@@ -182,7 +186,6 @@ void finish(ep_server *sv, Req *r) {
     r->t_done = now_s(sv);
     sv->stats.running--;
     sv->stats.completed++;
-    sv->stats.cell_steps += cell_steps;
     sv->cv_done.notify_all();
     sv->cv_driver.notify_all();
 }
@@ -269,16 +272,68 @@ void driver_main(ep_server *sv) {
             (void)hipEventRecord(rt.ev, sv->stream);
             retiring.push_back(rt);
         }
+        // ---- held: requests are admitted and uploaded, nothing steps
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            if (sv->hold && !sv->stop) {
+                sv->cv_driver.wait_for(lk, std::chrono::milliseconds(20), [&] {
+                    return sv->stop || !sv->hold || !sv->ready_q.empty();
+                });
+                continue;
+            }
+        }
+        // ---- autotune the schedule on the live batch when asked
+        bool tune = false;
+        int64_t trial = 0;
+        {
+            std::lock_guard<std::mutex> g(sv->mu);
+            const size_t n = live.size(), m = sv->tuned_live;
+            tune = n > 0 && sv->tune_trial > 0 &&
+                   (sv->tune_pending ||
+                    (sv->tune_retune && n >= 4 && (n >= 2 * m || 2 * n <= m)));
+            trial = sv->tune_trial;
+        }
+        // tet-steps issued by a stepping call (progress of the live batch)
+        auto issued_since = [&](const std::vector<int64_t> &h0) {
+            double c = 0;
+            for (size_t i = 0; i < live.size(); ++i)
+                c += (double)live[i]->inst.desc.nc * (double)(live[i]->inst.host_step - h0[i]);
+            return c;
+        };
+        auto steps_now = [&]() {
+            std::vector<int64_t> h(live.size());
+            for (size_t i = 0; i < live.size(); ++i) h[i] = live[i]->inst.host_step;
+            return h;
+        };
+        if (tune) {
+            ep::TuneResult r;
+            const std::vector<int64_t> h0 = steps_now();
+            std::string e = ep::stepper_autotune(sv->stepper, trial, r, false);
+            const double c = issued_since(h0);
+            std::lock_guard<std::mutex> g(sv->mu);
+            sv->stats.cell_steps += c;
+            if (!e.empty()) sv->driver_err = e;
+            sv->want_k = r.steps_per_graph;
+            sv->want_remap = r.xcd_remap;
+            sv->tune_pending = false;
+            sv->tuned_live = live.size();
+            sv->stats.autotune_runs++;
+            sv->stats.tuned_ms_per_step = r.ms_per_step;
+            sv->stats.graph_launches += r.n_trials;
+        }
         // ---- step every live instance
         if (!live.empty()) {
             const int64_t k = sv->stepper.steps_per_graph;
+            const std::vector<int64_t> h0 = steps_now();
             std::string e = ep::stepper_run(sv->stepper, k);
+            const double c = issued_since(h0);
             if (!e.empty()) { std::lock_guard<std::mutex> g(sv->mu); sv->driver_err = e; }
             hipEvent_t ev = new_event();
             (void)hipEventRecord(ev, sv->stream);
             inflight.push_back(ev);
             std::lock_guard<std::mutex> g(sv->mu);
             sv->stats.graph_launches++;
+            sv->stats.cell_steps += c;
         }
         // ---- keep at most two launches queued ahead of the host
         while (inflight.size() > 2) {
@@ -518,6 +573,8 @@ ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st) {
     std::lock_guard<std::mutex> g(sv->mu);
     *st = sv->stats;
     st->bytes_in_use = sv->in_use;
+    st->steps_per_graph = sv->want_k;
+    st->xcd_remap = sv->want_remap;
     if (!sv->driver_err.empty()) { sv->err = sv->driver_err; return EP_EDEVICE; }
     return EP_OK;
 }
@@ -527,6 +584,28 @@ ep_status ep_server_set_launch(ep_server *sv, int32_t steps_per_graph, int32_t x
     std::lock_guard<std::mutex> g(sv->mu);
     sv->want_k = steps_per_graph;           // applied by the driver between launches
     sv->want_remap = xcd_remap ? 1 : 0;
+    return EP_OK;
+}
+
+ep_status ep_server_hold(ep_server *sv, int32_t hold) {
+    if (!sv) return EP_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->hold = hold != 0;
+    }
+    sv->cv_driver.notify_all();
+    return EP_OK;
+}
+
+ep_status ep_server_autotune(ep_server *sv, int64_t trial_steps, int32_t retune) {
+    if (!sv || trial_steps <= 0) return EP_EINVAL;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        sv->tune_trial = trial_steps;
+        sv->tune_pending = true;
+        sv->tune_retune = retune != 0;
+    }
+    sv->cv_driver.notify_all();
     return EP_OK;
 }
 

@@ -61,7 +61,9 @@ class ep_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("running", C.c_int64),
                 ("queued", C.c_int64), ("cell_steps", C.c_double),
                 ("bytes_in_use", C.c_size_t), ("bytes_budget", C.c_size_t),
-                ("graph_launches", C.c_int64), ("table_updates", C.c_int64)]
+                ("graph_launches", C.c_int64), ("table_updates", C.c_int64),
+                ("steps_per_graph", C.c_int32), ("xcd_remap", C.c_int32),
+                ("autotune_runs", C.c_int64), ("tuned_ms_per_step", C.c_double)]
 
 
 class EPError(RuntimeError):
@@ -110,6 +112,8 @@ _SIGS = {
     "ep_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ep_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ep_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "ep_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32), _dp]),
     "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp]),
     "ep_algorithmic_bytes": (C.c_int, [C.c_void_p, _dp, _dp]),
     "ep_last_error": (C.c_char_p, [C.c_void_p]),
@@ -124,6 +128,8 @@ _SIGS = {
     "ep_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
     "ep_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ep_server_stats)]),
     "ep_server_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "ep_server_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32]),
+    "ep_server_hold": (C.c_int, [C.c_void_p, C.c_int32]),
     "ep_server_destroy": (None, [C.c_void_p]),
     "ep_server_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -327,6 +333,14 @@ class Sim:
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().ep_set_state(self.h, buf, len(blob)), self.h)
 
+    def autotune(self, trial_steps: int = 100) -> dict:
+        """Pick the fastest launch schedule on this simulation (the trial
+        steps advance it); returns the choice and its ms per step."""
+        k, r, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(lib().ep_autotune(self.h, int(trial_steps), C.byref(k), C.byref(r),
+                                 C.byref(ms)), self.h)
+        return {"steps_per_graph": k.value, "xcd_remap": r.value, "ms_per_step": ms.value}
+
     def profile_steps(self, n: int):
         a, b = C.c_double(), C.c_double()
         _check(lib().ep_profile_steps(self.h, int(n), C.byref(a), C.byref(b)), self.h)
@@ -442,6 +456,17 @@ class Server:
 
     def release(self, rid):
         self._chk(lib().ep_server_release(self.h, rid))
+
+    def set_launch(self, steps_per_graph: int = 50, xcd_remap: int = 1):
+        self._chk(lib().ep_server_set_launch(self.h, int(steps_per_graph), int(xcd_remap)))
+
+    def hold(self, on: bool = True):
+        """Admit and upload requests without stepping them (batch start)."""
+        self._chk(lib().ep_server_hold(self.h, int(bool(on))))
+
+    def autotune(self, trial_steps: int = 50, retune: bool = False):
+        """Tune the schedule on the batch live when the driver next steps."""
+        self._chk(lib().ep_server_autotune(self.h, int(trial_steps), int(bool(retune))))
 
     def stats(self) -> dict:
         s = ep_server_stats()

@@ -119,3 +119,36 @@ def test_malformed_and_oversized_requests(ep):
     else:
         assert sv.wait(rid)["status"] == ep.EP_ENOMEM
     sv.close()
+
+
+def test_autotuned_schedule_keeps_results(ep):
+    """The autotuner's trial steps are ordinary steps: a simulation tuned on
+    the way, and a server batch tuned (and re-tuned as it grows) while it
+    runs, give bitwise the results of a fixed schedule."""
+    w = M.config1(nx=10, ny=8, nz=2)
+    a = ep.Sim(w)
+    choice = a.autotune(20)
+    assert choice["steps_per_graph"] in (0, 10, 25, 50, 100)
+    assert choice["xcd_remap"] in (0, 1) and choice["ms_per_step"] > 0
+    used = 10 * 20 + 372
+    assert a.time()[0] == used
+    a.step(1000 - used)
+    b = ep.Sim(w)
+    b.step(1000)
+    assert np.array_equal(a.vm(), b.vm())
+    assert np.array_equal(a.apd90(), b.apd90(), equal_nan=True)
+
+    steps = 900
+    ws = requests(6, seed=9, steps=steps)
+    sv = ep.Server(prec=ep.EP_FP32_MIXED, max_slots=8)
+    sv.autotune(10, retune=True)
+    ids = [sv.submit(x, steps) for x in ws]
+    res = [sv.wait(i) for i in ids]
+    assert all(r["status"] == ep.EP_OK for r in res)
+    st = sv.stats()
+    assert st["autotune_runs"] >= 1 and st["steps_per_graph"] in (10, 25, 50, 100)
+    for x, i in zip(ws, ids):
+        vm, at, _ = alone(ep, x, ep.EP_FP32_MIXED, steps)
+        assert np.array_equal(sv.vm(i), vm)
+        assert np.array_equal(sv.activation(i), at, equal_nan=True)
+    sv.close()
