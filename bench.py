@@ -24,6 +24,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2112_12854_amd/csrc/kernels.hpp", "paper_2112_12854_amd/csrc/cellmodels.hpp",
+                  "paper_2112_12854_amd/csrc/instance.hip", "paper_2112_12854_amd/build.py")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_cell_slab-40x40x10mm-h0.25.md")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per cell-kernel launch from the rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
+    v = re.search(rf"{prec}_hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not v or m.group(1) != kernel_sources_sha256():
+        return None
+    return float(v.group(1))
 
 
 def log(msg):
@@ -54,7 +81,10 @@ def run_precision(ep, w, prec, steps, warmup, chunk, profile_steps):
     cell_ms, node_ms = sim.profile_steps(profile_steps)
     node_b, cell_b = sim.algorithmic_bytes()
     at = sim.activation()
+    n_sub = sim.purkinje_n_sub() if sim.n_purkinje else 0
     res = dict(ms_per_step=1e3 * elapsed / steps,
+               graph_node_steps_per_s=sim.n_purkinje * n_sub * steps / elapsed,
+               graph_substeps=n_sub,
                cell_steps_per_s=w.n_tets * steps / elapsed,
                p50_ms=1e3 * float(np.percentile(lat, 50)),
                p99_ms=1e3 * float(np.percentile(lat, 99)),
@@ -178,6 +208,43 @@ def run_uq(ep, n_inst, n_steps, prec, trial=25, seed=5):
                 resident_after_s=t_res)
 
 
+def run_heart(ep, meshgen, args):
+    """Three coupled media: the synthetic biventricle + atrial cap + Purkinje
+    tree (~11.6M tets, 60k graph nodes, dt 0.01 ms), FP32-mixed and FP64."""
+    t0 = time.time()
+    w = meshgen.heart(h=0.375, scale=1.0, purkinje_nodes=60000, n_pmj=2000)
+    log(f"workload {w.name}: {w.n_tets} tets, {w.purkinje.xyz.shape[0]} graph nodes, "
+        f"{len(w.purkinje.pmj_nodes)} junctions ({time.time() - t0:.1f}s)")
+    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, args.steps)
+    f64 = run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, args.steps)
+    achieved = f32["cell_bytes"] / (f32["cell_kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "cell-steps/s (ionic+FV step) FP32 vs FP64; p50/p99 solve latency",
+        "value": f32["cell_steps_per_s"], "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64conc", "data": "synthetic",
+        "config": {"workload": w.name, "n_tets": w.n_tets, "n_nodes": w.n_nodes,
+                   "graph_nodes": int(w.purkinje.xyz.shape[0]),
+                   "junctions": int(len(w.purkinje.pmj_nodes)), "dt_ms": w.dt,
+                   "cells": {"tp06": int((w.model <= 2).sum()), "crn": int((w.model == 3).sum())}},
+        "latency_ms": {"p50": f32["p50_ms"], "p99": f32["p99_ms"],
+                       "per": f"step (timed in chunks of {args.chunk} steps)"},
+        "graph": {"substeps": f32["graph_substeps"],
+                  "node_steps_per_s_fp32": f32["graph_node_steps_per_s"],
+                  "node_steps_per_s_fp64": f64["graph_node_steps_per_s"]},
+        "fp64": {"value": f64["cell_steps_per_s"], "ms_per_step": f64["ms_per_step"],
+                 "cell_kernel_ms": f64["cell_kernel_ms"], "node_kernel_ms": f64["node_kernel_ms"]},
+        "kernels_fp32": {"cell_kernel_ms": f32["cell_kernel_ms"],
+                         "node_kernel_ms": f32["node_kernel_ms"]},
+        "roofline": {"bound": "hbm", "kernel": "k_cell<float> (fused flux+ionic+update)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +268,8 @@ def main():
     ap.add_argument("--uq", type=str, default="1024x2000", metavar="NxSTEPS",
                     help="UQ batch sample (instances x steps; '0' skips; the full "
                          "batch is 1024x25000)")
+    ap.add_argument("--heart", action="store_true",
+                    help="the three-media heart instead of the slab (timed steps only)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times "
                          "(calibrates the HBM byte counters) and exit")
@@ -224,16 +293,18 @@ def main():
     from paper_2112_12854_amd import ep, meshgen
     ep.lib()
     torch.cuda.init()
+    if args.heart:
+        return run_heart(ep, meshgen, args)
     t0 = time.time()
     w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
     log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")
 
     if args.only_fp64:
-        run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, 5)
+        run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, args.steps)
         return
-    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, 20)
+    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, args.steps)
     f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
-                                                  args.warmup, args.chunk, 20)
+                                                  args.warmup, args.chunk, args.steps)
     hbm = None if args.only_fp32 else measure_hbm()
     serving = uq = None
     if not (args.only_fp32 or args.serving == "0"):
@@ -286,13 +357,17 @@ def main():
             "value": f64["cell_steps_per_s"], "ms_per_step": f64["ms_per_step"],
             "p50_ms": f64["p50_ms"], "p99_ms": f64["p99_ms"],
             "cell_kernel_ms": f64["cell_kernel_ms"], "node_kernel_ms": f64["node_kernel_ms"],
-            "cell_kernel_GBps": f64["cell_bytes"] / (f64["cell_kernel_ms"] * 1e-3) / 1e9},
+            "cell_kernel_GBps": f64["cell_bytes"] / (f64["cell_kernel_ms"] * 1e-3) / 1e9,
+            "cell_bytes": f64["cell_bytes"], "node_bytes": f64["node_bytes"],
+            "traffic": measured_traffic("fp64")},
         "kernels_fp32": {"cell_kernel_ms": f32["cell_kernel_ms"],
                          "node_kernel_ms": f32["node_kernel_ms"],
-                         "node_kernel_GBps": f32["node_bytes"] / (f32["node_kernel_ms"] * 1e-3) / 1e9},
+                         "node_kernel_GBps": f32["node_bytes"] / (f32["node_kernel_ms"] * 1e-3) / 1e9,
+                         "cell_bytes": f32["cell_bytes"], "node_bytes": f32["node_bytes"]},
         "roofline": {"bound": "hbm", "kernel": "k_cell<float> (fused flux+ionic+update)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("fp32"),
+                     "algorithmic_bytes": f32["cell_bytes"]},
         "cpu_baseline": cpu,
         "hbm_measured_GBps": hbm,
         "serving": serving,

@@ -73,7 +73,7 @@ size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
     b += round256(NC_MAX * c * 8) + round256(NG_MAX * c * r); // states
     b += 2 * round256(c * r) + 3 * round256(c * r) + round256(n * r);   // v0 v1 vrest vmax, vn
     b += round256(c) + 2 * round256(c * 8);                   // detection
-    b += round256(((c + TILE - 1) / TILE) * 8) + round256(8 * 4096) + round256(sizeof(Ctrl));
+    b += round256(((c + TILE - 1) / TILE + 3) * 8) + round256(8 * 4096) + round256(sizeof(Ctrl));
     return b;
 }
 
@@ -146,7 +146,7 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     b += round256(NC_MAX * c * 8) + round256(NG_MAX * c * r);
     b += 4 * round256(c * r) + round256(n * r);
     b += round256(c) + 2 * round256(c * 8);
-    b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE) * 8) + round256(sizeof(Ctrl));
+    b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE + 3) * 8) + round256(sizeof(Ctrl));
     return b + purkinje_bytes(I, rs);
 }
 
@@ -251,6 +251,21 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     int present = 0;
     for (uint8_t m : P.model) present |= m <= 2 ? 1 : (m == 3 ? 2 : (m == 4 ? 4 : 8));
     I.mset = present;
+    // class ranges (the host groups cells by class: TP06, CRN, Stewart, passive)
+    {
+        auto cls = [](uint8_t m) { return m <= 2 ? 0 : (m == 3 ? 1 : (m == 4 ? 2 : 3)); };
+        for (int k = 0; k < 4; ++k) I.cls_begin[k] = I.cls_end[k] = 0;
+        int64_t i = 0;
+        for (int k = 0; k < 4; ++k) {
+            I.cls_begin[k] = i;
+            while (i < nc && cls(P.model[i]) == k) ++i;
+            I.cls_end[k] = i;
+        }
+        if (i != nc) {
+            st = EP_EINVAL;
+            return "cells are not grouped by model class";
+        }
+    }
 
     InstDesc &D = I.desc;
     std::memset(&D, 0, sizeof(D));
@@ -300,8 +315,11 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         !up(I, (void **)&D.t_rep, std::vector<double>(nc, nan)))
         return fail_mem();
 
-    // vbar trace: sample 0 now, then one every trace_every steps
-    D.n_cell_tiles = (int32_t)((nc + TILE - 1) / TILE);
+    // vbar trace: sample 0 now, then one every trace_every steps; one partial
+    // per cell tile (tiles do not straddle model classes)
+    D.n_cell_tiles = 0;
+    for (int k = 0; k < 4; ++k)
+        D.n_cell_tiles += (int32_t)((I.cls_end[k] - I.cls_begin[k] + TILE - 1) / TILE);
     I.trace_cap = 4096;
     if (sp.trace_every > 0 && sp.target != INT64_MAX)
         I.trace_cap = std::max<int64_t>(2, sp.target / sp.trace_every + 2);
@@ -312,7 +330,7 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     std::vector<double> trace(I.trace_cap, nan);
     trace[0] = vt / tv;
     if (!up(I, (void **)&D.trace, trace) ||
-        !up(I, (void **)&D.part, std::vector<double>(D.n_cell_tiles, 0.0)))
+        !up(I, (void **)&D.part, std::vector<double>((nc + TILE - 1) / TILE + 3, 0.0)))
         return fail_mem();
     D.dt = sp.dt;
     D.thr = sp.thr;
@@ -381,15 +399,20 @@ Tables tables(const Stepper &s) {
 
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
+// Cell kernels of step offset `off`, one launch per model class present.
+template <typename R>
+void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
+    if (s.cls_tiles[0]) k_cell<R, 1><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[0]);
+    if (s.cls_tiles[1]) k_cell<R, 2><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[1]);
+    if (s.cls_tiles[2]) k_cell<R, 4><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[2]);
+    if (s.cls_tiles[3]) k_cell<R, 8><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[3]);
+}
+
 template <typename R>
 void launch_step(Stepper &s, int32_t off) {
     const Tables tb = tables(s);
     k_node_gather<R><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap);
-    switch (s.mset) {
-    case 1: k_cell<R, 1><<<s.grid_cell, TILE, 0, s.stream>>>(tb, off, s.remap); break;
-    case 8: k_cell<R, 8><<<s.grid_cell, TILE, 0, s.stream>>>(tb, off, s.remap); break;
-    default: k_cell<R, 15><<<s.grid_cell, TILE, 0, s.stream>>>(tb, off, s.remap); break;
-    }
+    launch_cells<R>(s, tb, off);
 }
 
 // Graph substeps and junction events of step offset `off` (after the tissue).
@@ -452,8 +475,19 @@ std::string stepper_sync_tables(Stepper &s) {
     std::vector<Tile> ct, nt;
     std::vector<PTile> pt;
     std::vector<PurkDesc> pk;
-    int mset = 0;
     int32_t nsub = 0;
+    // cell tiles class by class; tile `local` numbers run over the instance
+    std::vector<int32_t> next_local(s.insts.size(), 0);
+    for (int k = 0; k < 4; ++k) {
+        s.cls_base[k] = (int64_t)ct.size();
+        for (size_t i = 0; i < s.insts.size(); ++i) {
+            const Inst &I = *s.insts[i];
+            for (int64_t b = I.cls_begin[k]; b < I.cls_end[k]; b += TILE)
+                ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.cls_end[k] - b),
+                                  next_local[i]++});
+        }
+        s.cls_tiles[k] = (int64_t)ct.size() - s.cls_base[k];
+    }
     for (size_t i = 0; i < s.insts.size(); ++i) {
         const Inst &I = *s.insts[i];
         desc.push_back(I.desc);
@@ -463,13 +497,9 @@ std::string stepper_sync_tables(Stepper &s) {
             for (int64_t b = 0, t = 0; b < I.pdesc.np; b += TILE, ++t)
                 pt.push_back(PTile{I.pdesc, b, (int32_t)std::min<int64_t>(TILE, I.pdesc.np - b), (int32_t)t});
         }
-        mset |= I.mset;
-        for (int64_t b = 0, t = 0; b < I.desc.nc; b += TILE, ++t)
-            ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nc - b), (int32_t)t});
         for (int64_t b = 0, t = 0; b < I.desc.nn; b += TILE, ++t)
             nt.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nn - b), (int32_t)t});
     }
-    s.mset = (mset == 1 || mset == 8) ? mset : (mset ? 15 : 1);
     // grow device tables geometrically; growth invalidates the graph
     auto grow = [&](void **p, size_t &cap, size_t need, size_t elem) -> hipError_t {
         if (need <= cap && *p) return hipSuccess;
@@ -544,12 +574,11 @@ std::string stepper_run(Stepper &s, int64_t k) {
     }
     if (s.insts.empty()) return "";
     // one block per tile; a graph is reused until the tile counts change
-    s.grid_cell = grid_for(s.n_ct);
     s.grid_node = grid_for(s.n_nt);
     const int64_t glen = s.steps_per_graph > 0 ? s.steps_per_graph : 0;
     int64_t left = k;
     if (glen > 0 && left >= glen) {
-        if (s.graph && (s.graph_k != glen || s.graph_mset != s.mset || s.graph_gc != s.grid_cell ||
+        if (s.graph && (s.graph_k != glen || !std::equal(s.cls_tiles, s.cls_tiles + 4, s.graph_cls) ||
                         s.graph_gn != s.grid_node || s.graph_remap != s.remap ||
                         s.graph_pt != s.n_pt || s.graph_pk != s.n_pk || s.graph_nsub != s.n_sub_max))
             drop_graph(s);
@@ -564,8 +593,7 @@ std::string stepper_run(Stepper &s, int64_t k) {
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) { s.graph = nullptr; return hip_err("hipGraphInstantiate", e); }
             s.graph_k = (int)glen;
-            s.graph_mset = s.mset;
-            s.graph_gc = s.grid_cell;
+            std::copy(s.cls_tiles, s.cls_tiles + 4, s.graph_cls);
             s.graph_gn = s.grid_node;
             s.graph_remap = s.remap;
             s.graph_pt = s.n_pt;
@@ -634,9 +662,7 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
         std::string e = stepper_sync_tables(s);
         if (!e.empty()) return e;
     }
-    const int gc = grid_for(s.n_ct);
     const int gn = grid_for(s.n_nt);
-    s.grid_cell = gc;
     s.grid_node = gn;
     hipEvent_t ev[3];
     for (auto &x : ev)
@@ -648,19 +674,8 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
         if (s.rs == 8) k_node_gather<double><<<gn, TILE, 0, s.stream>>>(tb, 0, s.remap);
         else k_node_gather<float><<<gn, TILE, 0, s.stream>>>(tb, 0, s.remap);
         (void)hipEventRecord(ev[1], s.stream);
-        if (s.rs == 8) {
-            switch (s.mset) {
-            case 1: k_cell<double, 1><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
-            case 8: k_cell<double, 8><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
-            default: k_cell<double, 15><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
-            }
-        } else {
-            switch (s.mset) {
-            case 1: k_cell<float, 1><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
-            case 8: k_cell<float, 8><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
-            default: k_cell<float, 15><<<gc, TILE, 0, s.stream>>>(tb, 0, s.remap); break;
-            }
-        }
+        if (s.rs == 8) launch_cells<double>(s, tb, 0);
+        else launch_cells<float>(s, tb, 0);
         (void)hipEventRecord(ev[2], s.stream);
         if (s.n_pk > 0) {
             if (s.rs == 8) launch_purkinje<double>(s, 0);

@@ -59,6 +59,9 @@ struct Inst {
     int rs = 8;                        // sizeof(R): 8 FP64, 4 mixed
     PrepOut prep;
     int mset = 0;                      // model-set bits present
+    // internal cells of each model class (bits 1 TP06, 2 CRN, 4 Stewart,
+    // 8 passive, in that order): cells are grouped by class on the host
+    int64_t cls_begin[4] = {0, 0, 0, 0}, cls_end[4] = {0, 0, 0, 0};
     Allocator al;
     std::vector<std::pair<void *, size_t>> allocs;
     size_t footprint = 0;
@@ -97,8 +100,10 @@ struct Stepper {
     hipStream_t stream = nullptr;
     int device = 0;
     int rs = 8;
-    int mset = 0;
-    int grid_cell = 0, grid_node = 0;  // one block per tile (set when launching)
+    int grid_node = 0;                 // one block per tile (set when launching)
+    // cell tiles are listed class by class; one cell-kernel launch per class
+    // present, specialised to that class's cell model
+    int64_t cls_tiles[4] = {0, 0, 0, 0}, cls_base[4] = {0, 0, 0, 0};
     int remap = 1;
     int steps_per_graph = 50;
     std::vector<Inst *> insts;
@@ -116,7 +121,8 @@ struct Stepper {
     size_t stage_bytes = 0;
     hipEvent_t stage_done = nullptr;
     hipGraphExec_t graph = nullptr;
-    int graph_k = 0, graph_mset = -1, graph_gc = -1, graph_gn = -1, graph_remap = -1;
+    int graph_k = 0, graph_gn = -1, graph_remap = -1;
+    int64_t graph_cls[4] = {-1, -1, -1, -1};
     int64_t graph_pt = -1, graph_pk = -1;
     int32_t graph_nsub = -1;
     bool dirty = true;

@@ -442,15 +442,18 @@ def heart(h: float = 0.5, seed: int = 3, scale: float = 1.0, purkinje_nodes: int
     pk = purkinje_tree(lv, rv, rv_off, n_nodes=purkinje_nodes, n_pmj=n_pmj, seg=seg,
                        seed=seed, z_base=z_base)
     w.purkinje = pk
-    # the His-bundle root is stimulated at 130 ms (AV conduction, Sec. 1)
-    w.stimuli.append(Stimulus(ids=np.array([0], np.int32), t0=130.0, dur=2.0,
-                              amp=-100.0, domain=1))
+    # the His-bundle root is stimulated at 130 ms (AV conduction, Sec. 1); a
+    # pulse into one graph node cannot charge the cable around it, so the
+    # graph nodes within 0.5 mm of the root receive it
+    root = np.nonzero(np.linalg.norm(pk.xyz - pk.xyz[0], axis=1) <= 0.5)[0].astype(np.int32)
+    w.stimuli.append(Stimulus(ids=root, t0=130.0, dur=2.0, amp=-100.0, domain=1))
     return w
 
 
 def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_base=0.0):
     """Seeded fractal tree on the LV and RV endocardium: from a root near the
-    base of the septum, branches of random length (2-12 mm, segments of
+    base of the septum, branches of random length (1-4 mm, x4 for the two
+    bundle branches and their first split; segments of
     `seg` mm) split into two at +-20..50 deg, each point projected back onto
     the endocardial ellipsoid, until n_nodes nodes exist.  Leaves become the
     junctions, except those within 4 mm of the septal plane (the paper places
@@ -480,7 +483,7 @@ def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_
         stack.append((0, side, direc / np.linalg.norm(direc), 0))
     while stack and len(pts) < n_nodes:
         start, side, direc, depth = stack.pop(0)
-        length = rng.uniform(2.0, 12.0) * (1.6 if depth < 2 else 1.0)
+        length = rng.uniform(1.0, 4.0) * (4.0 if depth < 2 else 1.0)
         nseg = max(2, int(length / seg))
         prev = start
         for _ in range(nseg):

@@ -122,3 +122,32 @@ def test_purkinje_abi_errors(ep):
         assert L.ep_get_purkinje_substeps(h, C.byref(n)) == ep.EP_ESTATE
     finally:
         L.ep_destroy(h)
+
+
+def test_heart_three_media_fp64_parity(ep, oracle_lib):
+    """The synthetic three-media heart at a small scale: TP06 layers, the
+    CRN atrial cap, the Stewart tree and its junctions in one instance (His
+    root driven at t = 0 here), 20 ms: FP64 parity on tissue and graph, and
+    the FP32-mixed activation times within 0.5 ms."""
+    w = M.heart(h=1.0, scale=0.3, purkinje_nodes=1500, n_pmj=60)
+    w.stimuli[-1].t0 = 0.0
+    say(f"heart: {w.n_tets} tets, {w.purkinje.xyz.shape[0]} graph nodes, "
+        f"{len(w.purkinje.pmj_nodes)} junctions")
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    f = ep.Sim(w, prec=ep.EP_FP32_MIXED)
+    o = oracle_lib.Sim(w)
+    for chunk in range(4):
+        g.step(500)
+        f.step(500)
+        o.step(500)
+        dv = np.max(np.abs(g.vm() - o.vm()))
+        dp = np.max(np.abs(g.purkinje_vm() - o.purkinje_vm()))
+        assert dv <= TOL_MV and dp <= TOL_MV, (chunk, dv, dp)
+    ta_o, pa_o = o.activation(), o.purkinje_activation()
+    assert same_times(g.activation(), ta_o, 0) <= 1e-6
+    assert same_times(g.purkinje_activation(), pa_o, 0) <= 1e-6
+    assert np.isfinite(pa_o).all()
+    # junction-driven ventricular cells activated (not only the atrial ball)
+    assert np.isfinite(ta_o[w.model <= 2]).sum() > 0
+    assert same_times(f.purkinje_activation(), pa_o, 0) <= 0.5
+    assert same_times(f.activation(), ta_o, 0) <= 0.5
