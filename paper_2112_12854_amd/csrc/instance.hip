@@ -402,10 +402,12 @@ int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 // Cell kernels of step offset `off`, one launch per model class present.
 template <typename R>
 void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
-    if (s.cls_tiles[0]) k_cell<R, 1><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[0]);
-    if (s.cls_tiles[1]) k_cell<R, 2><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[1]);
-    if (s.cls_tiles[2]) k_cell<R, 4><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[2]);
-    if (s.cls_tiles[3]) k_cell<R, 8><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(tb, off, s.remap, s.cls_base[3]);
+    Tables t[4] = {tb, tb, tb, tb};
+    for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + s.cls_base[k];
+    if (s.cls_tiles[0]) k_cell<R, 1><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
+    if (s.cls_tiles[1]) k_cell<R, 2><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
+    if (s.cls_tiles[2]) k_cell<R, 4><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
+    if (s.cls_tiles[3]) k_cell<R, 8><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
 }
 
 template <typename R>

@@ -402,12 +402,12 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     }
 }
 
-// One launch per model class: tiles base .. base + gridDim.x - 1 of the
-// class-ordered cell tile list.
+// One launch per model class: the host passes tb.cell_tiles pointing at the
+// first tile of the class in the class-ordered tile list.
 template <typename R, int MSET>
-__global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap, int64_t base) {
+__global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
     __shared__ double red[TILE];
-    const Tile &T = tb.cell_tiles[base + my_tile(remap)];
+    const Tile &T = tb.cell_tiles[my_tile(remap)];
     const InstDesc &D = T.d;
     int64_t n;
     if (!stepping(D.ctrl, step_off, n)) return;
