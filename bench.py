@@ -193,15 +193,25 @@ def run_uq(ep, n_inst, n_steps, prec, trial=25, seed=5):
     sv.hold(False)
     while sv.stats()["autotune_runs"] < 1:
         time.sleep(0.005)
+    # steady state: from the end of the tuning to 90 % of the batch's steps
+    # issued (the counter advances as launches are queued, at most two
+    # launches ahead of the device, alike at both ends of the window)
     st1, t1 = sv.stats(), time.perf_counter()
+    goal = 0.9 * total * n_steps
+    while True:
+        st2, t2 = sv.stats(), time.perf_counter()
+        if st2["cell_steps"] >= goal or st2["completed"] == n_inst:
+            break
+        time.sleep(0.002)
     res = [sv.wait(r) for r in ids]
-    t2 = time.perf_counter()
-    st2 = sv.stats()
+    t3 = time.perf_counter()
     sv.close()
     if any(r["status"] != ep.EP_OK for r in res):
         raise RuntimeError("UQ instances failed")
     return dict(n_instances=n_inst, total_tets=total, steps=n_steps,
                 cell_steps_per_s=(st2["cell_steps"] - st1["cell_steps"]) / (t2 - t1),
+                end_to_end_cell_steps_per_s=total * n_steps / (t3 - t0),
+                end_to_end_s=t3 - t0,
                 tuned_ms_per_step=st1["tuned_ms_per_step"],
                 tuned_cell_steps_per_s=total / (st1["tuned_ms_per_step"] * 1e-3),
                 steps_per_graph=st1["steps_per_graph"], xcd_remap=st1["xcd_remap"],

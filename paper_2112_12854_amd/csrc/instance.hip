@@ -32,14 +32,24 @@ void model_init(int m, double *y) {
 
 namespace {
 
-void *dalloc(Inst &in, size_t bytes) {
-    bytes = std::max<size_t>(bytes, 256);
+void *raw_alloc(Inst &in, size_t bytes) {
     void *p = nullptr;
     if (in.al.alloc) p = in.al.alloc(bytes, in.al.ctx);
     else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    return p;
+}
+
+void *dalloc(Inst &in, size_t bytes) {
+    const size_t r = (std::max<size_t>(bytes, 256) + 255) / 256 * 256;
+    if (in.arena && in.arena_used + r <= in.arena_size) {
+        void *p = in.arena + in.arena_used;
+        in.arena_used += r;
+        return p;
+    }
+    void *p = raw_alloc(in, r);
     if (p) {
-        in.allocs.push_back({p, bytes});
-        in.footprint += bytes;
+        in.allocs.push_back({p, r});
+        in.footprint += r;
     }
     return p;
 }
@@ -243,6 +253,15 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     I.rs = rs;
     I.al = al;
     PrepOut &P = I.prep;
+    I.arena_size = instance_footprint(I, rs, sp);
+    I.arena_used = 0;
+    I.arena = (char *)raw_alloc(I, I.arena_size);
+    if (!I.arena) {
+        st = EP_ENOMEM;
+        I.arena_size = 0;
+        return "device allocation failed";
+    }
+    I.footprint = I.arena_size;
     const int64_t nc = sp.n_tets, nn = sp.n_nodes;
     I.n_slices = (int64_t)P.sell_off.size() - 1;
     I.dt = sp.dt;
@@ -382,6 +401,12 @@ void free_instance(Inst &I) {
         else (void)hipFree(a.first);
     }
     I.allocs.clear();
+    if (I.arena) {
+        if (I.al.free) I.al.free(I.arena, I.al.ctx);
+        else (void)hipFree(I.arena);
+    }
+    I.arena = nullptr;
+    I.arena_size = I.arena_used = 0;
     I.footprint = 0;
     I.d_ctrl = nullptr;
 }

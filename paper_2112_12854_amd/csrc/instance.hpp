@@ -64,6 +64,11 @@ struct Inst {
     int64_t cls_begin[4] = {0, 0, 0, 0}, cls_end[4] = {0, 0, 0, 0};
     Allocator al;
     std::vector<std::pair<void *, size_t>> allocs;
+    // one device block per instance, carved in 256-byte aligned pieces (one
+    // allocation and one free per instance); pieces beyond it are allocated
+    // on their own
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
     size_t footprint = 0;
     epdev::InstDesc desc{};            // device pointers and parameters
     epdev::Ctrl *d_ctrl = nullptr;

@@ -49,6 +49,7 @@ struct Req {
 struct Retire {
     std::vector<Req *> reqs;
     hipEvent_t ev = nullptr;
+    void *h_group = nullptr;           // pinned results of all of reqs
 };
 
 }  // namespace
@@ -137,27 +138,46 @@ void worker_main(ep_server *sv) {
     }
 }
 
-// Copy the results of finished instances into pinned buffers (stream order).
-void stage_results(ep_server *sv, Req *r) {
-    const size_t nc = (size_t)r->inst.desc.nc;
-    const size_t bytes = nc * 16 + nc * (size_t)sv->rs;
-    if (hipHostMalloc(&r->h_res, bytes) != hipSuccess) { r->h_res = nullptr; return; }
-    char *p = (char *)r->h_res;
-    const epdev::InstDesc &D = r->inst.desc;
-    (void)hipMemcpyAsync(p, D.t_act, nc * 8, hipMemcpyDeviceToHost, sv->stream);
-    (void)hipMemcpyAsync(p + nc * 8, D.t_rep, nc * 8, hipMemcpyDeviceToHost, sv->stream);
-    (void)hipMemcpyAsync(p + nc * 16, D.v[r->inst.host_step & 1], nc * sv->rs,
-                         hipMemcpyDeviceToHost, sv->stream);
+// Copy the results of a group of finished instances into one pinned buffer
+// (stream order): per request t_act, t_rep (f64), v (R) and the NaN flag.
+void *stage_results(ep_server *sv, const std::vector<Req *> &fin) {
+    auto bytes_of = [&](const Req *r) {
+        const size_t nc = (size_t)r->inst.desc.nc;
+        return (nc * 16 + nc * (size_t)sv->rs + 8 + 255) / 256 * 256;
+    };
+    size_t total = 0;
+    for (const Req *r : fin) total += bytes_of(r);
+    void *grp = nullptr;
+    if (hipHostMalloc(&grp, std::max<size_t>(total, 256)) != hipSuccess) {
+        for (Req *r : fin) r->h_res = nullptr;
+        return nullptr;
+    }
+    char *p = (char *)grp;
+    for (Req *r : fin) {
+        const size_t nc = (size_t)r->inst.desc.nc;
+        const epdev::InstDesc &D = r->inst.desc;
+        r->h_res = p;
+        (void)hipMemcpyAsync(p, D.t_act, nc * 8, hipMemcpyDeviceToHost, sv->stream);
+        (void)hipMemcpyAsync(p + nc * 8, D.t_rep, nc * 8, hipMemcpyDeviceToHost, sv->stream);
+        (void)hipMemcpyAsync(p + nc * 16, D.v[r->inst.host_step & 1], nc * sv->rs,
+                             hipMemcpyDeviceToHost, sv->stream);
+        (void)hipMemcpyAsync(p + nc * 16 + nc * sv->rs, &r->inst.d_ctrl->nan_flag, sizeof(int32_t),
+                             hipMemcpyDeviceToHost, sv->stream);
+        p += bytes_of(r);
+    }
+    return grp;
 }
 
+// Unpack the staged results of a request (after its group's copies are
+// done) and release its device memory.
 void finish(ep_server *sv, Req *r) {
     const int64_t nc = r->inst.desc.nc;
     int32_t nan_flag = 0;
-    (void)hipMemcpy(&nan_flag, &r->inst.d_ctrl->nan_flag, sizeof(nan_flag), hipMemcpyDeviceToHost);
     if (r->h_res) {
         const double *ta = (const double *)r->h_res;
         const double *tr = ta + nc;
         const char *vb = (const char *)(tr + nc);
+        std::memcpy(&nan_flag, vb + nc * sv->rs, sizeof(nan_flag));
         r->vm.assign(nc, 0.0);
         r->tact.assign(nc, 0.0);
         r->apd.assign(nc, 0.0);
@@ -167,8 +187,7 @@ void finish(ep_server *sv, Req *r) {
             r->apd[u] = tr[i] - ta[i];
             r->vm[u] = sv->rs == 8 ? ((const double *)vb)[i] : (double)((const float *)vb)[i];
         }
-        (void)hipHostFree(r->h_res);
-        r->h_res = nullptr;
+        r->h_res = nullptr;                 // part of its group's buffer
     } else if (r->status == EP_OK) {
         r->status = EP_ENOMEM;
         r->err = "pinned result buffer allocation failed";
@@ -250,8 +269,9 @@ void driver_main(ep_server *sv) {
         std::vector<Req *> fin;
         for (Req *r : live)
             if (r->inst.host_step >= r->inst.target) fin.push_back(r);
+        void *h_group = nullptr;
         if (!fin.empty()) {
-            for (Req *r : fin) stage_results(sv, r);
+            h_group = stage_results(sv, fin);
             live.erase(std::remove_if(live.begin(), live.end(),
                                       [&](Req *r) { return r->inst.host_step >= r->inst.target; }),
                        live.end());
@@ -268,6 +288,7 @@ void driver_main(ep_server *sv) {
         if (!fin.empty()) {
             Retire rt;
             rt.reqs = fin;
+            rt.h_group = h_group;
             rt.ev = new_event();
             (void)hipEventRecord(rt.ev, sv->stream);
             retiring.push_back(rt);
@@ -346,6 +367,7 @@ void driver_main(ep_server *sv) {
                (live.empty() || hipEventQuery(retiring.front().ev) == hipSuccess)) {
             (void)hipEventSynchronize(retiring.front().ev);
             for (Req *r : retiring.front().reqs) finish(sv, r);
+            if (retiring.front().h_group) (void)hipHostFree(retiring.front().h_group);
             (void)hipEventDestroy(retiring.front().ev);
             retiring.pop_front();
         }
@@ -364,6 +386,7 @@ void driver_main(ep_server *sv) {
     for (hipEvent_t e : inflight) (void)hipEventDestroy(e);
     for (Retire &rt : retiring) {
         for (Req *r : rt.reqs) finish(sv, r);
+        if (rt.h_group) (void)hipHostFree(rt.h_group);
         (void)hipEventDestroy(rt.ev);
     }
     for (Req *r : live) {
