@@ -252,36 +252,45 @@ typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, -1, 0x00020000);
 }
+// Cache policy of buffer accesses: kStream marks data touched once per step
+// (stencil coefficients, cell-model states) as non-temporal, so that it does
+// not evict the node values and neighbour potentials the gathers reuse.
+constexpr int kCached = 0, kStream = 2;
 template <typename T> struct BufIO;
 template <> struct BufIO<float> {
+    template <int P>
     static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, P));
     }
+    template <int P>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float x, uint32_t v, uint32_t s) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, P);
     }
 };
 template <> struct BufIO<int32_t> {
+    template <int P>
     static __device__ __forceinline__ int32_t ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-        return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0);
+        return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, v, s, P);
     }
 };
 template <> struct BufIO<double> {
+    template <int P>
     static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, P));
     }
+    template <int P>
     static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, double x, uint32_t v, uint32_t s) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, v, s, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, v, s, P);
     }
 };
 // element `c` of slot `s` of a slot-major array with n entries per slot
-template <typename T>
+template <typename T, int P = kStream>
 __device__ __forceinline__ T sld(__amdgpu_buffer_rsrc_t r, int s, int64_t n, uint32_t c) {
-    return BufIO<T>::ld(r, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
+    return BufIO<T>::template ld<P>(r, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
 }
-template <typename T>
+template <typename T, int P = kStream>
 __device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, int64_t n, uint32_t c, T x) {
-    BufIO<T>::st(r, x, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
+    BufIO<T>::template st<P>(r, x, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
 }
 
 // One cell-model update of cell c of a slot-major state set: gates by
