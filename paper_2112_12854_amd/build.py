@@ -10,7 +10,8 @@ SOURCES = ["ep_api.hip", "instance.hip", "serve.hip", "prep.cpp", "purkinje.cpp"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fno-fast-math", "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
+         "-fno-fast-math", "-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         "-Wall", "-Wno-unused-function",
          "-I", os.path.join(HERE, "..", "include")]
 
 
