@@ -218,6 +218,50 @@ def run_uq(ep, n_inst, n_steps, prec, trial=25, seed=5):
                 resident_after_s=t_res)
 
 
+def _err_stats(a, b):
+    d = np.abs(a - b)
+    d = d[np.isfinite(d)]
+    if d.size == 0:
+        return None
+    return {"max": float(d.max()), "p99": float(np.percentile(d, 99)), "mean": float(d.mean()),
+            "n": int(d.size)}
+
+
+def fp32_accuracy(ep, meshgen, n_uq=16, uq_steps=25000):
+    """FP32-mixed error per result: activation time and APD90 of every cell
+    against the GPU FP64 path (held to the FP64 oracle by the parity tests)
+    on a layered rotating-fibre slab and on a seeded subset of the UQ batch,
+    both over 500 ms."""
+    out = {}
+    w = meshgen.config2(n_steps=25000, nx=24, ny=20, nz=8, h=0.25)
+    r = {}
+    for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
+        g = ep.Sim(w, prec=prec)
+        g.step(w.n_steps)
+        r[name] = (g.activation(), g.apd90())
+        g.close()
+    out["slab_vs_gpu_fp64"] = {"workload": f"{w.name} {w.n_tets} tets, 500 ms",
+                               "at_ms": _err_stats(r["fp32"][0], r["fp64"][0]),
+                               "apd90_ms": _err_stats(r["fp32"][1], r["fp64"][1]),
+                               "at_nan_pattern_equal": bool(np.array_equal(np.isnan(r["fp32"][0]),
+                                                                           np.isnan(r["fp64"][0])))}
+    specs = meshgen.uq_instances(n=1024, seed=5)[:n_uq]
+    ws = [meshgen.uq_workload(sp, uq_steps) for sp in specs]
+    res = {}
+    for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
+        sv = ep.Server(prec=prec, max_slots=n_uq)
+        ids = [sv.submit(x, uq_steps) for x in ws]
+        for i in ids:
+            sv.wait(i)
+        res[name] = ([sv.activation(i) for i in ids], [sv.apd90(i) for i in ids])
+        sv.close()
+    at32, at64 = np.concatenate(res["fp32"][0]), np.concatenate(res["fp64"][0])
+    ap32, ap64 = np.concatenate(res["fp32"][1]), np.concatenate(res["fp64"][1])
+    out["uq_vs_gpu_fp64"] = {"workload": f"first {n_uq} UQ instances ({at32.size} tets), 500 ms",
+                             "at_ms": _err_stats(at32, at64), "apd90_ms": _err_stats(ap32, ap64)}
+    return out
+
+
 def run_heart(ep, meshgen, args):
     """Three coupled media: the synthetic biventricle + atrial cap + Purkinje
     tree (~11.6M tets, 60k graph nodes, dt 0.01 ms), FP32-mixed and FP64."""
@@ -278,6 +322,8 @@ def main():
     ap.add_argument("--uq", type=str, default="1024x2000", metavar="NxSTEPS",
                     help="UQ batch sample (instances x steps; '0' skips; the full "
                          "batch is 1024x25000)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-vs-FP64 error distributions")
     ap.add_argument("--heart", action="store_true",
                     help="the three-media heart instead of the slab (timed steps only)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -338,6 +384,12 @@ def main():
             uq[name] = run_uq(ep, ni, nst, prec)
             log(f"  {uq[name]['cell_steps_per_s']:.3e} cell-steps/s "
                 f"(k={uq[name]['steps_per_graph']}, remap={uq[name]['xcd_remap']})")
+    acc = None
+    if not (args.only_fp32 or args.no_accuracy):
+        log("FP32 accuracy (500 ms runs) ...")
+        acc = fp32_accuracy(ep, meshgen)
+        log(f"  slab: AT max {acc['slab_vs_gpu_fp64']['at_ms']['max']:.4f} ms, "
+            f"APD90 max {acc['slab_vs_gpu_fp64']['apd90_ms']['max']:.4f} ms")
     cpu = None
     if not (args.no_cpu or args.only_fp32):
         log("cpu baseline (oracle) ...")
@@ -382,6 +434,7 @@ def main():
         "hbm_measured_GBps": hbm,
         "serving": serving,
         "uq_batch": uq,
+        "fp32_error": acc,
     }
     print(json.dumps(out), flush=True)
 

@@ -259,6 +259,9 @@ def test_fp32_mixed_activation_apd_vs_oracle(ep, oracle_lib):
     assert (rep[odd] > t_end - 1.0).all()
     assert both.mean() > 0.9
     dapd = np.abs(ap_g - ap_r)[both].max()
-    say(f"  max|dAT| = {dat:.4f} ms, max|dAPD90| = {dapd:.4f} ms")
+    fa = np.abs(at_g - at_r)[np.isfinite(at_r)]
+    fp = np.abs(ap_g - ap_r)[both]
+    say(f"  |dAT| ms: max {dat:.4f} p99 {np.percentile(fa, 99):.4f} mean {fa.mean():.4f}; "
+        f"|dAPD90| ms: max {dapd:.4f} p99 {np.percentile(fp, 99):.4f} mean {fp.mean():.4f}")
     assert dat <= 0.5
     assert dapd <= 1.0
