@@ -118,7 +118,8 @@ def measure_hbm(mib: int = 2048, reps: int = 20):
 
 
 def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
-    """The oracle (as it stands) on a sub-slab of the same recipe."""
+    """The oracle (as it stands) on a sub-slab of the same recipe, on all host
+    threads, then on one thread (beside the paper's single-core figure)."""
     import oracle
     from paper_2112_12854_amd import meshgen
     w = meshgen.scaled_config2(nx, ny, nz, n_steps=steps)
@@ -127,10 +128,27 @@ def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
     t0 = time.perf_counter()
     ref.step(steps)
     el = time.perf_counter() - t0
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    s1 = max(2, steps // 10)
+    t0 = time.perf_counter()
+    ref.step(s1)
+    el1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=w.n_tets * steps / el, unit="cell-steps/s",
-                cores=oracle.num_threads(), kind="oracle",
+                cores=threads, kind="oracle",
                 sample=f"{w.n_tets} tets ({nx}x{ny}x{nz} hexes of the same slab recipe, "
-                       f"h=0.25 mm), {steps} FP64 steps after 2 untimed, {el:.1f} s")
+                       f"h=0.25 mm), {steps} FP64 steps after 2 untimed, {el:.1f} s",
+                single_thread={"value": w.n_tets * s1 / el1, "steps": s1},
+                host_cpu=cpu, host_cpus_visible=os.cpu_count())
 
 
 def run_serving(ep, n_req, n_steps, capacity, load=0.7, seed=4, prec=None, one_at_a_time=False,

@@ -59,6 +59,7 @@ def lib():
         L.orc_detect_waveform.argtypes = [_dp, C.c_int64, C.c_double, C.c_double,
                                           C.c_double, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_set_purkinje.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip,
                                        C.c_double, C.c_int, C.c_int32]
         L.orc_add_pmj.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
@@ -256,3 +257,7 @@ class Sim:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int):
+    lib().orc_set_num_threads(int(n))

@@ -110,6 +110,7 @@ void orc_detect_waveform(const double *v, int64_t n, double dt,
                          double threshold, double repol_frac, double *t_act,
                          double *apd90);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);   /* OpenMP threads of later calls */
 
 #ifdef __cplusplus
 }

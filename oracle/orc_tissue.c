@@ -148,6 +148,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ----------------------------------------------------------- geometry -- */
 static void sub3(const double *a, const double *b, double *o)
 {
