@@ -161,6 +161,27 @@ ep_status ep_get_purkinje_vm(ep_sim *s, double *out, int64_t n);
 ep_status ep_get_purkinje_activation(ep_sim *s, double *out, int64_t n);
 ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub);
 
+/* Bidomain model (Sec. 3.1 eq. electro, Sec. 3.2 eq. electro2_3d) instead of
+ * the monodomain one: the conductivities of ep_set_conductivity become the
+ * intracellular ones M_i; sigma_el / sigma_et (mS/mm) give the extracellular
+ * M_e with the same fibres and scale (the paper's ventricular values are
+ * 0.62 / 0.24).  Each step advances v with the intracellular flux of
+ * v + phi_e at level n, then solves
+ *   sum_f A_f ((M_i + M_e) grad phi_e).n = -sum_f A_f (M_i grad v^{n+1}).n
+ * for phi_e^{n+1} by restarted GMRES(restart) started from phi_e^n, until the
+ * residual is at most tol times the right-hand side's norm or max_iter Arnoldi
+ * steps, and shifts phi_e to zero volume-weighted mean (phi_e^0 = 0, exact for
+ * a uniform initial potential).  EP_FP64 only (EP_EINVAL otherwise); call
+ * before ep_init.  Each ep_step of a bidomain simulation synchronises its
+ * stream once per Arnoldi step. */
+ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t restart,
+                          double tol, int32_t max_iter);
+/* phi_e in caller numbering (n == n_tets) */
+ep_status ep_get_phi_e(ep_sim *s, double *out, int64_t n);
+/* Arnoldi steps of the last solve, their total, the last relative residual */
+ep_status ep_get_bidomain_stats(ep_sim *s, int64_t *last_iters, int64_t *total_iters,
+                                double *last_relres);
+
 /* Precompute geometry and flux coefficients (FP64, host), reorder the mesh,
  * upload to the device and set the standard initial state of every model.
  * After this the mesh, conductivity and models are frozen. */

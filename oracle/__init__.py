@@ -72,6 +72,15 @@ def lib():
         L.orc_get_purkinje_activation.argtypes = [C.c_void_p, _dp]
         L.orc_get_pmj_region.argtypes = [C.c_void_p, C.c_int, _ip, C.c_int64]
         L.orc_get_pmj_region.restype = C.c_int64
+        L.orc_set_bidomain.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.c_double,
+                                       C.c_int]
+        L.orc_get_phi_e.argtypes = [C.c_void_p, _dp]
+        L.orc_bidomain_iterations.argtypes = [C.c_void_p, C.POINTER(C.c_int64), _dp]
+        L.orc_bidomain_iterations.restype = C.c_int64
+        L.orc_apply_flux.argtypes = [C.c_void_p, _dp, C.c_double, C.c_double, _dp]
+        L.orc_gmres.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_double, C.c_int,
+                                C.c_double, C.c_int, _dp]
+        L.orc_gmres.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -168,6 +177,10 @@ class Sim:
         if w.ionic_scale:
             gs = np.array([w.ionic_scale.get(k, 1.0) for k in ("GKr", "GKs", "GCaL", "GNa")])
             L.orc_set_ionic_scale(self.h, _d(gs))
+        bd = getattr(w, "bidomain", None)
+        if bd is not None:
+            assert L.orc_set_bidomain(self.h, bd.sigma_el, bd.sigma_et, bd.restart, bd.tol,
+                                      bd.max_iter) == 0
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -215,6 +228,30 @@ class Sim:
         out = np.empty(self.nc, np.int32)
         n = lib().orc_get_pmj_region(self.h, k, out.ctypes.data_as(_ip), out.size)
         return out[:n].copy()
+
+    def phi_e(self):
+        out = np.empty(self.nc)
+        lib().orc_get_phi_e(self.h, _d(out))
+        return out
+
+    def bidomain_iterations(self):
+        """(Arnoldi steps of the last solve, total, last relative residual)"""
+        tot, rr = C.c_int64(), C.c_double()
+        last = lib().orc_bidomain_iterations(self.h, C.byref(tot), C.byref(rr))
+        return last, tot.value, rr.value
+
+    def apply_flux(self, x, sl, st):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.empty(self.nc)
+        lib().orc_apply_flux(self.h, _d(x), sl, st, _d(out))
+        return out
+
+    def gmres(self, b, x0, sl, st, restart=30, tol=1e-10, max_iter=10000):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.array(x0, dtype=np.float64)
+        rr = C.c_double()
+        it = lib().orc_gmres(self.h, _d(b), _d(x), sl, st, restart, tol, max_iter, C.byref(rr))
+        return x, it, rr.value
 
     def mean_vm(self) -> float:
         return lib().orc_mean_vm(self.h)

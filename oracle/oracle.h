@@ -95,6 +95,26 @@ void orc_get_purkinje_activation(const orc_sim *s, double *out);
 /* muscle region of junction k (at most cap ids); returns its size */
 int64_t orc_get_pmj_region(const orc_sim *s, int k, int32_t *out, int64_t cap);
 
+/* ----------------------------------------------------------- bidomain */
+/* Bidomain (Sec. 3.1 eq. electro, Sec. 3.2 eq. electro2_3d): the monodomain
+ * conductivities become the intracellular ones M_i, sigma_el / sigma_et the
+ * extracellular M_e (same fibres and scale).  Each step advances v with the
+ * intracellular flux of v + phi_e at level n, then solves
+ *   sum_f A_f ((M_i + M_e) grad phi).n = -sum_f A_f (M_i grad v^{n+1}).n
+ * for phi_e^{n+1} by restarted GMRES(restart) from phi_e^n, to a residual of
+ * tol ||rhs|| or max_iter Arnoldi steps, then shifts phi_e to zero
+ * volume-weighted mean.  phi_e^0 = 0. */
+int orc_set_bidomain(orc_sim *s, double sigma_el, double sigma_et, int restart, double tol,
+                     int max_iter);
+void orc_get_phi_e(const orc_sim *s, double *out);
+/* Arnoldi steps of the last solve (total over all solves, last residual) */
+int64_t orc_bidomain_iterations(const orc_sim *s, int64_t *total, double *relres);
+/* y = the flux sums sum_f A_f (M_f grad x_f).n_f for conductivities (sl, st) */
+void orc_apply_flux(const orc_sim *s, const double *x, double sl, double st, double *y);
+/* GMRES on that operator (x: start in, solution out); returns Arnoldi steps */
+int64_t orc_gmres(orc_sim *s, const double *b, double *x, double sl, double st, int restart,
+                  double tol, int max_iter, double *relres);
+
 /* ---------------------------------------- operator probes (for pinning) */
 /* Per tet: volume, 4 outward area vectors S_j (face opposite local node j),
  * 4 face neighbours (-1 = boundary face). */

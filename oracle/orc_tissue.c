@@ -79,6 +79,14 @@ struct orc_sim {
     /* junctions */
     int n_pmj;
     struct orc_pmj *pmj;
+    /* bidomain: extracellular conductivities, potential and its solver */
+    int bido;
+    double sel, set;
+    int restart, max_iter;
+    double tol;
+    double *phi;
+    int64_t last_iters, total_iters;
+    double last_relres;
 };
 
 struct orc_pmj {
@@ -251,14 +259,13 @@ static void build_geometry(orc_sim *s)
 }
 
 /* conductivity tensor of a cell: scale * (s_t I + (s_l - s_t) f f^T) */
-static void cell_tensor(const orc_sim *s, int64_t c, double M[3][3])
+static void cell_tensor_of(const orc_sim *s, int64_t c, double sl, double st, double M[3][3])
 {
     const double *f = s->fib + 3 * c;
     const double sc = s->scale ? s->scale[c] : 1.0;
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
-            M[a][b] = sc * ((a == b ? s->sigma_t : 0.0) +
-                            (s->sigma_l - s->sigma_t) * f[a] * f[b]);
+            M[a][b] = sc * ((a == b ? st : 0.0) + (sl - st) * f[a] * f[b]);
 }
 
 /* ------------------------------------------------------------ operator -- */
@@ -297,12 +304,13 @@ void orc_cell_gradients(const orc_sim *s, const double *v, double *g)
     free(vn);
 }
 
-/* the face-flux sum of one cell, divided by chi Cm V_c (mV/ms) */
-static double cell_flux_sum(const orc_sim *s, int64_t c, const double *v,
-                            const double *g)
+/* the face-flux sum sum_f A_f (M_f grad v_f).n_f of one cell for the tensor
+ * with conductivities (sl, st) (Sec. 3.2, eq. electro2_3d) */
+static double flux_sum(const orc_sim *s, int64_t c, const double *v, const double *g,
+                       double sl, double st)
 {
     double Mc[3][3];
-    cell_tensor(s, c, Mc);
+    cell_tensor_of(s, c, sl, st, Mc);
     const int32_t *t = s->tet + 4 * c;
     double total = 0.0;
     for (int j = 0; j < 4; ++j) {
@@ -329,7 +337,7 @@ static double cell_flux_sum(const orc_sim *s, int64_t c, const double *v,
         for (int a = 0; a < 3; ++a) gf[a] = gb[a] + corr * e[a];
         /* face tensor and flux */
         double M2[3][3];
-        cell_tensor(s, c2, M2);
+        cell_tensor_of(s, c2, sl, st, M2);
         const double *Sf = s->S + (c * 4 + j) * 3;
         double flux = 0.0;
         for (int a = 0; a < 3; ++a) {
@@ -340,7 +348,27 @@ static double cell_flux_sum(const orc_sim *s, int64_t c, const double *v,
         }
         total += flux;
     }
-    return total / (s->chi * s->cm * s->vol[c]);
+    return total;
+}
+
+/* monodomain: the flux sum with M, divided by chi Cm V_c (mV/ms) */
+static double cell_flux_sum(const orc_sim *s, int64_t c, const double *v,
+                            const double *g)
+{
+    return flux_sum(s, c, v, g, s->sigma_l, s->sigma_t) / (s->chi * s->cm * s->vol[c]);
+}
+
+/* y = the flux sums of field x for conductivities (sl, st) */
+static void apply_flux(const orc_sim *s, const double *x, double sl, double st, double *y)
+{
+    double *xn = malloc(sizeof(double) * (size_t)s->nn);
+    double *g = malloc(sizeof(double) * (size_t)s->nc * 3);
+    orc_node_values(s, x, xn);
+    gradients_from_nodes(s, xn, g);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < s->nc; ++c) y[c] = flux_sum(s, c, x, g, sl, st);
+    free(xn);
+    free(g);
 }
 
 void orc_apply_diffusion(const orc_sim *s, const double *v, double *L)
@@ -423,6 +451,7 @@ void orc_destroy(orc_sim *s)
     free(s->pstims);
     for (int k = 0; k < s->n_pmj; ++k) free(s->pmj[k].cells);
     free(s->pmj);
+    free(s->phi);
     free(s);
 }
 
@@ -668,6 +697,156 @@ int64_t orc_get_pmj_region(const orc_sim *s, int k, int32_t *out, int64_t cap)
     return J->n_cells;
 }
 
+/* ---------------------------------------------------------- bidomain -- */
+static double dot_n(const double *a, const double *b, int64_t n)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += a[i] * b[i];
+    return acc;
+}
+
+/* Restarted GMRES (Arnoldi with modified Gram-Schmidt, Givens rotations;
+ * Trefethen & Bau, lecture 35) for A x = b, A = the flux sums with the
+ * conductivities (sl, st), starting from x.  Stops when the residual norm is
+ * at most tol ||b|| or after max_iter Arnoldi steps; returns the steps. */
+static int64_t gmres(orc_sim *s, const double *b, double *x, double sl, double st,
+                     int m, double tol, int64_t max_iter, double *relres)
+{
+    const int64_t n = s->nc;
+    const double bnorm = sqrt(dot_n(b, b, n));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        *relres = 0.0;
+        return 0;
+    }
+    double *V = malloc(sizeof(double) * (size_t)n * (size_t)(m + 1));
+    double *H = calloc((size_t)(m + 1) * (size_t)m, sizeof(double));   /* H[i*m + j] */
+    double *cs = malloc(sizeof(double) * (size_t)m), *sn = malloc(sizeof(double) * (size_t)m);
+    double *g = malloc(sizeof(double) * (size_t)(m + 1)), *y = malloc(sizeof(double) * (size_t)m);
+    double *w = malloc(sizeof(double) * (size_t)n);
+    int64_t it = 0;
+    for (;;) {
+        apply_flux(s, x, sl, st, w);
+        for (int64_t i = 0; i < n; ++i) w[i] = b[i] - w[i];
+        const double beta = sqrt(dot_n(w, w, n));
+        *relres = beta / bnorm;
+        if (beta <= tol * bnorm || it >= max_iter) break;
+        for (int64_t i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && it < max_iter; ++j) {
+            double *vj = V + (size_t)j * (size_t)n;
+            apply_flux(s, vj, sl, st, w);
+            for (int i = 0; i <= j; ++i) {
+                const double *vi = V + (size_t)i * (size_t)n;
+                const double h = dot_n(w, vi, n);
+                H[i * m + j] = h;
+                for (int64_t q = 0; q < n; ++q) w[q] -= h * vi[q];
+            }
+            const double hn = sqrt(dot_n(w, w, n));
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {           /* earlier rotations */
+                const double a = H[i * m + j], c = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            const double den = hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = den > 0.0 ? H[j * m + j] / den : 1.0;
+            sn[j] = den > 0.0 ? H[(j + 1) * m + j] / den : 0.0;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            k = j + 1;
+            if (fabs(g[j + 1]) <= tol * bnorm || hn == 0.0) break;
+            double *vn1 = V + (size_t)(j + 1) * (size_t)n;
+            for (int64_t q = 0; q < n; ++q) vn1[q] = w[q] / hn;
+        }
+        for (int i = k - 1; i >= 0; --i) {          /* R y = g */
+            double acc = g[i];
+            for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * y[l];
+            y[i] = acc / H[i * m + i];
+        }
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (size_t)i * (size_t)n;
+            for (int64_t q = 0; q < n; ++q) x[q] += y[i] * vi[q];
+        }
+    }
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(w);
+    return it;
+}
+
+/* the extracellular potential of zero volume-weighted mean (the elliptic
+ * equation fixes it up to a constant) */
+static void zero_mean(const orc_sim *s, double *x)
+{
+    double num = 0.0, den = 0.0;
+    for (int64_t c = 0; c < s->nc; ++c) { num += s->vol[c] * x[c]; den += s->vol[c]; }
+    const double m = num / den;
+    for (int64_t c = 0; c < s->nc; ++c) x[c] -= m;
+}
+
+/* v^{n+1} known: solve sum_f A_f ((Mi+Me) grad phi).n = -sum_f A_f (Mi grad v).n
+ * for phi^{n+1}, starting from phi^n (Sec. 3.2) */
+static void bidomain_solve(orc_sim *s)
+{
+    const int64_t nc = s->nc;
+    double *v = malloc(sizeof(double) * (size_t)nc);
+    double *b = malloc(sizeof(double) * (size_t)nc);
+    for (int64_t c = 0; c < nc; ++c) v[c] = s->y[c * ORC_MAX_SLOTS];
+    apply_flux(s, v, s->sigma_l, s->sigma_t, b);
+    for (int64_t c = 0; c < nc; ++c) b[c] = -b[c];
+    s->last_iters = gmres(s, b, s->phi, s->sigma_l + s->sel, s->sigma_t + s->set, s->restart,
+                          s->tol, s->max_iter, &s->last_relres);
+    s->total_iters += s->last_iters;
+    zero_mean(s, s->phi);
+    free(v);
+    free(b);
+}
+
+int orc_set_bidomain(orc_sim *s, double sigma_el, double sigma_et, int restart, double tol,
+                     int max_iter)
+{
+    if (!(sigma_el >= 0) || !(sigma_et >= 0) || restart < 1 || !(tol > 0) || max_iter < 1)
+        return -1;
+    s->bido = 1;
+    s->sel = sigma_el;
+    s->set = sigma_et;
+    s->restart = restart;
+    s->tol = tol;
+    s->max_iter = max_iter;
+    free(s->phi);
+    s->phi = calloc((size_t)s->nc, sizeof(double));   /* exact for a uniform v^0 */
+    s->last_iters = s->total_iters = 0;
+    s->last_relres = 0.0;
+    return 0;
+}
+
+void orc_get_phi_e(const orc_sim *s, double *out)
+{
+    for (int64_t c = 0; c < s->nc; ++c) out[c] = s->phi ? s->phi[c] : 0.0;
+}
+
+int64_t orc_bidomain_iterations(const orc_sim *s, int64_t *total, double *relres)
+{
+    if (total) *total = s->total_iters;
+    if (relres) *relres = s->last_relres;
+    return s->last_iters;
+}
+
+void orc_apply_flux(const orc_sim *s, const double *x, double sl, double st, double *y)
+{
+    apply_flux(s, x, sl, st, y);
+}
+
+int64_t orc_gmres(orc_sim *s, const double *b, double *x, double sl, double st, int restart,
+                  double tol, int max_iter, double *relres)
+{
+    return gmres(s, b, x, sl, st, restart, tol, max_iter, relres);
+}
+
 /* ---------------------------------------------------------- time step -- */
 static void one_step(orc_sim *s)
 {
@@ -689,11 +868,22 @@ static void one_step(orc_sim *s)
             for (int64_t q = 0; q < J->n_cells; ++q) s->istim[J->cells[q]] += J->amp;
     }
 
-    /* diffusion at level n */
-    orc_node_values(s, v, s->vn);
-    gradients_from_nodes(s, s->vn, s->g);
+    /* diffusion at level n; bidomain: the intracellular flux of v + phi_e */
+    if (s->bido) {
+        double *u = malloc(sizeof(double) * (size_t)nc);
+        for (int64_t c = 0; c < nc; ++c) u[c] = v[c] + s->phi[c];
+        orc_node_values(s, u, s->vn);
+        gradients_from_nodes(s, s->vn, s->g);
 #pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < nc; ++c) s->L[c] = cell_flux_sum(s, c, v, s->g);
+        for (int64_t c = 0; c < nc; ++c)
+            s->L[c] = flux_sum(s, c, u, s->g, s->sigma_l, s->sigma_t) / (s->chi * s->cm * s->vol[c]);
+        free(u);
+    } else {
+        orc_node_values(s, v, s->vn);
+        gradients_from_nodes(s, s->vn, s->g);
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < nc; ++c) s->L[c] = cell_flux_sum(s, c, v, s->g);
+    }
 
     /* cells: ionic update, v update, detection */
 #pragma omp parallel for schedule(static)
@@ -720,6 +910,7 @@ static void one_step(orc_sim *s)
         }
     }
     if (s->np > 0) purkinje_step(s, v);
+    if (s->bido) bidomain_solve(s);
     free(v);
     s->step++;
 }

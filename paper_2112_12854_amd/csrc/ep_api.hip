@@ -19,7 +19,7 @@ using ep::model_ng;
 
 namespace {
 
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b34ULL;   // "EPSMCHK4"
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b35ULL;   // "EPSMCHK5"
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
@@ -266,6 +266,24 @@ ep_status ep_add_pmj(ep_sim *s, int32_t node, double radius, double delay_ortho,
     return EP_OK;
 }
 
+ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t restart,
+                          double tol, int32_t max_iter) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "the model is frozen after ep_init");
+    if (s->opt.prec != EP_FP64) return fail(s, EP_EINVAL, "the bidomain model runs in EP_FP64 only");
+    if (!(sigma_el >= 0) || !(sigma_et >= 0) || !std::isfinite(sigma_el) || !std::isfinite(sigma_et) ||
+        restart < 1 || restart > 1000 || !(tol > 0) || max_iter < 1)
+        return fail(s, EP_EINVAL, "bad bidomain parameters");
+    ep::InstSpec &sp = s->spec;
+    sp.bido = true;
+    sp.sigma_el = sigma_el;
+    sp.sigma_et = sigma_et;
+    sp.bido_restart = restart;
+    sp.bido_tol = tol;
+    sp.bido_max_iter = max_iter;
+    return EP_OK;
+}
+
 ep_status ep_init(ep_sim *s) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "already initialised");
@@ -313,7 +331,14 @@ ep_status ep_step(ep_sim *s, int64_t n) {
     if (n < 0) return fail(s, EP_EINVAL, "negative step count");
     if (n == 0) return EP_OK;
     HIP_TRY(s, hipSetDevice(s->opt.device));
-    return run_err(s, ep::stepper_run(s->stepper, n));
+    if (!s->inst.bido) return run_err(s, ep::stepper_run(s->stepper, n));
+    // bidomain: the elliptic solve follows every step
+    for (int64_t i = 0; i < n && s->inst.host_step < s->inst.target; ++i) {
+        std::string e = ep::stepper_run(s->stepper, 1);
+        if (e.empty()) e = ep::bidomain_solve(s->inst, s->stream);
+        if (!e.empty()) return fail(s, EP_EDEVICE, e);
+    }
+    return EP_OK;
 }
 
 ep_status ep_sync(ep_sim *s) {
@@ -453,6 +478,24 @@ ep_status ep_get_purkinje_activation(ep_sim *s, double *out, int64_t n) {
     return purkinje_readout(s, s->inst.pdesc.pt_act, 8, out, n);
 }
 
+ep_status ep_get_phi_e(ep_sim *s, double *out, int64_t n) {
+    if (!s) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    if (!s->inst.bido) return fail(s, EP_ESTATE, "not a bidomain simulation");
+    return readout(s, s->inst.bd.phi, 8, out, n);
+}
+
+ep_status ep_get_bidomain_stats(ep_sim *s, int64_t *last_iters, int64_t *total_iters,
+                                double *last_relres) {
+    if (!s) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    if (!s->inst.bido) return fail(s, EP_ESTATE, "not a bidomain simulation");
+    if (last_iters) *last_iters = s->inst.bd.last_iters;
+    if (total_iters) *total_iters = s->inst.bd.total_iters;
+    if (last_relres) *last_relres = s->inst.bd.last_relres;
+    return EP_OK;
+}
+
 ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub) {
     if (!s || !n_sub) return EP_EINVAL;
     if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
@@ -547,6 +590,7 @@ struct CkptHeader {
     int64_t n_tets, n_nodes, step;
     int32_t rs, n_pmj;
     int64_t trace_cap, n_purkinje;
+    int64_t bidomain;
 };
 
 static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
@@ -558,6 +602,7 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
         {D.t_rep, nc * 8},          {D.vmax, nc * r},        {(void *)D.vrest, nc * r},
         {D.trace, (size_t)s->inst.trace_cap * 8}, {D.part, (size_t)D.n_cell_tiles * 8},
         {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
+    if (s->inst.bido) a.push_back({s->inst.bd.phi, nc * 8});
     if (s->inst.pk.n > 0) {
         const epdev::PurkDesc &P = s->inst.pdesc;
         const size_t np = P.np;
@@ -588,7 +633,7 @@ ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes) {
     if (!buf || bytes < need) return fail(s, EP_EINVAL, "checkpoint buffer too small");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     CkptHeader h{CKPT_MAGIC, s->inst.desc.nc, s->inst.desc.nn, s->inst.host_step, s->inst.rs,
-                 (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n};
+                 (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n, s->inst.bido ? 1 : 0};
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
@@ -608,7 +653,7 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes) {
     std::memcpy(&h, buf, sizeof(h));
     if (h.magic != CKPT_MAGIC || h.n_tets != s->inst.desc.nc || h.n_nodes != s->inst.desc.nn ||
         h.rs != s->inst.rs || h.trace_cap != s->inst.trace_cap || h.n_purkinje != s->inst.pk.n ||
-        h.n_pmj != (int32_t)s->inst.n_pmj)
+        h.n_pmj != (int32_t)s->inst.n_pmj || h.bidomain != (s->inst.bido ? 1 : 0))
         return fail(s, EP_EINVAL, "checkpoint does not match this simulation");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const char *p = (const char *)buf + sizeof(h);

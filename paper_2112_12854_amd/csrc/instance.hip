@@ -102,6 +102,9 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     in.chi = sp.chi;
     in.cm = sp.cm;
     in.ordering = sp.ordering;
+    in.elliptic = sp.bido;
+    in.sigma_el = sp.sigma_el;
+    in.sigma_et = sp.sigma_et;
     std::string e = prepare(in, I.prep);
     if (!e.empty()) { st = EP_EINVAL; return e; }
     I.pk = PurkOut();
@@ -157,6 +160,11 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     b += 4 * round256(c * r) + round256(n * r);
     b += round256(c) + 2 * round256(c * 8);
     b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE + 3) * 8) + round256(sizeof(Ctrl));
+    if (sp.bido) {
+        const size_t m1 = (size_t)sp.bido_restart + 1;
+        b += round256(12 * c * 8) + 3 * round256(c * 8) + round256(n * 8) + round256(m1 * c * 8);
+        b += round256(m1 * kBidoBlocks * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8);
+    }
     return b + purkinje_bytes(I, rs);
 }
 
@@ -381,6 +389,32 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     }
     D.ctrl = I.d_ctrl;
     I.host_step = 0;
+    I.bido = sp.bido;
+    if (sp.bido) {
+        Bido &B = I.bd;
+        const size_t m1 = (size_t)sp.bido_restart + 1;
+        B.restart = sp.bido_restart;
+        B.max_iter = sp.bido_max_iter;
+        B.tol = sp.bido_tol;
+        B.chi_cm = sp.chi * sp.cm;
+        B.total_vol = tv;
+        B.last_iters = B.total_iters = 0;
+        B.last_relres = 0;
+        // phi_e^0 = 0: exact for a uniform initial potential
+        if (!up(I, (void **)&B.phi, std::vector<double>(nc, 0.0)) ||
+            !up(I, (void **)&B.ebeta, P.ebeta) || !up(I, (void **)&B.eb, P.eb))
+            return fail_mem();
+        B.b = (double *)dalloc(I, nc * 8);
+        B.w = (double *)dalloc(I, nc * 8);
+        B.xn = (double *)dalloc(I, nn * 8);
+        B.V = (double *)dalloc(I, m1 * nc * 8);
+        B.part = (double *)dalloc(I, m1 * kBidoBlocks * 8);
+        B.h = (double *)dalloc(I, (2 * m1 + 2) * 8);
+        B.y = (double *)dalloc(I, m1 * 8);
+        if (!B.b || !B.w || !B.xn || !B.V || !B.part || !B.h || !B.y) return fail_mem();
+        if (hipHostMalloc((void **)&B.h_host, (2 * m1 + 2) * 8) != hipSuccess) return fail_mem();
+        D.phi = B.phi;
+    }
     if (I.pk.n > 0) {
         std::string e = upload_purkinje(sp, rs, I, st);
         if (!e.empty()) return e;
@@ -401,6 +435,8 @@ void free_instance(Inst &I) {
         else (void)hipFree(a.first);
     }
     I.allocs.clear();
+    if (I.bd.h_host) (void)hipHostFree(I.bd.h_host);
+    I.bd = Bido();
     if (I.arena) {
         if (I.al.free) I.al.free(I.arena, I.al.ctx);
         else (void)hipFree(I.arena);
@@ -425,20 +461,37 @@ Tables tables(const Stepper &s) {
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
 // Cell kernels of step offset `off`, one launch per model class present.
-template <typename R>
-void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
+template <typename R, bool BIDO>
+void launch_cells_v(Stepper &s, const Tables &tb, int32_t off) {
     Tables t[4] = {tb, tb, tb, tb};
     for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + s.cls_base[k];
-    if (s.cls_tiles[0]) k_cell<R, 1><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
-    if (s.cls_tiles[1]) k_cell<R, 2><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
-    if (s.cls_tiles[2]) k_cell<R, 4><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
-    if (s.cls_tiles[3]) k_cell<R, 8><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
+    if (s.cls_tiles[0]) k_cell<R, 1, BIDO><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
+    if (s.cls_tiles[1]) k_cell<R, 2, BIDO><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
+    if (s.cls_tiles[2]) k_cell<R, 4, BIDO><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
+    if (s.cls_tiles[3]) k_cell<R, 8, BIDO><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
+}
+
+// bidomain instances run in FP64 only (checked at creation)
+template <typename R>
+void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
+    if constexpr (sizeof(R) == 8) {
+        if (s.bido) { launch_cells_v<R, true>(s, tb, off); return; }
+    }
+    launch_cells_v<R, false>(s, tb, off);
+}
+
+template <typename R>
+void launch_gather(Stepper &s, const Tables &tb, int32_t off) {
+    if constexpr (sizeof(R) == 8) {
+        if (s.bido) { k_node_gather<R, true><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap); return; }
+    }
+    k_node_gather<R, false><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap);
 }
 
 template <typename R>
 void launch_step(Stepper &s, int32_t off) {
     const Tables tb = tables(s);
-    k_node_gather<R><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap);
+    launch_gather<R>(s, tb, off);
     launch_cells<R>(s, tb, off);
 }
 
@@ -503,6 +556,8 @@ std::string stepper_sync_tables(Stepper &s) {
     std::vector<PTile> pt;
     std::vector<PurkDesc> pk;
     int32_t nsub = 0;
+    s.bido = false;
+    for (const Inst *I : s.insts) s.bido = s.bido || I->bido;
     // cell tiles class by class; tile `local` numbers run over the instance
     std::vector<int32_t> next_local(s.insts.size(), 0);
     for (int k = 0; k < 4; ++k) {
@@ -698,8 +753,8 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
     const Tables tb = tables(s);
     for (int64_t i = 0; i < n; ++i) {
         (void)hipEventRecord(ev[0], s.stream);
-        if (s.rs == 8) k_node_gather<double><<<gn, TILE, 0, s.stream>>>(tb, 0, s.remap);
-        else k_node_gather<float><<<gn, TILE, 0, s.stream>>>(tb, 0, s.remap);
+        if (s.rs == 8) launch_gather<double>(s, tb, 0);
+        else launch_gather<float>(s, tb, 0);
         (void)hipEventRecord(ev[1], s.stream);
         if (s.rs == 8) launch_cells<double>(s, tb, 0);
         else launch_cells<float>(s, tb, 0);

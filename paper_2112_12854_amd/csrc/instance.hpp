@@ -46,6 +46,28 @@ struct InstSpec {
     int32_t trace_every = 50;
     int64_t target = INT64_MAX;        // stop stepping at this step index
     PurkSpec purk;                     // n == 0: no graph
+    // bidomain (sigma_l / sigma_t become the intracellular conductivities)
+    bool bido = false;
+    double sigma_el = 0.62, sigma_et = 0.24, bido_tol = 1e-6;
+    int32_t bido_restart = 30, bido_max_iter = 2000;
+};
+
+// Device arrays of the extracellular solve of one bidomain instance.
+struct Bido {
+    double *phi = nullptr;             // [nc] phi_e, zero volume-weighted mean
+    const double *ebeta = nullptr;     // [8][nc] elliptic stencil (flux-sum form)
+    const double *eb = nullptr;        // [4][nc]
+    double *xn = nullptr;              // [nn] node values of the operand
+    double *b = nullptr, *w = nullptr; // [nc] right-hand side, work vector
+    double *V = nullptr;               // [(restart+1)][nc] Krylov basis
+    double *part = nullptr;            // [(restart+1)][blocks] reduction partials
+    double *h = nullptr;               // [2 restart + 4] reduced dot products
+    double *y = nullptr;               // [restart] update coefficients
+    int32_t restart = 30, max_iter = 2000;
+    double tol = 1e-6, total_vol = 0, chi_cm = 1.4;
+    int64_t last_iters = 0, total_iters = 0;
+    double last_relres = 0;
+    double *h_host = nullptr;          // pinned readback of h
 };
 
 struct Allocator {
@@ -83,6 +105,8 @@ struct Inst {
     int pmodel = 4;
     int64_t n_pmj = 0;
     epdev::PurkDesc pdesc{};
+    bool bido = false;
+    Bido bd;
 };
 
 // Host precompute only (thread-safe, no HIP calls).
@@ -121,6 +145,7 @@ struct Stepper {
     size_t cap_inst = 0, cap_ct = 0, cap_nt = 0, cap_pt = 0, cap_pk = 0;
     int64_t n_ct = 0, n_nt = 0, n_pt = 0, n_pk = 0;
     int32_t n_sub_max = 0;             // graph substeps per step (max over instances)
+    bool bido = false;                 // the (single) instance is a bidomain one
     // pinned staging of the tables
     void *h_stage = nullptr;
     size_t stage_bytes = 0;
@@ -156,6 +181,12 @@ struct TuneResult {
 };
 std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
                              bool allow_direct = true);
+
+// Bidomain: solve the extracellular equation for the instance's current
+// v^{n} (after a step), from its phi_e (instance must be synchronised with
+// nothing pending that writes v); enqueued on `stream`, synchronises it.
+std::string bidomain_solve(Inst &I, hipStream_t stream);
+constexpr int kBidoBlocks = 1024;      // blocks of the reduction kernels
 
 int model_ng(int m);
 int model_nc(int m);

@@ -79,6 +79,9 @@ struct InstDesc {
     int64_t trace_cap;
     int32_t trace_every;
     int32_t n_cell_tiles;
+    // bidomain: the extracellular potential phi_e^n (FP64; null otherwise);
+    // the flux of the time step is then that of v + phi_e
+    const double *phi;
     // junction stimuli of the muscle (null without a Purkinje graph)
     const int32_t *cpmj;          // [nc]: -1 or start of a -1-terminated list
     const int32_t *cpmj_list;
@@ -198,7 +201,8 @@ __device__ __forceinline__ uint32_t active_stimuli(const Ctrl *ctrl, int64_t n) 
 }
 
 // ------------------------------------------------------------ node gather
-template <typename R>
+// BIDO: node values of v + phi_e (bidomain time step, FP64).
+template <typename R, bool BIDO = false>
 __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_off, int remap) {
     const Tile &T = tb.node_tiles[my_tile(remap)];
     const InstDesc &D = T.d;
@@ -217,15 +221,28 @@ __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_of
     // four independent gathers in flight per lane; fixed summation order
     R a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
     int64_t e = e0;
-    for (; e + 192 < e1; e += 256) {
-        const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
-        const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
-        a0 += x0 * v[c0];
-        a1 += x1 * v[c1];
-        a2 += x2 * v[c2];
-        a3 += x3 * v[c3];
+    if constexpr (BIDO) {
+        const double *__restrict__ ph = D.phi;
+        for (; e + 192 < e1; e += 256) {
+            const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
+            const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
+            a0 += x0 * (v[c0] + R(ph[c0]));
+            a1 += x1 * (v[c1] + R(ph[c1]));
+            a2 += x2 * (v[c2] + R(ph[c2]));
+            a3 += x3 * (v[c3] + R(ph[c3]));
+        }
+        for (; e < e1; e += 64) a0 += w8[e] * (v[cell[e]] + R(ph[cell[e]]));
+    } else {
+        for (; e + 192 < e1; e += 256) {
+            const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
+            const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
+            a0 += x0 * v[c0];
+            a1 += x1 * v[c1];
+            a2 += x2 * v[c2];
+            a3 += x3 * v[c3];
+        }
+        for (; e < e1; e += 64) a0 += w8[e] * v[cell[e]];
     }
-    for (; e < e1; e += 64) a0 += w8[e] * v[cell[e]];
     ((R *)D.vn)[node] = (a0 + a1) + (a2 + a3);
 }
 
@@ -338,7 +355,7 @@ __device__ __forceinline__ R ionic(int md, R v, __amdgpu_buffer_rsrc_t rgate,
     return iion;
 }
 
-template <typename R, int MSET>
+template <typename R, int MSET, bool BIDO>
 __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
                                           uint32_t active, bool sample, double &vol_v) {
     const int64_t N = D.nc;
@@ -354,9 +371,19 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 #pragma unroll
     for (int s = 0; s < 8; ++s)
         L += sld<R>(rbeta, s, N, c) * at(vn, (uint32_t)sld<int32_t>(rnode, s, N, c));
+    if constexpr (BIDO) {
+        // the flux of u = v + phi_e (node values above are those of u)
+        const R uc = v + R(at(D.phi, c));
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-        L += sld<R>(rb, f, N, c) * (at(vin, (uint32_t)sld<int32_t>(rnbr, f, N, c)) - v);
+        for (int f = 0; f < 4; ++f) {
+            const uint32_t k = (uint32_t)sld<int32_t>(rnbr, f, N, c);
+            L += sld<R>(rb, f, N, c) * ((at(vin, k) + R(at(D.phi, k))) - uc);
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            L += sld<R>(rb, f, N, c) * (at(vin, (uint32_t)sld<int32_t>(rnbr, f, N, c)) - v);
+    }
 
     // ---- stimulus: protocol pulses, then junction pulses (junction order)
     R istim = R(0);
@@ -413,7 +440,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 
 // One launch per model class: the host passes tb.cell_tiles pointing at the
 // first tile of the class in the class-ordered tile list.
-template <typename R, int MSET>
+template <typename R, int MSET, bool BIDO = false>
 __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
     __shared__ double red[TILE];
     const Tile &T = tb.cell_tiles[my_tile(remap)];
@@ -424,7 +451,7 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
     double x = 0.0;
     const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
     if ((int32_t)threadIdx.x < T.count)
-        cell_step<R, MSET>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
+        cell_step<R, MSET, BIDO>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
     if (sample) tile_partial(D, T, x, red);
 }
 

@@ -367,15 +367,28 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
     out.cb.assign(4 * nc, 0.0);
     out.vol.assign(nc, 0.0);
     out.model.assign(nc, 0);
-    const double sl = in.sigma_l, st = in.sigma_t;
-    auto tensor = [&](int64_t c, double M[3][3]) {
-        const double *f = in.fibre + 3 * c;
-        const double s = in.scale ? in.scale[c] : 1.0;
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) M[a][b] = s * ((a == b ? st : 0.0) + (sl - st) * f[a] * f[b]);
-    };
+    if (in.elliptic) {
+        out.ebeta.assign(8 * nc, 0.0);
+        out.eb.assign(4 * nc, 0.0);
+    }
+    // the stencil for the tensor of conductivities (sl, st); into L form
+    // (divided by chi Cm V_c) for the time step, or flux-sum form
+    struct Set { double sl, st; std::vector<double> *beta, *b; bool lform; };
+    std::vector<Set> sets = {{in.sigma_l, in.sigma_t, &out.cbeta, &out.cb, true}};
+    if (in.elliptic)
+        sets.push_back({in.sigma_l + in.sigma_el, in.sigma_t + in.sigma_et, &out.ebeta, &out.eb, false});
     std::vector<double> rowsum(nc, 0.0);
+    for (const Set &set : sets)
     parallel_for(nc, [&](int64_t a, int64_t b) {
+        const double sl = set.sl, st = set.st;
+        auto tensor = [&](int64_t c, double M[3][3]) {
+            const double *f = in.fibre + 3 * c;
+            const double s = in.scale ? in.scale[c] : 1.0;
+            for (int a2 = 0; a2 < 3; ++a2)
+                for (int b2 = 0; b2 < 3; ++b2)
+                    M[a2][b2] = s * ((a2 == b2 ? st : 0.0) + (sl - st) * f[a2] * f[b2]);
+        };
+        std::vector<double> &obeta = *set.beta, &ob = *set.b;
         for (int64_t i = a; i < b; ++i) {
             const int64_t c = order[i];
             const int32_t *t = in.tets + 4 * c;
@@ -390,7 +403,7 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
                 const int64_t slot = (int64_t)f * nc + i;
                 if (c2 < 0) {                      // no-flux boundary face
                     out.cnbr[slot] = (int32_t)i;
-                    out.cb[slot] = 0.0;
+                    ob[slot] = 0.0;
                     continue;
                 }
                 const int32_t *t2 = in.tets + 4 * (int64_t)c2;
@@ -422,18 +435,22 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
                     else { beta[4 + f] = coef; nodes[4 + f] = nperm[t2[k2]]; }
                 }
                 out.cnbr[slot] = out.iperm[c2];
-                out.cb[slot] = we / d;
+                ob[slot] = we / d;
+            }
+            if (!set.lform) {
+                for (int s = 0; s < 8; ++s) obeta[(int64_t)s * nc + i] = beta[s];
+                continue;
             }
             const double inv = 1.0 / (in.chi * in.cm * g.vol[c]);
             double rs = 0.0;
             for (int s = 0; s < 8; ++s) {
                 out.cnode[(int64_t)s * nc + i] = nodes[s];
-                out.cbeta[(int64_t)s * nc + i] = beta[s] * inv;
+                obeta[(int64_t)s * nc + i] = beta[s] * inv;
                 rs += std::fabs(beta[s] * inv);
             }
             for (int f = 0; f < 4; ++f) {
-                out.cb[(int64_t)f * nc + i] *= inv;
-                rs += 2.0 * std::fabs(out.cb[(int64_t)f * nc + i]);
+                ob[(int64_t)f * nc + i] *= inv;
+                rs += 2.0 * std::fabs(ob[(int64_t)f * nc + i]);
             }
             rowsum[i] = rs;
             out.vol[i] = g.vol[c];

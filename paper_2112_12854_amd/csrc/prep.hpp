@@ -18,6 +18,10 @@ struct PrepIn {
     const uint8_t *model = nullptr;    // [n_tets]
     double sigma_l = 0.17, sigma_t = 0.019, chi = 140.0, cm = 0.01;
     int ordering = ORDER_RCM;
+    // bidomain: also the flux sums of the elliptic operator with the tensor
+    // of conductivities (sigma_l + sigma_el, sigma_t + sigma_et)
+    bool elliptic = false;
+    double sigma_el = 0.0, sigma_et = 0.0;
 };
 
 // Node gather in sliced ELL with slices of 64 nodes (one wavefront): slice
@@ -37,6 +41,11 @@ struct PrepOut {
     std::vector<double> cbeta;        // [8][n]
     std::vector<int32_t> cnbr;        // [4][n]: face neighbour or self on the boundary
     std::vector<double> cb;           // [4][n]
+    // elliptic operator (bidomain), same nodes and neighbours, flux-sum form
+    // (not divided by chi Cm V_c):  y_c = sum_s ebeta[s] x_n[node_s] +
+    // sum_f eb[f] (x[nbr_f] - x_c)
+    std::vector<double> ebeta;        // [8][n]
+    std::vector<double> eb;           // [4][n]
     std::vector<double> vol;          // [n] tet volume (internal order)
     std::vector<uint8_t> model;       // [n] internal order
     int64_t n_interior_faces = 0, n_boundary_faces = 0;

@@ -94,6 +94,11 @@ _SIGS = {
     "ep_get_purkinje_vm": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
     "ep_get_purkinje_activation": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
     "ep_get_purkinje_substeps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "ep_set_bidomain": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_int32, C.c_double,
+                                  C.c_int32]),
+    "ep_get_phi_e": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    "ep_get_bidomain_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                        _dp]),
     "ep_init": (C.c_int, [C.c_void_p]),
     "ep_footprint": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "ep_step": (C.c_int, [C.c_void_p, C.c_int64]),
@@ -240,6 +245,11 @@ class Sim:
             ids = np.ascontiguousarray(st.ids, np.int32)
             _check(L.ep_add_stimulus(h, st.domain, ids.size, ids.ctypes.data_as(_ip),
                                      st.t0, st.dur, st.amp, st.period, st.count), h)
+        bd = getattr(w, "bidomain", None)
+        self.bidomain = bd is not None
+        if bd is not None:
+            _check(L.ep_set_bidomain(h, bd.sigma_el, bd.sigma_et, bd.restart, bd.tol,
+                                     bd.max_iter), h)
         if launch is not None:
             self.set_launch(*launch)
         _check(L.ep_init(h), h)
@@ -291,6 +301,15 @@ class Sim:
 
     def purkinje_activation(self):
         return self._pvec(lib().ep_get_purkinje_activation)
+
+    def phi_e(self):
+        return self._vec(lib().ep_get_phi_e)
+
+    def bidomain_stats(self):
+        """(Arnoldi steps of the last solve, total, last relative residual)"""
+        a, b, r = C.c_int64(), C.c_int64(), C.c_double()
+        _check(lib().ep_get_bidomain_stats(self.h, C.byref(a), C.byref(b), C.byref(r)), self.h)
+        return a.value, b.value, r.value
 
     def purkinje_n_sub(self) -> int:
         n = C.c_int32()

@@ -68,6 +68,7 @@ class Workload:
     hex_ijk: np.ndarray | None = None  # [n_tets, 3] hex index of each tet
     dims: tuple = ()                   # (nx, ny, nz, h)
     purkinje: object = None            # Purkinje graph (heart workloads)
+    bidomain: object = None            # Bidomain parameters, or monodomain
 
     @property
     def n_tets(self) -> int:
@@ -76,6 +77,18 @@ class Workload:
     @property
     def n_nodes(self) -> int:
         return int(self.xyz.shape[0])
+
+
+@dataclass
+class Bidomain:
+    """Bidomain: the workload's sigma_l / sigma_t are the intracellular
+    conductivities, these the extracellular ones (Sec. 5 table, from the
+    benchmark of Niederer et al.), with the elliptic solver's settings."""
+    sigma_el: float = 0.62         # mS/mm along the fibre
+    sigma_et: float = 0.24         # mS/mm across
+    restart: int = 30
+    tol: float = 1e-8              # relative residual of the elliptic solve
+    max_iter: int = 2000           # Arnoldi steps per time step at most
 
 
 def slab(nx: int, ny: int, nz: int, h: float):
