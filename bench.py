@@ -280,6 +280,45 @@ def fp32_accuracy(ep, meshgen, n_uq=16, uq_steps=25000):
     return out
 
 
+def run_bidomain(ep, meshgen, args):
+    """The paper's benchmark box (20 x 7 x 3 mm, fibres along x, TP06, 1.5 mm
+    corner stimulus) at dx = 0.5, 0.2, 0.1 mm: wall time of one bidomain step
+    (FP64, GMRES(30) to a relative residual of 1e-6 from the previous
+    extracellular potential) and of one monodomain step, during the
+    upstroke, on the library stream."""
+    import torch
+    out = []
+    for h in (0.5, 0.2, 0.1):
+        w = meshgen.niederer_box(h=h, dt=0.005, n_steps=args.steps)
+        w.bidomain = meshgen.Bidomain(tol=1e-6, restart=30)
+        b = ep.Sim(w, prec=ep.EP_FP64)
+        b.step(args.warmup)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(args.steps)
+        b.sync()
+        tb = (time.perf_counter() - t0) / args.steps
+        last, total, rr = b.bidomain_stats()
+        b.close()
+        w.bidomain = None
+        m = ep.Sim(w, prec=ep.EP_FP64)
+        m.step(args.warmup)
+        m.sync()
+        t0 = time.perf_counter()
+        m.step(args.steps)
+        m.sync()
+        tm = (time.perf_counter() - t0) / args.steps
+        m.close()
+        r = {"dx_mm": h, "tets": w.n_tets, "bidomain_s_per_step": tb, "monodomain_s_per_step": tm,
+             "gmres_steps_per_time_step": total / (args.warmup + args.steps)}
+        log(f"box dx={h}: {w.n_tets} tets, bidomain {tb * 1e3:.2f} ms/step "
+            f"({r['gmres_steps_per_time_step']:.0f} GMRES steps), monodomain {tm * 1e3:.3f} ms/step")
+        out.append(r)
+    print(json.dumps({"metric": "wall time per time step (s), bidomain vs monodomain, FP64",
+                      "workload": "box-20x7x3mm, dt 0.005 ms, GMRES(30) rtol 1e-6",
+                      "steps": args.steps, "warmup": args.warmup, "grids": out}), flush=True)
+
+
 def run_heart(ep, meshgen, args):
     """Three coupled media: the synthetic biventricle + atrial cap + Purkinje
     tree (~11.6M tets, 60k graph nodes, dt 0.01 ms), FP32-mixed and FP64."""
@@ -342,6 +381,8 @@ def main():
                          "batch is 1024x25000)")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 error distributions")
+    ap.add_argument("--bidomain", action="store_true",
+                    help="bidomain vs monodomain step time on the paper's benchmark box")
     ap.add_argument("--heart", action="store_true",
                     help="the three-media heart instead of the slab (timed steps only)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -369,6 +410,8 @@ def main():
     torch.cuda.init()
     if args.heart:
         return run_heart(ep, meshgen, args)
+    if args.bidomain:
+        return run_bidomain(ep, meshgen, args)
     t0 = time.time()
     w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
     log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")

@@ -11,6 +11,10 @@
 // solve gives the same bits on every run.  Only the (restart + 1) x restart
 // Hessenberg least-squares problem (Givens rotations, back substitution) is
 // advanced on the host, from a few numbers read back per Arnoldi step.
+// GMRES is preconditioned on the right by a two-level additive method (the
+// residual it monitors stays the true one): Jacobi plus a dense solve on
+// aggregates of cells, which removes the growth of the iteration count with
+// the grid size that the plain method shows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -153,6 +157,70 @@ __global__ void __launch_bounds__(BT) k_shift(double *__restrict__ x, const doub
     if (e < n) x[e] -= s[0] * inv_total;
 }
 
+// ---- two-level preconditioner z = omega D^{-1} r + P A_c^{-1} P^T r
+// rc[I] = sum of r over aggregate I (one block per aggregate, fixed order)
+__global__ void __launch_bounds__(BT) k_restrict(const double *__restrict__ r,
+                                                 const int32_t *__restrict__ off,
+                                                 const int32_t *__restrict__ cells,
+                                                 double *__restrict__ rc) {
+    __shared__ double red[BT];
+    double acc = 0.0;
+    for (int32_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += BT) acc += r[cells[i]];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rc[blockIdx.x] = red[0];
+}
+
+// zc = A_c^{-1} rc (dense, row-major; one block per row)
+__global__ void __launch_bounds__(BT) k_coarse(const double *__restrict__ cinv,
+                                               const double *__restrict__ rc,
+                                               double *__restrict__ zc, int32_t na) {
+    __shared__ double red[BT];
+    const double *row = cinv + (int64_t)blockIdx.x * na;
+    double acc = 0.0;
+    for (int32_t j = threadIdx.x; j < na; j += BT) acc += row[j] * rc[j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) zc[blockIdx.x] = red[0];
+}
+
+// z = omega D^{-1} r + zc[aggregate]
+__global__ void __launch_bounds__(BT) k_smooth(const double *__restrict__ r,
+                                               const double *__restrict__ dinv,
+                                               const int32_t *__restrict__ agg_of,
+                                               const double *__restrict__ zc, double omega,
+                                               double *__restrict__ z, int64_t n) {
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    if (e < n) z[e] = omega * dinv[e] * r[e] + zc[agg_of[e]];
+}
+
+// t = sum_{q < cnt} y_q V_q
+__global__ void __launch_bounds__(BT) k_combine(double *__restrict__ t, const double *__restrict__ V,
+                                                const double *__restrict__ y, int cnt, int64_t n) {
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    if (e >= n) return;
+    double acc = 0.0;
+    for (int q = 0; q < cnt; ++q) acc += y[q] * V[q * n + e];
+    t[e] = acc;
+}
+
+// x += z
+__global__ void __launch_bounds__(BT) k_add(double *__restrict__ x, const double *__restrict__ z,
+                                            int64_t n) {
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    if (e < n) x[e] += z[e];
+}
+
+constexpr double kOmega = 0.7;   // Jacobi weight of the preconditioner
+
 struct Solver {
     Inst &I;
     hipStream_t st;
@@ -172,6 +240,13 @@ struct Solver {
         const InstDesc &D = I.desc;
         k_gather<<<grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, x, I.bd.xn, nn);
         k_flux<<<grid_c, BT, 0, st>>>(D.cnode, I.bd.ebeta, D.cnbr, I.bd.eb, x, I.bd.xn, nullptr, 1.0, y, nc);
+    }
+    // z = M^{-1} r
+    void prec(const double *r, double *z) {
+        const Bido &B = I.bd;
+        k_restrict<<<B.n_agg, BT, 0, st>>>(r, B.agg_off, B.agg_cells, B.rc);
+        k_coarse<<<B.n_agg, BT, 0, st>>>(B.cinv, B.rc, B.zc, B.n_agg);
+        k_smooth<<<grid_c, BT, 0, st>>>(r, B.dinv, B.agg_of, B.zc, kOmega, z, nc);
     }
     hipError_t read(const double *dev, int cnt) {
         hipError_t e = hipMemcpyAsync(I.bd.h_host, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -221,7 +296,12 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
             int k = 0;
             for (int j = 0; j < m && it < B.max_iter; ++j) {
                 const double *vj = B.V + (int64_t)j * nc;
-                S.apply(vj, B.w);
+                if (B.precond) {                     // right preconditioning: A M^{-1} v_j
+                    S.prec(vj, B.z);
+                    S.apply(B.z, B.w);
+                } else {
+                    S.apply(vj, B.w);
+                }
                 // classical Gram-Schmidt, twice
                 S.dots(B.w, B.V, j + 1, hd);
                 k_sub<<<S.grid_c, BT, 0, st>>>(B.w, B.V, hd, j + 1, nc);
@@ -259,7 +339,13 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
             }
             if ((e = hipMemcpyAsync(B.y, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess)
                 return fail("bidomain upload");
-            k_update<<<S.grid_c, BT, 0, st>>>(B.phi, B.V, B.y, k, nc);
+            if (B.precond) {                         // x += M^{-1} V y
+                k_combine<<<S.grid_c, BT, 0, st>>>(B.t, B.V, B.y, k, nc);
+                S.prec(B.t, B.z);
+                k_add<<<S.grid_c, BT, 0, st>>>(B.phi, B.z, nc);
+            } else {
+                k_update<<<S.grid_c, BT, 0, st>>>(B.phi, B.V, B.y, k, nc);
+            }
             // y is pageable host memory: wait before it is rewritten
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail("bidomain update");
         }

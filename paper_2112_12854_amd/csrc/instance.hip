@@ -107,6 +107,11 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     in.sigma_et = sp.sigma_et;
     std::string e = prepare(in, I.prep);
     if (!e.empty()) { st = EP_EINVAL; return e; }
+    I.coarse = Coarse();
+    if (sp.bido && sp.bido_coarse > 0) {
+        e = build_coarse(in, I.prep, sp.bido_coarse, I.coarse);
+        if (!e.empty()) { st = EP_EINVAL; return e; }
+    }
     I.pk = PurkOut();
     I.n_pmj = 0;
     if (sp.purk.n > 0) {
@@ -164,6 +169,10 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
         const size_t m1 = (size_t)sp.bido_restart + 1;
         b += round256(12 * c * 8) + 3 * round256(c * 8) + round256(n * 8) + round256(m1 * c * 8);
         b += round256(m1 * kBidoBlocks * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8);
+        const size_t na = (size_t)I.coarse.n_agg;
+        if (na > 0)
+            b += 2 * round256(c * 4) + round256((na + 1) * 4) + round256(c * 8) +
+                 round256(na * na * 8) + 2 * round256(c * 8) + 2 * round256(na * 8);
     }
     return b + purkinje_bytes(I, rs);
 }
@@ -414,6 +423,21 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         if (!B.b || !B.w || !B.xn || !B.V || !B.part || !B.h || !B.y) return fail_mem();
         if (hipHostMalloc((void **)&B.h_host, (2 * m1 + 2) * 8) != hipSuccess) return fail_mem();
         D.phi = B.phi;
+        const Coarse &Cs = I.coarse;
+        B.n_agg = Cs.n_agg;
+        B.precond = Cs.n_agg > 0;
+        if (B.precond) {
+            if (!up(I, (void **)&B.agg_of, Cs.agg_of) || !up(I, (void **)&B.agg_cells, Cs.agg_cells) ||
+                !up(I, (void **)&B.agg_off, Cs.agg_off) || !up(I, (void **)&B.dinv, Cs.dinv) ||
+                !up(I, (void **)&B.cinv, Cs.cinv))
+                return fail_mem();
+            B.z = (double *)dalloc(I, nc * 8);
+            B.t = (double *)dalloc(I, nc * 8);
+            B.rc = (double *)dalloc(I, (size_t)Cs.n_agg * 8);
+            B.zc = (double *)dalloc(I, (size_t)Cs.n_agg * 8);
+            if (!B.z || !B.t || !B.rc || !B.zc) return fail_mem();
+        }
+        I.coarse = Coarse();               // the host copy is no longer needed
     }
     if (I.pk.n > 0) {
         std::string e = upload_purkinje(sp, rs, I, st);

@@ -50,6 +50,7 @@ struct InstSpec {
     bool bido = false;
     double sigma_el = 0.62, sigma_et = 0.24, bido_tol = 1e-6;
     int32_t bido_restart = 30, bido_max_iter = 2000;
+    int32_t bido_coarse = 2048;        // aggregates of the preconditioner (0: none)
 };
 
 // Device arrays of the extracellular solve of one bidomain instance.
@@ -68,6 +69,13 @@ struct Bido {
     int64_t last_iters = 0, total_iters = 0;
     double last_relres = 0;
     double *h_host = nullptr;          // pinned readback of h
+    // two-level preconditioner
+    int32_t n_agg = 0;
+    const int32_t *agg_of = nullptr, *agg_off = nullptr, *agg_cells = nullptr;
+    const double *dinv = nullptr, *cinv = nullptr;
+    double *z = nullptr, *t = nullptr; // [nc] preconditioned vector, update
+    double *rc = nullptr, *zc = nullptr;   // [n_agg] coarse residual, correction
+    bool precond = true;
 };
 
 struct Allocator {
@@ -107,6 +115,7 @@ struct Inst {
     epdev::PurkDesc pdesc{};
     bool bido = false;
     Bido bd;
+    Coarse coarse;                     // host copy until upload
 };
 
 // Host precompute only (thread-safe, no HIP calls).

@@ -90,4 +90,15 @@ struct PurkOut {
 std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut &tout,
                              PurkOut &out);
 
+// Two-level preconditioner of the elliptic (bidomain) operator: aggregates
+// of cells (internal numbering, CSR agg_off / agg_cells, agg_of per cell),
+// the inverse diagonal, and the dense inverse of the aggregated operator
+// (row-major n_agg x n_agg).
+struct Coarse {
+    int32_t n_agg = 0;
+    std::vector<int32_t> agg_of, agg_off, agg_cells;
+    std::vector<double> dinv, cinv;
+};
+std::string build_coarse(const PrepIn &in, const PrepOut &P, int target, Coarse &out);
+
 }  // namespace ep
