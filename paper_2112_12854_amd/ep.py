@@ -147,6 +147,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "paper_2112_12854_amd/build.py (or __graft_entry__.build())")
+        # One HIP runtime per process: PyTorch ships its own, so load it
+        # first (when installed); the library then binds to that runtime and
+        # PyTorch's streams and caching allocator can be handed to it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
