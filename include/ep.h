@@ -142,6 +142,18 @@ ep_status ep_set_purkinje(ep_sim *s, int64_t n, const double *xyz, int64_t n_edg
                           const int32_t *edges, double sigma, int32_t model,
                           int32_t n_sub);
 
+/* Conductivity multiplier s_e >= 0 per graph segment (n_edges == the count
+ * given to ep_set_purkinje, same order; caller-owned, copied): segment e
+ * conducts with sigma * s_e, so the flux term above reads
+ * sum_j s_ij (v_j - v_i) / L_ij while l_i is unchanged.  The paper models a
+ * bundle-branch delay by lowering the bundles' conductivity in proportion to
+ * its severity and a complete block by a null conductivity (Sec. 6); the
+ * substep bound then uses sigma sum_j s_ij / L_ij (nodes whose segments are
+ * all blocked impose none).  ep_set_purkinje resets every s_e to 1.
+ * EP_EINVAL for a count mismatch or a negative or non-finite value.  Call
+ * before ep_init. */
+ep_status ep_set_purkinje_scale(ep_sim *s, int64_t n_edges, const double *scale);
+
 /* Purkinje-muscle junction at graph node `node` (Sec. 3.3): when the node's
  * potential crosses at_threshold upward during tissue step n, the tissue
  * cells whose centroid lies within `radius` of the node (if none: the cells
@@ -270,12 +282,36 @@ const char *ep_last_error(const ep_sim *s);
  * All server calls are thread-safe. */
 
 typedef struct {
-    int64_t n_ids;        /* tets of the stimulus region (caller numbering) */
+    int64_t n_ids;        /* tets (domain 0) or graph nodes (domain 1) of the
+                             stimulus region, caller numbering              */
     const int32_t *ids;
     double t0, dur, amp;  /* ms, ms, pA/pF                                   */
     double period;        /* 0 = single pulse                               */
     int32_t count;
+    int32_t domain;       /* 0 tissue, 1 Purkinje graph (as ep_add_stimulus) */
 } ep_stimulus;
+
+/* A Purkinje-muscle junction of a request (as ep_add_pmj). */
+typedef struct {
+    int32_t node;
+    int32_t two_way;
+    double radius, delay_ortho, delay_anti, amp, dur;
+} ep_pmj;
+
+/* The Purkinje graph of a request (as ep_set_purkinje, ep_set_purkinje_scale
+ * and ep_add_pmj; every array caller-owned and copied at submission). */
+typedef struct {
+    int64_t n;
+    const double *xyz;            /* [3*n]                                   */
+    int64_t n_edges;
+    const int32_t *edges;         /* [2*n_edges]                             */
+    const double *edge_scale;     /* [n_edges] or NULL (all 1)               */
+    double sigma;                 /* mS/mm                                   */
+    int32_t model;                /* ep_model, normally EP_STEWART           */
+    int32_t n_sub;                /* <= 0: from the stability bound          */
+    int32_t n_pmj;
+    const ep_pmj *pmj;
+} ep_purkinje;
 
 typedef struct {
     int64_t n_nodes;
@@ -290,6 +326,7 @@ typedef struct {
     const ep_stimulus *stimuli;
     double ionic_scale[4];        /* GKr, GKs, GCaL, GNa multipliers (0 = 1) */
     int64_t n_steps;              /* steps to run (> 0)                      */
+    const ep_purkinje *purkinje;  /* NULL: tissue only                       */
 } ep_request;
 
 typedef struct {
@@ -329,6 +366,11 @@ ep_status ep_server_wait(ep_server *sv, int64_t id, ep_result *res);
 ep_status ep_server_get_vm(ep_server *sv, int64_t id, double *out, int64_t n);
 ep_status ep_server_get_activation(ep_server *sv, int64_t id, double *out, int64_t n);
 ep_status ep_server_get_apd90(ep_server *sv, int64_t id, double *out, int64_t n);
+/* Graph results of a finished request with a Purkinje graph, n == its node
+ * count: potential and activation time (NaN: none).  EP_ESTATE without a
+ * graph. */
+ep_status ep_server_get_purkinje_vm(ep_server *sv, int64_t id, double *out, int64_t n);
+ep_status ep_server_get_purkinje_activation(ep_server *sv, int64_t id, double *out, int64_t n);
 ep_status ep_server_release(ep_server *sv, int64_t id);   /* drop stored results */
 ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st);
 /* Graph length in steps (> 0) and XCD remap, as ep_set_launch. */

@@ -60,7 +60,7 @@ def lib():
                                           C.c_double, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
-        L.orc_set_purkinje.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip,
+        L.orc_set_purkinje.argtypes = [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip, _dp,
                                        C.c_double, C.c_int, C.c_int32]
         L.orc_add_pmj.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
                                   C.c_double, C.c_int, C.c_double, C.c_double]
@@ -162,8 +162,12 @@ class Sim:
         if pk is not None:
             pxyz = np.ascontiguousarray(pk.xyz, np.float64)
             pe = np.ascontiguousarray(pk.edges, np.int32)
+            self._escale = (None if pk.edge_scale is None
+                            else np.ascontiguousarray(pk.edge_scale, np.float64))
             r = L.orc_set_purkinje(self.h, pxyz.shape[0], _d(pxyz), pe.shape[0],
-                                   pe.ctypes.data_as(_ip), pk.sigma, pk.model, pk.n_sub)
+                                   pe.ctypes.data_as(_ip),
+                                   None if self._escale is None else _d(self._escale),
+                                   pk.sigma, pk.model, pk.n_sub)
             assert r == 0
             self.np = pxyz.shape[0]
             for node in pk.pmj_nodes:

@@ -72,9 +72,12 @@ void orc_set_step(orc_sim *s, int64_t step);
 /* A 1D Purkinje graph discretised with vertex-centred finite volumes (the
  * paper's choice for branching 1D media, Sec. 3.2): node i owns half of every
  * incident segment, l_i = sum_j L_ij / 2, and
- *   dv_i/dt = sigma / (chi Cm l_i) sum_j (v_j - v_i) / L_ij - I_ion - I_stim.
+ *   dv_i/dt = sigma / (chi Cm l_i) sum_j s_ij (v_j - v_i) / L_ij - I_ion - I_stim,
+ * with s_ij >= 0 the segment's conductivity multiplier (edge_scale, NULL = 1;
+ * a reduced value models a bundle-branch delay, 0 a complete block, Sec. 6).
  * It advances in n_sub explicit substeps per tissue step (n_sub <= 0: the
- * smallest n_sub with dt/n_sub <= 0.9 min_i chi Cm l_i / (sigma sum_j 1/L_ij)).
+ * smallest n_sub with dt/n_sub <= 0.9 min_i chi Cm l_i / (sigma sum_j s_ij/L_ij),
+ * nodes whose segments are all blocked left out).
  * Junctions (Sec. 3.3): an upward crossing of the threshold at the junction
  * node during tissue step n stimulates its muscle region (cells whose
  * centroid lies within `radius`, else the cells sharing a node with the cell
@@ -83,7 +86,8 @@ void orc_set_step(orc_sim *s, int64_t step);
  * the node after delay_anti.  Each step: tissue, then Purkinje substeps, then
  * junction events. */
 int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
-                     const int32_t *edges, double sigma, int model, int32_t n_sub);
+                     const int32_t *edges, const double *edge_scale, double sigma,
+                     int model, int32_t n_sub);
 int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
                 double delay_anti, int two_way, double amp, double dur);
 int orc_add_purkinje_stimulus(orc_sim *s, int64_t n_ids, const int32_t *ids,

@@ -66,6 +66,7 @@ struct orc_sim {
     int64_t *padj_off;          /* node -> incident (neighbour, length) */
     int32_t *padj_nbr;
     double *padj_len;
+    double *padj_scale;         /* conductivity multiplier of the segment */
     double *pell;               /* control length l_i */
     double psigma;
     int pmodel;
@@ -446,6 +447,7 @@ void orc_destroy(orc_sim *s)
     for (int i = 0; i < s->n_stims; ++i) free(s->stims[i].ids);
     free(s->stims);
     free(s->pxyz); free(s->padj_off); free(s->padj_nbr); free(s->padj_len);
+    free(s->padj_scale);
     free(s->pell); free(s->py); free(s->pistim); free(s->pstatus); free(s->pt_act);
     for (int i = 0; i < s->n_pstims; ++i) free(s->pstims[i].ids);
     free(s->pstims);
@@ -526,7 +528,7 @@ static void purkinje_step(orc_sim *s, const double *v_old)
             double *y = s->py + i * ORC_MAX_SLOTS;
             double flux = 0.0;
             for (int64_t e = s->padj_off[i]; e < s->padj_off[i + 1]; ++e)
-                flux += (vp[s->padj_nbr[e]] - vp[i]) / s->padj_len[e];
+                flux += s->padj_scale[e] * (vp[s->padj_nbr[e]] - vp[i]) / s->padj_len[e];
             const double L = s->psigma * flux / (s->chi * s->cm * s->pell[i]);
             const double iion = orc_model_step(s->pmodel, y, dtp, s->pistim[i], s->gscale);
             const double vnew = vp[i] + dtp * (L - iion - s->pistim[i]);
@@ -556,11 +558,15 @@ static void purkinje_step(orc_sim *s, const double *v_old)
 }
 
 int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
-                     const int32_t *edges, double sigma, int model, int32_t n_sub)
+                     const int32_t *edges, const double *edge_scale, double sigma,
+                     int model, int32_t n_sub)
 {
     if (n <= 0 || n_edges < 0 || !(sigma > 0)) return -1;
     for (int64_t e = 0; e < 2 * n_edges; ++e)
         if (edges[e] < 0 || edges[e] >= n) return -1;
+    if (edge_scale)
+        for (int64_t e = 0; e < n_edges; ++e)
+            if (!(edge_scale[e] >= 0.0) || !isfinite(edge_scale[e])) return -1;
     s->np = n;
     s->pxyz = malloc(sizeof(double) * (size_t)n * 3);
     memcpy(s->pxyz, xyz, sizeof(double) * (size_t)n * 3);
@@ -574,15 +580,16 @@ int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
     for (int64_t i = 0; i < n; ++i) s->padj_off[i + 1] += s->padj_off[i];
     s->padj_nbr = malloc(sizeof(int32_t) * (size_t)(2 * n_edges + 1));
     s->padj_len = malloc(sizeof(double) * (size_t)(2 * n_edges + 1));
+    s->padj_scale = malloc(sizeof(double) * (size_t)(2 * n_edges + 1));
     int64_t *fill = malloc(sizeof(int64_t) * (size_t)n);
     memcpy(fill, s->padj_off, sizeof(int64_t) * (size_t)n);
     for (int64_t e = 0; e < n_edges; ++e) {
         const int32_t a = edges[2 * e], b = edges[2 * e + 1];
         double d[3];
         sub3(xyz + 3 * (int64_t)a, xyz + 3 * (int64_t)b, d);
-        const double len = norm3(d);
-        s->padj_nbr[fill[a]] = b; s->padj_len[fill[a]++] = len;
-        s->padj_nbr[fill[b]] = a; s->padj_len[fill[b]++] = len;
+        const double len = norm3(d), sc = edge_scale ? edge_scale[e] : 1.0;
+        s->padj_nbr[fill[a]] = b; s->padj_scale[fill[a]] = sc; s->padj_len[fill[a]++] = len;
+        s->padj_nbr[fill[b]] = a; s->padj_scale[fill[b]] = sc; s->padj_len[fill[b]++] = len;
     }
     free(fill);
     s->pell = calloc((size_t)n, sizeof(double));
@@ -591,7 +598,7 @@ int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
         double inv = 0.0;
         for (int64_t e = s->padj_off[i]; e < s->padj_off[i + 1]; ++e) {
             s->pell[i] += 0.5 * s->padj_len[e];
-            inv += 1.0 / s->padj_len[e];
+            inv += s->padj_scale[e] / s->padj_len[e];
         }
         if (inv > 0.0) {
             const double lim = s->chi * s->cm * s->pell[i] / (sigma * inv);

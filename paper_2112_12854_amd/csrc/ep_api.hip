@@ -197,23 +197,11 @@ ep_status ep_add_stimulus(ep_sim *s, int domain, int64_t n_ids, const int32_t *i
                           double dur, double amp, double period, int32_t count) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "stimuli are frozen after ep_init");
-    if (domain != 0 && domain != 1) return fail(s, EP_EINVAL, "domain must be 0 (tissue) or 1 (graph)");
     ep::InstSpec &sp = s->spec;
     if (sp.n_tets == 0) return fail(s, EP_ESTATE, "set the mesh first");
     if (domain == 1 && sp.purk.n == 0) return fail(s, EP_ESTATE, "set the Purkinje graph first");
-    if ((int)sp.stims.size() >= EP_MAX_STIMULI) return fail(s, EP_EINVAL, "too many stimuli");
-    if (n_ids < 0 || (n_ids > 0 && !ids) || !(dur >= 0) || !std::isfinite(amp) || period < 0)
-        return fail(s, EP_EINVAL, "bad stimulus");
-    const int64_t lim = domain == 0 ? sp.n_tets : sp.purk.n;
-    for (int64_t i = 0; i < n_ids; ++i)
-        if (ids[i] < 0 || ids[i] >= lim) return fail(s, EP_EINVAL, "stimulus id out of range");
-    ep::StimSpec st;
-    st.domain = domain;
-    st.ids.assign(ids, ids + n_ids);
-    st.t0 = t0; st.dur = dur; st.amp = amp; st.period = period;
-    st.count = count < 1 ? 1 : count;
-    sp.stims.push_back(std::move(st));
-    return EP_OK;
+    const std::string e = ep::spec_add_stimulus(sp, domain, n_ids, ids, t0, dur, amp, period, count);
+    return e.empty() ? EP_OK : fail(s, EP_EINVAL, e);
 }
 
 ep_status ep_set_purkinje(ep_sim *s, int64_t n, const double *xyz, int64_t n_edges,
@@ -222,48 +210,28 @@ ep_status ep_set_purkinje(ep_sim *s, int64_t n, const double *xyz, int64_t n_edg
     if (s->inited) return fail(s, EP_ESTATE, "the graph is frozen after ep_init");
     ep::InstSpec &sp = s->spec;
     if (sp.n_tets == 0) return fail(s, EP_ESTATE, "set the mesh first");
-    if (n <= 0 || n >= ((int64_t)1 << 25) || !xyz || n_edges < 0 || (n_edges > 0 && !edges))
-        return fail(s, EP_EINVAL, "empty graph or null array");
-    if (!(sigma > 0) || !std::isfinite(sigma)) return fail(s, EP_EINVAL, "sigma must be > 0");
-    if (model < 0 || model > EP_PASSIVE) return fail(s, EP_EINVAL, "model id out of range");
-    for (int64_t i = 0; i < 3 * n; ++i)
-        if (!std::isfinite(xyz[i])) return fail(s, EP_EINVAL, "non-finite node coordinate");
-    for (int64_t e = 0; e < 2 * n_edges; ++e)
-        if (edges[e] < 0 || edges[e] >= n) return fail(s, EP_EINVAL, "edge node index out of range");
     for (const ep::StimSpec &st : sp.stims)
         if (st.domain == 1) return fail(s, EP_ESTATE, "graph stimuli refer to the previous graph");
-    sp.purk = ep::PurkSpec();
-    sp.purk.n = n;
-    sp.purk.xyz.assign(xyz, xyz + 3 * n);
-    sp.purk.edges.assign(edges, edges + 2 * n_edges);
-    sp.purk.sigma = sigma;
-    sp.purk.model = model;
-    sp.purk.n_sub = n_sub;
-    return EP_OK;
+    const std::string e = ep::spec_set_purkinje(sp, n, xyz, n_edges, edges, sigma, model, n_sub);
+    return e.empty() ? EP_OK : fail(s, EP_EINVAL, e);
+}
+
+ep_status ep_set_purkinje_scale(ep_sim *s, int64_t n_edges, const double *scale) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "the graph is frozen after ep_init");
+    if (s->spec.purk.n == 0) return fail(s, EP_ESTATE, "set the Purkinje graph first");
+    const std::string e = ep::spec_set_purkinje_scale(s->spec, n_edges, scale);
+    return e.empty() ? EP_OK : fail(s, EP_EINVAL, e);
 }
 
 ep_status ep_add_pmj(ep_sim *s, int32_t node, double radius, double delay_ortho,
                      double delay_anti, int32_t two_way, double amp, double dur) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "junctions are frozen after ep_init");
-    ep::PurkSpec &pk = s->spec.purk;
-    if (pk.n == 0) return fail(s, EP_ESTATE, "set the Purkinje graph first");
-    if (node < 0 || node >= pk.n) return fail(s, EP_EINVAL, "junction node out of range");
-    if (!(radius >= 0) || !std::isfinite(radius) || !(delay_ortho >= 0) || !(delay_anti >= 0) ||
-        !std::isfinite(delay_ortho) || !std::isfinite(delay_anti) || !std::isfinite(amp) ||
-        !(dur >= 0) || !std::isfinite(dur))
-        return fail(s, EP_EINVAL, "bad junction parameters");
-    if (pk.pmjs.size() >= (size_t)1 << 24) return fail(s, EP_EINVAL, "too many junctions");
-    ep::PmjIn q;
-    q.node = node;
-    q.radius = radius;
-    q.delay_ortho = delay_ortho;
-    q.delay_anti = delay_anti;
-    q.two_way = two_way ? 1 : 0;
-    q.amp = amp;
-    q.dur = dur;
-    pk.pmjs.push_back(q);
-    return EP_OK;
+    if (s->spec.purk.n == 0) return fail(s, EP_ESTATE, "set the Purkinje graph first");
+    const std::string e = ep::spec_add_pmj(s->spec, node, radius, delay_ortho, delay_anti,
+                                           two_way, amp, dur);
+    return e.empty() ? EP_OK : fail(s, EP_EINVAL, e);
 }
 
 ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t restart,

@@ -87,6 +87,77 @@ size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
     return b;
 }
 
+std::string spec_set_purkinje(InstSpec &sp, int64_t n, const double *xyz, int64_t n_edges,
+                              const int32_t *edges, double sigma, int32_t model, int32_t n_sub) {
+    if (n <= 0 || n >= ((int64_t)1 << 25) || !xyz || n_edges < 0 || (n_edges > 0 && !edges))
+        return "empty graph or null array";
+    if (!(sigma > 0) || !std::isfinite(sigma)) return "sigma must be > 0";
+    if (model < 0 || model > EP_PASSIVE) return "model id out of range";
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(xyz[i])) return "non-finite node coordinate";
+    for (int64_t e = 0; e < 2 * n_edges; ++e)
+        if (edges[e] < 0 || edges[e] >= n) return "edge node index out of range";
+    sp.purk = PurkSpec();
+    sp.purk.n = n;
+    sp.purk.xyz.assign(xyz, xyz + 3 * n);
+    sp.purk.edges.assign(edges, edges + 2 * n_edges);
+    sp.purk.sigma = sigma;
+    sp.purk.model = model;
+    sp.purk.n_sub = n_sub;
+    return "";
+}
+
+std::string spec_set_purkinje_scale(InstSpec &sp, int64_t n_edges, const double *scale) {
+    PurkSpec &pk = sp.purk;
+    if (n_edges != (int64_t)pk.edges.size() / 2 || (n_edges > 0 && !scale))
+        return "one scale per graph segment";
+    for (int64_t e = 0; e < n_edges; ++e)
+        if (!(scale[e] >= 0.0) || !std::isfinite(scale[e]))
+            return "segment scales must be finite and >= 0";
+    pk.edge_scale.assign(scale, scale + n_edges);
+    return "";
+}
+
+std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay_ortho,
+                         double delay_anti, int32_t two_way, double amp, double dur) {
+    PurkSpec &pk = sp.purk;
+    if (node < 0 || node >= pk.n) return "junction node out of range";
+    if (!(radius >= 0) || !std::isfinite(radius) || !(delay_ortho >= 0) || !(delay_anti >= 0) ||
+        !std::isfinite(delay_ortho) || !std::isfinite(delay_anti) || !std::isfinite(amp) ||
+        !(dur >= 0) || !std::isfinite(dur))
+        return "bad junction parameters";
+    if (pk.pmjs.size() >= (size_t)1 << 24) return "too many junctions";
+    PmjIn q;
+    q.node = node;
+    q.radius = radius;
+    q.delay_ortho = delay_ortho;
+    q.delay_anti = delay_anti;
+    q.two_way = two_way ? 1 : 0;
+    q.amp = amp;
+    q.dur = dur;
+    pk.pmjs.push_back(q);
+    return "";
+}
+
+std::string spec_add_stimulus(InstSpec &sp, int domain, int64_t n_ids, const int32_t *ids,
+                              double t0, double dur, double amp, double period, int32_t count) {
+    if (domain != 0 && domain != 1) return "domain must be 0 (tissue) or 1 (graph)";
+    if ((int)sp.stims.size() >= EP_MAX_STIMULI) return "too many stimuli";
+    if (n_ids < 0 || (n_ids > 0 && !ids) || !(dur >= 0) || !std::isfinite(amp) || !(period >= 0) ||
+        !std::isfinite(t0) || !std::isfinite(dur) || !std::isfinite(period))
+        return "bad stimulus";
+    const int64_t lim = domain == 0 ? sp.n_tets : sp.purk.n;
+    for (int64_t i = 0; i < n_ids; ++i)
+        if (ids[i] < 0 || ids[i] >= lim) return "stimulus id out of range";
+    StimSpec st;
+    st.domain = domain;
+    st.ids.assign(ids, ids + n_ids);
+    st.t0 = t0; st.dur = dur; st.amp = amp; st.period = period;
+    st.count = count < 1 ? 1 : count;
+    sp.stims.push_back(std::move(st));
+    return "";
+}
+
 std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     st = EP_OK;
     PrepIn in;
@@ -120,6 +191,7 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
         pin.n_edges = (int64_t)sp.purk.edges.size() / 2;
         pin.xyz = sp.purk.xyz.data();
         pin.edges = sp.purk.edges.data();
+        pin.edge_scale = sp.purk.edge_scale.empty() ? nullptr : sp.purk.edge_scale.data();
         pin.sigma = sp.purk.sigma;
         pin.dt = sp.dt;
         pin.chi = sp.chi;

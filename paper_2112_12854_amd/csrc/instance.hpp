@@ -25,6 +25,7 @@ struct PurkSpec {
     int64_t n = 0;
     std::vector<double> xyz;
     std::vector<int32_t> edges;
+    std::vector<double> edge_scale;    // per segment, empty = 1
     double sigma = 3.95;
     int32_t model = 4;
     int32_t n_sub = 0;
@@ -119,6 +120,16 @@ struct Inst {
 };
 
 // Host precompute only (thread-safe, no HIP calls).
+// Validated edits of a spec, shared by the single-simulation API and the
+// server's request copy; an empty string means success (EP_EINVAL otherwise).
+std::string spec_set_purkinje(InstSpec &sp, int64_t n, const double *xyz, int64_t n_edges,
+                              const int32_t *edges, double sigma, int32_t model, int32_t n_sub);
+std::string spec_set_purkinje_scale(InstSpec &sp, int64_t n_edges, const double *scale);
+std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay_ortho,
+                         double delay_anti, int32_t two_way, double amp, double dur);
+std::string spec_add_stimulus(InstSpec &sp, int domain, int64_t n_ids, const int32_t *ids,
+                              double t0, double dur, double amp, double period, int32_t count);
+
 std::string prep_instance(const InstSpec &spec, Inst &out, ep_status &st);
 // Device bytes upload_instance will allocate for a prepared instance.
 size_t instance_footprint(const Inst &inst, int rs, const InstSpec &spec);

@@ -68,6 +68,7 @@ struct PurkIn {
     int64_t n = 0, n_edges = 0;
     const double *xyz = nullptr;       // [n*3]
     const int32_t *edges = nullptr;    // [n_edges*2]
+    const double *edge_scale = nullptr;  // [n_edges] conductivity multipliers >= 0, or null
     double sigma = 3.95, dt = 0.02, chi = 140.0, cm = 0.01;
     int32_t n_sub = 0;                 // <= 0: derived from the stability bound
     std::vector<PmjIn> pmjs;

@@ -53,7 +53,7 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
     out.off.assign(n + 1, 0);
     for (int64_t i = 0; i < n; ++i) out.off[i + 1] = out.off[i] + deg[i];
     out.nbr.assign(out.off[n], 0);
-    std::vector<double> len(out.off[n]);
+    std::vector<double> len(out.off[n]), sc(out.off[n]);
     std::vector<int32_t> fill(out.off.begin(), out.off.end() - 1);
     for (int64_t e = 0; e < in.n_edges; ++e) {
         const int32_t a = in.edges[2 * e], b = in.edges[2 * e + 1];
@@ -61,9 +61,13 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
         const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
         const double L = std::sqrt(dx * dx + dy * dy + dz * dz);
         if (!(L > 0)) return "Purkinje segment of zero length";
+        const double k = in.edge_scale ? in.edge_scale[e] : 1.0;
+        if (!(k >= 0.0) || !std::isfinite(k)) return "bad Purkinje segment conductivity scale";
         out.nbr[fill[a]] = b;
+        sc[fill[a]] = k;
         len[fill[a]++] = L;
         out.nbr[fill[b]] = a;
+        sc[fill[b]] = k;
         len[fill[b]++] = L;
     }
     out.g.assign(out.off[n], 0.0);
@@ -72,13 +76,14 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
         double ell = 0.0, inv = 0.0;
         for (int32_t e = out.off[i]; e < out.off[i + 1]; ++e) {
             ell += 0.5 * len[e];
-            inv += 1.0 / len[e];
+            inv += sc[e] / len[e];
         }
         for (int32_t e = out.off[i]; e < out.off[i + 1]; ++e)
-            out.g[e] = in.sigma / (in.chi * in.cm * ell * len[e]);
+            out.g[e] = in.sigma * sc[e] / (in.chi * in.cm * ell * len[e]);
         if (inv > 0) dtmax = std::min(dtmax, in.chi * in.cm * ell / (in.sigma * inv));
     }
     // explicit substeps: 90 % of the Gershgorin bound of the graph operator
+    // (nodes cut off by blocked segments on every side impose none)
     int32_t ns = in.n_sub;
     if (ns <= 0) {
         ns = 1;

@@ -42,8 +42,9 @@ struct Req {
     ep_status status = EP_OK;
     std::string err;
     double t_submit = 0, t_admit = 0, t_done = 0;
-    void *h_res = nullptr;             // pinned: t_act, t_rep (f64), v (R)
-    std::vector<double> vm, tact, apd;
+    void *h_res = nullptr;             // pinned: t_act, t_rep (f64), v (R), NaN flag,
+                                       // then graph t_act (f64) and v (R)
+    std::vector<double> vm, tact, apd, pvm, pact;
 };
 
 struct Retire {
@@ -138,12 +139,19 @@ void worker_main(ep_server *sv) {
     }
 }
 
+// Tissue part of a request's staged results: t_act, t_rep (f64), v (R), NaN
+// flag; the graph part (t_act f64, v R) follows at this offset.
+size_t tissue_bytes(const Req *r, int rs) {
+    const size_t nc = (size_t)r->inst.desc.nc;
+    return (nc * 16 + nc * (size_t)rs + 8 + 255) / 256 * 256;
+}
+
 // Copy the results of a group of finished instances into one pinned buffer
-// (stream order): per request t_act, t_rep (f64), v (R) and the NaN flag.
+// (stream order).
 void *stage_results(ep_server *sv, const std::vector<Req *> &fin) {
     auto bytes_of = [&](const Req *r) {
-        const size_t nc = (size_t)r->inst.desc.nc;
-        return (nc * 16 + nc * (size_t)sv->rs + 8 + 255) / 256 * 256;
+        const size_t np = (size_t)r->inst.pk.n;
+        return tissue_bytes(r, sv->rs) + (np * 8 + np * (size_t)sv->rs + 255) / 256 * 256;
     };
     size_t total = 0;
     for (const Req *r : fin) total += bytes_of(r);
@@ -163,6 +171,14 @@ void *stage_results(ep_server *sv, const std::vector<Req *> &fin) {
                              hipMemcpyDeviceToHost, sv->stream);
         (void)hipMemcpyAsync(p + nc * 16 + nc * sv->rs, &r->inst.d_ctrl->nan_flag, sizeof(int32_t),
                              hipMemcpyDeviceToHost, sv->stream);
+        if (r->inst.pk.n > 0) {
+            const epdev::PurkDesc &P = r->inst.pdesc;
+            const size_t np = (size_t)P.np;
+            char *q = p + tissue_bytes(r, sv->rs);
+            (void)hipMemcpyAsync(q, P.pt_act, np * 8, hipMemcpyDeviceToHost, sv->stream);
+            (void)hipMemcpyAsync(q + np * 8, P.pv[(r->inst.host_step * P.n_sub) & 1],
+                                 np * sv->rs, hipMemcpyDeviceToHost, sv->stream);
+        }
         p += bytes_of(r);
     }
     return grp;
@@ -186,6 +202,16 @@ void finish(ep_server *sv, Req *r) {
             r->tact[u] = ta[i];
             r->apd[u] = tr[i] - ta[i];
             r->vm[u] = sv->rs == 8 ? ((const double *)vb)[i] : (double)((const float *)vb)[i];
+        }
+        const int64_t np = r->inst.pk.n;
+        if (np > 0) {
+            // graph nodes keep the caller's numbering
+            const char *q = (const char *)r->h_res + tissue_bytes(r, sv->rs);
+            r->pact.assign((const double *)q, (const double *)q + np);
+            r->pvm.resize(np);
+            for (int64_t i = 0; i < np; ++i)
+                r->pvm[i] = sv->rs == 8 ? ((const double *)(q + np * 8))[i]
+                                        : (double)((const float *)(q + np * 8))[i];
         }
         r->h_res = nullptr;                 // part of its group's buffer
     } else if (r->status == EP_OK) {
@@ -431,20 +457,28 @@ ep_status copy_request(const ep_request *rq, const ep_options &o, ep::InstSpec &
         if (g < 0 || !std::isfinite(g)) { err = "bad ionic scale"; return EP_EINVAL; }
         sp.gscale[i] = g > 0 ? g : 1.0;
     }
+    if (const ep_purkinje *g = rq->purkinje) {
+        err = ep::spec_set_purkinje(sp, g->n, g->xyz, g->n_edges, g->edges, g->sigma, g->model,
+                                    g->n_sub);
+        if (err.empty() && g->edge_scale)
+            err = ep::spec_set_purkinje_scale(sp, g->n_edges, g->edge_scale);
+        if (err.empty() && (g->n_pmj < 0 || (g->n_pmj > 0 && !g->pmj))) err = "bad junction list";
+        for (int32_t k = 0; err.empty() && k < g->n_pmj; ++k) {
+            const ep_pmj &q = g->pmj[k];
+            err = ep::spec_add_pmj(sp, q.node, q.radius, q.delay_ortho, q.delay_anti, q.two_way,
+                                   q.amp, q.dur);
+        }
+        if (!err.empty()) return EP_EINVAL;
+    }
     for (int k = 0; k < rq->n_stimuli; ++k) {
         const ep_stimulus &q = rq->stimuli[k];
-        if (q.n_ids < 0 || (q.n_ids > 0 && !q.ids) || !(q.dur >= 0) || q.period < 0) {
-            err = "bad stimulus";
+        if (q.domain == 1 && sp.purk.n == 0) {
+            err = "graph stimulus without a Purkinje graph";
             return EP_EINVAL;
         }
-        ep::StimSpec s;
-        for (int64_t i = 0; i < q.n_ids; ++i) {
-            if (q.ids[i] < 0 || q.ids[i] >= rq->n_tets) { err = "stimulus id out of range"; return EP_EINVAL; }
-            s.ids.push_back(q.ids[i]);
-        }
-        s.t0 = q.t0; s.dur = q.dur; s.amp = q.amp; s.period = q.period;
-        s.count = q.count < 1 ? 1 : q.count;
-        sp.stims.push_back(std::move(s));
+        err = ep::spec_add_stimulus(sp, q.domain, q.n_ids, q.ids, q.t0, q.dur, q.amp, q.period,
+                                    q.count);
+        if (!err.empty()) return EP_EINVAL;
     }
     sp.dt = o.dt;
     sp.chi = o.chi;
@@ -564,15 +598,26 @@ static ep_status get_vec(ep_server *sv, int64_t id, double *out, int64_t n, int 
     if (it == sv->reqs.end()) { sv->err = "unknown request id"; return EP_EINVAL; }
     Req *r = it->second.get();
     if (r->state != Q_DONE) return EP_EBUSY;
-    const std::vector<double> &v = which == 0 ? r->vm : (which == 1 ? r->tact : r->apd);
+    const std::vector<double> &v = which == 0 ? r->vm : which == 1 ? r->tact : which == 2 ? r->apd
+                                 : which == 3 ? r->pvm : r->pact;
+    if (which >= 3 && r->spec.purk.n == 0) { sv->err = "request has no Purkinje graph"; return EP_ESTATE; }
     if (v.empty()) { sv->err = r->err.empty() ? "no results" : r->err; return EP_ESTATE; }
-    if (n != (int64_t)v.size()) { sv->err = "output length must equal n_tets"; return EP_EINVAL; }
+    if (n != (int64_t)v.size()) {
+        sv->err = which >= 3 ? "output length must equal the graph size" : "output length must equal n_tets";
+        return EP_EINVAL;
+    }
     std::memcpy(out, v.data(), n * sizeof(double));
     return r->status == EP_ENUMERIC ? EP_ENUMERIC : EP_OK;
 }
 
 ep_status ep_server_get_vm(ep_server *sv, int64_t id, double *out, int64_t n) {
     return get_vec(sv, id, out, n, 0);
+}
+ep_status ep_server_get_purkinje_vm(ep_server *sv, int64_t id, double *out, int64_t n) {
+    return get_vec(sv, id, out, n, 3);
+}
+ep_status ep_server_get_purkinje_activation(ep_server *sv, int64_t id, double *out, int64_t n) {
+    return get_vec(sv, id, out, n, 4);
 }
 ep_status ep_server_get_activation(ep_server *sv, int64_t id, double *out, int64_t n) {
     return get_vec(sv, id, out, n, 1);

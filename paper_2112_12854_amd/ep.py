@@ -38,7 +38,20 @@ class ep_options(C.Structure):
 class ep_stimulus(C.Structure):
     _fields_ = [("n_ids", C.c_int64), ("ids", C.POINTER(C.c_int32)), ("t0", C.c_double),
                 ("dur", C.c_double), ("amp", C.c_double), ("period", C.c_double),
-                ("count", C.c_int32)]
+                ("count", C.c_int32), ("domain", C.c_int32)]
+
+
+class ep_pmj(C.Structure):
+    _fields_ = [("node", C.c_int32), ("two_way", C.c_int32), ("radius", C.c_double),
+                ("delay_ortho", C.c_double), ("delay_anti", C.c_double), ("amp", C.c_double),
+                ("dur", C.c_double)]
+
+
+class ep_purkinje(C.Structure):
+    _fields_ = [("n", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_edges", C.c_int64),
+                ("edges", C.POINTER(C.c_int32)), ("edge_scale", C.POINTER(C.c_double)),
+                ("sigma", C.c_double), ("model", C.c_int32), ("n_sub", C.c_int32),
+                ("n_pmj", C.c_int32), ("pmj", C.POINTER(ep_pmj))]
 
 
 class ep_request(C.Structure):
@@ -48,7 +61,7 @@ class ep_request(C.Structure):
                 ("sigma_t", C.c_double), ("scale", C.POINTER(C.c_double)),
                 ("model", C.POINTER(C.c_uint8)), ("n_stimuli", C.c_int32),
                 ("stimuli", C.POINTER(ep_stimulus)), ("ionic_scale", C.c_double * 4),
-                ("n_steps", C.c_int64)]
+                ("n_steps", C.c_int64), ("purkinje", C.POINTER(ep_purkinje))]
 
 
 class ep_result(C.Structure):
@@ -89,6 +102,7 @@ _SIGS = {
                                   C.c_double, C.c_double, C.c_double, C.c_int32]),
     "ep_set_purkinje": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip, C.c_double,
                                   C.c_int32, C.c_int32]),
+    "ep_set_purkinje_scale": (C.c_int, [C.c_void_p, C.c_int64, _dp]),
     "ep_add_pmj": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
                              C.c_int32, C.c_double, C.c_double]),
     "ep_get_purkinje_vm": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
@@ -130,6 +144,8 @@ _SIGS = {
     "ep_server_get_vm": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
     "ep_server_get_activation": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
     "ep_server_get_apd90": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
+    "ep_server_get_purkinje_vm": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
+    "ep_server_get_purkinje_activation": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64]),
     "ep_server_release": (C.c_int, [C.c_void_p, C.c_int64]),
     "ep_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ep_server_stats)]),
     "ep_server_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
@@ -244,6 +260,9 @@ class Sim:
             pe = np.ascontiguousarray(pk.edges, np.int32)
             _check(L.ep_set_purkinje(h, pxyz.shape[0], _d(pxyz), pe.shape[0],
                                      pe.ctypes.data_as(_ip), pk.sigma, pk.model, pk.n_sub), h)
+            if pk.edge_scale is not None:
+                es = np.ascontiguousarray(pk.edge_scale, np.float64)
+                _check(L.ep_set_purkinje_scale(h, es.size, _d(es)), h)
             self.n_purkinje = pxyz.shape[0]
             for node in pk.pmj_nodes:
                 _check(L.ep_add_pmj(h, int(node), pk.pmj_radius, pk.delay_ortho, pk.delay_anti,
@@ -415,6 +434,7 @@ class Server:
         _check(L.ep_server_create(C.byref(o), int(hbm_budget), int(max_slots), C.byref(h)))
         self.h = h
         self.n_of = {}
+        self.np_of = {}
         _check(L.ep_server_set_launch(h, steps_per_graph, 1))
 
     def _err(self):
@@ -434,7 +454,7 @@ class Server:
         stims = (ep_stimulus * max(1, len(w.stimuli)))()
         for k, st in enumerate(w.stimuli):
             stims[k] = ep_stimulus(ids[k].size, ids[k].ctypes.data_as(_ip), st.t0, st.dur,
-                                   st.amp, st.period, st.count)
+                                   st.amp, st.period, st.count, st.domain)
         rq = ep_request()
         rq.n_nodes, rq.xyz = w.n_nodes, _d(xyz)
         rq.n_tets, rq.tet_nodes = w.n_tets, tets.ctypes.data_as(_ip)
@@ -446,9 +466,26 @@ class Server:
         for i, k in enumerate(("GKr", "GKs", "GCaL", "GNa")):
             rq.ionic_scale[i] = float(gs.get(k, 1.0))
         rq.n_steps = int(n_steps)
+        pk = getattr(w, "purkinje", None)
+        keep = []
+        if pk is not None:
+            pxyz = np.ascontiguousarray(pk.xyz, np.float64)
+            pe = np.ascontiguousarray(pk.edges, np.int32)
+            es = None if pk.edge_scale is None else np.ascontiguousarray(pk.edge_scale, np.float64)
+            jn = (ep_pmj * max(1, len(pk.pmj_nodes)))()
+            for k, node in enumerate(pk.pmj_nodes):
+                jn[k] = ep_pmj(int(node), int(pk.two_way), pk.pmj_radius, pk.delay_ortho,
+                               pk.delay_anti, pk.pmj_amp, pk.pmj_dur)
+            g = ep_purkinje(pxyz.shape[0], _d(pxyz), pe.shape[0], pe.ctypes.data_as(_ip),
+                            None if es is None else _d(es), pk.sigma, pk.model, pk.n_sub,
+                            len(pk.pmj_nodes), jn)
+            keep = [pxyz, pe, es, jn, g]
+            rq.purkinje = C.pointer(g)
         rid = C.c_int64()
         self._chk(lib().ep_server_submit(self.h, C.byref(rq), C.byref(rid)))
+        del keep
         self.n_of[rid.value] = w.n_tets
+        self.np_of[rid.value] = 0 if pk is None else int(np.asarray(pk.xyz).shape[0])
         return rid.value
 
     def poll(self, rid: int):
@@ -464,8 +501,8 @@ class Server:
         self._chk(lib().ep_server_wait(self.h, rid, C.byref(r)))
         return _result_dict(r)
 
-    def _vec(self, fn, rid):
-        out = np.empty(self.n_of[rid])
+    def _vec(self, fn, rid, graph=False):
+        out = np.empty(self.np_of[rid] if graph else self.n_of[rid])
         st = fn(self.h, rid, _d(out), out.size)
         if st not in (EP_OK, EP_ENUMERIC):
             self._chk(st)
@@ -479,6 +516,12 @@ class Server:
 
     def apd90(self, rid):
         return self._vec(lib().ep_server_get_apd90, rid)
+
+    def purkinje_vm(self, rid):
+        return self._vec(lib().ep_server_get_purkinje_vm, rid, graph=True)
+
+    def purkinje_activation(self, rid):
+        return self._vec(lib().ep_server_get_purkinje_activation, rid, graph=True)
 
     def release(self, rid):
         self._chk(lib().ep_server_release(self.h, rid))

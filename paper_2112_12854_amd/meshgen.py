@@ -69,6 +69,7 @@ class Workload:
     dims: tuple = ()                   # (nx, ny, nz, h)
     purkinje: object = None            # Purkinje graph (heart workloads)
     bidomain: object = None            # Bidomain parameters, or monodomain
+    landmarks: dict = field(default_factory=dict)   # name -> [3] point (mm)
 
     @property
     def n_tets(self) -> int:
@@ -309,7 +310,9 @@ def serving_workload(spec: dict, n_steps: int, dt: float = 0.02) -> Workload:
 @dataclass
 class Purkinje:
     """A 1D Purkinje graph: node coordinates [n,3], edges [m,2], terminal
-    (junction) nodes, conductivity sigma (mS/mm) and the cell model."""
+    (junction) nodes, conductivity sigma (mS/mm), the cell model, and
+    optionally a conductivity multiplier per edge (bundle-branch delay or
+    block) and per-edge labels of the generator (branch side and depth)."""
     xyz: np.ndarray
     edges: np.ndarray
     pmj_nodes: np.ndarray
@@ -322,6 +325,9 @@ class Purkinje:
     two_way: bool = False
     pmj_amp: float = -200.0        # pA/pF
     pmj_dur: float = 0.5           # ms, Sec. 3.3 (S_d of communication nodes)
+    edge_scale: np.ndarray | None = None   # [m] conductivity multipliers >= 0
+    edge_side: np.ndarray | None = None    # [m] 0 left, 1 right bundle (heart tree)
+    edge_depth: np.ndarray | None = None   # [m] branching generation (0 = bundle)
 
 
 def _ellipsoid_depth(p, a_in, c_in, a_out, c_out, iters=30):
@@ -460,6 +466,18 @@ def heart(h: float = 0.5, seed: int = 3, scale: float = 1.0, purkinje_nodes: int
     # graph nodes within 0.5 mm of the root receive it
     root = np.nonzero(np.linalg.norm(pk.xyz - pk.xyz[0], axis=1) <= 0.5)[0].astype(np.int32)
     w.stimuli.append(Stimulus(ids=root, t0=130.0, dur=2.0, amp=-100.0, domain=1))
+    # pacing-lead sites of Sec. 6 (mid-wall points of this geometry) and the
+    # His root
+    w.landmarks = {
+        "his": pk.xyz[0].copy(),
+        "rv_apex": np.array([rv_off[0], 0.0, rv_off[2] - 0.5 * (rv[1] + rv[3])]),
+        "lv_apex": np.array([0.0, 0.0, -0.5 * (lv[1] + lv[3])]),
+        "lv_lateral": np.array([-0.5 * (lv[0] + lv[2]), 0.0, -0.4 * lv[1]]),
+    }
+    if atr.any():
+        w.landmarks["sa_node"] = top.copy()
+        w.landmarks["ra_appendage"] = np.array([8 * L - (at_a + 0.5 * at_thick), 0.0,
+                                                at_gap + 0.2 * at_c])
     return w
 
 
@@ -489,6 +507,7 @@ def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_
     pts = [np.array([a_i * 0.9, 0.0, z_base - 2.0])]
     side_of = [0]
     edges = []
+    e_side, e_depth = [], []
     leaves = []
     # two bundle branches, one per ventricle
     stack = []
@@ -512,6 +531,8 @@ def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_
             pts.append(p)
             side_of.append(side)
             edges.append((prev, len(pts) - 1))
+            e_side.append(side)
+            e_depth.append(depth)
             prev = len(pts) - 1
         if len(pts) >= n_nodes or depth > 40:
             leaves.append(prev)
@@ -535,7 +556,8 @@ def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_
     leaves = leaves[~septal]
     if leaves.size > n_pmj:
         leaves = leaves[np.linspace(0, leaves.size - 1, n_pmj).astype(int)]
-    return Purkinje(xyz=xyz, edges=edges, pmj_nodes=leaves.astype(np.int32))
+    return Purkinje(xyz=xyz, edges=edges, pmj_nodes=leaves.astype(np.int32),
+                    edge_side=np.array(e_side, np.int8), edge_depth=np.array(e_depth, np.int32))
 
 
 def purkinje_slab(nx: int = 16, ny: int = 8, nz: int = 2, h: float = 0.5, seg: float = 0.1,
@@ -570,12 +592,19 @@ def purkinje_slab(nx: int = 16, ny: int = 8, nz: int = 2, h: float = 0.5, seg: f
         return prev
 
     f = line(0, root, fork)
-    leaf_ids = [line(f, fork, q) for q in leaves]
+    # branch labels: trunk -1, branch to leaf k: k (all generation 0)
+    side = [-1] * len(edges)
+    leaf_ids = []
+    for k, q in enumerate(leaves):
+        leaf_ids.append(line(f, fork, q))
+        side += [k] * (len(edges) - len(side))
+    side = np.array(side, np.int8)
     pxyz = np.array(pts)
     if pmj_amp is None:
         pmj_amp = -200.0 if drive == "graph" else -1000.0
     pk = Purkinje(xyz=pxyz, edges=np.array(edges, np.int32), pmj_nodes=np.array(leaf_ids, np.int32),
-                  pmj_radius=0.6, two_way=two_way, pmj_amp=pmj_amp)
+                  pmj_radius=0.6, two_way=two_way, pmj_amp=pmj_amp, edge_side=side,
+                  edge_depth=np.zeros(len(edges), np.int32))
     stimuli = []
     if drive == "graph":
         ids = np.nonzero(np.linalg.norm(pxyz - root, axis=1) <= 0.5)[0].astype(np.int32)

@@ -1,0 +1,160 @@
+"""GPU parity of the pathology and pacing scenarios (Sec. 6) through the C
+ABI: per-segment Purkinje conductivity (bundle-branch delay and block), AV
+block with a pacing lead and two-way junctions, and a severity sweep
+submitted to the server as one batch.
+
+Bars: FP64 max|dV| <= 1e-6 mV on tissue and graph against the oracle,
+activation times within 1e-6 ms (same NaN pattern); FP32-mixed activation
+times within 0.5 ms; server results bitwise equal to the same workload run
+alone.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2112_12854_amd import meshgen as M
+from paper_2112_12854_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+TOL_MV = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ep():
+    from paper_2112_12854_amd import ep as _ep
+    _ep.lib()
+    return _ep
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def same_times(a, b):
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    f = np.isfinite(a)
+    return float(np.max(np.abs(a[f] - b[f]))) if f.any() else 0.0
+
+
+@pytest.fixture(scope="module")
+def small_heart():
+    w = M.heart(h=1.0, scale=0.3, purkinje_nodes=1500, n_pmj=60)
+    w.stimuli[-1].t0 = 0.0
+    return w
+
+
+@pytest.mark.parametrize("case", ["rbbb", "lbbb-0.6", "avb-lead"])
+def test_heart_scenario_parity(ep, oracle_lib, small_heart, case):
+    w = small_heart
+    if case == "rbbb":
+        w = S.bundle_branch_block(w, "right")
+    elif case == "lbbb-0.6":
+        w = S.bundle_branch_block(w, "left", 0.6, generations=2)
+    else:
+        w = S.ventricular_pacing_with_av_block(w, site="lv_apex", t0=0.0)
+    say(f"heart scenario {case}: {w.n_tets} tets, {w.purkinje.xyz.shape[0]} graph nodes")
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    f = ep.Sim(w, prec=ep.EP_FP32_MIXED)
+    o = oracle_lib.Sim(w)
+    assert g.purkinje_n_sub() == o.purkinje_n_sub()
+    for chunk in range(3):
+        g.step(600)
+        f.step(600)
+        o.step(600)
+        dv = np.max(np.abs(g.vm() - o.vm()))
+        dp = np.max(np.abs(g.purkinje_vm() - o.purkinje_vm()))
+        assert dv <= TOL_MV and dp <= TOL_MV, (chunk, dv, dp)
+    ta_o, pa_o = o.activation(), o.purkinje_activation()
+    assert same_times(g.activation(), ta_o) <= 1e-6
+    assert same_times(g.purkinje_activation(), pa_o) <= 1e-6
+    assert same_times(f.activation(), ta_o) <= 0.5
+    assert same_times(f.purkinje_activation(), pa_o) <= 0.5
+    assert np.isfinite(ta_o).sum() > 0
+    say(f"  {np.isfinite(ta_o).sum()} cells and {np.isfinite(pa_o).sum()} graph nodes activated")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_server_severity_sweep(ep, oracle_lib, prec):
+    """Bundle-branch severities 0, 0.5, 0.8 and 1 of the slab's first branch,
+    submitted together with a tissue-only request: each result equals the
+    same workload run alone, bitwise; the FP64 0.8 case matches the oracle."""
+    p = ep.EP_FP64 if prec == "fp64" else ep.EP_FP32_MIXED
+    base = M.purkinje_slab(drive="graph")
+    sweep = S.sweep_requests(base, "left", [0.0, 0.5, 0.8, 1.0])
+    plain = M.config1(n_steps=0)
+    steps = 600
+    sv = ep.Server(prec=p, dt=base.dt, max_slots=8)
+    try:
+        sv.hold(True)
+        ids = [sv.submit(w, steps) for w in sweep] + [sv.submit(plain, steps)]
+        sv.hold(False)
+        res = [sv.wait(i) for i in ids]
+        assert all(r["status"] == ep.EP_OK for r in res)
+        leaf_t = []
+        for rid, w in zip(ids, sweep + [plain]):
+            solo = ep.Sim(w, prec=p)
+            solo.step(steps)
+            assert np.array_equal(sv.vm(rid), solo.vm())
+            assert np.array_equal(sv.activation(rid), solo.activation(), equal_nan=True)
+            if w.purkinje is not None:
+                assert np.array_equal(sv.purkinje_vm(rid), solo.purkinje_vm())
+                pa = sv.purkinje_activation(rid)
+                assert np.array_equal(pa, solo.purkinje_activation(), equal_nan=True)
+                leaf_t.append(pa[w.purkinje.pmj_nodes[0]])
+            else:
+                with pytest.raises(ep.EPError):
+                    sv.purkinje_vm(rid)
+        # delay grows with severity; a complete block never reaches the leaf
+        assert leaf_t[0] < leaf_t[1] < leaf_t[2] and np.isnan(leaf_t[3])
+        if p == ep.EP_FP64:
+            o = oracle_lib.Sim(sweep[2])
+            o.step(steps)
+            assert np.max(np.abs(sv.vm(ids[2]) - o.vm())) <= TOL_MV
+            assert np.max(np.abs(sv.purkinje_vm(ids[2]) - o.purkinje_vm())) <= TOL_MV
+    finally:
+        sv.close()
+
+
+def test_scenario_abi_errors(ep):
+    L = ep.lib()
+    w = M.purkinje_slab()
+    o = ep.ep_options()
+    L.ep_default_options(C.byref(o))
+    h = C.c_void_p()
+    assert L.ep_create(C.byref(o), C.byref(h)) == ep.EP_OK
+    try:
+        xyz = np.ascontiguousarray(w.xyz)
+        tets = np.ascontiguousarray(w.tets, np.int32)
+        assert L.ep_set_mesh(h, w.n_nodes, ep._d(xyz), w.n_tets, tets.ctypes.data_as(ep._ip)) == 0
+        m = w.purkinje.edges.shape[0]
+        ones = np.ones(m)
+        assert L.ep_set_purkinje_scale(h, m, ep._d(ones)) == ep.EP_ESTATE
+        px = np.ascontiguousarray(w.purkinje.xyz)
+        e = np.ascontiguousarray(w.purkinje.edges, np.int32)
+        assert L.ep_set_purkinje(h, px.shape[0], ep._d(px), m, e.ctypes.data_as(ep._ip),
+                                 3.95, M.STEWART, 0) == ep.EP_OK
+        assert L.ep_set_purkinje_scale(h, m - 1, ep._d(ones)) == ep.EP_EINVAL
+        bad = ones.copy()
+        bad[3] = -0.5
+        assert L.ep_set_purkinje_scale(h, m, ep._d(bad)) == ep.EP_EINVAL
+        bad[3] = np.inf
+        assert L.ep_set_purkinje_scale(h, m, ep._d(bad)) == ep.EP_EINVAL
+        assert L.ep_set_purkinje_scale(h, m, ep._d(ones)) == ep.EP_OK
+    finally:
+        L.ep_destroy(h)
+    # server: a graph stimulus needs a graph, segment scales must be valid
+    sv = ep.Server(prec=ep.EP_FP64, max_slots=2)
+    try:
+        g = M.config1(n_steps=0)
+        g.stimuli.append(M.Stimulus(ids=np.array([0], np.int32), t0=0.0, dur=1.0, amp=-50.0,
+                                    domain=1))
+        with pytest.raises(ep.EPError):
+            sv.submit(g, 10)
+        b = M.purkinje_slab()
+        b.purkinje.edge_scale = np.full(b.purkinje.edges.shape[0], -1.0)
+        with pytest.raises(ep.EPError):
+            sv.submit(b, 10)
+    finally:
+        sv.close()

@@ -236,3 +236,91 @@ def test_antidromic_pulse_and_one_way(oracle_lib):
     s1 = oracle_lib.Sim(w1)
     s1.step(600)
     assert np.isnan(s1.purkinje_activation()).all()
+
+
+# ------------------------------------------- segment conductivity (Sec. 6)
+def test_segment_scale_matches_variable_coefficient_fd(oracle_lib):
+    """Per-segment multipliers s_e (a bundle-branch delay lowers them, a
+    block sets them to 0): on a uniform chain the scheme is the textbook
+    conservative finite difference of (k v')' with k = sigma s at the
+    half-points, (k+ (v_{i+1} - v_i) - k- (v_i - v_{i-1})) / L^2, Neumann
+    ends by the ghost-node form (factor 2 at the ends); the substep count
+    is the Gershgorin bound of that matrix."""
+    n, L, dt = 30, 0.1, 0.02
+    rng = np.random.default_rng(11)
+    s_e = rng.uniform(0.2, 2.0, n - 1)
+    s_e[[4, 20]] = 0.0
+    w = chain_workload(n, L, model=M.PASSIVE, stim_nodes=[2, 10], stim_amp=-40.0,
+                       stim_dur=0.2, dt=dt)
+    w.purkinje.edge_scale = s_e
+    s = oracle_lib.Sim(w)
+    k = 3.95 * s_e / CHI_CM
+    A = np.zeros((n, n))
+    for i in range(n - 1):
+        A[i, i + 1] += k[i]
+        A[i + 1, i] += k[i]
+        A[i, i] -= k[i]
+        A[i + 1, i + 1] -= k[i]
+    A /= L * L
+    A[0] *= 2.0
+    A[-1] *= 2.0
+    lam = np.max(-np.diag(A) + np.abs(A - np.diag(np.diag(A))).sum(axis=1))
+    nsub = s.purkinje_n_sub()
+    assert nsub == max(1, math.ceil(dt * lam / (2 * 0.9) - 1e-12))
+    dtp = dt / nsub
+    v = s.purkinje_vm().copy()
+    nstim = int(round(0.2 / dt))
+    for step in range(40):
+        for _ in range(nsub):
+            ist = np.zeros(n)
+            if step < nstim:
+                ist[[2, 10]] = -40.0
+            v = v + dtp * (A @ v - ist)
+    s.step(40)
+    got = s.purkinje_vm()
+    np.testing.assert_allclose(got, v, rtol=0, atol=1e-10)
+    # nothing crosses a blocked segment: the nodes past node 20 never move
+    assert np.all(got[21:] == got[-1]) and got[-1] == w_rest(oracle_lib)
+
+
+def w_rest(oracle_lib):
+    return oracle_lib.model_init(M.PASSIVE)[0]
+
+
+def test_blocked_leaf_evolves_as_an_isolated_cell(oracle_lib):
+    """A complete block (s = 0) removes the segment's flux exactly: the
+    leaf behind it follows the single-cell Stewart model integrated with the
+    graph substep, while the driven chain in front of it activates."""
+    n, L, dt = 40, 0.1, 0.02
+    s_e = np.ones(n - 1)
+    s_e[-1] = 0.0
+    w = chain_workload(n, L, stim_nodes=list(range(5)), dt=dt)
+    w.purkinje.edge_scale = s_e
+    s = oracle_lib.Sim(w)
+    nsub = s.purkinje_n_sub()
+    steps = 400
+    s.step(steps)
+    _, trace = oracle_lib.single_cell(M.STEWART, steps * dt, dt / nsub, stim_amp=0.0)
+    assert s.purkinje_vm()[-1] == pytest.approx(trace[-1], abs=1e-12)
+    ta = s.purkinje_activation()
+    assert np.isfinite(ta[:-1]).all() and np.isnan(ta[-1])
+
+
+@pytest.mark.slow
+def test_bundle_delay_velocity_scales_with_sqrt_conductivity(oracle_lib):
+    """Cable theory: conduction velocity grows as the square root of the
+    axial conductivity, so a bundle at a quarter of its conductivity (the
+    paper's proportional bundle-branch delay) conducts at half the speed
+    (10 % band for the discrete chain)."""
+    cvs = []
+    for scale in (1.0, 0.25):
+        w = chain_workload(241, 0.1, stim_nodes=list(range(5)), stim_amp=-100.0, stim_dur=1.0)
+        w.purkinje.edge_scale = np.full(240, scale)
+        s = oracle_lib.Sim(w)
+        s.step(900)
+        ta = s.purkinje_activation()
+        x = w.purkinje.xyz[:, 0]
+        i0, i1 = np.argmin(abs(x - 8.0)), np.argmin(abs(x - 16.0))
+        assert np.isfinite(ta[[i0, i1]]).all()
+        cvs.append((x[i1] - x[i0]) / (ta[i1] - ta[i0]))
+    assert cvs[1] / cvs[0] == pytest.approx(0.5, rel=0.10)
