@@ -66,6 +66,7 @@ def lib():
                                   C.c_double, C.c_int, C.c_double, C.c_double]
         L.orc_add_purkinje_stimulus.argtypes = [C.c_void_p, C.c_int64, _ip, C.c_double,
                                                 C.c_double, C.c_double, C.c_double, C.c_int32]
+        L.orc_set_time_scheme.argtypes = [C.c_void_p, C.c_int]
         L.orc_purkinje_n_sub.argtypes = [C.c_void_p]
         L.orc_purkinje_n_sub.restype = C.c_int32
         L.orc_get_purkinje_vm.argtypes = [C.c_void_p, _dp]
@@ -181,6 +182,8 @@ class Sim:
         if w.ionic_scale:
             gs = np.array([w.ionic_scale.get(k, 1.0) for k in ("GKr", "GKs", "GCaL", "GNa")])
             L.orc_set_ionic_scale(self.h, _d(gs))
+        if getattr(w, "time_scheme", 0):
+            assert L.orc_set_time_scheme(self.h, int(w.time_scheme)) == 0
         bd = getattr(w, "bidomain", None)
         if bd is not None:
             assert L.orc_set_bidomain(self.h, bd.sigma_el, bd.sigma_et, bd.restart, bd.tol,

@@ -94,6 +94,16 @@ int orc_add_purkinje_stimulus(orc_sim *s, int64_t n_ids, const int32_t *ids,
                               double t0, double dur, double amp, double period,
                               int32_t count);
 int32_t orc_purkinje_n_sub(const orc_sim *s);
+
+/* Time scheme of the non-gating states (the potential of cells and graph
+ * nodes, the concentrations, Stewart's Rbar): 0 forward Euler (the paper's
+ * scheme, Sec. 3.2), 1 second-order Adams-Bashforth, which the paper names
+ * as the way to shrink the time error of those states (Sec. 4):
+ * y^{n+1} = y^n + dt (3/2 f^n - 1/2 f^{n-1}), forward Euler on step 0 (and
+ * graph substep 0).  Gates stay Rush-Larsen in both.  AB2 is stable on half
+ * the interval of forward Euler, so a derived substep count uses half the
+ * graph bound.  Call before stepping; returns -1 for an unknown scheme. */
+int orc_set_time_scheme(orc_sim *s, int scheme);
 void orc_get_purkinje_vm(const orc_sim *s, double *out);
 void orc_get_purkinje_activation(const orc_sim *s, double *out);
 /* muscle region of junction k (at most cap ids); returns its size */

@@ -65,7 +65,7 @@ static double rush_larsen(double y, double yinf, double tau, double dt)
     return yinf + (y - yinf) * exp(-dt / tau);
 }
 
-double orc_crn_step(double *y, double dt, double istim, const double *gs)
+double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hist *hist)
 {
     (void)istim;  /* the article's K_i balance carries no stimulus term */
     const double V = y[0];
@@ -203,12 +203,12 @@ double orc_crn_step(double *y, double dt, double istim, const double *gs)
         w = rush_larsen(w, 1.0 - 1.0 / (1.0 + exp(-(V - 40.0) / 17.0)), tau, dt);
     }
 
-    /* ---- concentrations, forward Euler ---- */
-    nai += dt * dNai;
-    ki += dt * dKi;
-    cai += dt * dCai;
-    caup += dt * dCaup;
-    carel += dt * dCarel;
+    /* ---- concentrations, forward Euler or Adams-Bashforth 2 ---- */
+    nai += dt * orc_rate(hist, 3, dNai);
+    ki += dt * orc_rate(hist, 4, dKi);
+    cai += dt * orc_rate(hist, 0, dCai);
+    caup += dt * orc_rate(hist, 1, dCaup);
+    carel += dt * orc_rate(hist, 2, dCarel);
 
     y[1] = m; y[2] = h; y[3] = j; y[4] = oa; y[5] = oi; y[6] = ua; y[7] = ui;
     y[8] = xr; y[9] = xs; y[10] = d; y[11] = f; y[12] = fca; y[13] = u;

@@ -78,7 +78,8 @@ static double total_from_free(double c, double B, double K)
     return c + B * c / (c + K);
 }
 
-double orc_stewart_step(double *y, double dt, double istim, const double *gs)
+double orc_stewart_step(double *y, double dt, double istim, const double *gs,
+                        orc_hist *hist)
 {
     const double V = y[0];
     double m = y[1], h = y[2], j = y[3], xr1 = y[4], xr2 = y[5], xs = y[6];
@@ -218,12 +219,15 @@ double orc_stewart_step(double *y, double dt, double istim, const double *gs)
     b = exp(3.6 + 0.11 * V);
     yf = rush_larsen(yf, yinf, 4000.0 / (a + b), dt);
 
-    rbar += dt * dRbar;
-    cai = free_from_total(total_from_free(cai, BUF_C, K_BUFC) + dt * dCaiT, BUF_C, K_BUFC);
-    casr = free_from_total(total_from_free(casr, BUF_SR, K_BUFSR) + dt * dCasrT, BUF_SR, K_BUFSR);
-    cass = free_from_total(total_from_free(cass, BUF_SS, K_BUFSS) + dt * dCassT, BUF_SS, K_BUFSS);
-    nai += dt * dNai;
-    ki += dt * dKi;
+    rbar += dt * orc_rate(hist, 0, dRbar);
+    cai = free_from_total(total_from_free(cai, BUF_C, K_BUFC) + dt * orc_rate(hist, 1, dCaiT),
+                          BUF_C, K_BUFC);
+    casr = free_from_total(total_from_free(casr, BUF_SR, K_BUFSR) + dt * orc_rate(hist, 2, dCasrT),
+                           BUF_SR, K_BUFSR);
+    cass = free_from_total(total_from_free(cass, BUF_SS, K_BUFSS) + dt * orc_rate(hist, 3, dCassT),
+                           BUF_SS, K_BUFSS);
+    nai += dt * orc_rate(hist, 4, dNai);
+    ki += dt * orc_rate(hist, 5, dKi);
 
     y[1] = m; y[2] = h; y[3] = j; y[4] = xr1; y[5] = xr2; y[6] = xs;
     y[7] = r; y[8] = s; y[9] = d; y[10] = f; y[11] = f2; y[12] = fcass;

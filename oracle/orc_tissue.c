@@ -60,6 +60,8 @@ struct orc_sim {
     int n_stims;
     double gscale[4];
     int64_t step;
+    int ab2;                    /* non-gating states by Adams-Bashforth 2 */
+    double *hist;               /* per cell: v rate, then the model's rates */
     /* Purkinje graph */
     int64_t np;
     double *pxyz;
@@ -68,9 +70,12 @@ struct orc_sim {
     double *padj_len;
     double *padj_scale;         /* conductivity multiplier of the segment */
     double *pell;               /* control length l_i */
+    double *phist;              /* Adams-Bashforth history per node: ORC_HIST_SLOTS */
     double psigma;
     int pmodel;
     int32_t n_sub;
+    int32_t n_sub_given;        /* <= 0: from the stability bound */
+    double pdtmax;              /* forward-Euler bound of the graph operator */
     double *py;                 /* py[i*ORC_MAX_SLOTS + slot] */
     double *pistim;
     uint8_t *pstatus;
@@ -136,16 +141,33 @@ void orc_model_init(int model, double *y)
     }
 }
 
-double orc_model_step(int model, double *y, double dt, double istim,
-                      const double *gscale)
+static double model_step(int model, double *y, double dt, double istim,
+                         const double *gscale, orc_hist *h)
 {
     switch (model) {
     case ORC_TP06_ENDO: case ORC_TP06_MID: case ORC_TP06_EPI:
-        return orc_tp06_step(model, y, dt, istim, gscale);
-    case ORC_CRN: return orc_crn_step(y, dt, istim, gscale);
-    case ORC_STEWART: return orc_stewart_step(y, dt, istim, gscale);
+        return orc_tp06_step(model, y, dt, istim, gscale, h);
+    case ORC_CRN: return orc_crn_step(y, dt, istim, gscale, h);
+    case ORC_STEWART: return orc_stewart_step(y, dt, istim, gscale, h);
     default: return 0.0;
     }
+}
+
+double orc_model_step(int model, double *y, double dt, double istim,
+                      const double *gscale)
+{
+    return model_step(model, y, dt, istim, gscale, NULL);
+}
+
+#define ORC_HIST_SLOTS 7   /* v, then at most 6 non-gating model states */
+
+/* the potential's rate under the configured scheme (see orc_rate) */
+static double v_rate(const orc_sim *s, double *hv, int first, double F)
+{
+    if (!s->ab2) return F;
+    const double prev = first ? F : *hv;
+    *hv = F;
+    return 1.5 * F - 0.5 * prev;
 }
 
 int orc_num_threads(void)
@@ -448,6 +470,7 @@ void orc_destroy(orc_sim *s)
     free(s->stims);
     free(s->pxyz); free(s->padj_off); free(s->padj_nbr); free(s->padj_len);
     free(s->padj_scale);
+    free(s->hist); free(s->phist);
     free(s->pell); free(s->py); free(s->pistim); free(s->pstatus); free(s->pt_act);
     for (int i = 0; i < s->n_pstims; ++i) free(s->pstims[i].ids);
     free(s->pstims);
@@ -530,8 +553,12 @@ static void purkinje_step(orc_sim *s, const double *v_old)
             for (int64_t e = s->padj_off[i]; e < s->padj_off[i + 1]; ++e)
                 flux += s->padj_scale[e] * (vp[s->padj_nbr[e]] - vp[i]) / s->padj_len[e];
             const double L = s->psigma * flux / (s->chi * s->cm * s->pell[i]);
-            const double iion = orc_model_step(s->pmodel, y, dtp, s->pistim[i], s->gscale);
-            const double vnew = vp[i] + dtp * (L - iion - s->pistim[i]);
+            double *hc = s->ab2 ? s->phist + i * ORC_HIST_SLOTS : NULL;
+            const int first = n == 0 && sub == 0;
+            orc_hist h = {hc ? hc + 1 : NULL, first};
+            const double iion = model_step(s->pmodel, y, dtp, s->pistim[i], s->gscale,
+                                           hc ? &h : NULL);
+            const double vnew = vp[i] + dtp * v_rate(s, hc, first, L - iion - s->pistim[i]);
             y[0] = vnew;
             if (!s->pstatus[i] && vp[i] <= s->thr && vnew > s->thr) {
                 s->pt_act[i] = ((double)(n * s->n_sub + sub) +
@@ -555,6 +582,19 @@ static void purkinje_step(orc_sim *s, const double *v_old)
     }
     free(vp);
     free(vp0);
+}
+
+/* Substeps per tissue step: as given, else the smallest count within 90 %
+ * of the stability bound: dtmax for forward Euler, dtmax / 2 for
+ * Adams-Bashforth 2 (its interval on the negative real axis is half as
+ * long). */
+static int32_t graph_substeps(const orc_sim *s)
+{
+    if (s->n_sub_given > 0) return s->n_sub_given;
+    const double lim = (s->ab2 ? 0.45 : 0.9) * s->pdtmax;
+    int32_t k = 1;
+    while (s->dt / k > lim) ++k;
+    return k;
 }
 
 int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
@@ -605,11 +645,9 @@ int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
             if (lim < dtmax) dtmax = lim;
         }
     }
-    if (n_sub <= 0) {
-        n_sub = 1;
-        while (s->dt / n_sub > 0.9 * dtmax) ++n_sub;
-    }
-    s->n_sub = n_sub;
+    s->n_sub_given = n_sub;
+    s->pdtmax = dtmax;
+    s->n_sub = graph_substeps(s);
     s->py = malloc(sizeof(double) * (size_t)n * ORC_MAX_SLOTS);
     s->pistim = calloc((size_t)n, sizeof(double));
     s->pstatus = calloc((size_t)n, 1);
@@ -859,6 +897,9 @@ static void one_step(orc_sim *s)
 {
     const int64_t nc = s->nc, n = s->step;
     const double dt = s->dt;
+    if (s->ab2 && !s->hist) s->hist = calloc((size_t)nc * ORC_HIST_SLOTS, sizeof(double));
+    if (s->ab2 && s->np > 0 && !s->phist)
+        s->phist = calloc((size_t)s->np * ORC_HIST_SLOTS, sizeof(double));
     double *v = malloc(sizeof(double) * (size_t)nc);
     for (int64_t c = 0; c < nc; ++c) v[c] = s->y[c * ORC_MAX_SLOTS];
 
@@ -897,8 +938,11 @@ static void one_step(orc_sim *s)
     for (int64_t c = 0; c < nc; ++c) {
         double *y = s->y + c * ORC_MAX_SLOTS;
         const double vold = v[c];
-        const double iion = orc_model_step(s->model[c], y, dt, s->istim[c], s->gscale);
-        const double vnew = vold + dt * (s->L[c] - iion - s->istim[c]);
+        double *hc = s->ab2 ? s->hist + c * ORC_HIST_SLOTS : NULL;
+        orc_hist h = {hc ? hc + 1 : NULL, n == 0};
+        const double iion = model_step(s->model[c], y, dt, s->istim[c], s->gscale,
+                                       hc ? &h : NULL);
+        const double vnew = vold + dt * v_rate(s, hc, n == 0, s->L[c] - iion - s->istim[c]);
         y[0] = vnew;
         /* activation: first upward crossing of the threshold */
         if (s->status[c] == 0) {
@@ -920,6 +964,14 @@ static void one_step(orc_sim *s)
     if (s->bido) bidomain_solve(s);
     free(v);
     s->step++;
+}
+
+int orc_set_time_scheme(orc_sim *s, int scheme)
+{
+    if ((scheme != 0 && scheme != 1) || s->step != 0) return -1;
+    s->ab2 = scheme;
+    if (s->np > 0) s->n_sub = graph_substeps(s);
+    return 0;
 }
 
 void orc_step(orc_sim *s, int64_t n_steps)

@@ -105,7 +105,7 @@ static double total_from_free(double c, double B, double K)
 }
 
 double orc_tp06_step(int celltype, double *y, double dt, double istim,
-                     const double *gs)
+                     const double *gs, orc_hist *hist)
 {
     const double V = y[0];
     double m = y[1], h = y[2], j = y[3], xr1 = y[4], xr2 = y[5], xs = y[6];
@@ -288,12 +288,16 @@ double orc_tp06_step(int celltype, double *y, double dt, double istim,
         rbar = rush_larsen(rbar, K4 / rate, 1.0 / rate, dt);
     }
 
-    /* ---- concentrations, forward Euler (buffered ones on the total) ---- */
-    cai = free_from_total(total_from_free(cai, BUF_C, K_BUFC) + dt * dCaiT, BUF_C, K_BUFC);
-    casr = free_from_total(total_from_free(casr, BUF_SR, K_BUFSR) + dt * dCasrT, BUF_SR, K_BUFSR);
-    cass = free_from_total(total_from_free(cass, BUF_SS, K_BUFSS) + dt * dCassT, BUF_SS, K_BUFSS);
-    nai += dt * dNai;
-    ki += dt * dKi;
+    /* ---- concentrations, forward Euler or Adams-Bashforth 2 (buffered
+     * ones on the total) ---- */
+    cai = free_from_total(total_from_free(cai, BUF_C, K_BUFC) + dt * orc_rate(hist, 0, dCaiT),
+                          BUF_C, K_BUFC);
+    casr = free_from_total(total_from_free(casr, BUF_SR, K_BUFSR) + dt * orc_rate(hist, 1, dCasrT),
+                           BUF_SR, K_BUFSR);
+    cass = free_from_total(total_from_free(cass, BUF_SS, K_BUFSS) + dt * orc_rate(hist, 2, dCassT),
+                           BUF_SS, K_BUFSS);
+    nai += dt * orc_rate(hist, 3, dNai);
+    ki += dt * orc_rate(hist, 4, dKi);
 
     y[1] = m; y[2] = h; y[3] = j; y[4] = xr1; y[5] = xr2; y[6] = xs;
     y[7] = r; y[8] = s; y[9] = d; y[10] = f; y[11] = f2; y[12] = fcass;

@@ -70,6 +70,7 @@ class Workload:
     purkinje: object = None            # Purkinje graph (heart workloads)
     bidomain: object = None            # Bidomain parameters, or monodomain
     landmarks: dict = field(default_factory=dict)   # name -> [3] point (mm)
+    time_scheme: int = 0               # 0 forward Euler, 1 Adams-Bashforth 2
 
     @property
     def n_tets(self) -> int:
