@@ -356,6 +356,37 @@ def run_heart(ep, meshgen, args):
     print(json.dumps(out), flush=True)
 
 
+def run_ab2(ep, meshgen, args):
+    """The default slab with the non-gating states stepped by Adams-Bashforth
+    2 (Sec. 4) instead of forward Euler: cost of the extra rate history."""
+    t0 = time.time()
+    w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
+    w.time_scheme = 1
+    log(f"workload {w.name} (AB2): {w.n_tets} tets ({time.time() - t0:.1f}s)")
+    res = {}
+    for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
+        r = run_precision(ep, w, prec, args.steps, args.warmup, args.chunk, args.steps)
+        r["cell_GBps"] = r["cell_bytes"] / (r["cell_kernel_ms"] * 1e-3) / 1e9
+        res[name] = r
+    f32 = res["fp32"]
+    out = {
+        "metric": "cell-steps/s (ionic+FV step, Adams-Bashforth 2 non-gating states)",
+        "value": f32["cell_steps_per_s"], "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64conc", "data": "synthetic",
+        "config": {"workload": w.name + "-ab2", "n_tets": w.n_tets, "dt_ms": w.dt},
+        "fp64": {"value": res["fp64"]["cell_steps_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
+                 "cell_kernel_ms": res["fp64"]["cell_kernel_ms"],
+                 "cell_GBps": res["fp64"]["cell_GBps"], "cell_bytes": res["fp64"]["cell_bytes"]},
+        "roofline": {"bound": "hbm", "kernel": "k_cell<float, AB2>", "achieved": f32["cell_GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": f32["cell_GBps"] / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": f32["cell_bytes"]},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +414,8 @@ def main():
                     help="skip the FP32-vs-FP64 error distributions")
     ap.add_argument("--bidomain", action="store_true",
                     help="bidomain vs monodomain step time on the paper's benchmark box")
+    ap.add_argument("--ab2", action="store_true",
+                    help="the slab with Adams-Bashforth 2 for the non-gating states")
     ap.add_argument("--heart", action="store_true",
                     help="the three-media heart instead of the slab (timed steps only)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -412,6 +445,8 @@ def main():
         return run_heart(ep, meshgen, args)
     if args.bidomain:
         return run_bidomain(ep, meshgen, args)
+    if args.ab2:
+        return run_ab2(ep, meshgen, args)
     t0 = time.time()
     w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
     log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")

@@ -173,6 +173,20 @@ ep_status ep_get_purkinje_vm(ep_sim *s, double *out, int64_t n);
 ep_status ep_get_purkinje_activation(ep_sim *s, double *out, int64_t n);
 ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub);
 
+/* Time scheme of the non-gating states: the potential v of cells and graph
+ * nodes, the concentrations and Stewart's Rbar.  EP_SCHEME_FE: forward
+ * Euler, the paper's scheme (Sec. 3.2).  EP_SCHEME_AB2: the second-order
+ * Adams-Bashforth step the paper names for a smaller time error (Sec. 4),
+ *   y^{n+1} = y^n + dt (3/2 f^n - 1/2 f^{n-1}),
+ * forward Euler on step 0 (graph: substep 0); the gates stay Rush-Larsen, so
+ * the scheme as a whole stays first order.  AB2 keeps one previous rate per
+ * non-gating state (device memory, part of the checkpoint) and is stable on
+ * half the interval of forward Euler: a derived graph substep count uses
+ * half the bound, and dt itself must suit.  Not with the bidomain model
+ * (EP_EINVAL).  Call before ep_init. */
+typedef enum { EP_SCHEME_FE = 0, EP_SCHEME_AB2 = 1 } ep_time_scheme;
+ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme);
+
 /* Bidomain model (Sec. 3.1 eq. electro, Sec. 3.2 eq. electro2_3d) instead of
  * the monodomain one: the conductivities of ep_set_conductivity become the
  * intracellular ones M_i; sigma_el / sigma_et (mS/mm) give the extracellular
@@ -183,7 +197,8 @@ ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub);
  * for phi_e^{n+1} by restarted GMRES(restart) started from phi_e^n, until the
  * residual is at most tol times the right-hand side's norm or max_iter Arnoldi
  * steps, and shifts phi_e to zero volume-weighted mean (phi_e^0 = 0, exact for
- * a uniform initial potential).  EP_FP64 only (EP_EINVAL otherwise); call
+ * a uniform initial potential).  EP_FP64 and forward Euler only (EP_EINVAL
+ * otherwise); call
  * before ep_init.  Each ep_step of a bidomain simulation synchronises its
  * stream once per Arnoldi step. */
 ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t restart,

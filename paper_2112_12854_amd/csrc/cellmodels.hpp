@@ -78,6 +78,23 @@ __device__ __forceinline__ double buffered_total(double c, double B, double K) {
     return c * (1.0 + B / (c + K));
 }
 
+// Rate of a non-gating state (concentrations; Stewart's Rbar) under the time
+// scheme: forward Euler uses the rate of step n; Adams-Bashforth 2 uses
+// 3/2 r^n - 1/2 r^{n-1}, h[k] holding r^{n-1} (forward Euler on the first
+// step) and receiving r^n.
+struct FwdEuler {
+    __device__ __forceinline__ double operator()(double r, int) const { return r; }
+};
+struct AdamsBashforth2 {
+    double *h;
+    bool first;
+    __device__ __forceinline__ double operator()(double r, int k) const {
+        const double p = first ? r : h[k];
+        h[k] = r;
+        return 1.5 * r - 0.5 * p;
+    }
+};
+
 // ===================================================================== TP06
 // ten Tusscher & Panfilov, Am J Physiol Heart Circ Physiol 291:H1088 (2006),
 // currents shared with ten Tusscher, Noble, Noble & Panfilov, AJP 286:H1573
@@ -102,9 +119,9 @@ __host__ __device__ inline void init(double *y) {
     for (int i = 0; i < 19; ++i) y[i] = s[i];
 }
 
-template <typename R>
+template <typename R, typename E = FwdEuler>
 __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
-                                  double dtd, R istim, const GScale &gs) {
+                                  double dtd, R istim, const GScale &gs, const E &e = E()) {
     const R frt = R(1.0 / RTF);
     const double cai = c[0], casr = c[1], cass = c[2], nai = c[3], ki = c[4];
     const R rtf = R(RTF);
@@ -249,11 +266,11 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
     }
 
     // ---- concentrations, forward Euler (FP64)
-    c[0] = buffered_free(buffered_total(cai, 0.2, 0.001) + dtd * rCai, 0.2, 0.001);
-    c[1] = buffered_free(buffered_total(casr, 10.0, 0.3) + dtd * rCasr, 10.0, 0.3);
-    c[2] = buffered_free(buffered_total(cass, 0.4, 0.00025) + dtd * rCass, 0.4, 0.00025);
-    c[3] = nai + dtd * rNai;
-    c[4] = ki + dtd * rKi;
+    c[0] = buffered_free(buffered_total(cai, 0.2, 0.001) + dtd * e(rCai, 0), 0.2, 0.001);
+    c[1] = buffered_free(buffered_total(casr, 10.0, 0.3) + dtd * e(rCasr, 1), 10.0, 0.3);
+    c[2] = buffered_free(buffered_total(cass, 0.4, 0.00025) + dtd * e(rCass, 2), 0.4, 0.00025);
+    c[3] = nai + dtd * e(rNai, 3);
+    c[4] = ki + dtd * e(rKi, 4);
     return Iion;
 }
 }  // namespace tp06
@@ -278,9 +295,9 @@ __host__ __device__ inline void init(double *y) {
     for (int i = 0; i < 21; ++i) y[i] = s[i];
 }
 
-template <typename R>
+template <typename R, typename E = FwdEuler>
 __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
-                                  const GScale &gs) {
+                                  const GScale &gs, const E &e = E()) {
     const R frt = R(1.0 / RTF), rtf = R(RTF);
     const double cai = c[0], caup = c[1], carel = c[2], nai = c[3], ki = c[4];
     const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
@@ -410,11 +427,11 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
         const R k = R(5.0 / 6.0) * z_expm1(-z) * (R(1) + R(0.3) * xexp(-z));
         g[14] = rl(w, R(1) - sig((V - R(40)) * R(-1.0 / 17.0)), k, dt);
     }
-    c[0] = cai + dtd * rCai;
-    c[1] = caup + dtd * rCaup;
-    c[2] = carel + dtd * rCarel;
-    c[3] = nai + dtd * rNai;
-    c[4] = ki + dtd * rKi;
+    c[0] = cai + dtd * e(rCai, 0);
+    c[1] = caup + dtd * e(rCaup, 1);
+    c[2] = carel + dtd * e(rCarel, 2);
+    c[3] = nai + dtd * e(rNai, 3);
+    c[4] = ki + dtd * e(rKi, 4);
     return Iion;
 }
 }  // namespace crn
@@ -446,9 +463,9 @@ __host__ __device__ inline void init(double *y) {
     for (int i = 0; i < 20; ++i) y[i] = s[i];
 }
 
-template <typename R>
+template <typename R, typename E = FwdEuler>
 __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
-                                  R istim, const GScale &gs) {
+                                  R istim, const GScale &gs, const E &e = E()) {
     const R frt = R(1.0 / RTF), rtf = R(RTF);
     const double rbar = c[0], cai = c[1], casr = c[2], cass = c[3], nai = c[4], ki = c[5];
     const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
@@ -579,12 +596,12 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
         const R k = (xexp(R(-2.9) - R(0.04) * V) + xexp(R(3.6) + R(0.11) * V)) * R(1.0 / 4000.0);
         g[12] = rl(y, sig((V + R(80.6)) * R(1.0 / 6.8)), k, dt);
     }
-    c[0] = rbar + dtd * rRbar;
-    c[1] = buffered_free(buffered_total(cai, 0.2, 0.001) + dtd * rCai, 0.2, 0.001);
-    c[2] = buffered_free(buffered_total(casr, 10.0, 0.3) + dtd * rCasr, 10.0, 0.3);
-    c[3] = buffered_free(buffered_total(cass, 0.4, 0.00025) + dtd * rCass, 0.4, 0.00025);
-    c[4] = nai + dtd * rNai;
-    c[5] = ki + dtd * rKi;
+    c[0] = rbar + dtd * e(rRbar, 0);
+    c[1] = buffered_free(buffered_total(cai, 0.2, 0.001) + dtd * e(rCai, 1), 0.2, 0.001);
+    c[2] = buffered_free(buffered_total(casr, 10.0, 0.3) + dtd * e(rCasr, 2), 10.0, 0.3);
+    c[3] = buffered_free(buffered_total(cass, 0.4, 0.00025) + dtd * e(rCass, 3), 0.4, 0.00025);
+    c[4] = nai + dtd * e(rNai, 4);
+    c[5] = ki + dtd * e(rKi, 5);
     return Iion;
 }
 }  // namespace stewart

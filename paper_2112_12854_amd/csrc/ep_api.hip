@@ -19,7 +19,7 @@ using ep::model_ng;
 
 namespace {
 
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b35ULL;   // "EPSMCHK5"
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b36ULL;   // "EPSMCHK6"
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
@@ -243,12 +243,23 @@ ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t r
         restart < 1 || restart > 1000 || !(tol > 0) || max_iter < 1)
         return fail(s, EP_EINVAL, "bad bidomain parameters");
     ep::InstSpec &sp = s->spec;
+    if (sp.ab2) return fail(s, EP_EINVAL, "the bidomain model steps by forward Euler only");
     sp.bido = true;
     sp.sigma_el = sigma_el;
     sp.sigma_et = sigma_et;
     sp.bido_restart = restart;
     sp.bido_tol = tol;
     sp.bido_max_iter = max_iter;
+    return EP_OK;
+}
+
+ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "the scheme is frozen after ep_init");
+    if (scheme != EP_SCHEME_FE && scheme != EP_SCHEME_AB2) return fail(s, EP_EINVAL, "unknown time scheme");
+    if (scheme == EP_SCHEME_AB2 && s->spec.bido)
+        return fail(s, EP_EINVAL, "the bidomain model steps by forward Euler only");
+    s->spec.ab2 = scheme == EP_SCHEME_AB2;
     return EP_OK;
 }
 
@@ -559,6 +570,7 @@ struct CkptHeader {
     int32_t rs, n_pmj;
     int64_t trace_cap, n_purkinje;
     int64_t bidomain;
+    int64_t time_scheme;
 };
 
 static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
@@ -571,6 +583,10 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
         {D.trace, (size_t)s->inst.trace_cap * 8}, {D.part, (size_t)D.n_cell_tiles * 8},
         {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
     if (s->inst.bido) a.push_back({s->inst.bd.phi, nc * 8});
+    if (s->inst.ab2) {
+        a.push_back({D.hv, nc * r});
+        a.push_back({D.hc, NC_MAX * nc * 8});
+    }
     if (s->inst.pk.n > 0) {
         const epdev::PurkDesc &P = s->inst.pdesc;
         const size_t np = P.np;
@@ -581,6 +597,10 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
         a.push_back({P.pstat, np});
         a.push_back({P.pt_act, np * 8});
         a.push_back({P.pmj, std::max<size_t>(P.n_pmj, 1) * sizeof(epdev::Pmj)});
+        if (s->inst.ab2) {
+            a.push_back({P.hv, np * r});
+            a.push_back({P.hc, NC_MAX * np * 8});
+        }
     }
     return a;
 }
@@ -601,7 +621,8 @@ ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes) {
     if (!buf || bytes < need) return fail(s, EP_EINVAL, "checkpoint buffer too small");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     CkptHeader h{CKPT_MAGIC, s->inst.desc.nc, s->inst.desc.nn, s->inst.host_step, s->inst.rs,
-                 (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n, s->inst.bido ? 1 : 0};
+                 (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n, s->inst.bido ? 1 : 0,
+                 s->inst.ab2 ? 1 : 0};
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
@@ -621,7 +642,8 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes) {
     std::memcpy(&h, buf, sizeof(h));
     if (h.magic != CKPT_MAGIC || h.n_tets != s->inst.desc.nc || h.n_nodes != s->inst.desc.nn ||
         h.rs != s->inst.rs || h.trace_cap != s->inst.trace_cap || h.n_purkinje != s->inst.pk.n ||
-        h.n_pmj != (int32_t)s->inst.n_pmj || h.bidomain != (s->inst.bido ? 1 : 0))
+        h.n_pmj != (int32_t)s->inst.n_pmj || h.bidomain != (s->inst.bido ? 1 : 0) ||
+        h.time_scheme != (s->inst.ab2 ? 1 : 0))
         return fail(s, EP_EINVAL, "checkpoint does not match this simulation");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const char *p = (const char *)buf + sizeof(h);
@@ -670,9 +692,14 @@ ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes, double *cell
     if (node_bytes) *node_bytes = 4.0 * nc * (4.0 + r) + nc * r + nn * r + 8.0 * s->inst.n_slices;
     // cell kernel: stencil (8 node ids + 8 coefficients + 4 neighbours + 4
     // coefficients), vn once, v^n once, v^{n+1} write, model byte, state
-    // read+write, detection status byte
+    // read+write, detection status byte; with Adams-Bashforth 2 the previous
+    // rates of v and of the non-gating states, read and written (none are
+    // read on step 0)
     double b = nc * (8 * 4.0 + 8 * r + 4 * 4.0 + 4 * r + r + r + 1.0 + 1.0) + nn * r;
-    for (uint8_t m : s->inst.prep.model) b += 2.0 * (model_ng(m) * r + model_nc(m) * 8.0);
+    for (uint8_t m : s->inst.prep.model) {
+        b += 2.0 * (model_ng(m) * r + model_nc(m) * 8.0);
+        if (s->inst.ab2) b += 2.0 * (r + model_nc(m) * 8.0);
+    }
     if (cell_bytes) *cell_bytes = b;
     return EP_OK;
 }

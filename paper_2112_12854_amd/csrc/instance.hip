@@ -62,6 +62,13 @@ bool up(Inst &in, void **dst, const std::vector<T> &src) {
     return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
 }
 
+// Zero-filled device array (set-up only: a synchronous fill).
+void *zalloc(Inst &in, size_t bytes) {
+    void *p = dalloc(in, bytes);
+    if (p && hipMemset(p, 0, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
 template <typename R>
 std::vector<R> conv(const std::vector<double> &v) {
     return std::vector<R>(v.begin(), v.end());
@@ -197,6 +204,7 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
         pin.chi = sp.chi;
         pin.cm = sp.cm;
         pin.n_sub = sp.purk.n_sub;
+        pin.ab2 = sp.ab2;
         pin.pmjs = sp.purk.pmjs;
         e = prepare_purkinje(pin, in, I.prep, I.pk);
         if (!e.empty()) { st = EP_EINVAL; return e; }
@@ -245,6 +253,10 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
         if (na > 0)
             b += 2 * round256(c * 4) + round256((na + 1) * 4) + round256(c * 8) +
                  round256(na * na * 8) + 2 * round256(c * 8) + 2 * round256(na * 8);
+    }
+    if (sp.ab2) {
+        b += round256(c * r) + round256(NC_MAX * c * 8);
+        if (I.pk.n > 0) b += round256((size_t)I.pk.n * r) + round256(NC_MAX * (size_t)I.pk.n * 8);
     }
     return b + purkinje_bytes(I, rs);
 }
@@ -327,6 +339,11 @@ std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) 
     P.model = I.pmodel;
     P.tv[0] = I.desc.v[0];
     P.tv[1] = I.desc.v[1];
+    if (sp.ab2) {
+        P.hv = zalloc(I, (size_t)np * rs);
+        P.hc = (double *)zalloc(I, NC_MAX * (size_t)np * 8);
+        if (!P.hv || !P.hc) return fail_mem();
+    }
     P.ctrl = I.d_ctrl;
     P.dtp = sp.dt / K.n_sub;
     P.thr = sp.thr;
@@ -470,6 +487,12 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     }
     D.ctrl = I.d_ctrl;
     I.host_step = 0;
+    I.ab2 = sp.ab2;
+    if (sp.ab2) {
+        D.hv = zalloc(I, nc * (size_t)rs);
+        D.hc = (double *)zalloc(I, NC_MAX * nc * 8);
+        if (!D.hv || !D.hc) return fail_mem();
+    }
     I.bido = sp.bido;
     if (sp.bido) {
         Bido &B = I.bd;
@@ -557,23 +580,29 @@ Tables tables(const Stepper &s) {
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
 // Cell kernels of step offset `off`, one launch per model class present.
-template <typename R, bool BIDO>
+template <typename R, bool BIDO, bool AB2>
 void launch_cells_v(Stepper &s, const Tables &tb, int32_t off) {
     Tables t[4] = {tb, tb, tb, tb};
     for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + s.cls_base[k];
-    if (s.cls_tiles[0]) k_cell<R, 1, BIDO><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
-    if (s.cls_tiles[1]) k_cell<R, 2, BIDO><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
-    if (s.cls_tiles[2]) k_cell<R, 4, BIDO><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
-    if (s.cls_tiles[3]) k_cell<R, 8, BIDO><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
+    if (s.cls_tiles[0])
+        k_cell<R, 1, BIDO, AB2><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
+    if (s.cls_tiles[1])
+        k_cell<R, 2, BIDO, AB2><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
+    if (s.cls_tiles[2])
+        k_cell<R, 4, BIDO, AB2><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
+    if (s.cls_tiles[3])
+        k_cell<R, 8, BIDO, AB2><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
 }
 
-// bidomain instances run in FP64 only (checked at creation)
+// bidomain instances run in FP64 with forward Euler only (checked at
+// creation); Adams-Bashforth 2 applies to every instance of a stepper or none
 template <typename R>
 void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
     if constexpr (sizeof(R) == 8) {
-        if (s.bido) { launch_cells_v<R, true>(s, tb, off); return; }
+        if (s.bido) { launch_cells_v<R, true, false>(s, tb, off); return; }
     }
-    launch_cells_v<R, false>(s, tb, off);
+    if (s.ab2) launch_cells_v<R, false, true>(s, tb, off);
+    else launch_cells_v<R, false, false>(s, tb, off);
 }
 
 template <typename R>
@@ -595,8 +624,10 @@ void launch_step(Stepper &s, int32_t off) {
 template <typename R>
 void launch_purkinje(Stepper &s, int32_t off) {
     const Tables tb = tables(s);
-    for (int32_t sub = 0; sub < s.n_sub_max; ++sub)
-        k_purkinje<R><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+    for (int32_t sub = 0; sub < s.n_sub_max; ++sub) {
+        if (s.ab2) k_purkinje<R, true><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+        else k_purkinje<R, false><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+    }
     k_junctions<R><<<(int)s.n_pk, TILE, 0, s.stream>>>(tb, off);
 }
 
@@ -653,7 +684,11 @@ std::string stepper_sync_tables(Stepper &s) {
     std::vector<PurkDesc> pk;
     int32_t nsub = 0;
     s.bido = false;
-    for (const Inst *I : s.insts) s.bido = s.bido || I->bido;
+    s.ab2 = false;
+    for (const Inst *I : s.insts) {
+        s.bido = s.bido || I->bido;
+        s.ab2 = s.ab2 || I->ab2;
+    }
     // cell tiles class by class; tile `local` numbers run over the instance
     std::vector<int32_t> next_local(s.insts.size(), 0);
     for (int k = 0; k < 4; ++k) {

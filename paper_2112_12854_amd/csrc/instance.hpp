@@ -52,6 +52,9 @@ struct InstSpec {
     double sigma_el = 0.62, sigma_et = 0.24, bido_tol = 1e-6;
     int32_t bido_restart = 30, bido_max_iter = 2000;
     int32_t bido_coarse = 2048;        // aggregates of the preconditioner (0: none)
+    // non-gating states (v, concentrations) by Adams-Bashforth 2 instead of
+    // forward Euler; gates stay Rush-Larsen
+    bool ab2 = false;
 };
 
 // Device arrays of the extracellular solve of one bidomain instance.
@@ -117,6 +120,7 @@ struct Inst {
     bool bido = false;
     Bido bd;
     Coarse coarse;                     // host copy until upload
+    bool ab2 = false;                  // Adams-Bashforth 2 history allocated
 };
 
 // Host precompute only (thread-safe, no HIP calls).
@@ -166,6 +170,7 @@ struct Stepper {
     int64_t n_ct = 0, n_nt = 0, n_pt = 0, n_pk = 0;
     int32_t n_sub_max = 0;             // graph substeps per step (max over instances)
     bool bido = false;                 // the (single) instance is a bidomain one
+    bool ab2 = false;                  // instances step by Adams-Bashforth 2 (all or none)
     // pinned staging of the tables
     void *h_stage = nullptr;
     size_t stage_bytes = 0;

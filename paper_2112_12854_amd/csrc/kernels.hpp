@@ -86,6 +86,11 @@ struct InstDesc {
     const int32_t *cpmj;          // [nc]: -1 or start of a -1-terminated list
     const int32_t *cpmj_list;
     const Pmj *pmj;
+    // Adams-Bashforth 2 for the non-gating states (null: forward Euler):
+    // the previous step's rate of v (R, [nc]) and of the model's non-gating
+    // states (FP64, [NC_MAX][nc])
+    void *hv;
+    double *hc;
 };
 
 // A Purkinje graph (vertex-centred finite volumes on a 1D graph) coupled to
@@ -109,6 +114,8 @@ struct PurkDesc {
     Ctrl *ctrl;
     double dtp, thr;
     GScale gs;
+    void *hv;                     // Adams-Bashforth 2 history, as in InstDesc
+    double *hc;
 };
 
 // A tile carries a copy of its instance's descriptor, so a block reaches
@@ -314,48 +321,78 @@ __device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, int64_t n, 
 // Rush-Larsen, FP64 concentrations by forward Euler, all from level-n values.
 // Returns I_ion at level n (0 for passive cells).
 // MSET: bit 0 TP06 (any layer), 1 CRN, 2 Stewart, 3 passive.
-template <typename R, int MSET>
+// One cell model over one step: load its gates and non-gating states (and,
+// with AB2, the previous rates of the latter), step, store.
+template <typename R, int NG, int NC, bool AB2, typename F>
+__device__ __forceinline__ R model_io(__amdgpu_buffer_rsrc_t rgate, __amdgpu_buffer_rsrc_t rconc,
+                                      __amdgpu_buffer_rsrc_t rhist, int64_t N, uint32_t c,
+                                      bool first, F &&fn) {
+    R g[NG_MAX];
+    double cc[NC_MAX], hh[NC_MAX];
+#pragma unroll
+    for (int s = 0; s < NG; ++s) g[s] = sld<R>(rgate, s, N, c);
+#pragma unroll
+    for (int s = 0; s < NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+    R iion;
+    if constexpr (AB2) {
+        if (!first) {
+#pragma unroll
+            for (int s = 0; s < NC; ++s) hh[s] = sld<double>(rhist, s, N, c);
+        }
+        iion = fn(g, cc, AdamsBashforth2{hh, first});
+#pragma unroll
+        for (int s = 0; s < NC; ++s) sst<double>(rhist, s, N, c, hh[s]);
+    } else {
+        iion = fn(g, cc, FwdEuler{});
+    }
+#pragma unroll
+    for (int s = 0; s < NG; ++s) sst<R>(rgate, s, N, c, g[s]);
+#pragma unroll
+    for (int s = 0; s < NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+    return iion;
+}
+
+template <typename R, int MSET, bool AB2 = false>
 __device__ __forceinline__ R ionic(int md, R v, __amdgpu_buffer_rsrc_t rgate,
                                    __amdgpu_buffer_rsrc_t rconc, int64_t N, uint32_t c, R dt,
-                                   double dtd, R istim, const GScale &gs) {
+                                   double dtd, R istim, const GScale &gs,
+                                   __amdgpu_buffer_rsrc_t rhist = rsrc(nullptr),
+                                   bool first = false) {
     R iion = R(0);
-    R g[NG_MAX];
-    double cc[NC_MAX];
     if ((MSET & 1) && md <= 2) {
-#pragma unroll
-        for (int s = 0; s < tp06::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
-#pragma unroll
-        for (int s = 0; s < tp06::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
-        iion = tp06::step<R>(md, v, g, cc, dt, dtd, istim, gs);
-#pragma unroll
-        for (int s = 0; s < tp06::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
-#pragma unroll
-        for (int s = 0; s < tp06::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+        iion = model_io<R, tp06::NG, tp06::NC, AB2>(
+            rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
+                return tp06::step<R>(md, v, g, cc, dt, dtd, istim, gs, e);
+            });
     } else if ((MSET & 2) && md == 3) {
-#pragma unroll
-        for (int s = 0; s < crn::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
-#pragma unroll
-        for (int s = 0; s < crn::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
-        iion = crn::step<R>(v, g, cc, dt, dtd, gs);
-#pragma unroll
-        for (int s = 0; s < crn::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
-#pragma unroll
-        for (int s = 0; s < crn::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+        iion = model_io<R, crn::NG, crn::NC, AB2>(
+            rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
+                return crn::step<R>(v, g, cc, dt, dtd, gs, e);
+            });
     } else if ((MSET & 4) && md == 4) {
-#pragma unroll
-        for (int s = 0; s < stewart::NG; ++s) g[s] = sld<R>(rgate, s, N, c);
-#pragma unroll
-        for (int s = 0; s < stewart::NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
-        iion = stewart::step<R>(v, g, cc, dt, dtd, istim, gs);
-#pragma unroll
-        for (int s = 0; s < stewart::NG; ++s) sst<R>(rgate, s, N, c, g[s]);
-#pragma unroll
-        for (int s = 0; s < stewart::NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+        iion = model_io<R, stewart::NG, stewart::NC, AB2>(
+            rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
+                return stewart::step<R>(v, g, cc, dt, dtd, istim, gs, e);
+            });
     }
     return iion;
 }
 
-template <typename R, int MSET, bool BIDO>
+// v^{n+1} from v^n and its rate: forward Euler, or Adams-Bashforth 2 with
+// the previous rate in hv[i] (forward Euler on the first step).
+template <typename R, bool AB2>
+__device__ __forceinline__ R v_update(R v, R dt, R F, void *hv, uint32_t i, bool first) {
+    if constexpr (AB2) {
+        R *h = (R *)hv;
+        const R p = first ? F : h[i];
+        h[i] = F;
+        return v + dt * (R(1.5) * F - R(0.5) * p);
+    } else {
+        return v + dt * F;
+    }
+}
+
+template <typename R, int MSET, bool BIDO, bool AB2>
 __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
                                           uint32_t active, bool sample, double &vol_v) {
     const int64_t N = D.nc;
@@ -407,10 +444,15 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     // ---- cell model
     const int md = (MSET == 8) ? 5 : at(D.model, c);   // TP06 layer or model id
     const R dt = R(D.dt);
-    const R iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim, D.gs);
+    R iion;
+    if constexpr (AB2)
+        iion = ionic<R, MSET, true>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim,
+                                    D.gs, rsrc(D.hc), n == 0);
+    else
+        iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim, D.gs);
 
     // ---- explicit update of v
-    const R vnew = v + dt * (L - iion - istim);
+    const R vnew = v_update<R, AB2>(v, dt, L - iion - istim, D.hv, c, n == 0);
     at(vout, c) = vnew;
     if (!(fabs(vnew) < R(1e30))) atomicOr(&D.ctrl->nan_flag, 1);
     if (sample) vol_v = at(D.vol, c) * double(vnew);
@@ -440,7 +482,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 
 // One launch per model class: the host passes tb.cell_tiles pointing at the
 // first tile of the class in the class-ordered tile list.
-template <typename R, int MSET, bool BIDO = false>
+template <typename R, int MSET, bool BIDO = false, bool AB2 = false>
 __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
     __shared__ double red[TILE];
     const Tile &T = tb.cell_tiles[my_tile(remap)];
@@ -451,7 +493,7 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
     double x = 0.0;
     const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
     if ((int32_t)threadIdx.x < T.count)
-        cell_step<R, MSET, BIDO>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
+        cell_step<R, MSET, BIDO, AB2>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
     if (sample) tile_partial(D, T, x, red);
 }
 
@@ -459,7 +501,7 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
 // Substep `sub` of step n of every graph: explicit update of node i with the
 // graph flux, the stimuli of the graph and of its two-way junctions, and the
 // node's cell model over dt / n_sub; first upward threshold crossing.
-template <typename R>
+template <typename R, bool AB2 = false>
 __global__ void __launch_bounds__(TILE) k_purkinje(Tables tb, int32_t step_off, int32_t sub) {
     const PTile &T = tb.purk_tiles[blockIdx.x];
     const PurkDesc &P = T.p;
@@ -489,8 +531,14 @@ __global__ void __launch_bounds__(TILE) k_purkinje(Tables tb, int32_t step_off, 
             if (n >= J.fire_a && n < J.fire_a + J.ndur) istim += R(J.amp);
         }
     const R dt = R(P.dtp);
-    const R iion = ionic<R, 15>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp, istim, P.gs);
-    const R vnew = v + dt * (L - iion - istim);
+    R iion;
+    if constexpr (AB2)
+        iion = ionic<R, 15, true>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp,
+                                  istim, P.gs, rsrc(P.hc), q == 0);
+    else
+        iion = ionic<R, 15>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp, istim,
+                            P.gs);
+    const R vnew = v_update<R, AB2>(v, dt, L - iion - istim, P.hv, i, q == 0);
     vout[i] = vnew;
     if (!(fabs(vnew) < R(1e30))) atomicOr(&P.ctrl->nan_flag, 1);
     const R thr = R(P.thr);

@@ -71,6 +71,7 @@ struct PurkIn {
     const double *edge_scale = nullptr;  // [n_edges] conductivity multipliers >= 0, or null
     double sigma = 3.95, dt = 0.02, chi = 140.0, cm = 0.01;
     int32_t n_sub = 0;                 // <= 0: derived from the stability bound
+    bool ab2 = false;                  // Adams-Bashforth 2: half the stable interval
     std::vector<PmjIn> pmjs;
 };
 

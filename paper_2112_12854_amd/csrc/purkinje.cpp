@@ -83,11 +83,13 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
         if (inv > 0) dtmax = std::min(dtmax, in.chi * in.cm * ell / (in.sigma * inv));
     }
     // explicit substeps: 90 % of the Gershgorin bound of the graph operator
-    // (nodes cut off by blocked segments on every side impose none)
+    // (nodes cut off by blocked segments on every side impose none); the
+    // Adams-Bashforth 2 interval on the negative real axis is half as long
     int32_t ns = in.n_sub;
     if (ns <= 0) {
+        const double lim = (in.ab2 ? 0.45 : 0.9) * dtmax;
         ns = 1;
-        while (in.dt / ns > 0.9 * dtmax) {
+        while (in.dt / ns > lim) {
             if (++ns > 100000) return "Purkinje graph needs more than 1e5 substeps";
         }
     }

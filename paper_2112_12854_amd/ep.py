@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libep.so")
 
 EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ESTATE, EP_ENUMERIC, EP_EBUSY = 0, -1, -2, -3, -4, -5, -6
 EP_FP64, EP_FP32_MIXED = 0, 1
+EP_SCHEME_FE, EP_SCHEME_AB2 = 0, 1
 EP_TP06_ENDO, EP_TP06_MID, EP_TP06_EPI, EP_CRN, EP_STEWART, EP_PASSIVE = range(6)
 EP_MAX_SLOTS = 21
 STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EDEVICE",
@@ -103,6 +104,7 @@ _SIGS = {
     "ep_set_purkinje": (C.c_int, [C.c_void_p, C.c_int64, _dp, C.c_int64, _ip, C.c_double,
                                   C.c_int32, C.c_int32]),
     "ep_set_purkinje_scale": (C.c_int, [C.c_void_p, C.c_int64, _dp]),
+    "ep_set_time_scheme": (C.c_int, [C.c_void_p, C.c_int32]),
     "ep_add_pmj": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
                              C.c_int32, C.c_double, C.c_double]),
     "ep_get_purkinje_vm": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
@@ -271,6 +273,8 @@ class Sim:
             ids = np.ascontiguousarray(st.ids, np.int32)
             _check(L.ep_add_stimulus(h, st.domain, ids.size, ids.ctypes.data_as(_ip),
                                      st.t0, st.dur, st.amp, st.period, st.count), h)
+        if getattr(w, "time_scheme", 0):
+            _check(L.ep_set_time_scheme(h, int(w.time_scheme)), h)
         bd = getattr(w, "bidomain", None)
         self.bidomain = bd is not None
         if bd is not None:
