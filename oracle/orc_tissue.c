@@ -44,6 +44,7 @@ struct orc_sim {
     double sigma_l, sigma_t, dt, chi, cm;
     /* geometry */
     double *vol, *cen, *S;      /* S[(c*4+j)*3+k] outward area vector      */
+    double *Sf;                 /* the area vector of the face's flux       */
     int32_t *nbr;               /* nbr[c*4+j], -1 boundary                 */
     int64_t *inc_off;           /* node -> cells                           */
     int32_t *inc_cell;
@@ -204,28 +205,90 @@ static int tet_has_node(const int32_t *t, int32_t n)
     return t[0] == n || t[1] == n || t[2] == n || t[3] == n;
 }
 
+/* vertices of cell c: 4 for a tetrahedron, 3 for a triangle of a 2D medium
+ * (fourth node -1) */
+static int nverts(const orc_sim *s, int64_t c) { return s->tet[4 * c + 3] < 0 ? 3 : 4; }
+
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Triangle c of a 2D medium (the paper's cell-centred FV on triangles,
+ * Sec. 3.2): area, and per edge j (opposite vertex j) the in-plane outward
+ * normal scaled by the edge length, the 2D counterpart of a face area
+ * vector. */
+static void triangle_geometry(orc_sim *s, int64_t c, const double *p[3])
+{
+    double u[3], v[3], N[3];
+    sub3(p[1], p[0], u);
+    sub3(p[2], p[0], v);
+    cross3(u, v, N);
+    const double twice = norm3(N);
+    s->vol[c] = 0.5 * twice;
+    for (int a = 0; a < 3; ++a) N[a] /= twice;
+    for (int j = 0; j < 3; ++j) {
+        const double *a0 = p[(j + 1) % 3], *a1 = p[(j + 2) % 3];
+        double t[3], S[3], out[3];
+        sub3(a1, a0, t);
+        cross3(t, N, S);                     /* |S| = |t|, in the plane */
+        sub3(a0, p[j], out);
+        const double sg = dot3(S, out) > 0.0 ? 1.0 : -1.0;
+        for (int a = 0; a < 3; ++a) s->S[(c * 4 + j) * 3 + a] = sg * S[a];
+    }
+    for (int a = 0; a < 3; ++a) s->S[(c * 4 + 3) * 3 + a] = 0.0;
+}
+
 static void build_geometry(orc_sim *s)
 {
     const int64_t nc = s->nc, nn = s->nn;
     /* node -> incident cells (cells listed in increasing id order) */
     s->inc_off = calloc((size_t)nn + 1, sizeof(int64_t));
     for (int64_t c = 0; c < nc; ++c)
-        for (int k = 0; k < 4; ++k) s->inc_off[s->tet[4 * c + k] + 1]++;
+        for (int k = 0; k < nverts(s, c); ++k) s->inc_off[s->tet[4 * c + k] + 1]++;
     for (int64_t n = 0; n < nn; ++n) s->inc_off[n + 1] += s->inc_off[n];
     s->inc_cell = malloc(sizeof(int32_t) * (size_t)(4 * nc));
     int64_t *fill = malloc(sizeof(int64_t) * (size_t)nn);
     memcpy(fill, s->inc_off, sizeof(int64_t) * (size_t)nn);
     for (int64_t c = 0; c < nc; ++c)
-        for (int k = 0; k < 4; ++k) s->inc_cell[fill[s->tet[4 * c + k]]++] = (int32_t)c;
+        for (int k = 0; k < nverts(s, c); ++k) s->inc_cell[fill[s->tet[4 * c + k]]++] = (int32_t)c;
     free(fill);
 
     s->vol = malloc(sizeof(double) * (size_t)nc);
     s->cen = malloc(sizeof(double) * (size_t)nc * 3);
     s->S = malloc(sizeof(double) * (size_t)nc * 12);
+    s->Sf = malloc(sizeof(double) * (size_t)nc * 12);
     s->nbr = malloc(sizeof(int32_t) * (size_t)nc * 4);
+
+    /* triangles: geometry and edge neighbours (the other triangle holding
+     * both edge vertices) */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        if (nverts(s, c) != 3) continue;
+        const int32_t *t = s->tet + 4 * c;
+        const double *p[3];
+        for (int k = 0; k < 3; ++k) p[k] = s->xyz + 3 * (int64_t)t[k];
+        for (int a = 0; a < 3; ++a) s->cen[3 * c + a] = (p[0][a] + p[1][a] + p[2][a]) / 3.0;
+        triangle_geometry(s, c, p);
+        for (int j = 0; j < 3; ++j) {
+            const int32_t na = t[(j + 1) % 3], nb = t[(j + 2) % 3];
+            int32_t found = -1;
+            for (int64_t i = s->inc_off[na]; i < s->inc_off[na + 1]; ++i) {
+                const int32_t k = s->inc_cell[i];
+                if (k == (int32_t)c || nverts(s, k) != 3) continue;
+                const int32_t *tk = s->tet + 4 * (int64_t)k;
+                if (tk[0] == nb || tk[1] == nb || tk[2] == nb) { found = k; break; }
+            }
+            s->nbr[4 * c + j] = found;
+        }
+        s->nbr[4 * c + 3] = -1;
+    }
 
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
+        if (nverts(s, c) != 4) continue;
         const int32_t *t = s->tet + 4 * c;
         const double *p[4];
         for (int k = 0; k < 4; ++k) p[k] = s->xyz + 3 * (int64_t)t[k];
@@ -263,6 +326,33 @@ static void build_geometry(orc_sim *s)
                 if (tet_has_node(tk, nb) && tet_has_node(tk, nd)) { found = k; break; }
             }
             s->nbr[4 * c + j] = found;
+        }
+    }
+
+    /* flux area vectors: a tetrahedron's own; across an edge between two
+     * triangles (not coplanar on a curved surface) the edge length times the
+     * unit bisector of the two outward in-plane normals, shared with opposite
+     * signs so that the flux is conservative */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        for (int j = 0; j < 4; ++j)
+            for (int a = 0; a < 3; ++a) s->Sf[(c * 4 + j) * 3 + a] = s->S[(c * 4 + j) * 3 + a];
+        if (nverts(s, c) != 3) continue;
+        const int32_t *t = s->tet + 4 * c;
+        for (int j = 0; j < 3; ++j) {
+            const int32_t c2 = s->nbr[4 * c + j];
+            if (c2 < 0) continue;
+            /* the neighbour's edge with the same two vertices */
+            const int32_t *t2 = s->tet + 4 * (int64_t)c2;
+            int j2 = 0;
+            for (int k = 0; k < 3; ++k)
+                if (t2[k] != t[(j + 1) % 3] && t2[k] != t[(j + 2) % 3]) j2 = k;
+            const double *S1 = s->S + (c * 4 + j) * 3, *S2 = s->S + (c2 * 4 + j2) * 3;
+            const double l = norm3(S1), l2 = norm3(S2);
+            double b[3];
+            for (int a = 0; a < 3; ++a) b[a] = S1[a] / l - S2[a] / l2;
+            const double nb = norm3(b);
+            for (int a = 0; a < 3; ++a) s->Sf[(c * 4 + j) * 3 + a] = l * b[a] / nb;
         }
     }
 
@@ -308,11 +398,13 @@ static void gradients_from_nodes(const orc_sim *s, const double *vn, double *g)
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < s->nc; ++c) {
         const int32_t *t = s->tet + 4 * c;
+        const int nv = nverts(s, c);
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < nv; ++j) {
+            /* face (edge) value: mean of its vertices' node values */
             double vf = 0.0;
-            for (int k = 0; k < 4; ++k) if (k != j) vf += vn[t[k]];
-            vf /= 3.0;
+            for (int k = 0; k < nv; ++k) if (k != j) vf += vn[t[k]];
+            vf /= (double)(nv - 1);
             for (int a = 0; a < 3; ++a) acc[a] += vf * s->S[(c * 4 + j) * 3 + a];
         }
         for (int a = 0; a < 3; ++a) g[3 * c + a] = acc[a] / s->vol[c];
@@ -335,15 +427,16 @@ static double flux_sum(const orc_sim *s, int64_t c, const double *v, const doubl
     double Mc[3][3];
     cell_tensor_of(s, c, sl, st, Mc);
     const int32_t *t = s->tet + 4 * c;
+    const int nv = nverts(s, c);
     double total = 0.0;
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < nv; ++j) {
         const int32_t c2 = s->nbr[4 * c + j];
         if (c2 < 0) continue;                      /* no-flux boundary */
-        /* face centroid */
+        /* face centroid (edge midpoint) */
         double xf[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < nv; ++k)
             if (k != j)
-                for (int a = 0; a < 3; ++a) xf[a] += s->xyz[3 * (int64_t)t[k] + a] / 3.0;
+                for (int a = 0; a < 3; ++a) xf[a] += s->xyz[3 * (int64_t)t[k] + a] / (double)(nv - 1);
         const double *x1 = s->cen + 3 * c, *x2 = s->cen + 3 * (int64_t)c2;
         double r1[3], r2[3], dd[3];
         sub3(x1, xf, r1); sub3(x2, xf, r2); sub3(x2, x1, dd);
@@ -361,7 +454,7 @@ static double flux_sum(const orc_sim *s, int64_t c, const double *v, const doubl
         /* face tensor and flux */
         double M2[3][3];
         cell_tensor_of(s, c2, sl, st, M2);
-        const double *Sf = s->S + (c * 4 + j) * 3;
+        const double *Sf = s->Sf + (c * 4 + j) * 3;
         double flux = 0.0;
         for (int a = 0; a < 3; ++a) {
             double Mg = 0.0;
@@ -460,7 +553,7 @@ orc_sim *orc_create(int64_t n_nodes, const double *xyz, int64_t n_tets,
 void orc_destroy(orc_sim *s)
 {
     if (!s) return;
-    free(s->xyz); free(s->tet); free(s->fib); free(s->scale); free(s->model);
+    free(s->xyz); free(s->tet); free(s->fib); free(s->scale); free(s->model); free(s->Sf);
     free(s->vol); free(s->cen); free(s->S); free(s->nbr);
     free(s->inc_off); free(s->inc_cell); free(s->inc_w);
     free(s->y); free(s->vn); free(s->g); free(s->L); free(s->istim);
@@ -692,8 +785,8 @@ int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
         for (int64_t c = 0; c < s->nc; ++c) {
             const int32_t *u = s->tet + 4 * c;
             int share = 0;
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b) share |= (t[a] == u[b]);
+            for (int a = 0; a < nverts(s, best); ++a)
+                for (int b = 0; b < nverts(s, c); ++b) share |= (t[a] == u[b]);
             if (share) J->cells[J->n_cells++] = (int32_t)c;
         }
     }

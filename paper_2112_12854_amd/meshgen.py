@@ -136,6 +136,82 @@ def slab(nx: int, ny: int, nz: int, h: float):
     return xyz, tets, hex_ijk
 
 
+def sheet(nx: int, ny: int, h: float, curvature_radius: float = 0.0):
+    """Triangulated sheet (a 2D medium, Sec. 3.2): the rectangle [0, nx h] x
+    [0, ny h] of squares of side h, each split into two triangles along the
+    diagonal that alternates with the parity of i + j (nodes numbered
+    i-major, id = i (ny+1) + j).  With curvature_radius R > 0 the sheet is
+    bent around the x axis onto a cylinder of radius R (y becomes arc
+    length).  Cells are returned as [n, 4] rows whose fourth entry is -1, the
+    library's mark of a triangle; also returns the square (i, j) of each."""
+    ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="ij")
+    x = (ii * h).ravel().astype(np.float64)
+    y = (jj * h).ravel().astype(np.float64)
+    if curvature_radius > 0:
+        R = curvature_radius
+        xyz = np.stack([x, R * np.sin(y / R), R - R * np.cos(y / R)], axis=1)
+    else:
+        xyz = np.stack([x, y, np.zeros_like(x)], axis=1)
+
+    def nid(i, j):
+        return i * (ny + 1) + j
+
+    si, sj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    si, sj = si.ravel(), sj.ravel()
+    a, b, c, d = nid(si, sj), nid(si + 1, sj), nid(si + 1, sj + 1), nid(si, sj + 1)
+    even = ((si + sj) % 2) == 0
+    t1 = np.where(even[:, None], np.stack([a, b, c], 1), np.stack([a, b, d], 1))
+    t2 = np.where(even[:, None], np.stack([a, c, d], 1), np.stack([b, c, d], 1))
+    tri = np.stack([t1, t2], axis=1).reshape(-1, 3)
+    cells = np.concatenate([tri, -np.ones((tri.shape[0], 1), np.int64)], axis=1).astype(np.int32)
+    sq = np.repeat(np.stack([si, sj], axis=1), 2, axis=0)
+    return xyz, cells, sq
+
+
+def sheet_workload(nx: int = 40, ny: int = 20, h: float = 0.25, model: int = TP06_ENDO,
+                   sigma_l: float = SIGMA_L, sigma_t: float = SIGMA_T,
+                   curvature_radius: float = 0.0, dt: float = 0.02, n_steps: int = 1000,
+                   fibre_angle_deg: float = 0.0) -> Workload:
+    """A 2D sheet of one cell model, fibres at fibre_angle_deg from the x
+    axis (in the sheet), stimulated for 1 ms at -52 pA/pF on the squares
+    with x < 1 mm."""
+    xyz, cells, sq = sheet(nx, ny, h, curvature_radius)
+    n = cells.shape[0]
+    a = np.deg2rad(fibre_angle_deg)
+    if curvature_radius > 0:
+        # in-sheet direction at arc length y: cos a x + sin a (tangent of the circle)
+        yc = (sq[:, 1] + 0.5) * h / curvature_radius
+        fib = np.stack([np.full(n, np.cos(a)), np.sin(a) * np.cos(yc), np.sin(a) * np.sin(yc)], 1)
+    else:
+        fib = np.tile([np.cos(a), np.sin(a), 0.0], (n, 1))
+    nstim = max(1, int(round(1.0 / h)))
+    ids = np.nonzero(sq[:, 0] < nstim)[0].astype(np.int32)
+    return Workload(f"sheet-{nx}x{ny}-h{h}" + (f"-R{curvature_radius}" if curvature_radius else ""),
+                    xyz, cells, fib, np.full(n, model, np.uint8), sigma_l=sigma_l,
+                    sigma_t=sigma_t, stimuli=[Stimulus(ids=ids, t0=0.0, dur=1.0, amp=-52.0)],
+                    dt=dt, n_steps=n_steps, hex_ijk=None, dims=(nx, ny, 0, h))
+
+
+def mixed_workload(w3: Workload, w2: Workload) -> Workload:
+    """One workload holding a tetrahedral medium and a separate triangulated
+    one (disjoint node sets; the sheet's nodes and cells follow the tets')."""
+    nn = w3.n_nodes
+    cells2 = w2.tets.copy()
+    cells2[:, :3] += nn
+    stims = list(w3.stimuli) + [Stimulus(ids=st.ids + w3.n_tets, t0=st.t0, dur=st.dur, amp=st.amp,
+                                         period=st.period, count=st.count)
+                                for st in w2.stimuli]
+    sc = None
+    if w3.scale is not None or w2.scale is not None:
+        sc = np.concatenate([np.ones(w3.n_tets) if w3.scale is None else w3.scale,
+                             np.ones(w2.n_tets) if w2.scale is None else w2.scale])
+    return Workload(f"{w3.name}+{w2.name}", np.concatenate([w3.xyz, w2.xyz]),
+                    np.concatenate([w3.tets, cells2]).astype(np.int32),
+                    np.concatenate([w3.fibre, w2.fibre]), np.concatenate([w3.model, w2.model]),
+                    sigma_l=w3.sigma_l, sigma_t=w3.sigma_t, scale=sc, stimuli=stims, dt=w3.dt,
+                    n_steps=w3.n_steps)
+
+
 def hex_box_ids(hex_ijk: np.ndarray, lo, hi) -> np.ndarray:
     """Ids of the tets whose hex index lies in [lo, hi) per axis (None = open)."""
     sel = np.ones(hex_ijk.shape[0], dtype=bool)
