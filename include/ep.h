@@ -99,9 +99,21 @@ void ep_default_options(ep_options *o);
 ep_status ep_create(const ep_options *o, ep_sim **out);
 void ep_destroy(ep_sim *s);                 /* frees host and device memory */
 
-/* Mesh: n_nodes coordinates xyz[3*i+k] (mm) and n_tets tetrahedra
- * tet_nodes[4*c+k] (node ids, any orientation).  EP_EINVAL on an index out of
- * range or a zero-volume tetrahedron. */
+/* Mesh: n_nodes coordinates xyz[3*i+k] (mm) and n_tets cells
+ * tet_nodes[4*c+k] (node ids, any orientation).  A cell is a tetrahedron of
+ * the 3D myocardium, or, when tet_nodes[4*c+3] == -1, a triangle of a 2D
+ * medium (the paper's Purkinje shell, Sec. 3.2), discretised by the same
+ * cell-centred scheme on its edges: the area takes the volume's place, edge
+ * values are the means of their two node values, and across an edge between
+ * two triangles that are not coplanar the flux uses the edge length times the
+ * unit bisector of the two in-plane outward normals (conservative).  The 2D
+ * medium behaves as a sheet of unit thickness: its fluxes are sigma (mS/mm)
+ * times gradients times edge lengths.  A node belongs to tetrahedra or to
+ * triangles, not both; triangles do not couple to tetrahedra except through
+ * junctions.  Every "tet" argument and count of this interface means a cell
+ * of either kind, in this order.  EP_EINVAL on an index out of range, a
+ * degenerate cell, a node shared by both kinds, or triangles in a bidomain
+ * simulation. */
 ep_status ep_set_mesh(ep_sim *s, int64_t n_nodes, const double *xyz,
                       int64_t n_tets, const int32_t *tet_nodes);
 

@@ -136,7 +136,7 @@ ep_status ep_set_mesh(ep_sim *s, int64_t n_nodes, const double *xyz, int64_t n_t
     if (n_nodes <= 0 || n_tets <= 0 || !xyz || !tet_nodes)
         return fail(s, EP_EINVAL, "empty mesh or null array");
     for (int64_t i = 0; i < 4 * n_tets; ++i)
-        if (tet_nodes[i] < 0 || tet_nodes[i] >= n_nodes)
+        if ((tet_nodes[i] < 0 && !(i % 4 == 3 && tet_nodes[i] == -1)) || tet_nodes[i] >= n_nodes)
             return fail(s, EP_EINVAL, "tet node index out of range");
     ep::InstSpec &sp = s->spec;
     sp.xyz.assign(xyz, xyz + 3 * n_nodes);
@@ -688,8 +688,10 @@ ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes, double *cell
     if (!s) return EP_EINVAL;
     if (!s->inited) return EP_ESTATE;
     const double r = s->inst.rs, nc = (double)s->inst.desc.nc, nn = (double)s->inst.desc.nn;
-    // node gather: 4 incidences per tet (index + weight), every v once, vn write
-    if (node_bytes) *node_bytes = 4.0 * nc * (4.0 + r) + nc * r + nn * r + 8.0 * s->inst.n_slices;
+    // node gather: every incidence (index + weight; 4 per tet, 3 per
+    // triangle), every v once, vn write
+    const double ninc = (double)s->inst.prep.n_incidences;
+    if (node_bytes) *node_bytes = ninc * (4.0 + r) + nc * r + nn * r + 8.0 * s->inst.n_slices;
     // cell kernel: stencil (8 node ids + 8 coefficients + 4 neighbours + 4
     // coefficients), vn once, v^n once, v^{n+1} write, model byte, state
     // read+write, detection status byte; with Adams-Bashforth 2 the previous

@@ -59,10 +59,17 @@ inline double len(const V3 &a) { return std::sqrt(dot(a, a)); }
 
 struct Geo {
     std::vector<V3> cen;                 // centroid
-    std::vector<double> vol;
+    std::vector<double> vol;             // volume (tet) or area (triangle)
     std::vector<std::array<V3, 4>> S;    // outward area vector opposite vertex k
+    std::vector<std::array<V3, 4>> Sf;   // area vector of the face's flux
     std::vector<std::array<int32_t, 4>> nb;  // face neighbour opposite vertex k
 };
+
+// Cells are tetrahedra, or triangles of a 2D medium when the fourth node is
+// -1 (the paper's 2D Purkinje shell, Sec. 3.2): there a "face" is the edge
+// opposite vertex k, its area vector the in-plane outward normal times the
+// edge length, and the "volume" the area.
+inline int nverts(const PrepIn &in, int64_t c) { return in.tets[4 * c + 3] < 0 ? 3 : 4; }
 
 V3 node(const PrepIn &in, int32_t i) {
     return {in.xyz[3 * (int64_t)i], in.xyz[3 * (int64_t)i + 1], in.xyz[3 * (int64_t)i + 2]};
@@ -74,13 +81,27 @@ std::string validate(const PrepIn &in) {
     if (in.n_tets >= ((int64_t)1 << 25) || in.n_nodes >= ((int64_t)1 << 28))
         return "mesh too large for one instance (limit 2^25 tets)";
     for (int64_t i = 0; i < 4 * in.n_tets; ++i)
-        if (in.tets[i] < 0 || in.tets[i] >= in.n_nodes)
-            return "tet " + std::to_string(i / 4) + " references node out of range";
+        if ((in.tets[i] < 0 && !(i % 4 == 3 && in.tets[i] == -1)) || in.tets[i] >= in.n_nodes)
+            return "cell " + std::to_string(i / 4) + " references node out of range";
+    // a node belongs to tetrahedra or to triangles, not both (separate media)
+    std::vector<uint8_t> kind(in.n_nodes, 0);
+    bool tris = false;
+    for (int64_t c = 0; c < in.n_tets; ++c) {
+        const int nv = nverts(in, c);
+        tris = tris || nv == 3;
+        for (int k = 0; k < nv; ++k) {
+            uint8_t &m = kind[in.tets[4 * c + k]];
+            m |= nv == 3 ? 2 : 1;
+            if (m == 3) return "node " + std::to_string(in.tets[4 * c + k]) +
+                               " belongs to both tetrahedra and triangles";
+        }
+    }
+    if (tris && in.elliptic) return "the bidomain model takes tetrahedral meshes only";
     for (int64_t c = 0; c < in.n_tets; ++c) {
         const int32_t *t = in.tets + 4 * c;
-        if (t[0] == t[1] || t[0] == t[2] || t[0] == t[3] || t[1] == t[2] || t[1] == t[3] ||
-            t[2] == t[3])
-            return "tet " + std::to_string(c) + " repeats a node";
+        if (t[0] == t[1] || t[0] == t[2] || t[1] == t[2] ||
+            (t[3] >= 0 && (t[0] == t[3] || t[1] == t[3] || t[2] == t[3])))
+            return "cell " + std::to_string(c) + " repeats a node";
         if (in.model && in.model[c] > 5) return "bad model id at tet " + std::to_string(c);
         const double *f = in.fibre + 3 * c;
         double n2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
@@ -98,25 +119,29 @@ std::string validate(const PrepIn &in) {
 std::string match_faces(const PrepIn &in, Geo &g, int64_t &n_int, int64_t &n_bnd) {
     const int64_t nc = in.n_tets, nn = in.n_nodes;
     std::vector<int64_t> cnt(nn + 1, 0);
+    // a triangle's edge (two vertices) is keyed with d = -1; the node sets of
+    // the two media are disjoint, so keys of the two kinds never meet
     for (int64_t c = 0; c < nc; ++c) {
         const int32_t *t = in.tets + 4 * c;
-        for (int k = 0; k < 4; ++k) {
+        const int nv = nverts(in, c);
+        for (int k = 0; k < nv; ++k) {
             int32_t lo = INT32_MAX;
-            for (int q = 0; q < 4; ++q) if (q != k) lo = std::min(lo, t[q]);
+            for (int q = 0; q < nv; ++q) if (q != k) lo = std::min(lo, t[q]);
             cnt[lo + 1]++;
         }
     }
     for (int64_t i = 0; i < nn; ++i) cnt[i + 1] += cnt[i];
     struct E { int32_t b, d; int64_t id; };
-    std::vector<E> ent(4 * nc);
+    std::vector<E> ent(cnt[nn]);
     std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
     for (int64_t c = 0; c < nc; ++c) {
         const int32_t *t = in.tets + 4 * c;
-        for (int k = 0; k < 4; ++k) {
-            int32_t v[3], m = 0;
-            for (int q = 0; q < 4; ++q) if (q != k) v[m++] = t[q];
-            std::sort(v, v + 3);
-            ent[pos[v[0]]++] = E{v[1], v[2], 4 * c + k};
+        const int nv = nverts(in, c);
+        for (int k = 0; k < nv; ++k) {
+            int32_t v[3] = {0, 0, -1}, m = 0;
+            for (int q = 0; q < nv; ++q) if (q != k) v[m++] = t[q];
+            std::sort(v, v + m);
+            ent[pos[v[0]]++] = E{v[1], m == 3 ? v[2] : -1, 4 * c + k};
         }
     }
     g.nb.assign(nc, {-1, -1, -1, -1});
@@ -140,11 +165,33 @@ std::string match_faces(const PrepIn &in, Geo &g, int64_t &n_int, int64_t &n_bnd
             }
         }
     });
-    if (bad >= 0) return "non-manifold mesh: a face is shared by more than two tets";
+    if (bad >= 0) return "non-manifold mesh: a face is shared by more than two cells";
     n_int = n_bnd = 0;
     for (int64_t c = 0; c < nc; ++c)
-        for (int k = 0; k < 4; ++k) (g.nb[c][k] >= 0 ? n_int : n_bnd)++;
+        for (int k = 0; k < nverts(in, c); ++k) (g.nb[c][k] >= 0 ? n_int : n_bnd)++;
     n_int /= 2;
+    // flux area vectors: a tetrahedron's own; across an edge between two
+    // triangles (not coplanar on a bent surface) the edge length times the
+    // unit bisector of the two outward in-plane normals, the same vector with
+    // opposite signs on the two sides, so the flux stays conservative
+    g.Sf = g.S;
+    for (int64_t c = 0; c < nc; ++c) {
+        if (nverts(in, c) != 3) continue;
+        const int32_t *t = in.tets + 4 * c;
+        for (int k = 0; k < 3; ++k) {
+            const int32_t c2 = g.nb[c][k];
+            if (c2 < 0) continue;
+            const int32_t *t2 = in.tets + 4 * (int64_t)c2;
+            int k2 = 0;
+            for (int q = 0; q < 3; ++q)
+                if (t2[q] != t[(k + 1) % 3] && t2[q] != t[(k + 2) % 3]) k2 = q;
+            const V3 &a = g.S[c][k], &b = g.S[c2][k2];
+            const double la = len(a), lb = len(b);
+            V3 m{a[0] / la - b[0] / lb, a[1] / la - b[1] / lb, a[2] / la - b[2] / lb};
+            const double lm = len(m);
+            g.Sf[c][k] = {la * m[0] / lm, la * m[1] / lm, la * m[2] / lm};
+        }
+    }
     return "";
 }
 
@@ -157,6 +204,24 @@ std::string geometry(const PrepIn &in, Geo &g) {
     parallel_for(nc, [&](int64_t a, int64_t b) {
         for (int64_t c = a; c < b; ++c) {
             const int32_t *t = in.tets + 4 * c;
+            if (nverts(in, c) == 3) {
+                V3 p[3];
+                for (int k = 0; k < 3; ++k) p[k] = node(in, t[k]);
+                V3 N = cross(sub(p[1], p[0]), sub(p[2], p[0]));
+                const double twice = len(N);
+                if (!(twice > 1e-12 * len(sub(p[1], p[0])) * len(sub(p[2], p[0])))) degenerate = c;
+                g.vol[c] = 0.5 * twice;
+                for (int i = 0; i < 3; ++i) g.cen[c][i] = (p[0][i] + p[1][i] + p[2][i]) / 3.0;
+                N = {N[0] / twice, N[1] / twice, N[2] / twice};
+                for (int k = 0; k < 3; ++k) {
+                    const V3 &q0 = p[(k + 1) % 3], &q1 = p[(k + 2) % 3];
+                    V3 Sk = cross(sub(q1, q0), N);           // |Sk| = edge length
+                    const double sg = dot(Sk, sub(q0, p[k])) > 0 ? 1.0 : -1.0;
+                    g.S[c][k] = {sg * Sk[0], sg * Sk[1], sg * Sk[2]};
+                }
+                g.S[c][3] = {0, 0, 0};
+                continue;
+            }
             V3 p[4];
             for (int k = 0; k < 4; ++k) p[k] = node(in, t[k]);
             V3 e1 = sub(p[1], p[0]), e2 = sub(p[2], p[0]), e3 = sub(p[3], p[0]);
@@ -173,7 +238,7 @@ std::string geometry(const PrepIn &in, Geo &g) {
             }
         }
     });
-    if (degenerate >= 0) return "tet " + std::to_string((int64_t)degenerate) + " has zero volume";
+    if (degenerate >= 0) return "cell " + std::to_string((int64_t)degenerate) + " has zero volume or area";
     return "";
 }
 
@@ -292,7 +357,7 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
     std::vector<int32_t> nperm(nn, -1);   // caller node -> internal node
     int32_t nnext = 0;
     for (int64_t i = 0; i < nc; ++i)
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < nverts(in, order[i]); ++k) {
             int32_t n = in.tets[4 * (int64_t)order[i] + k];
             if (nperm[n] < 0) nperm[n] = nnext++;
         }
@@ -305,7 +370,7 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
         // 5-tet lattice mixes valence-32 and valence-8 nodes)
         std::vector<int32_t> degree(nn, 0);
         for (int64_t c = 0; c < nc; ++c)
-            for (int k = 0; k < 4; ++k) degree[in.tets[4 * c + k]]++;
+            for (int k = 0; k < nverts(in, c); ++k) degree[in.tets[4 * c + k]]++;
         const int64_t W = 1024;
         for (int64_t a = 0; a < nn; a += W) {
             const int64_t b = std::min(nn, a + W);
@@ -318,17 +383,19 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
     // ---- node gather: inverse-distance weights (step a), internal numbering
     std::vector<int64_t> ioff(nn + 1, 0);
     for (int64_t c = 0; c < nc; ++c)
-        for (int k = 0; k < 4; ++k) ioff[nperm[in.tets[4 * c + k]] + 1]++;
+        for (int k = 0; k < nverts(in, c); ++k) ioff[nperm[in.tets[4 * c + k]] + 1]++;
     for (int64_t i = 0; i < nn; ++i) ioff[i + 1] += ioff[i];
-    std::vector<int32_t> icell(4 * nc);
+    const int64_t n_inc = ioff[nn];
+    std::vector<int32_t> icell(n_inc);
     {
         std::vector<int64_t> fill(ioff.begin(), ioff.end() - 1);
         for (int64_t i = 0; i < nc; ++i) {       // internal cell order
             int32_t c = order[i];
-            for (int k = 0; k < 4; ++k) icell[fill[nperm[in.tets[4 * (int64_t)c + k]]]++] = (int32_t)i;
+            for (int k = 0; k < nverts(in, c); ++k)
+                icell[fill[nperm[in.tets[4 * (int64_t)c + k]]]++] = (int32_t)i;
         }
     }
-    std::vector<double> iw(4 * nc);
+    std::vector<double> iw(n_inc);
     parallel_for(nn, [&](int64_t a, int64_t b) {
         for (int64_t n = a; n < b; ++n) {
             V3 x = node(in, ninv[n]);
@@ -349,7 +416,8 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
         out.max_node_degree = std::max<int>(out.max_node_degree, (int)w);
         out.sell_off[k + 1] = out.sell_off[k] + 64 * w;
     }
-    out.sell_padding = (double)out.sell_off[nslice] / (double)(4 * nc) - 1.0;
+    out.sell_padding = (double)out.sell_off[nslice] / (double)n_inc - 1.0;
+    out.n_incidences = n_inc;
     out.sell_cell.assign(out.sell_off[nslice], 0);
     out.sell_w.assign(out.sell_off[nslice], 0.0);
     for (int64_t n = 0; n < nn; ++n) {
@@ -392,24 +460,30 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
         for (int64_t i = a; i < b; ++i) {
             const int64_t c = order[i];
             const int32_t *t = in.tets + 4 * c;
+            const int nv = nverts(in, c);
             double Mc[3][3];
             tensor(c, Mc);
-            const double kvol = 1.0 / (3.0 * g.vol[c]);
+            // Gauss-Green with face values = means of the nv - 1 face
+            // vertices: G_ck = -S_k / ((nv - 1) V_c)
+            const double kvol = 1.0 / ((nv - 1) * g.vol[c]);
             double beta[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             int32_t nodes[8];
-            for (int k = 0; k < 4; ++k) { nodes[k] = nperm[t[k]]; nodes[4 + k] = nodes[0]; }
+            for (int k = 0; k < 4; ++k) { nodes[k] = nperm[t[k < nv ? k : 0]]; nodes[4 + k] = nodes[0]; }
             for (int f = 0; f < 4; ++f) {
-                const int32_t c2 = g.nb[c][f];
+                const int32_t c2 = f < nv ? g.nb[c][f] : -1;
                 const int64_t slot = (int64_t)f * nc + i;
-                if (c2 < 0) {                      // no-flux boundary face
+                if (c2 < 0) {                      // no-flux boundary face (or none)
                     out.cnbr[slot] = (int32_t)i;
                     ob[slot] = 0.0;
                     continue;
                 }
                 const int32_t *t2 = in.tets + 4 * (int64_t)c2;
                 V3 xf{0, 0, 0};
-                for (int k = 0; k < 4; ++k)
-                    if (k != f) { V3 p = node(in, t[k]); for (int q = 0; q < 3; ++q) xf[q] += p[q] / 3.0; }
+                for (int k = 0; k < nv; ++k)
+                    if (k != f) {
+                        V3 p = node(in, t[k]);
+                        for (int q = 0; q < 3; ++q) xf[q] += p[q] / (nv - 1);
+                    }
                 const double r1 = len(sub(g.cen[c], xf)), r2 = len(sub(g.cen[c2], xf));
                 const double alpha = r2 / (r1 + r2);
                 V3 dv = sub(g.cen[c2], g.cen[c]);
@@ -420,17 +494,17 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
                 V3 w{0, 0, 0};
                 for (int p = 0; p < 3; ++p)
                     for (int q = 0; q < 3; ++q)
-                        w[p] += (alpha * Mc[p][q] + (1.0 - alpha) * M2[p][q]) * g.S[c][f][q];
+                        w[p] += (alpha * Mc[p][q] + (1.0 - alpha) * M2[p][q]) * g.Sf[c][f][q];
                 const double we = dot(w, e);
                 V3 af{w[0] - we * e[0], w[1] - we * e[1], w[2] - we * e[2]};
-                // own gradient: G_ck = -S_k / (3 V_c)
-                for (int k = 0; k < 4; ++k) beta[k] -= alpha * dot(af, g.S[c][k]) * kvol;
-                // neighbour gradient
-                const double kvol2 = 1.0 / (3.0 * g.vol[c2]);
-                for (int k2 = 0; k2 < 4; ++k2) {
+                // own gradient
+                for (int k = 0; k < nv; ++k) beta[k] -= alpha * dot(af, g.S[c][k]) * kvol;
+                // neighbour gradient (same medium, so as many vertices)
+                const double kvol2 = 1.0 / ((nv - 1) * g.vol[c2]);
+                for (int k2 = 0; k2 < nv; ++k2) {
                     const double coef = -(1.0 - alpha) * dot(af, g.S[c2][k2]) * kvol2;
                     int own = -1;
-                    for (int k = 0; k < 4; ++k) if (t[k] == t2[k2]) own = k;
+                    for (int k = 0; k < nv; ++k) if (t[k] == t2[k2]) own = k;
                     if (own >= 0) beta[own] += coef;
                     else { beta[4 + f] = coef; nodes[4 + f] = nperm[t2[k2]]; }
                 }

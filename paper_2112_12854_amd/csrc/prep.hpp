@@ -37,7 +37,9 @@ struct PrepOut {
     std::vector<double> sell_w;
     // fused cell stencil, slot-major ([slot][n_tets]), internal numbering:
     //   L_c = sum_{s<8} beta[s] vn[node[s]] + sum_{f<4} b[f] (v[nbr[f]] - v_c)
-    std::vector<int32_t> cnode;       // [8][n]: 4 own vertices, 4 opposite vertices
+    std::vector<int32_t> cnode;       // [8][n]: own vertices, then the vertices opposite
+                                      // the faces in the neighbours (triangles: 3 + 3,
+                                      // slots 3 and 7 padded with coefficient 0)
     std::vector<double> cbeta;        // [8][n]
     std::vector<int32_t> cnbr;        // [4][n]: face neighbour or self on the boundary
     std::vector<double> cb;           // [4][n]
@@ -46,11 +48,12 @@ struct PrepOut {
     // sum_f eb[f] (x[nbr_f] - x_c)
     std::vector<double> ebeta;        // [8][n]
     std::vector<double> eb;           // [4][n]
-    std::vector<double> vol;          // [n] tet volume (internal order)
+    std::vector<double> vol;          // [n] tet volume or triangle area (internal order)
     std::vector<uint8_t> model;       // [n] internal order
     int64_t n_interior_faces = 0, n_boundary_faces = 0;
     int max_node_degree = 0;
     double sell_padding = 0.0;        // padded / real incidences - 1
+    int64_t n_incidences = 0;         // (cell, vertex) pairs: 4 per tet, 3 per triangle
     double max_abs_L_row = 0.0;       // max_c sum of |coefficients| (stability hint)
 };
 

@@ -97,12 +97,17 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
 
     // ---- junction regions
     const int64_t nc = tin.n_tets;
+    // cells: tetrahedra, or triangles (fourth node -1)
+    auto nverts = [&](int64_t c) { return tin.tets[4 * c + 3] < 0 ? 3 : 4; };
     std::vector<double> cen(3 * nc);
     for (int64_t c = 0; c < nc; ++c) {
         const int32_t *t = tin.tets + 4 * c;
-        for (int a = 0; a < 3; ++a)
-            cen[3 * c + a] = 0.25 * (tin.xyz[3 * (int64_t)t[0] + a] + tin.xyz[3 * (int64_t)t[1] + a] +
-                                     tin.xyz[3 * (int64_t)t[2] + a] + tin.xyz[3 * (int64_t)t[3] + a]);
+        const int nv = nverts(c);
+        for (int a = 0; a < 3; ++a) {
+            double x = 0.0;
+            for (int k = 0; k < nv; ++k) x += tin.xyz[3 * (int64_t)t[k] + a];
+            cen[3 * c + a] = x / nv;
+        }
     }
     Grid grid;
     double hi[3];
@@ -121,12 +126,13 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
     }
     // node -> incident cells (for the fallback region)
     std::vector<int32_t> noff(tin.n_nodes + 1, 0), ncell(4 * nc);
-    for (int64_t i = 0; i < 4 * nc; ++i) noff[tin.tets[i] + 1]++;
+    for (int64_t c = 0; c < nc; ++c)
+        for (int a = 0; a < nverts(c); ++a) noff[tin.tets[4 * c + a] + 1]++;
     for (int64_t i = 0; i < tin.n_nodes; ++i) noff[i + 1] += noff[i];
     {
         std::vector<int32_t> f(noff.begin(), noff.end() - 1);
         for (int64_t c = 0; c < nc; ++c)
-            for (int a = 0; a < 4; ++a) ncell[f[tin.tets[4 * c + a]]++] = (int32_t)c;
+            for (int a = 0; a < nverts(c); ++a) ncell[f[tin.tets[4 * c + a]]++] = (int32_t)c;
     }
 
     out.jroff.assign(1, 0);
@@ -182,7 +188,7 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
                 for (int64_t c = 0; c < nc; ++c) consider((int32_t)c);
             }
             if (bc < 0) return "no tissue cell for a junction";
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < nverts(bc); ++a) {
                 const int32_t node = tin.tets[4 * (int64_t)bc + a];
                 for (int32_t e = noff[node]; e < noff[node + 1]; ++e) region.push_back(ncell[e]);
             }

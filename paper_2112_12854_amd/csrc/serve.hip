@@ -432,7 +432,8 @@ ep_status copy_request(const ep_request *rq, const ep_options &o, ep::InstSpec &
         return EP_EINVAL;
     }
     for (int64_t i = 0; i < 4 * rq->n_tets; ++i)
-        if (rq->tet_nodes[i] < 0 || rq->tet_nodes[i] >= rq->n_nodes) {
+        if ((rq->tet_nodes[i] < 0 && !(i % 4 == 3 && rq->tet_nodes[i] == -1)) ||
+            rq->tet_nodes[i] >= rq->n_nodes) {
             err = "tet node index out of range";
             return EP_EINVAL;
         }
