@@ -64,6 +64,8 @@ def lib():
                                        C.c_double, C.c_int, C.c_int32]
         L.orc_add_pmj.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
                                   C.c_double, C.c_int, C.c_double, C.c_double]
+        L.orc_add_cell_junction.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double,
+                                            C.c_double, C.c_int, C.c_double, C.c_double]
         L.orc_add_purkinje_stimulus.argtypes = [C.c_void_p, C.c_int64, _ip, C.c_double,
                                                 C.c_double, C.c_double, C.c_double, C.c_int32]
         L.orc_set_time_scheme.argtypes = [C.c_void_p, C.c_int]
@@ -174,6 +176,9 @@ class Sim:
             for node in pk.pmj_nodes:
                 L.orc_add_pmj(self.h, int(node), pk.pmj_radius, pk.delay_ortho,
                               pk.delay_anti, int(pk.two_way), pk.pmj_amp, pk.pmj_dur)
+        for cj in getattr(w, "cell_junctions", []):
+            assert L.orc_add_cell_junction(self.h, int(cj.cell), cj.radius, cj.delay_ortho,
+                                           cj.delay_anti, int(cj.two_way), cj.amp, cj.dur) >= 0
         for st in w.stimuli:
             ids = np.ascontiguousarray(st.ids, dtype=np.int32)
             fn = L.orc_add_stimulus if st.domain == 0 else L.orc_add_purkinje_stimulus

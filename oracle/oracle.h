@@ -106,6 +106,16 @@ int32_t orc_purkinje_n_sub(const orc_sim *s);
 int orc_set_time_scheme(orc_sim *s, int scheme);
 void orc_get_purkinje_vm(const orc_sim *s, double *out);
 void orc_get_purkinje_activation(const orc_sim *s, double *out);
+/* Junction whose source is a cell (the coupling of the 2D Purkinje shell
+ * to the 3D myocardium through communication nodes, Sec. 3.3): the region
+ * is the cells of the other kind (tets for a triangle source, triangles for
+ * a tet) whose centroid lies within `radius` of the source's centroid, else
+ * the cells of that kind sharing a node with the nearest one; the source's
+ * upward crossing during step n pulses the region from n + 1 + round(delay/dt),
+ * and with two_way the region mean's crossing pulses the source cell.
+ * Shares the index sequence of orc_add_pmj; -1 for a bad cell or no region. */
+int orc_add_cell_junction(orc_sim *s, int32_t cell, double radius, double delay_ortho,
+                          double delay_anti, int two_way, double amp, double dur);
 /* muscle region of junction k (at most cap ids); returns its size */
 int64_t orc_get_pmj_region(const orc_sim *s, int k, int32_t *out, int64_t cap);
 

@@ -97,7 +97,8 @@ struct orc_sim {
 };
 
 struct orc_pmj {
-    int32_t node;
+    int32_t node;               /* graph node of the source, or -1 */
+    int32_t src_cell;           /* cell of the source (2D-3D coupling), or -1 */
     int32_t *cells;
     int64_t n_cells;
     int64_t delay_o, delay_a, ndur;
@@ -617,6 +618,24 @@ static double region_mean(const struct orc_pmj *J, const double *v)
     return acc / (double)J->n_cells;
 }
 
+/* Events of junction J after step n: the source potential went from a to b
+ * (an upward threshold crossing schedules the pulse on the region); with
+ * two-way coupling an upward crossing of the region's mean schedules the
+ * pulse on the source.  v_old holds the tissue at level n, the cells level
+ * n+1. */
+static void junction_event(orc_sim *s, struct orc_pmj *J, double a, double b, const double *v_old)
+{
+    const int64_t n = s->step;
+    if (a <= s->thr && b > s->thr) J->fire_o = n + 1 + J->delay_o;
+    if (J->two_way) {
+        const double m0 = region_mean(J, v_old);
+        double m1 = 0.0;
+        for (int64_t q = 0; q < J->n_cells; ++q) m1 += s->y[(int64_t)J->cells[q] * ORC_MAX_SLOTS];
+        m1 /= (double)J->n_cells;
+        if (m0 <= s->thr && m1 > s->thr) J->fire_a = n + 1 + J->delay_a;
+    }
+}
+
 /* n_sub substeps of the graph over tissue step n, then junction events;
  * v_old is the tissue potential at level n (the cells hold level n+1). */
 static void purkinje_step(orc_sim *s, const double *v_old)
@@ -635,7 +654,8 @@ static void purkinje_step(orc_sim *s, const double *v_old)
     }
     for (int k = 0; k < s->n_pmj; ++k) {
         const struct orc_pmj *J = &s->pmj[k];
-        if (J->two_way && n >= J->fire_a && n < J->fire_a + J->ndur) s->pistim[J->node] += J->amp;
+        if (J->src_cell < 0 && J->two_way && n >= J->fire_a && n < J->fire_a + J->ndur)
+            s->pistim[J->node] += J->amp;
     }
     for (int sub = 0; sub < s->n_sub; ++sub) {
         for (int64_t i = 0; i < np; ++i) vp[i] = s->py[i * ORC_MAX_SLOTS];
@@ -663,15 +683,8 @@ static void purkinje_step(orc_sim *s, const double *v_old)
     /* junction events: upward crossings during this step fire later */
     for (int k = 0; k < s->n_pmj; ++k) {
         struct orc_pmj *J = &s->pmj[k];
-        const double a = vp0[J->node], b = s->py[(int64_t)J->node * ORC_MAX_SLOTS];
-        if (a <= s->thr && b > s->thr) J->fire_o = n + 1 + J->delay_o;
-        if (J->two_way) {
-            const double m0 = region_mean(J, v_old);
-            double m1 = 0.0;
-            for (int64_t q = 0; q < J->n_cells; ++q) m1 += s->y[(int64_t)J->cells[q] * ORC_MAX_SLOTS];
-            m1 /= (double)J->n_cells;
-            if (m0 <= s->thr && m1 > s->thr) J->fire_a = n + 1 + J->delay_a;
-        }
+        if (J->src_cell >= 0) continue;
+        junction_event(s, J, vp0[J->node], s->py[(int64_t)J->node * ORC_MAX_SLOTS], v_old);
     }
     free(vp);
     free(vp0);
@@ -752,19 +765,16 @@ int orc_set_purkinje(orc_sim *s, int64_t n, const double *xyz, int64_t n_edges,
     return 0;
 }
 
-int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
-                double delay_anti, int two_way, double amp, double dur)
+/* Muscle region of a junction at point x: the cells whose centroid lies
+ * within the radius, else the cells sharing a node with the cell of nearest
+ * centroid; only cells with `kind` vertices count (0: any). */
+static void junction_region(orc_sim *s, struct orc_pmj *J, const double *x, double radius,
+                            int kind)
 {
-    if (node < 0 || node >= s->np) return -1;
-    s->pmj = realloc(s->pmj, sizeof(struct orc_pmj) * (size_t)(s->n_pmj + 1));
-    struct orc_pmj *J = &s->pmj[s->n_pmj++];
-    memset(J, 0, sizeof(*J));
-    J->node = node;
-    const double *x = s->pxyz + 3 * (int64_t)node;
-    /* region: centroids within the radius */
     int64_t cnt = 0, best = -1;
     double bestd = 1e300;
     for (int64_t c = 0; c < s->nc; ++c) {
+        if (kind && nverts(s, c) != kind) continue;
         double r[3];
         sub3(s->cen + 3 * c, x, r);
         const double d = norm3(r);
@@ -774,12 +784,12 @@ int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
     if (cnt > 0) {
         J->cells = malloc(sizeof(int32_t) * (size_t)cnt);
         for (int64_t c = 0; c < s->nc; ++c) {
+            if (kind && nverts(s, c) != kind) continue;
             double r[3];
             sub3(s->cen + 3 * c, x, r);
             if (norm3(r) <= radius) J->cells[J->n_cells++] = (int32_t)c;
         }
     } else {
-        /* the cells sharing a node with the cell of nearest centroid */
         const int32_t *t = s->tet + 4 * best;
         J->cells = malloc(sizeof(int32_t) * (size_t)s->nc);
         for (int64_t c = 0; c < s->nc; ++c) {
@@ -790,12 +800,46 @@ int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
             if (share) J->cells[J->n_cells++] = (int32_t)c;
         }
     }
+}
+
+static void junction_timing(orc_sim *s, struct orc_pmj *J, double delay_ortho,
+                            double delay_anti, int two_way, double amp, double dur)
+{
     J->delay_o = llround(delay_ortho / s->dt);
     J->delay_a = llround(delay_anti / s->dt);
     J->ndur = llround(dur / s->dt);
     J->two_way = two_way;
     J->amp = amp;
     J->fire_o = J->fire_a = INT64_MIN / 2;
+}
+
+int orc_add_cell_junction(orc_sim *s, int32_t cell, double radius, double delay_ortho,
+                          double delay_anti, int two_way, double amp, double dur)
+{
+    if (cell < 0 || cell >= s->nc) return -1;
+    s->pmj = realloc(s->pmj, sizeof(struct orc_pmj) * (size_t)(s->n_pmj + 1));
+    struct orc_pmj *J = &s->pmj[s->n_pmj++];
+    memset(J, 0, sizeof(*J));
+    J->node = -1;
+    J->src_cell = cell;
+    /* the region lies in the other medium (a triangle couples to tets) */
+    junction_region(s, J, s->cen + 3 * (int64_t)cell, radius, nverts(s, cell) == 3 ? 4 : 3);
+    if (J->n_cells == 0) { s->n_pmj--; free(J->cells); return -1; }
+    junction_timing(s, J, delay_ortho, delay_anti, two_way, amp, dur);
+    return s->n_pmj - 1;
+}
+
+int orc_add_pmj(orc_sim *s, int32_t node, double radius, double delay_ortho,
+                double delay_anti, int two_way, double amp, double dur)
+{
+    if (node < 0 || node >= s->np) return -1;
+    s->pmj = realloc(s->pmj, sizeof(struct orc_pmj) * (size_t)(s->n_pmj + 1));
+    struct orc_pmj *J = &s->pmj[s->n_pmj++];
+    memset(J, 0, sizeof(*J));
+    J->node = node;
+    J->src_cell = -1;
+    junction_region(s, J, s->pxyz + 3 * (int64_t)node, radius, 0);
+    junction_timing(s, J, delay_ortho, delay_anti, two_way, amp, dur);
     return s->n_pmj - 1;
 }
 
@@ -1007,6 +1051,8 @@ static void one_step(orc_sim *s)
         const struct orc_pmj *J = &s->pmj[k];
         if (n >= J->fire_o && n < J->fire_o + J->ndur)
             for (int64_t q = 0; q < J->n_cells; ++q) s->istim[J->cells[q]] += J->amp;
+        if (J->src_cell >= 0 && J->two_way && n >= J->fire_a && n < J->fire_a + J->ndur)
+            s->istim[J->src_cell] += J->amp;
     }
 
     /* diffusion at level n; bidomain: the intracellular flux of v + phi_e */
@@ -1054,6 +1100,11 @@ static void one_step(orc_sim *s)
         }
     }
     if (s->np > 0) purkinje_step(s, v);
+    for (int k = 0; k < s->n_pmj; ++k) {
+        struct orc_pmj *J = &s->pmj[k];
+        if (J->src_cell >= 0)
+            junction_event(s, J, v[J->src_cell], s->y[(int64_t)J->src_cell * ORC_MAX_SLOTS], v);
+    }
     if (s->bido) bidomain_solve(s);
     free(v);
     s->step++;

@@ -50,6 +50,22 @@ class Stimulus:
 
 
 @dataclass
+class CellJunction:
+    """A communication node whose source is a cell (Sec. 3.3: the 2D
+    Purkinje shell excites the 3D myocardium through them): the cells of the
+    other kind within `radius` of the source's centroid get `amp` for `dur`
+    ms, `delay_ortho` ms after the source's upward crossing; with two_way the
+    region's mean crossing pulses the source after `delay_anti`."""
+    cell: int
+    radius: float = 0.1
+    delay_ortho: float = 5.0
+    delay_anti: float = 3.0
+    two_way: bool = False
+    amp: float = -200.0
+    dur: float = 0.5
+
+
+@dataclass
 class Workload:
     name: str
     xyz: np.ndarray                  # [n_nodes, 3] float64
@@ -71,6 +87,7 @@ class Workload:
     bidomain: object = None            # Bidomain parameters, or monodomain
     landmarks: dict = field(default_factory=dict)   # name -> [3] point (mm)
     time_scheme: int = 0               # 0 forward Euler, 1 Adams-Bashforth 2
+    cell_junctions: list = field(default_factory=list)   # CellJunction, after the graph's
 
     @property
     def n_tets(self) -> int:
@@ -210,6 +227,48 @@ def mixed_workload(w3: Workload, w2: Workload) -> Workload:
                     np.concatenate([w3.fibre, w2.fibre]), np.concatenate([w3.model, w2.model]),
                     sigma_l=w3.sigma_l, sigma_t=w3.sigma_t, scale=sc, stimuli=stims, dt=w3.dt,
                     n_steps=w3.n_steps)
+
+
+def shell_on_slab(nx: int = 16, ny: int = 8, nz: int = 2, h: float = 0.5, gap: float = 0.05,
+                  cn_spacing: float = 1.0, radius: float = 0.6, drive: str = "sheet",
+                  two_way: bool = False, amp: float = -200.0, sheet_scale: float = 10.0,
+                  dt: float = 0.02, n_steps: int = 750) -> Workload:
+    """A 2D Stewart sheet (the Purkinje shell, Sec. 2) lying `gap` mm above
+    a TP06 slab, coupled to it by communication nodes: the sheet triangles
+    nearest to a square grid of spacing cn_spacing (the paper spaces its
+    nodes about 1 mm apart) are sources of junctions onto the tets within
+    `radius`.  The sheet conducts with sheet_scale times the tissue's
+    conductivities.  drive="sheet": -100 pA/pF for 1 ms on the sheet's
+    triangles with x < 1 mm; drive="slab": -52 pA/pF for 1 ms on the slab's
+    cells with x < 1 mm (with two_way the slab then excites the sheet)."""
+    xyz3, tets, hijk = slab(nx, ny, nz, h)
+    n3 = tets.shape[0]
+    w3 = Workload("slab", xyz3, tets, _uniform_fibre(n3), np.full(n3, TP06_ENDO, np.uint8),
+                  dt=dt, n_steps=n_steps, hex_ijk=hijk, dims=(nx, ny, nz, h))
+    w2 = sheet_workload(nx, ny, h, model=STEWART, dt=dt, n_steps=n_steps)
+    w2.xyz = w2.xyz + np.array([0.0, 0.0, nz * h + gap])
+    w2.scale = np.full(w2.n_tets, sheet_scale)
+    sheet_stim = w2.stimuli[0]
+    w2.stimuli = []
+    w = mixed_workload(w3, w2)
+    w.name = f"shell-on-slab-{nx}x{ny}x{nz}-h{h}"
+    w.hex_ijk, w.dims = None, (nx, ny, nz, h)
+    cen2 = w2.xyz[w2.tets[:, :3]].mean(axis=1)
+    gx = np.arange(0.5 * cn_spacing, nx * h, cn_spacing)
+    gy = np.arange(0.5 * cn_spacing, ny * h, cn_spacing)
+    src = []
+    for x in gx:
+        for y in gy:
+            src.append(int(np.argmin((cen2[:, 0] - x) ** 2 + (cen2[:, 1] - y) ** 2)))
+    w.cell_junctions = [CellJunction(cell=n3 + c, radius=radius, two_way=two_way, amp=amp)
+                        for c in sorted(set(src))]
+    if drive == "sheet":
+        w.stimuli.append(Stimulus(ids=(sheet_stim.ids + n3).astype(np.int32), t0=0.0, dur=1.0,
+                                  amp=-100.0))
+    else:
+        w.stimuli.append(Stimulus(ids=hex_box_ids(hijk, (0, None, None), (int(round(1.0 / h)), None, None)),
+                                  t0=0.0, dur=1.0, amp=-52.0))
+    return w
 
 
 def hex_box_ids(hex_ijk: np.ndarray, lo, hi) -> np.ndarray:

@@ -196,3 +196,81 @@ def test_mixed_mesh_equals_media_apart(oracle_lib):
     assert np.array_equal(v[w3.n_tets:], c.vm())
     at = a.activation()
     assert np.isfinite(at[w3.n_tets:]).any() and np.isfinite(at[:w3.n_tets]).any()
+
+
+# ----------------------------------- communication nodes from the 2D shell
+N3 = 16 * 8 * 2 * 5          # tets of the default shell_on_slab
+
+
+def test_cell_junction_region_is_the_other_medium(oracle_lib):
+    """Sec. 3.3: a communication node stimulates the cells of the other
+    medium within R_S: brute-force centroid search restricted to tets; with
+    a radius that holds no centroid, the tets sharing a node with the
+    nearest tet."""
+    w = M.shell_on_slab()
+    s = oracle_lib.Sim(w)
+    cen = w.xyz[np.where(w.tets >= 0, w.tets, w.tets[:, :1])].mean(axis=1)
+    cen[N3:] = w.xyz[w.tets[N3:, :3]].mean(axis=1)
+    for k, cj in enumerate(w.cell_junctions[:6]):
+        d = np.linalg.norm(cen[:N3] - cen[cj.cell], axis=1)
+        assert np.array_equal(np.sort(s.pmj_region(k)), np.nonzero(d <= cj.radius)[0])
+    w0 = M.shell_on_slab(radius=0.0)
+    s0 = oracle_lib.Sim(w0)
+    cj = w0.cell_junctions[0]
+    d = np.linalg.norm(cen[:N3] - cen[cj.cell], axis=1)
+    near = w0.tets[int(np.argmin(d))]
+    star = np.nonzero(np.isin(w0.tets[:N3], near).any(axis=1))[0]
+    assert np.array_equal(np.sort(s0.pmj_region(0)), star)
+
+
+def test_cell_junction_orthodromic_timing(oracle_lib):
+    """The source triangle crossing the threshold during step n pulses the
+    tets of its region from step n + 1 + round(5 ms / dt): at rest until
+    then, then raised by about -amp dt per pulsed step."""
+    w = M.shell_on_slab(drive="sheet")
+    s = oracle_lib.Sim(w)
+    dt = w.dt
+    cj = w.cell_junctions[0]
+    s.step(200)
+    tn = s.activation()[cj.cell]
+    assert np.isfinite(tn)
+    fire = int(math.floor(tn / dt)) + 1 + int(round(cj.delay_ortho / dt))
+    region = s.pmj_region(0)
+    v_rest = s.vm()[region]
+    s.step(fire - 200)
+    v_before = s.vm()[region]
+    assert np.all(abs(v_before - v_rest) < 0.05)
+    s.step(1)
+    assert np.all(s.vm()[region] - v_before > 0.5 * (-cj.amp) * dt)
+
+
+def test_cell_junction_two_way(oracle_lib):
+    """Driving the slab: with two-way nodes the region mean crossing during
+    step n pulses the source triangle from n + 1 + round(3 ms / dt), and the
+    shell then activates; one-way nodes leave the shell at rest."""
+    w = M.shell_on_slab(drive="slab", two_way=True)
+    s = oracle_lib.Sim(w)
+    dt = w.dt
+    region = s.pmj_region(0)
+    cj = w.cell_junctions[0]
+    m_prev = s.vm()[region].mean()
+    n_cross = None
+    for n in range(400):
+        s.step(1)
+        m = s.vm()[region].mean()
+        if m_prev <= 0.0 < m:
+            n_cross = n
+            break
+        m_prev = m
+    assert n_cross is not None
+    fire = n_cross + 1 + int(round(cj.delay_anti / dt))
+    s.step(fire - s.step_index)               # steps 0 .. fire-1 done
+    assert np.isnan(s.activation()[N3:]).all()   # no shell cell has fired yet
+    v_src = s.vm()[cj.cell]
+    s.step(1)                                 # step `fire`: first pulse on the source
+    assert s.vm()[cj.cell] - v_src > 0.5 * (-cj.amp) * dt
+    s.step(300)
+    assert np.isfinite(s.activation()[N3:]).all()
+    s1 = oracle_lib.Sim(M.shell_on_slab(drive="slab", two_way=False))
+    s1.step(750)
+    assert np.isnan(s1.activation()[N3:]).all()
