@@ -178,6 +178,21 @@ ep_status ep_set_purkinje_scale(ep_sim *s, int64_t n_edges, const double *scale)
 ep_status ep_add_pmj(ep_sim *s, int32_t node, double radius, double delay_ortho,
                      double delay_anti, int32_t two_way, double amp, double dur);
 
+/* Communication node whose source is a cell (Sec. 3.3: the 2D Purkinje
+ * shell excites the 3D myocardium through such nodes, about 1 mm apart,
+ * with a 0.1 mm range and the 5 ms junction delay): when cell `cell`
+ * crosses at_threshold upward during step n, the cells of the other kind
+ * (tets for a triangle, triangles for a tet) whose centroid lies within
+ * `radius` of its centroid (if none: those sharing a mesh node with the
+ * nearest one) receive amp for dur ms from step n + 1 + round(delay_ortho/dt);
+ * with two_way the upward crossing of that region's mean pulses the source
+ * cell from step n + 1 + round(delay_anti/dt).  Shares one index sequence
+ * with ep_add_pmj (call order); needs no graph.  EP_EINVAL for a cell out of
+ * range, bad parameters, or (at ep_init) no cell of the other kind.  Call
+ * after ep_set_mesh and before ep_init. */
+ep_status ep_add_cell_junction(ep_sim *s, int32_t cell, double radius, double delay_ortho,
+                               double delay_anti, int32_t two_way, double amp, double dur);
+
 /* Graph readouts (caller numbering of graph nodes, n == graph size):
  * potential and activation time (first upward threshold crossing, NaN if
  * none); and the substep count in use. */

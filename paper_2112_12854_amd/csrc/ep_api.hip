@@ -234,6 +234,16 @@ ep_status ep_add_pmj(ep_sim *s, int32_t node, double radius, double delay_ortho,
     return e.empty() ? EP_OK : fail(s, EP_EINVAL, e);
 }
 
+ep_status ep_add_cell_junction(ep_sim *s, int32_t cell, double radius, double delay_ortho,
+                               double delay_anti, int32_t two_way, double amp, double dur) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "junctions are frozen after ep_init");
+    if (s->spec.n_tets == 0) return fail(s, EP_ESTATE, "set the mesh first");
+    const std::string e = ep::spec_add_cell_junction(s->spec, cell, radius, delay_ortho, delay_anti,
+                                                     two_way, amp, dur);
+    return e.empty() ? EP_OK : fail(s, EP_EINVAL, e);
+}
+
 ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t restart,
                           double tol, int32_t max_iter) {
     if (!s) return EP_EINVAL;
@@ -587,9 +597,9 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
         a.push_back({D.hv, nc * r});
         a.push_back({D.hc, NC_MAX * nc * 8});
     }
-    if (s->inst.pk.n > 0) {
+    if (ep::has_junction_block(s->inst)) {
         const epdev::PurkDesc &P = s->inst.pdesc;
-        const size_t np = P.np;
+        const size_t np = P.np;             // 0 when only cells are junction sources
         a.push_back({P.pv[0], np * r});
         a.push_back({P.pv[1], np * r});
         a.push_back({P.gate, NG_MAX * np * r});
@@ -602,6 +612,7 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
             a.push_back({P.hc, NC_MAX * np * 8});
         }
     }
+    a.erase(std::remove_if(a.begin(), a.end(), [](const auto &x) { return x.second == 0; }), a.end());
     return a;
 }
 

@@ -104,7 +104,12 @@ std::string spec_set_purkinje(InstSpec &sp, int64_t n, const double *xyz, int64_
         if (!std::isfinite(xyz[i])) return "non-finite node coordinate";
     for (int64_t e = 0; e < 2 * n_edges; ++e)
         if (edges[e] < 0 || edges[e] >= n) return "edge node index out of range";
+    // junctions of cells outlive a change of graph; those of graph nodes do not
+    std::vector<PmjIn> keep;
+    for (const PmjIn &q : sp.purk.pmjs)
+        if (q.cell >= 0) keep.push_back(q);
     sp.purk = PurkSpec();
+    sp.purk.pmjs = keep;
     sp.purk.n = n;
     sp.purk.xyz.assign(xyz, xyz + 3 * n);
     sp.purk.edges.assign(edges, edges + 2 * n_edges);
@@ -125,10 +130,10 @@ std::string spec_set_purkinje_scale(InstSpec &sp, int64_t n_edges, const double 
     return "";
 }
 
-std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay_ortho,
+namespace {
+std::string add_junction(InstSpec &sp, int32_t node, int32_t cell, double radius, double delay_ortho,
                          double delay_anti, int32_t two_way, double amp, double dur) {
     PurkSpec &pk = sp.purk;
-    if (node < 0 || node >= pk.n) return "junction node out of range";
     if (!(radius >= 0) || !std::isfinite(radius) || !(delay_ortho >= 0) || !(delay_anti >= 0) ||
         !std::isfinite(delay_ortho) || !std::isfinite(delay_anti) || !std::isfinite(amp) ||
         !(dur >= 0) || !std::isfinite(dur))
@@ -136,6 +141,7 @@ std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay
     if (pk.pmjs.size() >= (size_t)1 << 24) return "too many junctions";
     PmjIn q;
     q.node = node;
+    q.cell = cell;
     q.radius = radius;
     q.delay_ortho = delay_ortho;
     q.delay_anti = delay_anti;
@@ -144,6 +150,19 @@ std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay
     q.dur = dur;
     pk.pmjs.push_back(q);
     return "";
+}
+}  // namespace
+
+std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay_ortho,
+                         double delay_anti, int32_t two_way, double amp, double dur) {
+    if (node < 0 || node >= sp.purk.n) return "junction node out of range";
+    return add_junction(sp, node, -1, radius, delay_ortho, delay_anti, two_way, amp, dur);
+}
+
+std::string spec_add_cell_junction(InstSpec &sp, int32_t cell, double radius, double delay_ortho,
+                                   double delay_anti, int32_t two_way, double amp, double dur) {
+    if (cell < 0 || cell >= sp.n_tets) return "junction source cell out of range";
+    return add_junction(sp, -1, cell, radius, delay_ortho, delay_anti, two_way, amp, dur);
 }
 
 std::string spec_add_stimulus(InstSpec &sp, int domain, int64_t n_ids, const int32_t *ids,
@@ -192,7 +211,7 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     }
     I.pk = PurkOut();
     I.n_pmj = 0;
-    if (sp.purk.n > 0) {
+    if (sp.purk.n > 0 || !sp.purk.pmjs.empty()) {
         PurkIn pin;
         pin.n = sp.purk.n;
         pin.n_edges = (int64_t)sp.purk.edges.size() / 2;
@@ -217,7 +236,7 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
 namespace {
 
 size_t purkinje_bytes(const Inst &I, int rs) {
-    if (I.pk.n == 0) return 0;
+    if (!has_junction_block(I)) return 0;
     const size_t np = (size_t)I.pk.n, E = I.pk.nbr.size(), r = (size_t)rs, c = (size_t)I.prep.n_tets;
     size_t b = round256((np + 1) * 4) + round256(E * 4) + round256(E * r);
     b += 2 * round256(np * r) + round256(NG_MAX * np * r) + round256(NC_MAX * np * 8);
@@ -290,7 +309,8 @@ std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) 
     {
         std::vector<std::vector<int32_t>> at(np);
         for (size_t k = 0; k < sp.purk.pmjs.size(); ++k)
-            if (sp.purk.pmjs[k].two_way) at[sp.purk.pmjs[k].node].push_back((int32_t)k);
+            if (sp.purk.pmjs[k].two_way && sp.purk.pmjs[k].cell < 0)
+                at[sp.purk.pmjs[k].node].push_back((int32_t)k);
         for (int64_t i = 0; i < np; ++i)
             if (!at[i].empty()) {
                 npmj[i] = (int32_t)nlist.size();
@@ -308,8 +328,9 @@ std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) 
         J.delay_a = std::llround(q.delay_anti / sp.dt);
         J.ndur = std::llround(q.dur / sp.dt);
         J.amp = q.amp;
-        J.vprev = rs == 8 ? v0[q.node] : (double)(float)v0[q.node];
+        J.vprev = q.cell >= 0 ? 0.0 : rs == 8 ? v0[q.node] : (double)(float)v0[q.node];
         J.node = q.node;
+        J.src_cell = K.jsrc[k];
         J.two_way = q.two_way ? 1 : 0;
         J.roff = K.jroff[k];
         J.rcnt = K.jroff[k + 1] - K.jroff[k];
@@ -534,7 +555,7 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         }
         I.coarse = Coarse();               // the host copy is no longer needed
     }
-    if (I.pk.n > 0) {
+    if (has_junction_block(I)) {
         std::string e = upload_purkinje(sp, rs, I, st);
         if (!e.empty()) return e;
     }
@@ -624,7 +645,8 @@ void launch_step(Stepper &s, int32_t off) {
 template <typename R>
 void launch_purkinje(Stepper &s, int32_t off) {
     const Tables tb = tables(s);
-    for (int32_t sub = 0; sub < s.n_sub_max; ++sub) {
+    // (no graph tiles when every junction has a source cell)
+    for (int32_t sub = 0; s.n_pt > 0 && sub < s.n_sub_max; ++sub) {
         if (s.ab2) k_purkinje<R, true><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
         else k_purkinje<R, false><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
     }
@@ -704,7 +726,7 @@ std::string stepper_sync_tables(Stepper &s) {
     for (size_t i = 0; i < s.insts.size(); ++i) {
         const Inst &I = *s.insts[i];
         desc.push_back(I.desc);
-        if (I.pk.n > 0) {
+        if (has_junction_block(I)) {
             pk.push_back(I.pdesc);
             nsub = std::max(nsub, I.pdesc.n_sub);
             for (int64_t b = 0, t = 0; b < I.pdesc.np; b += TILE, ++t)

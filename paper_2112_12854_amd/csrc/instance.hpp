@@ -113,7 +113,7 @@ struct Inst {
     double dt = 0.02;
     int64_t n_slices = 0;
     // Purkinje graph (pk.n == 0: none)
-    PurkOut pk;
+    PurkOut pk;                        // graph (pk.n nodes, possibly 0) and junctions
     int pmodel = 4;
     int64_t n_pmj = 0;
     epdev::PurkDesc pdesc{};
@@ -123,6 +123,11 @@ struct Inst {
     bool ab2 = false;                  // Adams-Bashforth 2 history allocated
 };
 
+// An instance with a Purkinje graph or with junctions (of graph nodes or of
+// cells) carries a PurkDesc: graph substeps (none for an empty graph) and the
+// junction events.
+inline bool has_junction_block(const Inst &I) { return I.pk.n > 0 || I.n_pmj > 0; }
+
 // Host precompute only (thread-safe, no HIP calls).
 // Validated edits of a spec, shared by the single-simulation API and the
 // server's request copy; an empty string means success (EP_EINVAL otherwise).
@@ -131,6 +136,8 @@ std::string spec_set_purkinje(InstSpec &sp, int64_t n, const double *xyz, int64_
 std::string spec_set_purkinje_scale(InstSpec &sp, int64_t n_edges, const double *scale);
 std::string spec_add_pmj(InstSpec &sp, int32_t node, double radius, double delay_ortho,
                          double delay_anti, int32_t two_way, double amp, double dur);
+std::string spec_add_cell_junction(InstSpec &sp, int32_t cell, double radius, double delay_ortho,
+                                   double delay_anti, int32_t two_way, double amp, double dur);
 std::string spec_add_stimulus(InstSpec &sp, int domain, int64_t n_ids, const int32_t *ids,
                               double t0, double dur, double amp, double period, int32_t count);
 

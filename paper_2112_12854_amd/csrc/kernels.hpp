@@ -47,7 +47,12 @@ struct Pmj {
     double vprev;                     // junction node potential at the start of the step
     int32_t node, two_way;
     int32_t roff, rcnt;               // region: jcells[roff .. roff + rcnt)
+    int32_t src_cell;                 // internal source cell, or -1 (graph node `node`)
+    int32_t pad;
 };
+// cpmj_list entry: k pulses the cell with junction k's region pulse; k with
+// kAntiFlag set with its two-way pulse (the cell is k's source)
+constexpr int32_t kAntiFlag = 1 << 30;
 
 // Everything a block needs to work on one instance (R = double or float
 // arrays are passed as void and typed inside the kernels).
@@ -436,8 +441,9 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
         int32_t q = at(D.cpmj, c);
         if (q >= 0)
             for (int32_t k; (k = D.cpmj_list[q]) >= 0; ++q) {
-                const Pmj &J = D.pmj[k];
-                if (n >= J.fire_o && n < J.fire_o + J.ndur) istim += R(J.amp);
+                const Pmj &J = D.pmj[k & (kAntiFlag - 1)];
+                const int64_t f = (k & kAntiFlag) ? J.fire_a : J.fire_o;
+                if (n >= f && n < f + J.ndur) istim += R(J.amp);
             }
     }
 
@@ -563,9 +569,18 @@ __global__ void __launch_bounds__(TILE) k_junctions(Tables tb, int32_t step_off)
     const R thr = R(P.thr);
     for (int32_t k = threadIdx.x; k < P.n_pmj; k += blockDim.x) {
         Pmj &J = P.pmj[k];
-        const R a = R(J.vprev), b = vp[J.node];
+        // source: a graph node (its potential at the start of the step is
+        // kept in vprev) or a cell (the tissue's v^n and v^{n+1})
+        R a, b;
+        if (J.src_cell >= 0) {
+            a = v0[J.src_cell];
+            b = v1[J.src_cell];
+        } else {
+            a = R(J.vprev);
+            b = vp[J.node];
+            J.vprev = double(b);
+        }
         if (a <= thr && b > thr) J.fire_o = n + 1 + J.delay_o;
-        J.vprev = double(b);
         if (J.two_way) {
             double m0 = 0.0, m1 = 0.0;
             for (int32_t r = J.roff; r < J.roff + J.rcnt; ++r) m0 += double(v0[P.jcells[r]]);

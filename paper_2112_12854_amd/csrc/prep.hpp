@@ -63,6 +63,7 @@ std::string prepare(const PrepIn &in, PrepOut &out);
 // ---------------------------------------------- Purkinje graph, junctions
 struct PmjIn {
     int32_t node = 0;                  // Purkinje node of the junction
+    int32_t cell = -1;                 // or its source cell (caller id; node ignored)
     double radius = 0.1, delay_ortho = 5.0, delay_anti = 3.0, amp = -200.0, dur = 0.5;
     int32_t two_way = 0;
 };
@@ -82,15 +83,20 @@ struct PurkIn {
 //   dv_i/dt += sum_{e in [off[i], off[i+1])} g[e] (v[nbr[e]] - v_i).
 // Junction k stimulates the cells jcells[jroff[k] .. jroff[k+1]) (internal
 // ids, listed in increasing caller id).  cpmj[c] (internal cell) is -1 or the
-// start of a -1-terminated list in cpmj_list of the junctions holding c.
+// start of a -1-terminated list in cpmj_list of the junctions pulsing c.
+// The graph may be empty (n == 0) when every junction has a source cell.
 struct PurkOut {
     int64_t n = 0;
     int32_t n_sub = 1;
     std::vector<int32_t> off, nbr;
     std::vector<double> g;
     std::vector<int32_t> jroff, jcells;
+    std::vector<int32_t> jsrc;         // per junction: internal source cell, or -1 (graph node)
+    // cpmj_list entries: k (pulse of junction k's region) or k | kAntiBit
+    // (two-way pulse of junction k onto this cell, its source)
     std::vector<int32_t> cpmj, cpmj_list;
 };
+constexpr int32_t kAntiBit = 1 << 30;
 
 std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut &tout,
                              PurkOut &out);

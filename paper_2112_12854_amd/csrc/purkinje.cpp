@@ -34,9 +34,10 @@ struct Grid {
 std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut &tout,
                              PurkOut &out) {
     const int64_t n = in.n;
-    if (n <= 0 || in.n_edges < 0 || !in.xyz || (in.n_edges > 0 && !in.edges))
+    if (n < 0 || (n == 0 && in.pmjs.empty())) return "empty Purkinje graph";
+    if (n > 0 && (in.n_edges < 0 || !in.xyz || (in.n_edges > 0 && !in.edges)))
         return "empty Purkinje graph";
-    if (!(in.sigma > 0)) return "Purkinje conductivity must be positive";
+    if (n > 0 && !(in.sigma > 0)) return "Purkinje conductivity must be positive";
     // slot offsets of the state arrays are 32-bit byte offsets
     if (n >= (int64_t)1 << 25) return "Purkinje graph too large";
     out.n = n;
@@ -137,9 +138,23 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
 
     out.jroff.assign(1, 0);
     out.jcells.clear();
+    out.jsrc.clear();
     for (const PmjIn &p : in.pmjs) {
-        if (p.node < 0 || p.node >= n) return "junction node out of range";
-        const double *x = in.xyz + 3 * (int64_t)p.node;
+        // source point and the kind of cell the region takes (0: any; a cell
+        // source couples to the other medium)
+        const double *x;
+        int kind = 0;
+        if (p.cell >= 0) {
+            if (p.cell >= nc) return "junction source cell out of range";
+            x = &cen[3 * (int64_t)p.cell];
+            kind = nverts(p.cell) == 3 ? 4 : 3;
+            out.jsrc.push_back(tout.iperm[p.cell]);
+        } else {
+            if (p.node < 0 || p.node >= n) return "junction node out of range";
+            x = in.xyz + 3 * (int64_t)p.node;
+            out.jsrc.push_back(-1);
+        }
+        auto ok = [&](int32_t c) { return kind == 0 || nverts(c) == kind; };
         auto dist = [&](int32_t c) {
             const double dx = cen[3 * (int64_t)c] - x[0], dy = cen[3 * (int64_t)c + 1] - x[1],
                          dz = cen[3 * (int64_t)c + 2] - x[2];
@@ -154,7 +169,7 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
                     auto it = grid.cells.find(Grid::pack(kx[0] + a, kx[1] + b, kx[2] + c));
                     if (it == grid.cells.end()) continue;
                     for (int32_t q : it->second)
-                        if (dist(q) <= p.radius) region.push_back(q);
+                        if (ok(q) && dist(q) <= p.radius) region.push_back(q);
                 }
         std::sort(region.begin(), region.end());
         region.erase(std::unique(region.begin(), region.end()), region.end());
@@ -164,6 +179,7 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
             double best = HUGE_VAL;
             int32_t bc = -1;
             auto consider = [&](int32_t c) {
+                if (!ok(c)) return;
                 const double d = dist(c);
                 if (d < best || (d == best && c < bc)) { best = d; bc = c; }
             };
@@ -187,7 +203,8 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
             } else {
                 for (int64_t c = 0; c < nc; ++c) consider((int32_t)c);
             }
-            if (bc < 0) return "no tissue cell for a junction";
+            if (bc < 0) return p.cell >= 0 ? "no cell of the other medium for a junction"
+                                           : "no tissue cell for a junction";
             for (int a = 0; a < nverts(bc); ++a) {
                 const int32_t node = tin.tets[4 * (int64_t)bc + a];
                 for (int32_t e = noff[node]; e < noff[node + 1]; ++e) region.push_back(ncell[e]);
@@ -199,10 +216,13 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
         out.jroff.push_back((int32_t)out.jcells.size());
     }
 
-    // ---- per cell: junctions holding it, in junction order
+    // ---- per cell: junctions pulsing it, in junction order (its regions'
+    // pulses, and the two-way pulses of junctions it is the source of)
     out.cpmj.assign(nc, -1);
     std::vector<int32_t> cnt(nc, 0);
     for (int32_t c : out.jcells) cnt[c]++;
+    for (size_t k = 0; k < in.pmjs.size(); ++k)
+        if (out.jsrc[k] >= 0 && in.pmjs[k].two_way) cnt[out.jsrc[k]]++;
     out.cpmj_list.clear();
     for (int64_t c = 0; c < nc; ++c)
         if (cnt[c] > 0) {
@@ -210,9 +230,12 @@ std::string prepare_purkinje(const PurkIn &in, const PrepIn &tin, const PrepOut 
             out.cpmj_list.resize(out.cpmj_list.size() + cnt[c] + 1, -1);
             cnt[c] = out.cpmj[c];   // next free entry
         }
-    for (size_t k = 0; k + 1 < out.jroff.size(); ++k)
+    for (size_t k = 0; k + 1 < out.jroff.size(); ++k) {
         for (int32_t q = out.jroff[k]; q < out.jroff[k + 1]; ++q)
             out.cpmj_list[cnt[out.jcells[q]]++] = (int32_t)k;
+        if (out.jsrc[k] >= 0 && in.pmjs[k].two_way)
+            out.cpmj_list[cnt[out.jsrc[k]]++] = (int32_t)k | kAntiBit;
+    }
     if (out.cpmj_list.empty()) out.cpmj_list.push_back(-1);
     return "";
 }

@@ -105,6 +105,8 @@ _SIGS = {
                                   C.c_int32, C.c_int32]),
     "ep_set_purkinje_scale": (C.c_int, [C.c_void_p, C.c_int64, _dp]),
     "ep_set_time_scheme": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ep_add_cell_junction": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                       C.c_int32, C.c_double, C.c_double]),
     "ep_add_pmj": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
                              C.c_int32, C.c_double, C.c_double]),
     "ep_get_purkinje_vm": (C.c_int, [C.c_void_p, _dp, C.c_int64]),
@@ -269,6 +271,9 @@ class Sim:
             for node in pk.pmj_nodes:
                 _check(L.ep_add_pmj(h, int(node), pk.pmj_radius, pk.delay_ortho, pk.delay_anti,
                                     int(pk.two_way), pk.pmj_amp, pk.pmj_dur), h)
+        for cj in getattr(w, "cell_junctions", []):
+            _check(L.ep_add_cell_junction(h, int(cj.cell), cj.radius, cj.delay_ortho, cj.delay_anti,
+                                          int(cj.two_way), cj.amp, cj.dur), h)
         for st in w.stimuli:
             ids = np.ascontiguousarray(st.ids, np.int32)
             _check(L.ep_add_stimulus(h, st.domain, ids.size, ids.ctypes.data_as(_ip),

@@ -134,3 +134,57 @@ def test_mixed_mesh_abi_errors(ep):
             assert r == ep.EP_EINVAL
         finally:
             L.ep_destroy(h)
+
+
+@pytest.mark.parametrize("drive,two_way", [("sheet", False), ("slab", True)])
+def test_shell_on_slab_junction_parity(ep, oracle_lib, drive, two_way):
+    """Communication nodes from the 2D shell onto the 3D slab (Sec. 3.3):
+    orthodromic (shell drives the slab) and two-way (the slab re-enters the
+    shell), FP64 parity with the oracle, FP32-mixed activation times within
+    0.5 ms, and a checkpoint that restores the junction schedule bitwise."""
+    w = M.shell_on_slab(drive=drive, two_way=two_way)
+    say(f"shell on slab drive={drive} two_way={two_way}: {w.n_tets} cells, "
+        f"{len(w.cell_junctions)} nodes")
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    f = ep.Sim(w, prec=ep.EP_FP32_MIXED)
+    o = oracle_lib.Sim(w)
+    for chunk in range(5):
+        g.step(150)
+        f.step(150)
+        o.step(150)
+        dv = np.max(np.abs(g.vm() - o.vm()))
+        assert dv <= TOL_MV, (chunk, dv)
+    ta = o.activation()
+    assert np.isfinite(ta).all()
+    assert same_times(g.activation(), ta) <= 1e-6
+    assert same_times(f.activation(), ta) <= 0.5
+    blob = g.checkpoint()
+    g.step(200)
+    c = ep.Sim(w, prec=ep.EP_FP64)
+    c.restore(blob)
+    c.step(200)
+    assert np.array_equal(g.vm(), c.vm())
+
+
+def test_cell_junction_abi_errors(ep):
+    L = ep.lib()
+    w = M.shell_on_slab()
+    o = ep.ep_options()
+    L.ep_default_options(C.byref(o))
+    h = C.c_void_p()
+    assert L.ep_create(C.byref(o), C.byref(h)) == ep.EP_OK
+    try:
+        assert L.ep_add_cell_junction(h, 0, 0.1, 5.0, 3.0, 0, -200.0, 0.5) == ep.EP_ESTATE
+        xyz = np.ascontiguousarray(w.xyz)
+        cells = np.ascontiguousarray(w.tets, np.int32)
+        assert L.ep_set_mesh(h, w.n_nodes, ep._d(xyz), w.n_tets, cells.ctypes.data_as(ep._ip)) == 0
+        assert L.ep_add_cell_junction(h, w.n_tets, 0.1, 5.0, 3.0, 0, -200.0, 0.5) == ep.EP_EINVAL
+        assert L.ep_add_cell_junction(h, 0, -0.1, 5.0, 3.0, 0, -200.0, 0.5) == ep.EP_EINVAL
+        assert L.ep_add_cell_junction(h, 0, 0.1, 5.0, 3.0, 0, -200.0, 0.5) == ep.EP_OK
+    finally:
+        L.ep_destroy(h)
+    # a tet-only mesh: a cell junction finds no cell of the other medium
+    t = M.config1(n_steps=0)
+    t.cell_junctions = [M.CellJunction(cell=5)]
+    with pytest.raises(ep.EPError):
+        ep.Sim(t)
