@@ -142,3 +142,58 @@ def sweep_requests(w: M.Workload, side: str, severities) -> list[M.Workload]:
     """One workload per bundle-branch severity, for submission to the
     server (`ep.Server.submit`) as a batch."""
     return [bundle_branch_block(w, side, float(s)) for s in severities]
+
+
+# --------------------------------------------- communication nodes (Sec. 3.3)
+# The paper spaces the nodes along its 1D bundles varsigma * tau apart:
+# internodal conduction speed 2 m/s times 0.5 ms, the largest activation
+# delay allowed between consecutive nodes (about 1 mm).
+BUNDLE_SPEED_MM_PER_MS = 2.0
+NODE_DELAY_MS = 0.5
+
+
+def communication_nodes(pk: M.Purkinje, spacing: float = BUNDLE_SPEED_MM_PER_MS * NODE_DELAY_MS,
+                        root: int = 0) -> np.ndarray:
+    """Graph nodes chosen as communication nodes: walking the graph from
+    `root`, a node is taken when its path distance from the last taken node
+    on its path reaches `spacing`; leaves are always taken."""
+    n = pk.xyz.shape[0]
+    adj = [[] for _ in range(n)]
+    for a, b in pk.edges:
+        L = float(np.linalg.norm(pk.xyz[a] - pk.xyz[b]))
+        adj[a].append((int(b), L))
+        adj[b].append((int(a), L))
+    chosen, seen = [], np.zeros(n, bool)
+    stack = [(root, 0.0)]
+    seen[root] = True
+    chosen.append(root)
+    while stack:
+        i, since = stack.pop()
+        kids = [(j, L) for j, L in adj[i] if not seen[j]]
+        for j, L in kids:
+            seen[j] = True
+            d = since + L
+            if d >= spacing - 1e-9 or len(adj[j]) == 1:
+                chosen.append(j)
+                d = 0.0
+            stack.append((j, d))
+    return np.array(sorted(chosen), np.int32)
+
+
+def bundle_coupling(w: M.Workload, spacing: float = BUNDLE_SPEED_MM_PER_MS * NODE_DELAY_MS,
+                    radius: float = 1.0, delay: float = 0.0, amp: float = -200.0,
+                    two_way: bool = False) -> M.Workload:
+    """Couple a workload's graph to the tissue through communication nodes
+    every `spacing` mm (Sec. 3.3: range R_S = 1 mm onto the atria, 0.1 mm
+    onto the Purkinje shell; the bundles fire the atria without delay)."""
+    if w.purkinje is None:
+        raise ValueError("needs a Purkinje / bundle graph")
+    c = _copy(w)
+    pk = c.purkinje
+    pk.pmj_nodes = communication_nodes(pk, spacing)
+    pk.pmj_radius = radius
+    pk.delay_ortho = delay
+    pk.pmj_amp = amp
+    pk.two_way = two_way
+    c.name = f"{w.name}-cn{spacing:g}"
+    return c

@@ -158,3 +158,22 @@ def test_scenario_abi_errors(ep):
             sv.submit(b, 10)
     finally:
         sv.close()
+
+
+def test_bundle_communication_nodes_parity(ep, oracle_lib):
+    """A bundle through a CRN atrial slab coupled by communication nodes
+    every 1 mm (range 1 mm, no delay): FP64 parity on tissue and graph."""
+    w = M.purkinje_slab(drive="graph", nx=40, ny=8, nz=2, n_steps=0)
+    w.model = np.full(w.n_tets, M.CRN, np.uint8)
+    w = S.bundle_coupling(w, radius=1.0)
+    say(f"bundle coupling: {len(w.purkinje.pmj_nodes)} communication nodes")
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    o = oracle_lib.Sim(w)
+    for chunk in range(4):
+        g.step(200)
+        o.step(200)
+        assert np.max(np.abs(g.vm() - o.vm())) <= TOL_MV
+        assert np.max(np.abs(g.purkinje_vm() - o.purkinje_vm())) <= TOL_MV
+    ta = o.activation()
+    assert np.isfinite(ta).sum() > 0.5 * w.n_tets
+    assert same_times(g.activation(), ta) <= 1e-6

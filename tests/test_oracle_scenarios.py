@@ -129,3 +129,55 @@ def test_tissue_block_isolates_its_core(oracle_lib):
     h = w.dims[3]
     assert np.isfinite(ta[d > r + h]).mean() > 0.99
     assert not np.isfinite(ta[d < r - 2 * h]).any()
+
+
+def test_communication_node_spacing():
+    """Sec. 3.3: nodes varsigma tau = 1 mm apart along the bundles; on a
+    chain of 0.1 mm segments that is every tenth node, plus the far end;
+    on the two-branch network each branch gets its own sequence."""
+    from test_oracle_purkinje import chain_workload
+    w = chain_workload(96, 0.1)
+    cn = S.communication_nodes(w.purkinje)
+    assert np.array_equal(cn, np.r_[np.arange(0, 96, 10), 95])
+    y = M.purkinje_slab().purkinje
+    cn = S.communication_nodes(y, spacing=1.0)
+    assert set(y.pmj_nodes.tolist()) <= set(cn.tolist())
+    # consecutive nodes along every path are at most spacing + one segment apart
+    x = y.xyz
+    d = np.linalg.norm(x[cn][:, None] - x[cn][None], axis=2)
+    np.fill_diagonal(d, np.inf)
+    assert d.min(axis=1).max() <= 1.0 + 0.1 + 1e-9
+
+
+def test_bundle_coupling_speeds_the_atrium(oracle_lib):
+    """A fast bundle (the graph) laid through a CRN atrial slab, both driven
+    at x = 0 and coupled by communication nodes (R_S = 1 mm, no delay): the
+    wave reaches the far half of the slab earlier than through the atrial
+    tissue alone, and the nodes' regions activate in the order of their
+    distance from the driven root."""
+    w = M.purkinje_slab(drive="graph", nx=40, ny=8, nz=2, n_steps=0)
+    w.model = np.full(w.n_tets, M.CRN, np.uint8)
+    w.purkinje.pmj_nodes = np.array([], np.int32)
+    x = w.xyz[w.tets].mean(axis=1)[:, 0]
+    w.stimuli.append(M.Stimulus(ids=np.nonzero(x < 1.0)[0].astype(np.int32), t0=0.0, dur=2.0,
+                                amp=-40.0))
+    coupled = S.bundle_coupling(w, radius=1.0)
+    ta = {}
+    regions = None
+    for name, ww in (("plain", w), ("coupled", coupled)):
+        o = oracle_lib.Sim(ww)
+        o.step(1000)
+        ta[name] = o.activation()
+        if name == "coupled":
+            regions = [o.pmj_region(k) for k in range(len(ww.purkinje.pmj_nodes))]
+    far = (x > 12.0) & (x < 14.0)
+    assert np.isfinite(ta["coupled"][far]).all()
+    plain = np.where(np.isfinite(ta["plain"][far]), ta["plain"][far], np.inf)
+    assert np.mean(ta["coupled"][far]) < plain.min() - 2.0
+    # along the trunk (nodes on the line y = const before the fork): regions
+    # activate in the order of their distance from the root
+    pk = coupled.purkinje
+    trunk = [k for k, i in enumerate(pk.pmj_nodes) if pk.edge_side is not None
+             and i < (pk.edge_side == -1).sum()]
+    t_reg = [np.nanmin(ta["coupled"][regions[k]]) for k in trunk]
+    assert len(t_reg) >= 3 and np.all(np.diff(t_reg) > 0)
