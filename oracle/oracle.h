@@ -100,7 +100,12 @@ int32_t orc_purkinje_n_sub(const orc_sim *s);
  * scheme, Sec. 3.2), 1 second-order Adams-Bashforth, which the paper names
  * as the way to shrink the time error of those states (Sec. 4):
  * y^{n+1} = y^n + dt (3/2 f^n - 1/2 f^{n-1}), forward Euler on step 0 (and
- * graph substep 0).  Gates stay Rush-Larsen in both.  AB2 is stable on half
+ * graph substep 0).  Gates stay Rush-Larsen in both; 2 adds the
+ * second-order Rush-Larsen step the paper names as the way to second order
+ * overall: each gate's steady state and time constant are evaluated at the
+ * midpoint predictions v^n + dt/2 f_v^n and c^n + dt/2 f_c^n of the potential
+ * and of the calcium concentrations it depends on (CRN's release gates u, v
+ * keep their level-n driver).  AB2 is stable on half
  * the interval of forward Euler, so a derived substep count uses half the
  * graph bound.  Call before stepping; returns -1 for an unknown scheme. */
 int orc_set_time_scheme(orc_sim *s, int scheme);

@@ -65,7 +65,8 @@ static double rush_larsen(double y, double yinf, double tau, double dt)
     return yinf + (y - yinf) * exp(-dt / tau);
 }
 
-double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hist *hist)
+double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hist *hist,
+                    const orc_mid *mid)
 {
     (void)istim;  /* the article's K_i balance carries no stimulus term */
     const double V = y[0];
@@ -129,7 +130,13 @@ double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hi
     const double Fn = 1e-12 * V_RELV * I_rel -
                       5e-13 / F_C * (0.5 * CM * I_CaL - 0.2 * CM * I_NaCa);
 
-    /* ---- gates, Rush-Larsen ---- */
+    /* ---- gates, Rush-Larsen at level n, or at the midpoint predictions of
+     * V and Ca_i (second-order variant; u and v keep the level-n release
+     * driver Fn) ---- */
+    const double Vg = mid ? V + 0.5 * dt * (mid->lmi - I_ion) : V;
+    const double cai_g = mid ? cai + 0.5 * dt * dCai : cai;
+    {
+    const double V = Vg, cai = cai_g;
     double a, b, yinf, tau;
     /* m: alpha = 0.32 (V+47.13)/(1 - exp(-0.1 (V+47.13))) */
     a = 3.2 * z_over_expm1(-0.1 * (V + 47.13));
@@ -201,6 +208,8 @@ double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hi
         const double ratio = 1.0 / z_over_expm1(-zz);  /* (1-e^{-z})/z */
         tau = 6.0 * ratio / (5.0 * (1.0 + 0.3 * exp(-zz)));
         w = rush_larsen(w, 1.0 - 1.0 / (1.0 + exp(-(V - 40.0) / 17.0)), tau, dt);
+    }
+
     }
 
     /* ---- concentrations, forward Euler or Adams-Bashforth 2 ---- */

@@ -22,18 +22,28 @@ static inline double orc_rate(orc_hist *h, int k, double r)
     return 1.5 * r - 0.5 * prev;
 }
 
+/* Second-order Rush-Larsen (with AB2 above): the gates' steady states and
+ * time constants are evaluated at midpoint predictions of the states they
+ * depend on, V + dt/2 (lmi - I_ion) with lmi = L - I_stim the rest of the
+ * potential's rate, and c + dt/2 (rate) for the calcium concentrations
+ * (through their buffered totals).  NULL: everything at level n. */
+typedef struct {
+    double lmi;
+} orc_mid;
+
 const char *orc_tp06_slot_name(int slot);
 void orc_tp06_init(double *y);
 double orc_tp06_step(int celltype, double *y, double dt, double istim,
-                     const double *gs, orc_hist *h);
+                     const double *gs, orc_hist *h, const orc_mid *mid);
 
 const char *orc_crn_slot_name(int slot);
 void orc_crn_init(double *y);
-double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hist *h);
+double orc_crn_step(double *y, double dt, double istim, const double *gs, orc_hist *h,
+                    const orc_mid *mid);
 
 const char *orc_stewart_slot_name(int slot);
 void orc_stewart_init(double *y);
 double orc_stewart_step(double *y, double dt, double istim, const double *gs,
-                        orc_hist *h);
+                        orc_hist *h, const orc_mid *mid);
 
 #endif

@@ -79,7 +79,7 @@ static double total_from_free(double c, double B, double K)
 }
 
 double orc_stewart_step(double *y, double dt, double istim, const double *gs,
-                        orc_hist *hist)
+                        orc_hist *hist, const orc_mid *mid)
 {
     const double V = y[0];
     double m = y[1], h = y[2], j = y[3], xr1 = y[4], xr2 = y[5], xs = y[6];
@@ -151,6 +151,14 @@ double orc_stewart_step(double *y, double dt, double istim, const double *gs,
     const double dKi = -(I_K1 + I_to + I_sus + I_fK + I_Kr + I_Ks - 2.0 * I_NaK +
                          I_pK + istim) * CAP / (V_C * F_C);
 
+    /* gates at level n, or at the midpoint predictions of V and Ca_SS
+     * (second-order variant) */
+    const double Vg = mid ? V + 0.5 * dt * (mid->lmi - I_ion) : V;
+    const double cass_g = mid ? free_from_total(total_from_free(cass, BUF_SS, K_BUFSS) +
+                                                    0.5 * dt * dCassT, BUF_SS, K_BUFSS)
+                              : cass;
+    {
+    const double V = Vg, cass = cass_g;
     double yinf, tau, a, b, c;
     yinf = 1.0 / ((1.0 + exp((-56.86 - V) / 9.03)) * (1.0 + exp((-56.86 - V) / 9.03)));
     a = 1.0 / (1.0 + exp((-60.0 - V) / 5.0));
@@ -218,6 +226,7 @@ double orc_stewart_step(double *y, double dt, double istim, const double *gs,
     a = exp(-2.9 - 0.04 * V);
     b = exp(3.6 + 0.11 * V);
     yf = rush_larsen(yf, yinf, 4000.0 / (a + b), dt);
+    }
 
     rbar += dt * orc_rate(hist, 0, dRbar);
     cai = free_from_total(total_from_free(cai, BUF_C, K_BUFC) + dt * orc_rate(hist, 1, dCaiT),

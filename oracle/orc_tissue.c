@@ -62,6 +62,7 @@ struct orc_sim {
     double gscale[4];
     int64_t step;
     int ab2;                    /* non-gating states by Adams-Bashforth 2 */
+    int rl2;                    /* gates at midpoint predictions (second order) */
     double *hist;               /* per cell: v rate, then the model's rates */
     /* Purkinje graph */
     int64_t np;
@@ -144,13 +145,13 @@ void orc_model_init(int model, double *y)
 }
 
 static double model_step(int model, double *y, double dt, double istim,
-                         const double *gscale, orc_hist *h)
+                         const double *gscale, orc_hist *h, const orc_mid *mid)
 {
     switch (model) {
     case ORC_TP06_ENDO: case ORC_TP06_MID: case ORC_TP06_EPI:
-        return orc_tp06_step(model, y, dt, istim, gscale, h);
-    case ORC_CRN: return orc_crn_step(y, dt, istim, gscale, h);
-    case ORC_STEWART: return orc_stewart_step(y, dt, istim, gscale, h);
+        return orc_tp06_step(model, y, dt, istim, gscale, h, mid);
+    case ORC_CRN: return orc_crn_step(y, dt, istim, gscale, h, mid);
+    case ORC_STEWART: return orc_stewart_step(y, dt, istim, gscale, h, mid);
     default: return 0.0;
     }
 }
@@ -158,7 +159,7 @@ static double model_step(int model, double *y, double dt, double istim,
 double orc_model_step(int model, double *y, double dt, double istim,
                       const double *gscale)
 {
-    return model_step(model, y, dt, istim, gscale, NULL);
+    return model_step(model, y, dt, istim, gscale, NULL, NULL);
 }
 
 #define ORC_HIST_SLOTS 7   /* v, then at most 6 non-gating model states */
@@ -669,8 +670,9 @@ static void purkinje_step(orc_sim *s, const double *v_old)
             double *hc = s->ab2 ? s->phist + i * ORC_HIST_SLOTS : NULL;
             const int first = n == 0 && sub == 0;
             orc_hist h = {hc ? hc + 1 : NULL, first};
+            const orc_mid mid = {L - s->pistim[i]};
             const double iion = model_step(s->pmodel, y, dtp, s->pistim[i], s->gscale,
-                                           hc ? &h : NULL);
+                                           hc ? &h : NULL, s->rl2 ? &mid : NULL);
             const double vnew = vp[i] + dtp * v_rate(s, hc, first, L - iion - s->pistim[i]);
             y[0] = vnew;
             if (!s->pstatus[i] && vp[i] <= s->thr && vnew > s->thr) {
@@ -1079,8 +1081,9 @@ static void one_step(orc_sim *s)
         const double vold = v[c];
         double *hc = s->ab2 ? s->hist + c * ORC_HIST_SLOTS : NULL;
         orc_hist h = {hc ? hc + 1 : NULL, n == 0};
+        const orc_mid mid = {s->L[c] - s->istim[c]};
         const double iion = model_step(s->model[c], y, dt, s->istim[c], s->gscale,
-                                       hc ? &h : NULL);
+                                       hc ? &h : NULL, s->rl2 ? &mid : NULL);
         const double vnew = vold + dt * v_rate(s, hc, n == 0, s->L[c] - iion - s->istim[c]);
         y[0] = vnew;
         /* activation: first upward crossing of the threshold */
@@ -1112,8 +1115,9 @@ static void one_step(orc_sim *s)
 
 int orc_set_time_scheme(orc_sim *s, int scheme)
 {
-    if ((scheme != 0 && scheme != 1) || s->step != 0) return -1;
-    s->ab2 = scheme;
+    if (scheme < 0 || scheme > 2 || s->step != 0) return -1;
+    s->ab2 = scheme >= 1;
+    s->rl2 = scheme == 2;
     if (s->np > 0) s->n_sub = graph_substeps(s);
     return 0;
 }

@@ -105,7 +105,7 @@ static double total_from_free(double c, double B, double K)
 }
 
 double orc_tp06_step(int celltype, double *y, double dt, double istim,
-                     const double *gs, orc_hist *hist)
+                     const double *gs, orc_hist *hist, const orc_mid *mid)
 {
     const double V = y[0];
     double m = y[1], h = y[2], j = y[3], xr1 = y[4], xr2 = y[5], xs = y[6];
@@ -183,7 +183,6 @@ double orc_tp06_step(int celltype, double *y, double dt, double istim,
     /* ---- calcium dynamics at level n ---- */
     const double kcasr = MAX_SR - (MAX_SR - MIN_SR) / (1.0 + (EC / casr) * (EC / casr));
     const double k1 = K1P / kcasr;
-    const double k2 = K2P * kcasr;
     const double O = k1 * cass * cass * rbar / (K3 + k1 * cass * cass);
     const double I_rel = V_REL * O * (casr - cass);
     const double I_up = VMAX_UP / (1.0 + (K_UP * K_UP) / (cai * cai));
@@ -201,7 +200,19 @@ double orc_tp06_step(int celltype, double *y, double dt, double istim,
     const double dKi = -(I_K1 + I_to + I_Kr + I_Ks - 2.0 * I_NaK + I_pK + istim) *
                        CAP / (V_C * F_C);
 
-    /* ---- gating variables, Rush-Larsen at V^n ---- */
+    /* ---- gating variables, Rush-Larsen at V^n, or at the midpoint
+     * predictions of V, Ca_SS and Ca_SR (second-order variant) ---- */
+    double Vg = V, cass_g = cass, casr_g = casr;
+    if (mid) {
+        Vg = V + 0.5 * dt * (mid->lmi - I_ion);
+        cass_g = free_from_total(total_from_free(cass, BUF_SS, K_BUFSS) + 0.5 * dt * dCassT,
+                                 BUF_SS, K_BUFSS);
+        casr_g = free_from_total(total_from_free(casr, BUF_SR, K_BUFSR) + 0.5 * dt * dCasrT,
+                                 BUF_SR, K_BUFSR);
+    }
+    {
+    const double V = Vg, cass = cass_g;
+    const double k2 = K2P * (MAX_SR - (MAX_SR - MIN_SR) / (1.0 + (EC / casr_g) * (EC / casr_g)));
     double yinf, tau, a, b, c;
     /* m */
     yinf = 1.0 / ((1.0 + exp((-56.86 - V) / 9.03)) * (1.0 + exp((-56.86 - V) / 9.03)));
@@ -286,6 +297,7 @@ double orc_tp06_step(int celltype, double *y, double dt, double istim,
     {
         const double rate = k2 * cass + K4;
         rbar = rush_larsen(rbar, K4 / rate, 1.0 / rate, dt);
+    }
     }
 
     /* ---- concentrations, forward Euler or Adams-Bashforth 2 (buffered
