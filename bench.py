@@ -361,8 +361,9 @@ def run_ab2(ep, meshgen, args):
     2 (Sec. 4) instead of forward Euler: cost of the extra rate history."""
     t0 = time.time()
     w = meshgen.config2(n_steps=args.steps, nx=args.nx, ny=args.ny, nz=args.nz)
-    w.time_scheme = 1
-    log(f"workload {w.name} (AB2): {w.n_tets} tets ({time.time() - t0:.1f}s)")
+    w.time_scheme = args.ab2
+    tag = "ab2" if args.ab2 == 1 else "rl2-ab2"
+    log(f"workload {w.name} ({tag}): {w.n_tets} tets ({time.time() - t0:.1f}s)")
     res = {}
     for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
         r = run_precision(ep, w, prec, args.steps, args.warmup, args.chunk, args.steps)
@@ -370,16 +371,17 @@ def run_ab2(ep, meshgen, args):
         res[name] = r
     f32 = res["fp32"]
     out = {
-        "metric": "cell-steps/s (ionic+FV step, Adams-Bashforth 2 non-gating states)",
+        "metric": "cell-steps/s (ionic+FV step, " + ("Adams-Bashforth 2 non-gating states)"
+                   if args.ab2 == 1 else "second-order Rush-Larsen + Adams-Bashforth 2)"),
         "value": f32["cell_steps_per_s"], "unit": "cell-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64conc", "data": "synthetic",
-        "config": {"workload": w.name + "-ab2", "n_tets": w.n_tets, "dt_ms": w.dt},
+        "config": {"workload": w.name + "-" + tag, "n_tets": w.n_tets, "dt_ms": w.dt},
         "fp64": {"value": res["fp64"]["cell_steps_per_s"], "ms_per_step": res["fp64"]["ms_per_step"],
                  "cell_kernel_ms": res["fp64"]["cell_kernel_ms"],
                  "cell_GBps": res["fp64"]["cell_GBps"], "cell_bytes": res["fp64"]["cell_bytes"]},
-        "roofline": {"bound": "hbm", "kernel": "k_cell<float, AB2>", "achieved": f32["cell_GBps"],
+        "roofline": {"bound": "hbm", "kernel": f"k_cell<float, scheme {args.ab2}>", "achieved": f32["cell_GBps"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": f32["cell_GBps"] / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes": f32["cell_bytes"]},
         "cpu_baseline": None,
@@ -449,8 +451,9 @@ def main():
                     help="bidomain vs monodomain step time on the paper's benchmark box")
     ap.add_argument("--sheet", action="store_true",
                     help="a 2D medium of 5.12M triangles instead of the slab")
-    ap.add_argument("--ab2", action="store_true",
-                    help="the slab with Adams-Bashforth 2 for the non-gating states")
+    ap.add_argument("--ab2", type=int, nargs="?", const=1, default=0, metavar="SCHEME",
+                    help="the slab with Adams-Bashforth 2 for the non-gating states "
+                         "(1), also with second-order Rush-Larsen gates (2)")
     ap.add_argument("--heart", action="store_true",
                     help="the three-media heart instead of the slab (timed steps only)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",

@@ -206,12 +206,17 @@ ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub);
  * Adams-Bashforth step the paper names for a smaller time error (Sec. 4),
  *   y^{n+1} = y^n + dt (3/2 f^n - 1/2 f^{n-1}),
  * forward Euler on step 0 (graph: substep 0); the gates stay Rush-Larsen, so
- * the scheme as a whole stays first order.  AB2 keeps one previous rate per
+ * the scheme as a whole stays first order.  EP_SCHEME_RL2_AB2: also the
+ * second-order Rush-Larsen step the paper names for second order overall:
+ * each gate's steady state and time constant are taken at the midpoint
+ * predictions v^n + dt/2 f_v^n and c^n + dt/2 f_c^n of the potential and of
+ * the calcium concentrations it depends on (CRN's release gates u, v keep
+ * their level-n driver).  AB2 keeps one previous rate per
  * non-gating state (device memory, part of the checkpoint) and is stable on
  * half the interval of forward Euler: a derived graph substep count uses
  * half the bound, and dt itself must suit.  Not with the bidomain model
  * (EP_EINVAL).  Call before ep_init. */
-typedef enum { EP_SCHEME_FE = 0, EP_SCHEME_AB2 = 1 } ep_time_scheme;
+typedef enum { EP_SCHEME_FE = 0, EP_SCHEME_AB2 = 1, EP_SCHEME_RL2_AB2 = 2 } ep_time_scheme;
 ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme);
 
 /* Bidomain model (Sec. 3.1 eq. electro, Sec. 3.2 eq. electro2_3d) instead of

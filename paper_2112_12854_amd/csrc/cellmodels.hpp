@@ -119,9 +119,10 @@ __host__ __device__ inline void init(double *y) {
     for (int i = 0; i < 19; ++i) y[i] = s[i];
 }
 
-template <typename R, typename E = FwdEuler>
+template <typename R, bool RL2 = false, typename E = FwdEuler>
 __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
-                                  double dtd, R istim, const GScale &gs, const E &e = E()) {
+                                  double dtd, R istim, const GScale &gs, const E &e = E(),
+                                  R lmi = R(0)) {
     const R frt = R(1.0 / RTF);
     const double cai = c[0], casr = c[1], cass = c[2], nai = c[3], ki = c[4];
     const R rtf = R(RTF);
@@ -183,7 +184,21 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
     const double rNai = -double(INa + IbNa + R(3) * (INaK + INaCa)) * INV_VCF;
     const double rKi = -double(IK1 + Ito + IKr + IKs - R(2) * INaK + IpK + istim) * INV_VCF;
 
-    // ---- gates (Rush-Larsen at V^n)
+    // ---- gates: Rush-Larsen at level n, or (second-order variant) with
+    // their rates at the midpoint predictions of V, Ca_SS and Ca_SR
+    R Vg = V;
+    double cass_g = cass, k2g = k2;
+    if constexpr (RL2) {
+        Vg = V + R(0.5) * dt * (lmi - Iion);
+        cass_g = buffered_free(buffered_total(cass, 0.4, 0.00025) + 0.5 * dtd * rCass, 0.4, 0.00025);
+        const double casr_g = buffered_free(buffered_total(casr, 10.0, 0.3) + 0.5 * dtd * rCasr,
+                                            10.0, 0.3);
+        const double ecg = 1.5 / casr_g;
+        k2g = 0.045 * (2.5 - 1.5 / (1.0 + ecg * ecg));
+    }
+    {
+    const R V = Vg;
+    const double cass = cass_g, k2 = k2g;
     {   // m
         const R s1 = sig((R(-56.86) - V) * R(1.0 / 9.03));
         const R am = sig((R(-60) - V) * R(0.2));
@@ -265,7 +280,9 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
         g[12] = rl(rbar, R(0.005 / kk), R(kk), dt);
     }
 
-    // ---- concentrations, forward Euler (FP64)
+    }
+
+    // ---- concentrations, forward Euler or Adams-Bashforth 2 (FP64)
     c[0] = buffered_free(buffered_total(cai, 0.2, 0.001) + dtd * e(rCai, 0), 0.2, 0.001);
     c[1] = buffered_free(buffered_total(casr, 10.0, 0.3) + dtd * e(rCasr, 1), 10.0, 0.3);
     c[2] = buffered_free(buffered_total(cass, 0.4, 0.00025) + dtd * e(rCass, 2), 0.4, 0.00025);
@@ -295,9 +312,9 @@ __host__ __device__ inline void init(double *y) {
     for (int i = 0; i < 21; ++i) y[i] = s[i];
 }
 
-template <typename R, typename E = FwdEuler>
+template <typename R, bool RL2 = false, typename E = FwdEuler>
 __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
-                                  const GScale &gs, const E &e = E()) {
+                                  const GScale &gs, const E &e = E(), R lmi = R(0)) {
     const R frt = R(1.0 / RTF), rtf = R(RTF);
     const double cai = c[0], caup = c[1], carel = c[2], nai = c[3], ki = c[4];
     const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
@@ -352,7 +369,17 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     const double Fn = 1e-12 * VREL * Irel -
                       (5e-13 / FARADAY) * CM * (0.5 * double(ICaL) - 0.2 * double(INaCa));
 
-    // gates
+    // gates: at level n, or (second-order variant) at the midpoint
+    // predictions of V and Ca_i; u and v keep the level-n driver Fn
+    R Vg = V;
+    double cai_g = cai;
+    if constexpr (RL2) {
+        Vg = V + R(0.5) * dt * (lmi - Iion);
+        cai_g = cai + 0.5 * dtd * rCai;
+    }
+    {
+    const R V = Vg;
+    const double cai = cai_g;
     {   // m: alpha = 0.32 (V+47.13) / (1 - e^{-0.1 (V+47.13)})
         const R a = R(3.2) * z_expm1(R(-0.1) * (V + R(47.13)));
         const R b = R(0.08) * xexp(-V * R(1.0 / 11.0));
@@ -427,6 +454,7 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
         const R k = R(5.0 / 6.0) * z_expm1(-z) * (R(1) + R(0.3) * xexp(-z));
         g[14] = rl(w, R(1) - sig((V - R(40)) * R(-1.0 / 17.0)), k, dt);
     }
+    }
     c[0] = cai + dtd * e(rCai, 0);
     c[1] = caup + dtd * e(rCaup, 1);
     c[2] = carel + dtd * e(rCarel, 2);
@@ -463,9 +491,9 @@ __host__ __device__ inline void init(double *y) {
     for (int i = 0; i < 20; ++i) y[i] = s[i];
 }
 
-template <typename R, typename E = FwdEuler>
+template <typename R, bool RL2 = false, typename E = FwdEuler>
 __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
-                                  R istim, const GScale &gs, const E &e = E()) {
+                                  R istim, const GScale &gs, const E &e = E(), R lmi = R(0)) {
     const R frt = R(1.0 / RTF), rtf = R(RTF);
     const double rbar = c[0], cai = c[1], casr = c[2], cass = c[3], nai = c[4], ki = c[5];
     const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
@@ -526,6 +554,17 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     const double rKi = -double(IK1 + Ito + Isus + IfK + IKr + IKs - R(2) * INaK + IpK + istim) *
                        INV_VCF;
 
+    // gates: at level n, or (second-order variant) at the midpoint
+    // predictions of V and Ca_SS
+    R Vg = V;
+    double cass_g = cass;
+    if constexpr (RL2) {
+        Vg = V + R(0.5) * dt * (lmi - Iion);
+        cass_g = buffered_free(buffered_total(cass, 0.4, 0.00025) + 0.5 * dtd * rCass, 0.4, 0.00025);
+    }
+    {
+    const R V = Vg;
+    const double cass = cass_g;
     {
         const R s1 = sig((R(-56.86) - V) * R(1.0 / 9.03));
         const R am = sig((R(-60) - V) * R(0.2));
@@ -595,6 +634,7 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     {   // I_f gate
         const R k = (xexp(R(-2.9) - R(0.04) * V) + xexp(R(3.6) + R(0.11) * V)) * R(1.0 / 4000.0);
         g[12] = rl(y, sig((V + R(80.6)) * R(1.0 / 6.8)), k, dt);
+    }
     }
     c[0] = rbar + dtd * e(rRbar, 0);
     c[1] = buffered_free(buffered_total(cai, 0.2, 0.001) + dtd * e(rCai, 1), 0.2, 0.001);

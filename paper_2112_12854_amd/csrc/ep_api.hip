@@ -253,7 +253,7 @@ ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t r
         restart < 1 || restart > 1000 || !(tol > 0) || max_iter < 1)
         return fail(s, EP_EINVAL, "bad bidomain parameters");
     ep::InstSpec &sp = s->spec;
-    if (sp.ab2) return fail(s, EP_EINVAL, "the bidomain model steps by forward Euler only");
+    if (sp.scheme != 0) return fail(s, EP_EINVAL, "the bidomain model steps by forward Euler only");
     sp.bido = true;
     sp.sigma_el = sigma_el;
     sp.sigma_et = sigma_et;
@@ -266,10 +266,11 @@ ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t r
 ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "the scheme is frozen after ep_init");
-    if (scheme != EP_SCHEME_FE && scheme != EP_SCHEME_AB2) return fail(s, EP_EINVAL, "unknown time scheme");
-    if (scheme == EP_SCHEME_AB2 && s->spec.bido)
+    if (scheme != EP_SCHEME_FE && scheme != EP_SCHEME_AB2 && scheme != EP_SCHEME_RL2_AB2)
+        return fail(s, EP_EINVAL, "unknown time scheme");
+    if (scheme != EP_SCHEME_FE && s->spec.bido)
         return fail(s, EP_EINVAL, "the bidomain model steps by forward Euler only");
-    s->spec.ab2 = scheme == EP_SCHEME_AB2;
+    s->spec.scheme = scheme;
     return EP_OK;
 }
 
@@ -633,7 +634,7 @@ ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes) {
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     CkptHeader h{CKPT_MAGIC, s->inst.desc.nc, s->inst.desc.nn, s->inst.host_step, s->inst.rs,
                  (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n, s->inst.bido ? 1 : 0,
-                 s->inst.ab2 ? 1 : 0};
+                 s->inst.scheme};
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
@@ -654,7 +655,7 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes) {
     if (h.magic != CKPT_MAGIC || h.n_tets != s->inst.desc.nc || h.n_nodes != s->inst.desc.nn ||
         h.rs != s->inst.rs || h.trace_cap != s->inst.trace_cap || h.n_purkinje != s->inst.pk.n ||
         h.n_pmj != (int32_t)s->inst.n_pmj || h.bidomain != (s->inst.bido ? 1 : 0) ||
-        h.time_scheme != (s->inst.ab2 ? 1 : 0))
+        h.time_scheme != s->inst.scheme)
         return fail(s, EP_EINVAL, "checkpoint does not match this simulation");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const char *p = (const char *)buf + sizeof(h);

@@ -223,7 +223,7 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
         pin.chi = sp.chi;
         pin.cm = sp.cm;
         pin.n_sub = sp.purk.n_sub;
-        pin.ab2 = sp.ab2;
+        pin.ab2 = sp.scheme >= 1;
         pin.pmjs = sp.purk.pmjs;
         e = prepare_purkinje(pin, in, I.prep, I.pk);
         if (!e.empty()) { st = EP_EINVAL; return e; }
@@ -273,7 +273,7 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
             b += 2 * round256(c * 4) + round256((na + 1) * 4) + round256(c * 8) +
                  round256(na * na * 8) + 2 * round256(c * 8) + 2 * round256(na * 8);
     }
-    if (sp.ab2) {
+    if (sp.scheme >= 1) {
         b += round256(c * r) + round256(NC_MAX * c * 8);
         if (I.pk.n > 0) b += round256((size_t)I.pk.n * r) + round256(NC_MAX * (size_t)I.pk.n * 8);
     }
@@ -360,7 +360,7 @@ std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) 
     P.model = I.pmodel;
     P.tv[0] = I.desc.v[0];
     P.tv[1] = I.desc.v[1];
-    if (sp.ab2) {
+    if (sp.scheme >= 1) {
         P.hv = zalloc(I, (size_t)np * rs);
         P.hc = (double *)zalloc(I, NC_MAX * (size_t)np * 8);
         if (!P.hv || !P.hc) return fail_mem();
@@ -508,8 +508,9 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     }
     D.ctrl = I.d_ctrl;
     I.host_step = 0;
-    I.ab2 = sp.ab2;
-    if (sp.ab2) {
+    I.ab2 = sp.scheme >= 1;
+    I.scheme = sp.scheme;
+    if (I.ab2) {
         D.hv = zalloc(I, nc * (size_t)rs);
         D.hc = (double *)zalloc(I, NC_MAX * nc * 8);
         if (!D.hv || !D.hc) return fail_mem();
@@ -601,18 +602,18 @@ Tables tables(const Stepper &s) {
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
 // Cell kernels of step offset `off`, one launch per model class present.
-template <typename R, bool BIDO, bool AB2>
+template <typename R, bool BIDO, int SCH>
 void launch_cells_v(Stepper &s, const Tables &tb, int32_t off) {
     Tables t[4] = {tb, tb, tb, tb};
     for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + s.cls_base[k];
     if (s.cls_tiles[0])
-        k_cell<R, 1, BIDO, AB2><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
+        k_cell<R, 1, BIDO, SCH><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
     if (s.cls_tiles[1])
-        k_cell<R, 2, BIDO, AB2><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
+        k_cell<R, 2, BIDO, SCH><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
     if (s.cls_tiles[2])
-        k_cell<R, 4, BIDO, AB2><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
+        k_cell<R, 4, BIDO, SCH><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
     if (s.cls_tiles[3])
-        k_cell<R, 8, BIDO, AB2><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
+        k_cell<R, 8, BIDO, SCH><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
 }
 
 // bidomain instances run in FP64 with forward Euler only (checked at
@@ -620,10 +621,11 @@ void launch_cells_v(Stepper &s, const Tables &tb, int32_t off) {
 template <typename R>
 void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
     if constexpr (sizeof(R) == 8) {
-        if (s.bido) { launch_cells_v<R, true, false>(s, tb, off); return; }
+        if (s.bido) { launch_cells_v<R, true, 0>(s, tb, off); return; }
     }
-    if (s.ab2) launch_cells_v<R, false, true>(s, tb, off);
-    else launch_cells_v<R, false, false>(s, tb, off);
+    if (s.scheme == 2) launch_cells_v<R, false, 2>(s, tb, off);
+    else if (s.scheme == 1) launch_cells_v<R, false, 1>(s, tb, off);
+    else launch_cells_v<R, false, 0>(s, tb, off);
 }
 
 template <typename R>
@@ -647,8 +649,9 @@ void launch_purkinje(Stepper &s, int32_t off) {
     const Tables tb = tables(s);
     // (no graph tiles when every junction has a source cell)
     for (int32_t sub = 0; s.n_pt > 0 && sub < s.n_sub_max; ++sub) {
-        if (s.ab2) k_purkinje<R, true><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
-        else k_purkinje<R, false><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+        if (s.scheme == 2) k_purkinje<R, 2><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+        else if (s.scheme == 1) k_purkinje<R, 1><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+        else k_purkinje<R, 0><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
     }
     k_junctions<R><<<(int)s.n_pk, TILE, 0, s.stream>>>(tb, off);
 }
@@ -706,10 +709,10 @@ std::string stepper_sync_tables(Stepper &s) {
     std::vector<PurkDesc> pk;
     int32_t nsub = 0;
     s.bido = false;
-    s.ab2 = false;
+    s.scheme = 0;
     for (const Inst *I : s.insts) {
         s.bido = s.bido || I->bido;
-        s.ab2 = s.ab2 || I->ab2;
+        s.scheme = std::max(s.scheme, I->scheme);
     }
     // cell tiles class by class; tile `local` numbers run over the instance
     std::vector<int32_t> next_local(s.insts.size(), 0);

@@ -52,9 +52,10 @@ struct InstSpec {
     double sigma_el = 0.62, sigma_et = 0.24, bido_tol = 1e-6;
     int32_t bido_restart = 30, bido_max_iter = 2000;
     int32_t bido_coarse = 2048;        // aggregates of the preconditioner (0: none)
-    // non-gating states (v, concentrations) by Adams-Bashforth 2 instead of
-    // forward Euler; gates stay Rush-Larsen
-    bool ab2 = false;
+    // time scheme: 0 Rush-Larsen + forward Euler, 1 with Adams-Bashforth 2
+    // for the non-gating states, 2 also with midpoint-rate (second-order)
+    // Rush-Larsen gates
+    int scheme = 0;
 };
 
 // Device arrays of the extracellular solve of one bidomain instance.
@@ -121,6 +122,7 @@ struct Inst {
     Bido bd;
     Coarse coarse;                     // host copy until upload
     bool ab2 = false;                  // Adams-Bashforth 2 history allocated
+    int scheme = 0;
 };
 
 // An instance with a Purkinje graph or with junctions (of graph nodes or of
@@ -177,7 +179,7 @@ struct Stepper {
     int64_t n_ct = 0, n_nt = 0, n_pt = 0, n_pk = 0;
     int32_t n_sub_max = 0;             // graph substeps per step (max over instances)
     bool bido = false;                 // the (single) instance is a bidomain one
-    bool ab2 = false;                  // instances step by Adams-Bashforth 2 (all or none)
+    int scheme = 0;                    // time scheme of the instances (all the same)
     // pinned staging of the tables
     void *h_stage = nullptr;
     size_t stage_bytes = 0;

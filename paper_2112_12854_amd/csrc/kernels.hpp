@@ -357,27 +357,31 @@ __device__ __forceinline__ R model_io(__amdgpu_buffer_rsrc_t rgate, __amdgpu_buf
     return iion;
 }
 
-template <typename R, int MSET, bool AB2 = false>
+// Time schemes: 0 Rush-Larsen + forward Euler (the paper's), 1 Rush-Larsen
+// + Adams-Bashforth 2 for the non-gating states, 2 as 1 with the gates'
+// rates at midpoint predictions (second order overall).
+template <typename R, int MSET, int SCH = 0>
 __device__ __forceinline__ R ionic(int md, R v, __amdgpu_buffer_rsrc_t rgate,
                                    __amdgpu_buffer_rsrc_t rconc, int64_t N, uint32_t c, R dt,
                                    double dtd, R istim, const GScale &gs,
                                    __amdgpu_buffer_rsrc_t rhist = rsrc(nullptr),
-                                   bool first = false) {
+                                   bool first = false, R lmi = R(0)) {
+    constexpr bool HIST = SCH >= 1, MID = SCH == 2;
     R iion = R(0);
     if ((MSET & 1) && md <= 2) {
-        iion = model_io<R, tp06::NG, tp06::NC, AB2>(
+        iion = model_io<R, tp06::NG, tp06::NC, HIST>(
             rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
-                return tp06::step<R>(md, v, g, cc, dt, dtd, istim, gs, e);
+                return tp06::step<R, MID>(md, v, g, cc, dt, dtd, istim, gs, e, lmi);
             });
     } else if ((MSET & 2) && md == 3) {
-        iion = model_io<R, crn::NG, crn::NC, AB2>(
+        iion = model_io<R, crn::NG, crn::NC, HIST>(
             rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
-                return crn::step<R>(v, g, cc, dt, dtd, gs, e);
+                return crn::step<R, MID>(v, g, cc, dt, dtd, gs, e, lmi);
             });
     } else if ((MSET & 4) && md == 4) {
-        iion = model_io<R, stewart::NG, stewart::NC, AB2>(
+        iion = model_io<R, stewart::NG, stewart::NC, HIST>(
             rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
-                return stewart::step<R>(v, g, cc, dt, dtd, istim, gs, e);
+                return stewart::step<R, MID>(v, g, cc, dt, dtd, istim, gs, e, lmi);
             });
     }
     return iion;
@@ -397,9 +401,10 @@ __device__ __forceinline__ R v_update(R v, R dt, R F, void *hv, uint32_t i, bool
     }
 }
 
-template <typename R, int MSET, bool BIDO, bool AB2>
+template <typename R, int MSET, bool BIDO, int SCH>
 __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
                                           uint32_t active, bool sample, double &vol_v) {
+    constexpr bool AB2 = SCH >= 1;
     const int64_t N = D.nc;
     const R *__restrict__ vin = (const R *)D.v[n & 1];
     R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
@@ -452,8 +457,8 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     const R dt = R(D.dt);
     R iion;
     if constexpr (AB2)
-        iion = ionic<R, MSET, true>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim,
-                                    D.gs, rsrc(D.hc), n == 0);
+        iion = ionic<R, MSET, SCH>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim,
+                                   D.gs, rsrc(D.hc), n == 0, L - istim);
     else
         iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim, D.gs);
 
@@ -488,7 +493,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 
 // One launch per model class: the host passes tb.cell_tiles pointing at the
 // first tile of the class in the class-ordered tile list.
-template <typename R, int MSET, bool BIDO = false, bool AB2 = false>
+template <typename R, int MSET, bool BIDO = false, int SCH = 0>
 __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
     __shared__ double red[TILE];
     const Tile &T = tb.cell_tiles[my_tile(remap)];
@@ -499,7 +504,7 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
     double x = 0.0;
     const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
     if ((int32_t)threadIdx.x < T.count)
-        cell_step<R, MSET, BIDO, AB2>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
+        cell_step<R, MSET, BIDO, SCH>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
     if (sample) tile_partial(D, T, x, red);
 }
 
@@ -507,8 +512,9 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
 // Substep `sub` of step n of every graph: explicit update of node i with the
 // graph flux, the stimuli of the graph and of its two-way junctions, and the
 // node's cell model over dt / n_sub; first upward threshold crossing.
-template <typename R, bool AB2 = false>
+template <typename R, int SCH = 0>
 __global__ void __launch_bounds__(TILE) k_purkinje(Tables tb, int32_t step_off, int32_t sub) {
+    constexpr bool AB2 = SCH >= 1;
     const PTile &T = tb.purk_tiles[blockIdx.x];
     const PurkDesc &P = T.p;
     int64_t n;
@@ -539,8 +545,8 @@ __global__ void __launch_bounds__(TILE) k_purkinje(Tables tb, int32_t step_off, 
     const R dt = R(P.dtp);
     R iion;
     if constexpr (AB2)
-        iion = ionic<R, 15, true>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp,
-                                  istim, P.gs, rsrc(P.hc), q == 0);
+        iion = ionic<R, 15, SCH>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp,
+                                 istim, P.gs, rsrc(P.hc), q == 0, L - istim);
     else
         iion = ionic<R, 15>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp, istim,
                             P.gs);

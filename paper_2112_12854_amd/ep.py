@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libep.so")
 
 EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ESTATE, EP_ENUMERIC, EP_EBUSY = 0, -1, -2, -3, -4, -5, -6
 EP_FP64, EP_FP32_MIXED = 0, 1
-EP_SCHEME_FE, EP_SCHEME_AB2 = 0, 1
+EP_SCHEME_FE, EP_SCHEME_AB2, EP_SCHEME_RL2_AB2 = 0, 1, 2
 EP_TP06_ENDO, EP_TP06_MID, EP_TP06_EPI, EP_CRN, EP_STEWART, EP_PASSIVE = range(6)
 EP_MAX_SLOTS = 21
 STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EDEVICE",

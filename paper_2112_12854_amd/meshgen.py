@@ -86,7 +86,7 @@ class Workload:
     purkinje: object = None            # Purkinje graph (heart workloads)
     bidomain: object = None            # Bidomain parameters, or monodomain
     landmarks: dict = field(default_factory=dict)   # name -> [3] point (mm)
-    time_scheme: int = 0               # 0 forward Euler, 1 Adams-Bashforth 2
+    time_scheme: int = 0               # 0 forward Euler, 1 AB2, 2 AB2 + second-order RL
     cell_junctions: list = field(default_factory=list)   # CellJunction, after the graph's
 
     @property

@@ -114,7 +114,7 @@ def test_time_scheme_abi_errors(ep):
     h = C.c_void_p()
     assert L.ep_create(C.byref(o), C.byref(h)) == ep.EP_OK
     try:
-        assert L.ep_set_time_scheme(h, 2) == ep.EP_EINVAL
+        assert L.ep_set_time_scheme(h, 3) == ep.EP_EINVAL
         assert L.ep_set_time_scheme(h, -1) == ep.EP_EINVAL
         assert L.ep_set_time_scheme(h, ep.EP_SCHEME_AB2) == ep.EP_OK
         xyz = np.ascontiguousarray(w.xyz)
@@ -124,5 +124,45 @@ def test_time_scheme_abi_errors(ep):
         assert L.ep_set_time_scheme(h, ep.EP_SCHEME_FE) == ep.EP_OK
         assert L.ep_set_bidomain(h, 0.62, 0.24, 30, 1e-6, 100) == ep.EP_OK
         assert L.ep_set_time_scheme(h, ep.EP_SCHEME_AB2) == ep.EP_EINVAL
+        assert L.ep_set_time_scheme(h, ep.EP_SCHEME_RL2_AB2) == ep.EP_EINVAL
     finally:
         L.ep_destroy(h)
+
+
+@pytest.mark.parametrize("model", [M.TP06_ENDO, M.CRN, M.STEWART])
+def test_second_order_rush_larsen_parity(ep, oracle_lib, model):
+    """The second-order Rush-Larsen option (gates at midpoint predictions,
+    AB2 for the rest) on each cell model: FP64 parity with the oracle,
+    FP32-mixed activation times within 0.5 ms."""
+    w = M.config1(n_steps=0)
+    w.model = np.full(w.n_tets, model, np.uint8)
+    if model != M.TP06_ENDO:
+        w.stimuli[0].amp = -100.0
+    w.time_scheme = 2
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    f = ep.Sim(w, prec=ep.EP_FP32_MIXED)
+    o = oracle_lib.Sim(w)
+    for chunk in range(4):
+        g.step(250)
+        f.step(250)
+        o.step(250)
+        dv = np.max(np.abs(g.vm() - o.vm()))
+        assert dv <= TOL_MV, (chunk, dv)
+    ta = o.activation()
+    assert np.isfinite(ta).sum() > 0.3 * w.n_tets
+    assert same_times(g.activation(), ta) <= 1e-6
+    assert same_times(f.activation(), ta) <= 0.5
+
+
+def test_second_order_graph_parity(ep, oracle_lib):
+    w = M.purkinje_slab(drive="graph")
+    w.time_scheme = 2
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    o = oracle_lib.Sim(w)
+    assert g.purkinje_n_sub() == o.purkinje_n_sub()
+    for chunk in range(4):
+        g.step(150)
+        o.step(150)
+        assert np.max(np.abs(g.vm() - o.vm())) <= TOL_MV
+        assert np.max(np.abs(g.purkinje_vm() - o.purkinje_vm())) <= TOL_MV
+    assert same_times(g.purkinje_activation(), o.purkinje_activation()) <= 1e-6
