@@ -79,3 +79,33 @@ def test_full_heart_fp64_every_cell(ep, oracle_lib):
     say(f"  max|dV| tissue {dv:.2e}, graph {dp:.2e} mV")
     assert dv <= TOL_MV and dp <= TOL_MV
     assert g.purkinje_n_sub() == o.purkinje_n_sub()
+
+
+def test_full_sheet_fp64_every_cell(ep, oracle_lib):
+    """The 5.12M-triangle sheet of the 2D bench leg, 50 FP64 steps in the
+    benchmark's launch configuration: every cell within 1e-6 mV."""
+    w = M.sheet_workload(1600, 1600, 0.25, n_steps=50)
+    say(f"full sheet: {w.n_tets} triangles; oracle 50 steps ...")
+    o = oracle_lib.Sim(w)
+    o.step(50)
+    g = ep.Sim(w, prec=ep.EP_FP64, allocator="torch", launch=LAUNCH)
+    g.step(50)
+    dv = np.abs(g.vm() - o.vm()).max()
+    say(f"  max|dV| {dv:.2e} mV")
+    assert dv <= TOL_MV
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_full_slab_time_schemes_fp64(ep, slab_ref, oracle_lib, scheme):
+    """The bench's slab with Adams-Bashforth 2 (1) and the second-order
+    Rush-Larsen variant (2), 60 FP64 steps: every cell within 1e-6 mV."""
+    w = M.config2(n_steps=60)
+    w.time_scheme = scheme
+    say(f"full slab scheme {scheme}: oracle 60 steps ...")
+    o = oracle_lib.Sim(w)
+    o.step(60)
+    g = ep.Sim(w, prec=ep.EP_FP64, allocator="torch", launch=LAUNCH)
+    g.step(60)
+    dv = np.abs(g.vm() - o.vm()).max()
+    say(f"  max|dV| {dv:.2e} mV")
+    assert dv <= TOL_MV
