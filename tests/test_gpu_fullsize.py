@@ -96,7 +96,7 @@ def test_full_sheet_fp64_every_cell(ep, oracle_lib):
 
 
 @pytest.mark.parametrize("scheme", [1, 2])
-def test_full_slab_time_schemes_fp64(ep, slab_ref, oracle_lib, scheme):
+def test_full_slab_time_schemes_fp64(ep, oracle_lib, scheme):
     """The bench's slab with Adams-Bashforth 2 (1) and the second-order
     Rush-Larsen variant (2), 60 FP64 steps: every cell within 1e-6 mV."""
     w = M.config2(n_steps=60)
