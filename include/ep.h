@@ -345,6 +345,13 @@ typedef struct {
     double radius, delay_ortho, delay_anti, amp, dur;
 } ep_pmj;
 
+/* A junction whose source is a cell, in a request (as ep_add_cell_junction). */
+typedef struct {
+    int32_t cell;
+    int32_t two_way;
+    double radius, delay_ortho, delay_anti, amp, dur;
+} ep_cell_junction;
+
 /* The Purkinje graph of a request (as ep_set_purkinje, ep_set_purkinje_scale
  * and ep_add_pmj; every array caller-owned and copied at submission). */
 typedef struct {
@@ -374,6 +381,9 @@ typedef struct {
     double ionic_scale[4];        /* GKr, GKs, GCaL, GNa multipliers (0 = 1) */
     int64_t n_steps;              /* steps to run (> 0)                      */
     const ep_purkinje *purkinje;  /* NULL: tissue only                       */
+    int32_t n_cell_junctions;     /* junctions with a source cell, after the
+                                     graph's (as ep_add_cell_junction)       */
+    const ep_cell_junction *cell_junctions;
 } ep_request;
 
 typedef struct {
@@ -422,6 +432,10 @@ ep_status ep_server_release(ep_server *sv, int64_t id);   /* drop stored results
 ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st);
 /* Graph length in steps (> 0) and XCD remap, as ep_set_launch. */
 ep_status ep_server_set_launch(ep_server *sv, int32_t steps_per_graph, int32_t xcd_remap);
+/* Time scheme of every request of the server (as ep_set_time_scheme; one
+ * scheme per server because the batched kernels are specialised on it).
+ * EP_ESTATE once a request has been submitted. */
+ep_status ep_server_set_time_scheme(ep_server *sv, int32_t scheme);
 /* hold != 0: keep admitting and uploading requests but step none, so that a
  * batch can start together (a UQ sweep); hold == 0 resumes stepping. */
 ep_status ep_server_hold(ep_server *sv, int32_t hold);

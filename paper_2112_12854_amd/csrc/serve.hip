@@ -78,6 +78,7 @@ struct ep_server {
     std::string err;
     std::string driver_err;
     int32_t want_k = 50, want_remap = 1;   // launch settings, applied by the driver
+    int32_t scheme = 0;                    // time scheme of every request
     // autotuning requests, served by the driver on the live batch
     bool hold = false;                     // admit and upload, but do not step
     bool tune_pending = false, tune_retune = false;
@@ -424,7 +425,8 @@ void driver_main(ep_server *sv) {
     }
 }
 
-ep_status copy_request(const ep_request *rq, const ep_options &o, ep::InstSpec &sp, std::string &err) {
+ep_status copy_request(const ep_request *rq, const ep_options &o, int32_t scheme, ep::InstSpec &sp,
+                       std::string &err) {
     if (!rq || rq->n_nodes <= 0 || rq->n_tets <= 0 || !rq->xyz || !rq->tet_nodes || !rq->fibre ||
         rq->n_steps <= 0 || rq->n_stimuli < 0 || rq->n_stimuli > EP_MAX_STIMULI ||
         (rq->n_stimuli > 0 && !rq->stimuli) || !(rq->sigma_l >= 0) || !(rq->sigma_t >= 0)) {
@@ -471,6 +473,17 @@ ep_status copy_request(const ep_request *rq, const ep_options &o, ep::InstSpec &
         }
         if (!err.empty()) return EP_EINVAL;
     }
+    if (rq->n_cell_junctions < 0 || (rq->n_cell_junctions > 0 && !rq->cell_junctions)) {
+        err = "bad cell junction list";
+        return EP_EINVAL;
+    }
+    for (int32_t k = 0; k < rq->n_cell_junctions; ++k) {
+        const ep_cell_junction &q = rq->cell_junctions[k];
+        err = ep::spec_add_cell_junction(sp, q.cell, q.radius, q.delay_ortho, q.delay_anti,
+                                         q.two_way, q.amp, q.dur);
+        if (!err.empty()) return EP_EINVAL;
+    }
+    sp.scheme = scheme;
     for (int k = 0; k < rq->n_stimuli; ++k) {
         const ep_stimulus &q = rq->stimuli[k];
         if (q.domain == 1 && sp.purk.n == 0) {
@@ -543,7 +556,12 @@ ep_status ep_server_submit(ep_server *sv, const ep_request *rq, int64_t *id) {
     if (!sv || !id) return EP_EINVAL;
     auto r = std::make_unique<Req>();
     std::string err;
-    ep_status st = copy_request(rq, sv->opt, r->spec, err);
+    int32_t scheme;
+    {
+        std::lock_guard<std::mutex> g(sv->mu);
+        scheme = sv->scheme;
+    }
+    ep_status st = copy_request(rq, sv->opt, scheme, r->spec, err);
     if (st != EP_OK) return sfail(sv, st, err);
     if (ep::estimate_footprint(rq->n_tets, rq->n_nodes, sv->rs) > sv->budget * 2)
         return sfail(sv, EP_ENOMEM, "request cannot fit the HBM budget");
@@ -653,6 +671,15 @@ ep_status ep_server_set_launch(ep_server *sv, int32_t steps_per_graph, int32_t x
     std::lock_guard<std::mutex> g(sv->mu);
     sv->want_k = steps_per_graph;           // applied by the driver between launches
     sv->want_remap = xcd_remap ? 1 : 0;
+    return EP_OK;
+}
+
+ep_status ep_server_set_time_scheme(ep_server *sv, int32_t scheme) {
+    if (!sv) return EP_EINVAL;
+    if (scheme < EP_SCHEME_FE || scheme > EP_SCHEME_RL2_AB2) return sfail(sv, EP_EINVAL, "unknown time scheme");
+    std::lock_guard<std::mutex> g(sv->mu);
+    if (sv->stats.submitted > 0) { sv->err = "the scheme is fixed once requests arrive"; return EP_ESTATE; }
+    sv->scheme = scheme;
     return EP_OK;
 }
 

@@ -48,6 +48,12 @@ class ep_pmj(C.Structure):
                 ("dur", C.c_double)]
 
 
+class ep_cell_junction(C.Structure):
+    _fields_ = [("cell", C.c_int32), ("two_way", C.c_int32), ("radius", C.c_double),
+                ("delay_ortho", C.c_double), ("delay_anti", C.c_double), ("amp", C.c_double),
+                ("dur", C.c_double)]
+
+
 class ep_purkinje(C.Structure):
     _fields_ = [("n", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("n_edges", C.c_int64),
                 ("edges", C.POINTER(C.c_int32)), ("edge_scale", C.POINTER(C.c_double)),
@@ -62,7 +68,8 @@ class ep_request(C.Structure):
                 ("sigma_t", C.c_double), ("scale", C.POINTER(C.c_double)),
                 ("model", C.POINTER(C.c_uint8)), ("n_stimuli", C.c_int32),
                 ("stimuli", C.POINTER(ep_stimulus)), ("ionic_scale", C.c_double * 4),
-                ("n_steps", C.c_int64), ("purkinje", C.POINTER(ep_purkinje))]
+                ("n_steps", C.c_int64), ("purkinje", C.POINTER(ep_purkinje)),
+                ("n_cell_junctions", C.c_int32), ("cell_junctions", C.POINTER(ep_cell_junction))]
 
 
 class ep_result(C.Structure):
@@ -154,6 +161,7 @@ _SIGS = {
     "ep_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ep_server_stats)]),
     "ep_server_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "ep_server_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32]),
+    "ep_server_set_time_scheme": (C.c_int, [C.c_void_p, C.c_int32]),
     "ep_server_hold": (C.c_int, [C.c_void_p, C.c_int32]),
     "ep_server_destroy": (None, [C.c_void_p]),
     "ep_server_last_error": (C.c_char_p, [C.c_void_p]),
@@ -425,7 +433,8 @@ class Server:
 
     def __init__(self, prec: int = EP_FP32_MIXED, dt: float = 0.02, hbm_budget: int = 0,
                  max_slots: int = 64, device: int = 0, trace_every: int = 50,
-                 allocator: str = "hip", steps_per_graph: int = 50, chi=140.0, cm=0.01):
+                 allocator: str = "hip", steps_per_graph: int = 50, chi=140.0, cm=0.01,
+                 time_scheme: int = 0):
         L = lib()
         o = ep_options()
         L.ep_default_options(C.byref(o))
@@ -445,6 +454,8 @@ class Server:
         self.n_of = {}
         self.np_of = {}
         _check(L.ep_server_set_launch(h, steps_per_graph, 1))
+        if time_scheme:
+            _check(L.ep_server_set_time_scheme(h, int(time_scheme)))
 
     def _err(self):
         return lib().ep_server_last_error(self.h).decode()
@@ -490,6 +501,14 @@ class Server:
                             len(pk.pmj_nodes), jn)
             keep = [pxyz, pe, es, jn, g]
             rq.purkinje = C.pointer(g)
+        cjs = list(getattr(w, "cell_junctions", []))
+        if cjs:
+            arr = (ep_cell_junction * len(cjs))()
+            for k, cj in enumerate(cjs):
+                arr[k] = ep_cell_junction(int(cj.cell), int(cj.two_way), cj.radius, cj.delay_ortho,
+                                          cj.delay_anti, cj.amp, cj.dur)
+            rq.n_cell_junctions, rq.cell_junctions = len(cjs), arr
+            keep.append(arr)
         rid = C.c_int64()
         self._chk(lib().ep_server_submit(self.h, C.byref(rq), C.byref(rid)))
         del keep

@@ -152,3 +152,35 @@ def test_autotuned_schedule_keeps_results(ep):
         assert np.array_equal(sv.vm(i), vm)
         assert np.array_equal(sv.activation(i), at, equal_nan=True)
     sv.close()
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+def test_server_time_scheme_and_cell_junctions(ep, scheme):
+    """A server whose requests step with Adams-Bashforth 2 (1) or the
+    second-order Rush-Larsen variant (2): a plain slab, a slab with a graph
+    and a shell-on-slab request with cell junctions, run together, each
+    bitwise equal to the same workload run alone with that scheme; the
+    scheme cannot change once requests have arrived."""
+    plain = M.config1(n_steps=0)
+    graph = M.purkinje_slab(drive="tissue", two_way=True)
+    # (a 4x sheet: AB2's stable interval is half forward Euler's, and the
+    # default 10x sheet exceeds it at dt = 0.02 ms)
+    shell = M.shell_on_slab(drive="slab", two_way=True, sheet_scale=4.0)
+    ws = [plain, graph, shell]
+    for w in ws:
+        w.time_scheme = scheme
+    sv = ep.Server(prec=ep.EP_FP32_MIXED, dt=0.02, max_slots=4, time_scheme=scheme)
+    try:
+        ids = [sv.submit(w, 600) for w in ws]
+        assert all(sv.wait(i)["status"] == ep.EP_OK for i in ids)
+        for rid, w in zip(ids, ws):
+            solo = ep.Sim(w, prec=ep.EP_FP32_MIXED)
+            solo.step(600)
+            assert np.array_equal(sv.vm(rid), solo.vm())
+            assert np.array_equal(sv.activation(rid), solo.activation(), equal_nan=True)
+        # the slab re-entered the shell through its two-way nodes
+        assert np.isfinite(sv.activation(ids[2])[16 * 8 * 2 * 5:]).any()
+        with pytest.raises(ep.EPError):
+            sv._chk(ep.lib().ep_server_set_time_scheme(sv.h, 0))
+    finally:
+        sv.close()
