@@ -271,6 +271,34 @@ def shell_on_slab(nx: int = 16, ny: int = 8, nz: int = 2, h: float = 0.5, gap: f
     return w
 
 
+def slab6(nx: int, ny: int, nz: int, h: float):
+    """Box of hexes split into six tets each around the main diagonal
+    (0,0,0)-(1,1,1) (Kuhn's split: the tets along the six monotone corner
+    paths; every hex is split alike, so the mesh is conforming and
+    translation invariant).  Returns like slab()."""
+    ii, jj, kk = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1),
+                             np.arange(nz + 1), indexing="ij")
+    xyz = np.stack([ii.ravel() * h, jj.ravel() * h, kk.ravel() * h],
+                   axis=1).astype(np.float64)
+
+    def nid(i, j, k):
+        return (i * (ny + 1) + j) * (nz + 1) + k
+
+    hi, hj, hk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    hi, hj, hk = hi.ravel(), hj.ravel(), hk.ravel()
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    tets = np.empty((hi.size, 6, 4), np.int64)
+    for t, p in enumerate(perms):
+        step = np.zeros(3, int)
+        tets[:, t, 0] = nid(hi, hj, hk)
+        for m in range(3):
+            step[p[m]] += 1
+            tets[:, t, m + 1] = nid(hi + step[0], hj + step[1], hk + step[2])
+    tets = tets.reshape(-1, 4).astype(np.int32)
+    hex_ijk = np.repeat(np.stack([hi, hj, hk], axis=1), 6, axis=0).astype(np.int32)
+    return xyz, tets, hex_ijk
+
+
 def hex_box_ids(hex_ijk: np.ndarray, lo, hi) -> np.ndarray:
     """Ids of the tets whose hex index lies in [lo, hi) per axis (None = open)."""
     sel = np.ones(hex_ijk.shape[0], dtype=bool)
@@ -347,12 +375,13 @@ def scaled_config2(nx: int, ny: int, nz: int, h: float = 0.25, seed: int = 2,
 
 
 def niederer_box(h: float, dt: float, n_steps: int, lx=20.0, ly=7.0, lz=3.0,
-                 stim_side: float = 1.5) -> Workload:
+                 stim_side: float = 1.5, split: int = 5) -> Workload:
     """The paper's convergence box (Sec. 4): 20 x 7 x 3 mm, fibres along the
     long (x) axis, TP06 (endocardial parameters), stimulus on a corner cube of
-    side 1.5 mm at the origin (-52 pA/pF for 2 ms)."""
+    side 1.5 mm at the origin (-52 pA/pF for 2 ms); hexes split into 5 or 6
+    tets."""
     nx, ny, nz = int(round(lx / h)), int(round(ly / h)), int(round(lz / h))
-    xyz, tets, hijk = slab(nx, ny, nz, h)
+    xyz, tets, hijk = (slab if split == 5 else slab6)(nx, ny, nz, h)
     n = tets.shape[0]
     m = int(round(stim_side / h))
     stim = Stimulus(ids=hex_box_ids(hijk, (0, 0, 0), (m, m, m)), t0=0.0,
