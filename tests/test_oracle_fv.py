@@ -13,8 +13,8 @@ CHI, CM = M.CHI, M.CM
 
 
 def passive(nx, ny, nz, h=0.5, fibre=None, sl=M.SIGMA_L, st=M.SIGMA_T,
-            dt=0.02, perm_seed=None, scale=None):
-    xyz, tets, hijk = M.slab(nx, ny, nz, h)
+            dt=0.02, perm_seed=None, scale=None, split=5):
+    xyz, tets, hijk = (M.slab if split == 5 else M.slab6)(nx, ny, nz, h)
     if perm_seed is not None:
         rng = np.random.default_rng(perm_seed)
         tets = np.array([t[rng.permutation(4)] for t in tets], dtype=np.int32)
@@ -72,6 +72,29 @@ def test_geometry_closed_forms(oracle_lib, dims):
     cen = centroids(w)
     opp = w.xyz[w.tets[c, j]]
     assert (np.einsum("ij,ij->i", S[c, j], cen[c] - opp) > 0).all()
+
+
+def test_kuhn_split_geometry_and_operator(oracle_lib):
+    """The 6-tet (Kuhn) split of the convergence study: six tets of volume
+    h^3/6 per hex, the same boundary-triangle count, closed area vectors,
+    and the operator invariants P3-P5 (constants steady, conservation,
+    linear fields null at stencil-interior cells: every node of this lattice
+    is point-symmetric too)."""
+    nx, ny, nz, h = 8, 7, 7, 0.5
+    w = passive(nx, ny, nz, h, fibre=np.array([math.cos(0.3), math.sin(0.3), 0.0]), split=6)
+    s = oracle_lib.Sim(w)
+    vol, S, nbr = s.geometry()
+    assert np.allclose(vol, h ** 3 / 6, rtol=1e-13)
+    assert np.abs(S.sum(axis=1)).max() < 1e-14
+    assert (nbr < 0).sum() == 2 * 2 * (nx * ny + nx * nz + ny * nz)
+    assert np.abs(s.apply_diffusion(np.full(w.n_tets, -80.0))).max() < 1e-11
+    v = np.random.default_rng(2).normal(size=w.n_tets) * 30
+    L = s.apply_diffusion(v)
+    assert abs((vol * L).sum()) < 1e-12 * (vol * np.abs(L)).sum()
+    lin = centroids(w) @ np.array([1.0, -2.0, 0.5]) + 4.0
+    inner = interior_cells(w, rings=1)
+    assert inner.size > 50
+    assert np.abs(s.apply_diffusion(lin)[inner]).max() < 1e-11
 
 
 def test_orientation_invariance(oracle_lib):
