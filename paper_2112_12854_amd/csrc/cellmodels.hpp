@@ -25,8 +25,8 @@ struct GScale {
 };
 
 // --------------------------------------------------------------- helpers
-// FP64: the correctly rounded library functions.  FP32 (the mixed path,
-// judged on activation time and APD90): the hardware exp2 / log2 /
+// FP64: the full-precision library functions (within an ulp).  FP32 (the
+// mixed path, whose bar is activation time and APD90): the hardware exp2 / log2 /
 // reciprocal instructions, a few ulp each, which cuts the instruction count
 // of the cell kernel by about a fifth.
 __device__ __forceinline__ double xexp(double x) { return exp(x); }
