@@ -26,6 +26,7 @@
 namespace ep {
 
 using epdev::InstDesc;
+using epdev::tix;
 
 namespace {
 
@@ -54,7 +55,8 @@ __global__ void __launch_bounds__(BT) k_gather(const int64_t *__restrict__ off,
     xn[node] = (a0 + a1) + (a2 + a3);
 }
 
-// y_c = f_c (sum_s beta_s x_n[node_s] + sum_f b_f (x[nbr_f] - x_c)),
+// y_c = f_c (sum_s beta_s x_n[node_s] + sum_f b_f (x[nbr_f] - x_c)) with the
+// stencil in tile-major slot arrays,
 // f_c = factor * V_c with a volume array, else factor
 __global__ void __launch_bounds__(BT) k_flux(const int32_t *__restrict__ cnode,
                                              const double *__restrict__ beta,
@@ -69,9 +71,9 @@ __global__ void __launch_bounds__(BT) k_flux(const int32_t *__restrict__ cnode,
     const double xc = x[c];
     double acc = 0.0;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc += beta[s * nc + c] * xn[cnode[s * nc + c]];
+    for (int s = 0; s < 8; ++s) acc += beta[tix(c, s, 8)] * xn[cnode[tix(c, s, 8)]];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) acc += bf[f * nc + c] * (x[cnbr[f * nc + c]] - xc);
+    for (int f = 0; f < 4; ++f) acc += bf[tix(c, f, 4)] * (x[cnbr[tix(c, f, 4)]] - xc);
     y[c] = (vol ? factor * vol[c] : factor) * acc;
 }
 

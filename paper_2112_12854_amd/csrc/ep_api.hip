@@ -518,7 +518,7 @@ ep_status ep_get_states(ep_sim *s, double *out, int64_t n, int32_t n_slots) {
     if (!out || n != nc || n_slots != EP_MAX_SLOTS) return fail(s, EP_EINVAL, "bad state buffer");
     ep_status st = ep_sync(s);
     if (st != EP_OK && st != EP_ENUMERIC) return st;
-    std::vector<double> v, gate((size_t)NG_MAX * nc), conc((size_t)NC_MAX * nc);
+    std::vector<double> v, gate(tiled_len(nc, NG_MAX)), conc(tiled_len(nc, NC_MAX));
     ep_status e = read_cells(s, cur_v(s), s->inst.rs, v);
     if (e != EP_OK) return e;
     if (s->inst.rs == 8) {
@@ -536,8 +536,8 @@ ep_status ep_get_states(ep_sim *s, double *out, int64_t n, int32_t n_slots) {
         const int ng = model_ng(m), ncc = model_nc(m);
         for (int k = 0; k < EP_MAX_SLOTS; ++k) out[(size_t)k * nc + u] = nan;
         out[u] = v[i];
-        for (int k = 0; k < ng; ++k) out[(size_t)(1 + k) * nc + u] = gate[(size_t)k * nc + i];
-        for (int k = 0; k < ncc; ++k) out[(size_t)(1 + ng + k) * nc + u] = conc[(size_t)k * nc + i];
+        for (int k = 0; k < ng; ++k) out[(size_t)(1 + k) * nc + u] = gate[tix(i, k, NG_MAX)];
+        for (int k = 0; k < ncc; ++k) out[(size_t)(1 + ng + k) * nc + u] = conc[tix(i, k, NC_MAX)];
     }
     return st;
 }
@@ -548,14 +548,14 @@ ep_status ep_set_states(ep_sim *s, const double *in, int64_t n, int32_t n_slots)
     const int64_t nc = s->inst.desc.nc;
     if (!in || n != nc || n_slots != EP_MAX_SLOTS) return fail(s, EP_EINVAL, "bad state buffer");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
-    std::vector<double> v(nc), gate((size_t)NG_MAX * nc, 0.0), conc((size_t)NC_MAX * nc, 0.0);
+    std::vector<double> v(nc), gate(tiled_len(nc, NG_MAX), 0.0), conc(tiled_len(nc, NC_MAX), 0.0);
     for (int64_t i = 0; i < nc; ++i) {
         const int64_t u = s->inst.prep.perm[i];
         const int m = s->inst.prep.model[i];
         const int ng = model_ng(m), ncc = model_nc(m);
         v[i] = in[u];
-        for (int k = 0; k < ng; ++k) gate[(size_t)k * nc + i] = in[(size_t)(1 + k) * nc + u];
-        for (int k = 0; k < ncc; ++k) conc[(size_t)k * nc + i] = in[(size_t)(1 + ng + k) * nc + u];
+        for (int k = 0; k < ng; ++k) gate[tix(i, k, NG_MAX)] = in[(size_t)(1 + k) * nc + u];
+        for (int k = 0; k < ncc; ++k) conc[tix(i, k, NC_MAX)] = in[(size_t)(1 + ng + k) * nc + u];
     }
     void *dv = cur_v(s);
     if (s->inst.rs == 8) {
@@ -588,29 +588,29 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
     const epdev::InstDesc &D = s->inst.desc;
     const size_t nc = D.nc, r = s->inst.rs;
     std::vector<std::pair<void *, size_t>> a = {
-        {D.v[0], nc * r},           {D.v[1], nc * r},        {D.gate, NG_MAX * nc * r},
-        {D.conc, NC_MAX * nc * 8},  {D.dstat, nc},           {D.t_act, nc * 8},
+        {D.v[0], nc * r},           {D.v[1], nc * r},        {D.gate, tiled_len(nc, NG_MAX) * r},
+        {D.conc, tiled_len(nc, NC_MAX) * 8},  {D.dstat, nc}, {D.t_act, nc * 8},
         {D.t_rep, nc * 8},          {D.vmax, nc * r},        {(void *)D.vrest, nc * r},
         {D.trace, (size_t)s->inst.trace_cap * 8}, {D.part, (size_t)D.n_cell_tiles * 8},
         {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
     if (s->inst.bido) a.push_back({s->inst.bd.phi, nc * 8});
     if (s->inst.ab2) {
         a.push_back({D.hv, nc * r});
-        a.push_back({D.hc, NC_MAX * nc * 8});
+        a.push_back({D.hc, tiled_len(nc, NC_MAX) * 8});
     }
     if (ep::has_junction_block(s->inst)) {
         const epdev::PurkDesc &P = s->inst.pdesc;
         const size_t np = P.np;             // 0 when only cells are junction sources
         a.push_back({P.pv[0], np * r});
         a.push_back({P.pv[1], np * r});
-        a.push_back({P.gate, NG_MAX * np * r});
-        a.push_back({P.conc, NC_MAX * np * 8});
+        a.push_back({P.gate, tiled_len(np, NG_MAX) * r});
+        a.push_back({P.conc, tiled_len(np, NC_MAX) * 8});
         a.push_back({P.pstat, np});
         a.push_back({P.pt_act, np * 8});
         a.push_back({P.pmj, std::max<size_t>(P.n_pmj, 1) * sizeof(epdev::Pmj)});
         if (s->inst.ab2) {
             a.push_back({P.hv, np * r});
-            a.push_back({P.hc, NC_MAX * np * 8});
+            a.push_back({P.hc, tiled_len(np, NC_MAX) * 8});
         }
     }
     a.erase(std::remove_if(a.begin(), a.end(), [](const auto &x) { return x.second == 0; }), a.end());

@@ -76,6 +76,15 @@ std::vector<R> conv(const std::vector<double> &v) {
 
 size_t round256(size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; }
 
+// slot-major [S][n] host array -> the device's tile-major layout
+template <typename T>
+std::vector<T> tiled(const std::vector<T> &a, int S, int64_t n) {
+    std::vector<T> t(tiled_len(n, S), T(0));
+    for (int s = 0; s < S; ++s)
+        for (int64_t c = 0; c < n; ++c) t[tix(c, s, S)] = a[(size_t)s * n + c];
+    return t;
+}
+
 }  // namespace
 
 size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
@@ -84,10 +93,11 @@ size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
     const size_t ent = (size_t)(4.4 * c) + 64 * 8;   // incidences incl. slice padding
     size_t b = 0;
     b += round256(((n + 63) / 64 + 1) * 8) + round256(ent * 4) + round256(ent * r);
-    b += round256(8 * c * 4) + round256(8 * c * r) + round256(4 * c * 4) + round256(4 * c * r);
+    b += round256(tiled_len(c, 8) * 4) + round256(tiled_len(c, 8) * r) + round256(tiled_len(c, 4) * 4) +
+         round256(tiled_len(c, 4) * r);
     b += round256(c) + round256(c * 8);                       // model, volume
     b += round256(c * 4);                                     // stimulus mask
-    b += round256(NC_MAX * c * 8) + round256(NG_MAX * c * r); // states
+    b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);   // states
     b += 2 * round256(c * r) + 3 * round256(c * r) + round256(n * r);   // v0 v1 vrest vmax, vn
     b += round256(c) + 2 * round256(c * 8);                   // detection
     b += round256(((c + TILE - 1) / TILE + 3) * 8) + round256(8 * 4096) + round256(sizeof(Ctrl));
@@ -239,7 +249,7 @@ size_t purkinje_bytes(const Inst &I, int rs) {
     if (!has_junction_block(I)) return 0;
     const size_t np = (size_t)I.pk.n, E = I.pk.nbr.size(), r = (size_t)rs, c = (size_t)I.prep.n_tets;
     size_t b = round256((np + 1) * 4) + round256(E * 4) + round256(E * r);
-    b += 2 * round256(np * r) + round256(NG_MAX * np * r) + round256(NC_MAX * np * 8);
+    b += 2 * round256(np * r) + round256(tiled_len(np, NG_MAX) * r) + round256(tiled_len(np, NC_MAX) * 8);
     b += round256(np * 4) + round256(np) + round256(np * 8) + round256(np * 4);
     b += round256((np + (size_t)I.n_pmj + 1) * 4) + round256(std::max<size_t>(I.n_pmj, 1) * sizeof(Pmj));
     b += round256(std::max<size_t>(I.pk.jcells.size(), 1) * 4);
@@ -258,15 +268,17 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     else if (sp.trace_every > 0) cap = 1 << 16;
     size_t b = 0;
     b += round256(P.sell_off.size() * 8) + round256(ent * 4) + round256(ent * r);
-    b += round256(8 * c * 4) + round256(8 * c * r) + round256(4 * c * 4) + round256(4 * c * r);
+    b += round256(tiled_len(c, 8) * 4) + round256(tiled_len(c, 8) * r) + round256(tiled_len(c, 4) * 4) +
+         round256(tiled_len(c, 4) * r);
     b += round256(c) + round256(c * 8) + round256(c * 4);
-    b += round256(NC_MAX * c * 8) + round256(NG_MAX * c * r);
+    b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);
     b += 4 * round256(c * r) + round256(n * r);
     b += round256(c) + 2 * round256(c * 8);
     b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE + 3) * 8) + round256(sizeof(Ctrl));
     if (sp.bido) {
         const size_t m1 = (size_t)sp.bido_restart + 1;
-        b += round256(12 * c * 8) + 3 * round256(c * 8) + round256(n * 8) + round256(m1 * c * 8);
+        b += round256(tiled_len(c, 8) * 8) + round256(tiled_len(c, 4) * 8) + 3 * round256(c * 8) +
+             round256(n * 8) + round256(m1 * c * 8);
         b += round256(m1 * kBidoBlocks * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8);
         const size_t na = (size_t)I.coarse.n_agg;
         if (na > 0)
@@ -274,8 +286,8 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
                  round256(na * na * 8) + 2 * round256(c * 8) + 2 * round256(na * 8);
     }
     if (sp.scheme >= 1) {
-        b += round256(c * r) + round256(NC_MAX * c * 8);
-        if (I.pk.n > 0) b += round256((size_t)I.pk.n * r) + round256(NC_MAX * (size_t)I.pk.n * 8);
+        b += round256(c * r) + round256(tiled_len(c, NC_MAX) * 8);
+        if (I.pk.n > 0) b += round256((size_t)I.pk.n * r) + round256(tiled_len(I.pk.n, NC_MAX) * 8);
     }
     return b + purkinje_bytes(I, rs);
 }
@@ -289,15 +301,15 @@ std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) 
     PurkDesc &P = I.pdesc;
     std::memset(&P, 0, sizeof(P));
     auto fail_mem = [&]() { st = EP_ENOMEM; free_instance(I); return std::string("device allocation failed"); };
-    std::vector<double> v0(np), gate((size_t)NG_MAX * np, 0.0), conc((size_t)NC_MAX * np, 0.0);
+    std::vector<double> v0(np), gate(tiled_len(np, NG_MAX), 0.0), conc(tiled_len(np, NC_MAX), 0.0);
     {
         double y[EP_MAX_SLOTS];
         model_init(I.pmodel, y);
         const int ng = model_ng(I.pmodel), ncc = model_nc(I.pmodel);
         for (int64_t i = 0; i < np; ++i) {
             v0[i] = y[0];
-            for (int k = 0; k < ng; ++k) gate[(size_t)k * np + i] = y[1 + k];
-            for (int k = 0; k < ncc; ++k) conc[(size_t)k * np + i] = y[1 + ng + k];
+            for (int k = 0; k < ng; ++k) gate[tix(i, k, NG_MAX)] = y[1 + k];
+            for (int k = 0; k < ncc; ++k) conc[tix(i, k, NC_MAX)] = y[1 + ng + k];
         }
     }
     std::vector<uint32_t> pmask(np, 0);
@@ -362,7 +374,7 @@ std::string upload_purkinje(const InstSpec &sp, int rs, Inst &I, ep_status &st) 
     P.tv[1] = I.desc.v[1];
     if (sp.scheme >= 1) {
         P.hv = zalloc(I, (size_t)np * rs);
-        P.hc = (double *)zalloc(I, NC_MAX * (size_t)np * 8);
+        P.hc = (double *)zalloc(I, tiled_len(np, NC_MAX) * 8);
         if (!P.hv || !P.hc) return fail_mem();
     }
     P.ctrl = I.d_ctrl;
@@ -419,26 +431,27 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     D.nn = nn;
     auto fail_mem = [&]() { st = EP_ENOMEM; free_instance(I); return std::string("device allocation failed"); };
     if (!up(I, (void **)&D.sell_off, P.sell_off) || !up(I, (void **)&D.sell_cell, P.sell_cell) ||
-        !up(I, (void **)&D.cnode, P.cnode) || !up(I, (void **)&D.cnbr, P.cnbr) ||
+        !up(I, (void **)&D.cnode, tiled(P.cnode, 8, nc)) || !up(I, (void **)&D.cnbr, tiled(P.cnbr, 4, nc)) ||
         !up(I, (void **)&D.model, P.model) || !up(I, (void **)&D.vol, P.vol))
         return fail_mem();
-    bool ok = rs == 8 ? (up(I, (void **)&D.sell_w, P.sell_w) && up(I, (void **)&D.cbeta, P.cbeta) &&
-                         up(I, (void **)&D.cb, P.cb))
+    bool ok = rs == 8 ? (up(I, (void **)&D.sell_w, P.sell_w) &&
+                         up(I, (void **)&D.cbeta, tiled(P.cbeta, 8, nc)) &&
+                         up(I, (void **)&D.cb, tiled(P.cb, 4, nc)))
                       : (up(I, (void **)&D.sell_w, conv<float>(P.sell_w)) &&
-                         up(I, (void **)&D.cbeta, conv<float>(P.cbeta)) &&
-                         up(I, (void **)&D.cb, conv<float>(P.cb)));
+                         up(I, (void **)&D.cbeta, tiled(conv<float>(P.cbeta), 8, nc)) &&
+                         up(I, (void **)&D.cb, tiled(conv<float>(P.cb), 4, nc)));
     if (!ok) return fail_mem();
 
-    // initial state (structure of arrays, internal order)
-    std::vector<double> v0(nc), gate((size_t)NG_MAX * nc, 0.0), conc((size_t)NC_MAX * nc, 0.0);
+    // initial state (tile-major slot arrays, internal order)
+    std::vector<double> v0(nc), gate(tiled_len(nc, NG_MAX), 0.0), conc(tiled_len(nc, NC_MAX), 0.0);
     for (int64_t i = 0; i < nc; ++i) {
         double y[EP_MAX_SLOTS];
         const int m = P.model[i];
         model_init(m, y);
         v0[i] = y[0];
         const int ng = model_ng(m), ncc = model_nc(m);
-        for (int k = 0; k < ng; ++k) gate[(size_t)k * nc + i] = y[1 + k];
-        for (int k = 0; k < ncc; ++k) conc[(size_t)k * nc + i] = y[1 + ng + k];
+        for (int k = 0; k < ng; ++k) gate[tix(i, k, NG_MAX)] = y[1 + k];
+        for (int k = 0; k < ncc; ++k) conc[tix(i, k, NC_MAX)] = y[1 + ng + k];
     }
     std::vector<uint32_t> smask(nc, 0);
     for (size_t k = 0; k < sp.stims.size(); ++k)
@@ -512,7 +525,7 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     I.scheme = sp.scheme;
     if (I.ab2) {
         D.hv = zalloc(I, nc * (size_t)rs);
-        D.hc = (double *)zalloc(I, NC_MAX * nc * 8);
+        D.hc = (double *)zalloc(I, tiled_len(nc, NC_MAX) * 8);
         if (!D.hv || !D.hc) return fail_mem();
     }
     I.bido = sp.bido;
@@ -528,7 +541,7 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         B.last_relres = 0;
         // phi_e^0 = 0: exact for a uniform initial potential
         if (!up(I, (void **)&B.phi, std::vector<double>(nc, 0.0)) ||
-            !up(I, (void **)&B.ebeta, P.ebeta) || !up(I, (void **)&B.eb, P.eb))
+            !up(I, (void **)&B.ebeta, tiled(P.ebeta, 8, nc)) || !up(I, (void **)&B.eb, tiled(P.eb, 4, nc)))
             return fail_mem();
         B.b = (double *)dalloc(I, nc * 8);
         B.w = (double *)dalloc(I, nc * 8);

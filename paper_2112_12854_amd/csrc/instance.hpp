@@ -61,8 +61,8 @@ struct InstSpec {
 // Device arrays of the extracellular solve of one bidomain instance.
 struct Bido {
     double *phi = nullptr;             // [nc] phi_e, zero volume-weighted mean
-    const double *ebeta = nullptr;     // [8][nc] elliptic stencil (flux-sum form)
-    const double *eb = nullptr;        // [4][nc]
+    const double *ebeta = nullptr;     // elliptic stencil (flux-sum form), tile-major, 8 slots
+    const double *eb = nullptr;        // tile-major, 4 slots
     double *xn = nullptr;              // [nn] node values of the operand
     double *b = nullptr, *w = nullptr; // [nc] right-hand side, work vector
     double *V = nullptr;               // [(restart+1)][nc] Krylov basis

@@ -24,6 +24,19 @@ constexpr int NG_MAX = 15;   // gate slots (CRN)
 constexpr int NC_MAX = 6;    // FP64 slots (Stewart)
 constexpr int TILE = 256;    // cells or nodes per tile (= block size)
 
+// Per-cell slot arrays (stencil indices and coefficients, cell-model states)
+// are tile-major: the S slots of the 256 cells of block b = c / 256 lie
+// together, slot after slot ([block][slot][256]), so the accesses of a block
+// to every slot of its cells stay inside one contiguous range.  An array
+// holds S * ceil(n / 256) * 256 entries; the padding is never read.
+constexpr int LB = 256;      // cells per layout block
+__host__ __device__ constexpr size_t tiled_len(int64_t n, int S) {
+    return (size_t)S * (size_t)((n + LB - 1) / LB) * LB;
+}
+__host__ __device__ constexpr size_t tix(int64_t c, int s, int S) {
+    return ((size_t)(c / LB) * S + s) * LB + (size_t)(c % LB);
+}
+
 // Per-instance control block, device resident.
 struct Ctrl {
     int64_t step;                 // index n of the next step of this instance
@@ -61,14 +74,14 @@ struct InstDesc {
     const int64_t *sell_off;
     const int32_t *sell_cell;
     const void *sell_w;
-    const int32_t *cnode;         // [8][nc]
-    const void *cbeta;            // [8][nc]
-    const int32_t *cnbr;          // [4][nc]
-    const void *cb;               // [4][nc]
+    const int32_t *cnode;         // tile-major, 8 slots
+    const void *cbeta;            // tile-major, 8 slots
+    const int32_t *cnbr;          // tile-major, 4 slots
+    const void *cb;               // tile-major, 4 slots
     void *vn;                     // [nn]
     void *v[2];                   // v^n in v[n & 1]
-    void *gate;                   // [NG_MAX][nc]
-    double *conc;                 // [NC_MAX][nc]
+    void *gate;                   // tile-major, NG_MAX slots
+    double *conc;                 // tile-major, NC_MAX slots
     const uint8_t *model;
     const uint32_t *smask;
     uint8_t *dstat;
@@ -93,7 +106,7 @@ struct InstDesc {
     const Pmj *pmj;
     // Adams-Bashforth 2 for the non-gating states (null: forward Euler):
     // the previous step's rate of v (R, [nc]) and of the model's non-gating
-    // states (FP64, [NC_MAX][nc])
+    // states (FP64, tile-major, NC_MAX slots)
     void *hv;
     double *hc;
 };
@@ -106,8 +119,8 @@ struct PurkDesc {
     const int32_t *off, *nbr;
     const void *g;                // [off[np]] coefficients of (v_j - v_i)
     void *pv[2];                  // substep q reads pv[q & 1], writes pv[(q+1) & 1]
-    void *gate;                   // [NG_MAX][np]
-    double *conc;                 // [NC_MAX][np]
+    void *gate;                   // tile-major over nodes, NG_MAX slots
+    double *conc;                 // tile-major over nodes, NC_MAX slots
     const uint32_t *pmask;        // graph stimuli holding the node
     uint8_t *pstat;
     double *pt_act;
@@ -274,9 +287,10 @@ __device__ __forceinline__ const T &at(const T *p, uint32_t c) {
     return *(const T *)((const char *)p + c * (uint32_t)sizeof(T));
 }
 
-// Slot-major arrays ([slot][n]) go through buffer resources: one resource and
-// one lane offset serve every slot, the slot is a scalar offset.  Offsets are
-// 32-bit, so an instance holds fewer than 2^25 cells (checked on the host).
+// Tile-major slot arrays go through buffer resources: one resource and one
+// lane offset serve every slot of an array, the slot is a constant scalar
+// offset.  Offsets are 32-bit, so an instance holds fewer than 2^25 cells
+// (checked on the host).
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, -1, 0x00020000);
@@ -312,17 +326,22 @@ template <> struct BufIO<double> {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, v, s, P);
     }
 };
-// element `c` of slot `s` of a slot-major array with n entries per slot
-template <typename T, int P = kStream>
-__device__ __forceinline__ T sld(__amdgpu_buffer_rsrc_t r, int s, int64_t n, uint32_t c) {
-    return BufIO<T>::template ld<P>(r, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
+// byte offset of slot 0 of element c in a tile-major array of S slots
+template <typename T, int S>
+__device__ __forceinline__ uint32_t lane_off(uint32_t c) {
+    return ((c >> 8) * (uint32_t)(S * LB) + (c & (uint32_t)(LB - 1))) * (uint32_t)sizeof(T);
 }
-template <typename T, int P = kStream>
-__device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, int64_t n, uint32_t c, T x) {
-    BufIO<T>::template st<P>(r, x, c * (uint32_t)sizeof(T), (uint32_t)(s * n * (int64_t)sizeof(T)));
+// slot s of element c of a tile-major array of S slots
+template <typename T, int S, int P = kStream>
+__device__ __forceinline__ T sld(__amdgpu_buffer_rsrc_t r, int s, uint32_t c) {
+    return BufIO<T>::template ld<P>(r, lane_off<T, S>(c), (uint32_t)(s * LB * (int)sizeof(T)));
+}
+template <typename T, int S, int P = kStream>
+__device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, uint32_t c, T x) {
+    BufIO<T>::template st<P>(r, x, lane_off<T, S>(c), (uint32_t)(s * LB * (int)sizeof(T)));
 }
 
-// One cell-model update of cell c of a slot-major state set: gates by
+// One cell-model update of cell c of a tile-major state set: gates by
 // Rush-Larsen, FP64 concentrations by forward Euler, all from level-n values.
 // Returns I_ion at level n (0 for passive cells).
 // MSET: bit 0 TP06 (any layer), 1 CRN, 2 Stewart, 3 passive.
@@ -330,30 +349,30 @@ __device__ __forceinline__ void sst(__amdgpu_buffer_rsrc_t r, int s, int64_t n, 
 // with AB2, the previous rates of the latter), step, store.
 template <typename R, int NG, int NC, bool AB2, typename F>
 __device__ __forceinline__ R model_io(__amdgpu_buffer_rsrc_t rgate, __amdgpu_buffer_rsrc_t rconc,
-                                      __amdgpu_buffer_rsrc_t rhist, int64_t N, uint32_t c,
-                                      bool first, F &&fn) {
+                                      __amdgpu_buffer_rsrc_t rhist, uint32_t c, bool first,
+                                      F &&fn) {
     R g[NG_MAX];
     double cc[NC_MAX], hh[NC_MAX];
 #pragma unroll
-    for (int s = 0; s < NG; ++s) g[s] = sld<R>(rgate, s, N, c);
+    for (int s = 0; s < NG; ++s) g[s] = sld<R, NG_MAX>(rgate, s, c);
 #pragma unroll
-    for (int s = 0; s < NC; ++s) cc[s] = sld<double>(rconc, s, N, c);
+    for (int s = 0; s < NC; ++s) cc[s] = sld<double, NC_MAX>(rconc, s, c);
     R iion;
     if constexpr (AB2) {
         if (!first) {
 #pragma unroll
-            for (int s = 0; s < NC; ++s) hh[s] = sld<double>(rhist, s, N, c);
+            for (int s = 0; s < NC; ++s) hh[s] = sld<double, NC_MAX>(rhist, s, c);
         }
         iion = fn(g, cc, AdamsBashforth2{hh, first});
 #pragma unroll
-        for (int s = 0; s < NC; ++s) sst<double>(rhist, s, N, c, hh[s]);
+        for (int s = 0; s < NC; ++s) sst<double, NC_MAX>(rhist, s, c, hh[s]);
     } else {
         iion = fn(g, cc, FwdEuler{});
     }
 #pragma unroll
-    for (int s = 0; s < NG; ++s) sst<R>(rgate, s, N, c, g[s]);
+    for (int s = 0; s < NG; ++s) sst<R, NG_MAX>(rgate, s, c, g[s]);
 #pragma unroll
-    for (int s = 0; s < NC; ++s) sst<double>(rconc, s, N, c, cc[s]);
+    for (int s = 0; s < NC; ++s) sst<double, NC_MAX>(rconc, s, c, cc[s]);
     return iion;
 }
 
@@ -362,7 +381,7 @@ __device__ __forceinline__ R model_io(__amdgpu_buffer_rsrc_t rgate, __amdgpu_buf
 // rates at midpoint predictions (second order overall).
 template <typename R, int MSET, int SCH = 0>
 __device__ __forceinline__ R ionic(int md, R v, __amdgpu_buffer_rsrc_t rgate,
-                                   __amdgpu_buffer_rsrc_t rconc, int64_t N, uint32_t c, R dt,
+                                   __amdgpu_buffer_rsrc_t rconc, uint32_t c, R dt,
                                    double dtd, R istim, const GScale &gs,
                                    __amdgpu_buffer_rsrc_t rhist = rsrc(nullptr),
                                    bool first = false, R lmi = R(0)) {
@@ -370,17 +389,17 @@ __device__ __forceinline__ R ionic(int md, R v, __amdgpu_buffer_rsrc_t rgate,
     R iion = R(0);
     if ((MSET & 1) && md <= 2) {
         iion = model_io<R, tp06::NG, tp06::NC, HIST>(
-            rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
+            rgate, rconc, rhist, c, first, [&](R *g, double *cc, const auto &e) {
                 return tp06::step<R, MID>(md, v, g, cc, dt, dtd, istim, gs, e, lmi);
             });
     } else if ((MSET & 2) && md == 3) {
         iion = model_io<R, crn::NG, crn::NC, HIST>(
-            rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
+            rgate, rconc, rhist, c, first, [&](R *g, double *cc, const auto &e) {
                 return crn::step<R, MID>(v, g, cc, dt, dtd, gs, e, lmi);
             });
     } else if ((MSET & 4) && md == 4) {
         iion = model_io<R, stewart::NG, stewart::NC, HIST>(
-            rgate, rconc, rhist, N, c, first, [&](R *g, double *cc, const auto &e) {
+            rgate, rconc, rhist, c, first, [&](R *g, double *cc, const auto &e) {
                 return stewart::step<R, MID>(v, g, cc, dt, dtd, istim, gs, e, lmi);
             });
     }
@@ -405,7 +424,6 @@ template <typename R, int MSET, bool BIDO, int SCH>
 __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
                                           uint32_t active, bool sample, double &vol_v) {
     constexpr bool AB2 = SCH >= 1;
-    const int64_t N = D.nc;
     const R *__restrict__ vin = (const R *)D.v[n & 1];
     R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
     const R *__restrict__ vn = (const R *)D.vn;
@@ -417,19 +435,19 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     R L = R(0);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
-        L += sld<R>(rbeta, s, N, c) * at(vn, (uint32_t)sld<int32_t>(rnode, s, N, c));
+        L += sld<R, 8>(rbeta, s, c) * at(vn, (uint32_t)sld<int32_t, 8>(rnode, s, c));
     if constexpr (BIDO) {
         // the flux of u = v + phi_e (node values above are those of u)
         const R uc = v + R(at(D.phi, c));
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const uint32_t k = (uint32_t)sld<int32_t>(rnbr, f, N, c);
-            L += sld<R>(rb, f, N, c) * ((at(vin, k) + R(at(D.phi, k))) - uc);
+            const uint32_t k = (uint32_t)sld<int32_t, 4>(rnbr, f, c);
+            L += sld<R, 4>(rb, f, c) * ((at(vin, k) + R(at(D.phi, k))) - uc);
         }
     } else {
 #pragma unroll
         for (int f = 0; f < 4; ++f)
-            L += sld<R>(rb, f, N, c) * (at(vin, (uint32_t)sld<int32_t>(rnbr, f, N, c)) - v);
+            L += sld<R, 4>(rb, f, c) * (at(vin, (uint32_t)sld<int32_t, 4>(rnbr, f, c)) - v);
     }
 
     // ---- stimulus: protocol pulses, then junction pulses (junction order)
@@ -457,10 +475,10 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     const R dt = R(D.dt);
     R iion;
     if constexpr (AB2)
-        iion = ionic<R, MSET, SCH>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim,
+        iion = ionic<R, MSET, SCH>(md, v, rsrc(D.gate), rsrc(D.conc), c, dt, D.dt, istim,
                                    D.gs, rsrc(D.hc), n == 0, L - istim);
     else
-        iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), N, c, dt, D.dt, istim, D.gs);
+        iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), c, dt, D.dt, istim, D.gs);
 
     // ---- explicit update of v
     const R vnew = v_update<R, AB2>(v, dt, L - iion - istim, D.hv, c, n == 0);
@@ -545,10 +563,10 @@ __global__ void __launch_bounds__(TILE) k_purkinje(Tables tb, int32_t step_off, 
     const R dt = R(P.dtp);
     R iion;
     if constexpr (AB2)
-        iion = ionic<R, 15, SCH>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp,
+        iion = ionic<R, 15, SCH>(P.model, v, rsrc(P.gate), rsrc(P.conc), i, dt, P.dtp,
                                  istim, P.gs, rsrc(P.hc), q == 0, L - istim);
     else
-        iion = ionic<R, 15>(P.model, v, rsrc(P.gate), rsrc(P.conc), P.np, i, dt, P.dtp, istim,
+        iion = ionic<R, 15>(P.model, v, rsrc(P.gate), rsrc(P.conc), i, dt, P.dtp, istim,
                             P.gs);
     const R vnew = v_update<R, AB2>(v, dt, L - iion - istim, P.hv, i, q == 0);
     vout[i] = vnew;
