@@ -705,11 +705,13 @@ ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes, double *cell
     const double ninc = (double)s->inst.prep.n_incidences;
     if (node_bytes) *node_bytes = ninc * (4.0 + r) + nc * r + nn * r + 8.0 * s->inst.n_slices;
     // cell kernel: stencil (8 node ids + 8 coefficients + 4 neighbours + 4
-    // coefficients), vn once, v^n once, v^{n+1} write, model byte, state
+    // coefficients; 16-bit ids plus two 32-bit bases per 256 cells when the
+    // instance has them), vn once, v^n once, v^{n+1} write, model byte, state
     // read+write, detection status byte; with Adams-Bashforth 2 the previous
     // rates of v and of the non-gating states, read and written (none are
     // read on step 0)
-    double b = nc * (8 * 4.0 + 8 * r + 4 * 4.0 + 4 * r + r + r + 1.0 + 1.0) + nn * r;
+    const double ids = s->inst.idx16 ? 12 * 2.0 + 8.0 / epdev::LB : 12 * 4.0;
+    double b = nc * (ids + 8 * r + 4 * r + r + r + 1.0 + 1.0) + nn * r;
     for (uint8_t m : s->inst.prep.model) {
         b += 2.0 * (model_ng(m) * r + model_nc(m) * 8.0);
         if (s->inst.ab2) b += 2.0 * (r + model_nc(m) * 8.0);

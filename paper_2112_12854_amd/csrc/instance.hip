@@ -76,6 +76,34 @@ std::vector<R> conv(const std::vector<double> &v) {
 
 size_t round256(size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; }
 
+// Per 256-cell block, the smallest id over the S slot-major rows of `a`
+// (into *base when given); false when some block's ids span more than 65,535.
+bool block_bases(const std::vector<int32_t> &a, int S, int64_t n, std::vector<int32_t> *base) {
+    const int64_t nb = (n + LB - 1) / LB;
+    if (base) base->assign(nb, 0);
+    for (int64_t b = 0; b < nb; ++b) {
+        int32_t lo = INT32_MAX, hi = INT32_MIN;
+        for (int s = 0; s < S; ++s)
+            for (int64_t c = b * LB; c < std::min<int64_t>(n, (b + 1) * LB); ++c) {
+                const int32_t x = a[(size_t)s * n + c];
+                lo = std::min(lo, x);
+                hi = std::max(hi, x);
+            }
+        if ((int64_t)hi - lo > 65535) return false;
+        if (base) (*base)[b] = lo;
+    }
+    return true;
+}
+
+// tile-major 16-bit offsets of the ids of `a` from their block's base
+std::vector<uint16_t> offsets16(const std::vector<int32_t> &a, int S, int64_t n,
+                                const std::vector<int32_t> &base) {
+    std::vector<uint16_t> t(tiled_len(n, S), 0);
+    for (int s = 0; s < S; ++s)
+        for (int64_t c = 0; c < n; ++c) t[tix(c, s, S)] = (uint16_t)(a[(size_t)s * n + c] - base[c / LB]);
+    return t;
+}
+
 // slot-major [S][n] host array -> the device's tile-major layout
 template <typename T>
 std::vector<T> tiled(const std::vector<T> &a, int S, int64_t n) {
@@ -214,6 +242,10 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     in.sigma_et = sp.sigma_et;
     std::string e = prepare(in, I.prep);
     if (!e.empty()) { st = EP_EINVAL; return e; }
+    // 16-bit stencil ids when every block allows them (the elliptic operator
+    // of the bidomain model reads the 32-bit ones)
+    I.idx16 = !sp.bido && block_bases(I.prep.cnode, 8, I.prep.n_tets, nullptr) &&
+              block_bases(I.prep.cnbr, 4, I.prep.n_tets, nullptr);
     I.coarse = Coarse();
     if (sp.bido && sp.bido_coarse > 0) {
         e = build_coarse(in, I.prep, sp.bido_coarse, I.coarse);
@@ -268,8 +300,11 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     else if (sp.trace_every > 0) cap = 1 << 16;
     size_t b = 0;
     b += round256(P.sell_off.size() * 8) + round256(ent * 4) + round256(ent * r);
-    b += round256(tiled_len(c, 8) * 4) + round256(tiled_len(c, 8) * r) + round256(tiled_len(c, 4) * 4) +
-         round256(tiled_len(c, 4) * r);
+    if (I.idx16)
+        b += round256(tiled_len(c, 8) * 2) + round256(tiled_len(c, 4) * 2) + 2 * round256((c + LB - 1) / LB * 4);
+    else
+        b += round256(tiled_len(c, 8) * 4) + round256(tiled_len(c, 4) * 4);
+    b += round256(tiled_len(c, 8) * r) + round256(tiled_len(c, 4) * r);
     b += round256(c) + round256(c * 8) + round256(c * 4);
     b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);
     b += 4 * round256(c * r) + round256(n * r);
@@ -431,10 +466,22 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     D.nn = nn;
     auto fail_mem = [&]() { st = EP_ENOMEM; free_instance(I); return std::string("device allocation failed"); };
     if (!up(I, (void **)&D.sell_off, P.sell_off) || !up(I, (void **)&D.sell_cell, P.sell_cell) ||
-        !up(I, (void **)&D.cnode, tiled(P.cnode, 8, nc)) || !up(I, (void **)&D.cnbr, tiled(P.cnbr, 4, nc)) ||
         !up(I, (void **)&D.model, P.model) || !up(I, (void **)&D.vol, P.vol))
         return fail_mem();
-    bool ok = rs == 8 ? (up(I, (void **)&D.sell_w, P.sell_w) &&
+    bool ok;
+    if (I.idx16) {
+        std::vector<int32_t> nbs, cbs;
+        block_bases(P.cnode, 8, nc, &nbs);
+        block_bases(P.cnbr, 4, nc, &cbs);
+        ok = up(I, (void **)&D.cnode16, offsets16(P.cnode, 8, nc, nbs)) &&
+             up(I, (void **)&D.cnbr16, offsets16(P.cnbr, 4, nc, cbs)) && up(I, (void **)&D.nbase, nbs) &&
+             up(I, (void **)&D.cbase, cbs);
+        D.idx16 = 1;
+    } else {
+        ok = up(I, (void **)&D.cnode, tiled(P.cnode, 8, nc)) && up(I, (void **)&D.cnbr, tiled(P.cnbr, 4, nc));
+    }
+    if (!ok) return fail_mem();
+    ok = rs == 8 ? (up(I, (void **)&D.sell_w, P.sell_w) &&
                          up(I, (void **)&D.cbeta, tiled(P.cbeta, 8, nc)) &&
                          up(I, (void **)&D.cb, tiled(P.cb, 4, nc)))
                       : (up(I, (void **)&D.sell_w, conv<float>(P.sell_w)) &&

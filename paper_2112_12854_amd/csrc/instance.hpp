@@ -94,6 +94,7 @@ struct Inst {
     int rs = 8;                        // sizeof(R): 8 FP64, 4 mixed
     PrepOut prep;
     int mset = 0;                      // model-set bits present
+    bool idx16 = false;                // 16-bit stencil ids (InstDesc::idx16)
     // internal cells of each model class (bits 1 TP06, 2 CRN, 4 Stewart,
     // 8 passive, in that order): cells are grouped by class on the host
     int64_t cls_begin[4] = {0, 0, 0, 0}, cls_end[4] = {0, 0, 0, 0};

@@ -74,10 +74,17 @@ struct InstDesc {
     const int64_t *sell_off;
     const int32_t *sell_cell;
     const void *sell_w;
-    const int32_t *cnode;         // tile-major, 8 slots
+    const int32_t *cnode;         // tile-major, 8 slots (null with 16-bit ids)
     const void *cbeta;            // tile-major, 8 slots
-    const int32_t *cnbr;          // tile-major, 4 slots
+    const int32_t *cnbr;          // tile-major, 4 slots (null with 16-bit ids)
     const void *cb;               // tile-major, 4 slots
+    // 16-bit stencil ids (idx16 != 0): node id = nbase[c / 256] + cnode16,
+    // neighbour id = cbase[c / 256] + cnbr16, when every 256-cell block's ids
+    // span at most 65,535
+    const uint16_t *cnode16;      // tile-major, 8 slots
+    const uint16_t *cnbr16;       // tile-major, 4 slots
+    const int32_t *nbase, *cbase; // [ceil(nc / 256)]
+    int32_t idx16, pad16;
     void *vn;                     // [nn]
     void *v[2];                   // v^n in v[n & 1]
     void *gate;                   // tile-major, NG_MAX slots
@@ -310,6 +317,12 @@ template <> struct BufIO<float> {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, v, s, P);
     }
 };
+template <> struct BufIO<uint16_t> {
+    template <int P>
+    static __device__ __forceinline__ uint16_t ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, P);
+    }
+};
 template <> struct BufIO<int32_t> {
     template <int P>
     static __device__ __forceinline__ int32_t ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
@@ -428,26 +441,35 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
     const R *__restrict__ vn = (const R *)D.vn;
     const __amdgpu_buffer_rsrc_t rbeta = rsrc(D.cbeta), rb = rsrc(D.cb);
-    const __amdgpu_buffer_rsrc_t rnode = rsrc(D.cnode), rnbr = rsrc(D.cnbr);
 
     // ---- diffusion: fused node-coefficient stencil plus two-point terms
     const R v = at(vin, c);
     R L = R(0);
+    auto stencil = [&](auto node_id, auto nbr_id) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
-        L += sld<R, 8>(rbeta, s, c) * at(vn, (uint32_t)sld<int32_t, 8>(rnode, s, c));
-    if constexpr (BIDO) {
-        // the flux of u = v + phi_e (node values above are those of u)
-        const R uc = v + R(at(D.phi, c));
+        for (int s = 0; s < 8; ++s) L += sld<R, 8>(rbeta, s, c) * at(vn, node_id(s));
+        if constexpr (BIDO) {
+            // the flux of u = v + phi_e (node values above are those of u)
+            const R uc = v + R(at(D.phi, c));
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            const uint32_t k = (uint32_t)sld<int32_t, 4>(rnbr, f, c);
-            L += sld<R, 4>(rb, f, c) * ((at(vin, k) + R(at(D.phi, k))) - uc);
+            for (int f = 0; f < 4; ++f) {
+                const uint32_t k = nbr_id(f);
+                L += sld<R, 4>(rb, f, c) * ((at(vin, k) + R(at(D.phi, k))) - uc);
+            }
+        } else {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) L += sld<R, 4>(rb, f, c) * (at(vin, nbr_id(f)) - v);
         }
+    };
+    if (D.idx16) {
+        const __amdgpu_buffer_rsrc_t rn16 = rsrc(D.cnode16), rf16 = rsrc(D.cnbr16);
+        const uint32_t nb = (uint32_t)at(D.nbase, c >> 8), fb = (uint32_t)at(D.cbase, c >> 8);
+        stencil([&](int s) { return nb + (uint32_t)sld<uint16_t, 8>(rn16, s, c); },
+                [&](int f) { return fb + (uint32_t)sld<uint16_t, 4>(rf16, f, c); });
     } else {
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-            L += sld<R, 4>(rb, f, c) * (at(vin, (uint32_t)sld<int32_t, 4>(rnbr, f, c)) - v);
+        const __amdgpu_buffer_rsrc_t rnode = rsrc(D.cnode), rnbr = rsrc(D.cnbr);
+        stencil([&](int s) { return (uint32_t)sld<int32_t, 8>(rnode, s, c); },
+                [&](int f) { return (uint32_t)sld<int32_t, 4>(rnbr, f, c); });
     }
 
     // ---- stimulus: protocol pulses, then junction pulses (junction order)
