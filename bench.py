@@ -151,17 +151,16 @@ def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
                 host_cpu=cpu, host_cpus_visible=os.cpu_count())
 
 
-def run_serving(ep, n_req, n_steps, capacity, load=0.7, seed=4, prec=None, one_at_a_time=False,
-                trial=20):
-    """Config-4 stream: slab requests log-uniform in [1e4, 1e6] tets with
-    Poisson arrivals at `load` x capacity (cell-steps/s) / mean request work;
-    continuous batching with the autotuned schedule (re-tuned as the batch
-    grows or shrinks), or one request at a time."""
+def run_serving(ep, n_req, n_steps, rate, seed=4, prec=None, one_at_a_time=False, trial=20):
+    """Serving stream: slab requests log-uniform in [1e4, 1e6] tets with
+    Poisson arrivals at a fixed `rate` (requests/s); continuous batching with
+    the autotuned schedule (re-tuned as the batch grows or shrinks), or one
+    request at a time."""
     from paper_2112_12854_amd import meshgen
     specs = meshgen.serving_requests(n=n_req, seed=seed)
     ws = [meshgen.serving_workload(sp, n_steps) for sp in specs]
     work = np.array([w.n_tets * n_steps for w in ws], dtype=np.float64)
-    lam = load * capacity / work.mean()
+    lam = rate
     rng = np.random.default_rng(seed + 1000)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
     sv = ep.Server(prec=prec, max_slots=1 if one_at_a_time else 256)
@@ -442,6 +441,8 @@ def main():
     ap.add_argument("--serving", type=str, default="32x2500", metavar="NxSTEPS",
                     help="serving stream sample (requests x steps each; '0' skips; "
                          "the full stream is 256x15000)")
+    ap.add_argument("--serve-rate", type=float, default=17.0, metavar="PER_S",
+                    help="Poisson arrival rate of the serving stream (requests/s)")
     ap.add_argument("--uq", type=str, default="1024x2000", metavar="NxSTEPS",
                     help="UQ batch sample (instances x steps; '0' skips; the full "
                          "batch is 1024x25000)")
@@ -502,15 +503,14 @@ def main():
     if not (args.only_fp32 or args.serving == "0"):
         nreq, nst = (int(x) for x in args.serving.split("x"))
         log(f"serving stream: {nreq} requests x {nst} steps (batched FP32-mixed) ...")
-        bat = run_serving(ep, nreq, nst, f32["cell_steps_per_s"], prec=ep.EP_FP32_MIXED)
+        bat = run_serving(ep, nreq, nst, args.serve_rate, prec=ep.EP_FP32_MIXED)
         log(f"  p50 {bat['p50_s']:.3f}s p99 {bat['p99_s']:.3f}s, {bat['cell_steps_per_s']:.3e} cell-steps/s")
         log("serving stream: one at a time, FP64 ...")
-        one = run_serving(ep, nreq, nst, f32["cell_steps_per_s"], prec=ep.EP_FP64,
-                          one_at_a_time=True)
+        one = run_serving(ep, nreq, nst, args.serve_rate, prec=ep.EP_FP64, one_at_a_time=True)
         log(f"  p50 {one['p50_s']:.3f}s p99 {one['p99_s']:.3f}s, {one['cell_steps_per_s']:.3e} cell-steps/s")
         serving = {"workload": f"{nreq} slab requests, 1e4-1e6 tets log-uniform, sigma scale "
                                f"U[0.5,2], random stimulus face, {nst} steps each, Poisson "
-                               f"arrivals at 0.7 x the FP32 slab throughput",
+                               f"arrivals at a fixed {args.serve_rate:g} requests/s",
                    "batched_fp32": bat, "one_at_a_time_fp64": one}
     if not (args.only_fp32 or args.uq == "0"):
         ni, nst = (int(x) for x in args.uq.split("x"))
