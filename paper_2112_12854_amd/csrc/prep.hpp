@@ -35,7 +35,8 @@ struct PrepOut {
     std::vector<int64_t> sell_off;    // [n_slices+1]
     std::vector<int32_t> sell_cell;
     std::vector<double> sell_w;
-    // fused cell stencil, slot-major ([slot][n_tets]), internal numbering:
+    // fused cell stencil, slot-major ([slot][n_tets]; the upload converts it
+    // to the device's tile-major layout), internal numbering:
     //   L_c = sum_{s<8} beta[s] vn[node[s]] + sum_{f<4} b[f] (v[nbr[f]] - v_c)
     std::vector<int32_t> cnode;       // [8][n]: own vertices, then the vertices opposite
                                       // the faces in the neighbours (triangles: 3 + 3,
