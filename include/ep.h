@@ -219,6 +219,18 @@ ep_status ep_get_purkinje_substeps(ep_sim *s, int32_t *n_sub);
 typedef enum { EP_SCHEME_FE = 0, EP_SCHEME_AB2 = 1, EP_SCHEME_RL2_AB2 = 2 } ep_time_scheme;
 ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme);
 
+/* Internal numbering of the cells, which is their order in device memory:
+ * reverse Cuthill-McKee from a peripheral cell (the default), Morton order of
+ * the centroids, or the caller's order; cells stay grouped by model class.
+ * Results and readouts (always in the caller's order) are the same up to the
+ * order of rounding; the memory traffic is not: with EP_ORDER_INPUT on an
+ * unordered mesh the node and neighbour ids of a 256-cell block usually span
+ * more than 16 bits, and the cell kernel then reads 32-bit ids
+ * (ep_algorithmic_bytes shows which).  Call before ep_init; EP_EINVAL for an
+ * unknown order. */
+typedef enum { EP_ORDER_RCM = 0, EP_ORDER_MORTON = 1, EP_ORDER_INPUT = 2 } ep_cell_order;
+ep_status ep_set_cell_order(ep_sim *s, int32_t order);
+
 /* Bidomain model (Sec. 3.1 eq. electro, Sec. 3.2 eq. electro2_3d) instead of
  * the monodomain one: the conductivities of ep_set_conductivity become the
  * intracellular ones M_i; sigma_el / sigma_et (mS/mm) give the extracellular

@@ -274,6 +274,15 @@ ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme) {
     return EP_OK;
 }
 
+ep_status ep_set_cell_order(ep_sim *s, int32_t order) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "the cell order is frozen after ep_init");
+    if (order != EP_ORDER_RCM && order != EP_ORDER_MORTON && order != EP_ORDER_INPUT)
+        return fail(s, EP_EINVAL, "unknown cell order");
+    s->spec.ordering = order;
+    return EP_OK;
+}
+
 ep_status ep_init(ep_sim *s) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "already initialised");

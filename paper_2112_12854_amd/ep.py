@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libep.so")
 EP_OK, EP_EINVAL, EP_ENOMEM, EP_EDEVICE, EP_ESTATE, EP_ENUMERIC, EP_EBUSY = 0, -1, -2, -3, -4, -5, -6
 EP_FP64, EP_FP32_MIXED = 0, 1
 EP_SCHEME_FE, EP_SCHEME_AB2, EP_SCHEME_RL2_AB2 = 0, 1, 2
+EP_ORDER_RCM, EP_ORDER_MORTON, EP_ORDER_INPUT = 0, 1, 2
 EP_TP06_ENDO, EP_TP06_MID, EP_TP06_EPI, EP_CRN, EP_STEWART, EP_PASSIVE = range(6)
 EP_MAX_SLOTS = 21
 STATUS_NAMES = {0: "EP_OK", -1: "EP_EINVAL", -2: "EP_ENOMEM", -3: "EP_EDEVICE",
@@ -112,6 +113,7 @@ _SIGS = {
                                   C.c_int32, C.c_int32]),
     "ep_set_purkinje_scale": (C.c_int, [C.c_void_p, C.c_int64, _dp]),
     "ep_set_time_scheme": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ep_set_cell_order": (C.c_int, [C.c_void_p, C.c_int32]),
     "ep_add_cell_junction": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
                                        C.c_int32, C.c_double, C.c_double]),
     "ep_add_pmj": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
@@ -234,7 +236,7 @@ class Sim:
 
     def __init__(self, w, prec: int = EP_FP64, device: int = 0,
                  allocator: str = "hip", trace_every: int = 50,
-                 launch=None):
+                 launch=None, cell_order=None):
         L = lib()
         o = ep_options()
         L.ep_default_options(C.byref(o))
@@ -295,6 +297,8 @@ class Sim:
                                      bd.max_iter), h)
         if launch is not None:
             self.set_launch(*launch)
+        if cell_order is not None:
+            _check(L.ep_set_cell_order(h, int(cell_order)), h)
         _check(L.ep_init(h), h)
 
     def close(self):

@@ -180,6 +180,57 @@ def test_single_tet_and_ordering_edge_cases(ep, oracle_lib):
         sim.step(-1)
 
 
+def shuffled(w, seed):
+    """The same workload with its cells listed in a random order."""
+    import dataclasses
+    p = np.random.default_rng(seed).permutation(w.n_tets)
+    inv = np.empty_like(p)
+    inv[p] = np.arange(w.n_tets)
+    stims = [dataclasses.replace(st, ids=np.sort(inv[st.ids]).astype(np.int32)) for st in w.stimuli]
+    return dataclasses.replace(w, tets=w.tets[p], fibre=w.fibre[p], model=w.model[p],
+                               scale=None if w.scale is None else w.scale[p], stimuli=stims,
+                               hex_ijk=None if w.hex_ijk is None else w.hex_ijk[p]), p
+
+
+def test_cell_orders_and_32bit_stencil_ids(ep, oracle_lib):
+    """Every cell order gives the oracle's potentials.  A mesh listed in
+    random order and kept in that order has stencil ids spanning more than 16
+    bits in a 256-cell block, so the cell kernel reads 32-bit ids there (24
+    algorithmic bytes more per cell than with 16-bit ids).  FP32-mixed is
+    compared during the stimulus (0.5 ms), before the front steepens."""
+    base = M.config1(n_steps=0, nx=64, ny=64, nz=16)
+    base.scale = np.random.default_rng(3).uniform(0.5, 2.0, base.n_tets)
+    w, p = shuffled(base, 11)
+    assert w.n_nodes > 65536
+    orders = (ep.EP_ORDER_RCM, ep.EP_ORDER_MORTON, ep.EP_ORDER_INPUT)
+    sims = {(o, q): ep.Sim(w, prec=q, cell_order=o) for o in orders
+            for q in (ep.EP_FP64, ep.EP_FP32_MIXED)}
+    ref = oracle_lib.Sim(w)
+    ref.step(25)
+    say(f"cell orders: {w.n_tets} tets, {w.n_nodes} nodes")
+    for (o, q), sim in sims.items():
+        sim.step(25)
+        dv = np.abs(sim.vm() - ref.vm()).max()
+        assert dv <= (FP64_TOL_MV if q == ep.EP_FP64 else 1e-2), (o, q, dv)
+    ref.step(125)
+    per_cell = {}
+    for o in orders:
+        sim = sims[(o, ep.EP_FP64)]
+        sim.step(125)
+        dv = np.abs(sim.vm() - ref.vm()).max()
+        assert dv <= FP64_TOL_MV, (o, dv)
+        per_cell[o] = sim.algorithmic_bytes()[1] / w.n_tets
+    for sim in sims.values():
+        sim.close()
+    wide = per_cell[ep.EP_ORDER_RCM] + (24 - 8 / 256)
+    assert abs(per_cell[ep.EP_ORDER_INPUT] - wide) < 1e-6
+    # Morton order numbers nodes by first touch along a space-filling curve,
+    # whose blocks may reach back to nodes touched long before: either width
+    assert min(abs(per_cell[ep.EP_ORDER_MORTON] - x) for x in (per_cell[ep.EP_ORDER_RCM], wide)) < 1e-6
+    with pytest.raises(ep.EPError):
+        ep.Sim(base, cell_order=3)
+
+
 # -------------------------------------------------- stepping machinery
 def test_graph_replay_equals_direct_launch(ep):
     w = M.config1(nx=8, ny=8, nz=2)
