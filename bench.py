@@ -471,8 +471,8 @@ def main():
         log(f"copied {args.copy_calib} MiB x 10")
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multi-GPU path of this build is "
-              "a design (instances or mesh partitions per GPU), not an implementation",
+        print("bench.py runs on one GPU only: spreading instances or mesh partitions "
+              "over several GPUs is designed, not implemented",
               file=sys.stderr)
         sys.exit(2)
 
