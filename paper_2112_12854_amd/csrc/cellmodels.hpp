@@ -11,8 +11,8 @@
 // FP64: they integrate small increments over hundreds of thousands of steps.
 //
 // Rush-Larsen is written as y += (y_inf - y) * (-expm1(-dt k)), k = 1/tau,
-// which keeps the per-step increment of slow gates accurate in FP32 where
-// exp(-dt/tau) would round to 1.
+// in FP32, which keeps the per-step increment of slow gates accurate where
+// exp(-dt/tau) would round to 1; FP64 uses y_inf + (y - y_inf) exp(-dt k).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cmath>
@@ -57,6 +57,11 @@ template <typename R> __device__ __forceinline__ R sig(R z) { return xrcp(R(1) +
 template <typename R>
 __device__ __forceinline__ R rl(R y, R yinf, R k, R dt) {
     return y + (yinf - y) * (-xexpm1(-dt * k));
+}
+// FP64 has the digits for the plain form, and exp is cheaper than expm1
+template <>
+__device__ __forceinline__ double rl(double y, double yinf, double k, double dt) {
+    return yinf + (y - yinf) * exp(-dt * k);
 }
 
 // z / (e^z - 1), continuous at 0
