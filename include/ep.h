@@ -291,7 +291,10 @@ const char *ep_model_slot_name(int model, int slot);     /* NULL if bad       */
 
 /* Checkpoint: an opaque byte image of every state array, the detection
  * state, the step counter and the trace.  Restoring it into a simulation
- * built from the same inputs continues bitwise identically. */
+ * built from the same inputs continues bitwise identically.  The image holds
+ * the device layout, tagged by a version in its header: ep_set_state returns
+ * EP_EINVAL for an image of another layout version, mesh size, precision,
+ * time scheme or model configuration. */
 ep_status ep_state_size(ep_sim *s, size_t *bytes);
 ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes);
 ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);

@@ -19,7 +19,8 @@ using ep::model_ng;
 
 namespace {
 
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b36ULL;   // "EPSMCHK6"
+// "EPSMCHK7": states in the tile-major layout
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b37ULL;
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
