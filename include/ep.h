@@ -326,7 +326,9 @@ ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms,
                            double *node_ms);
 
 /* Algorithmic bytes moved per step by the node gather and by the cell
- * kernel for this mesh and precision (the roofline numerators). */
+ * kernel for this mesh, precision, time scheme and stencil-id width (16-bit
+ * offsets from per-block bases when every 256-cell block allows them, else
+ * 32-bit ids): the roofline numerators.  EP_ESTATE before ep_init. */
 ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes,
                                double *cell_bytes);
 
