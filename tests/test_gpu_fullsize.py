@@ -66,6 +66,36 @@ def test_full_slab_fp32_activation(ep, slab_ref):
     assert d.max() <= 0.5
 
 
+def test_full_slab_400ms_fp32_error_per_cell(ep):
+    """The benchmark slab run for its whole 400 ms: activation time and APD90
+    of every cell in the FP32-mixed path against the FP64 path, which equals
+    the oracle to 1e-13 mV at this size (above); the oracle itself would need
+    about an hour here.  Bars: |dAT| <= 0.5 ms, |dAPD90| <= 1 ms per cell.
+    A cell whose crossing falls in the last steps may be detected by one path
+    only; at most 0.1 % of the cells may differ so."""
+    w = M.config2(n_steps=20000)
+    res = {}
+    for prec in (ep.EP_FP64, ep.EP_FP32_MIXED):
+        g = ep.Sim(w, prec=prec, allocator="torch", launch=LAUNCH)
+        g.step(20000)
+        res[prec] = (g.activation(), g.apd90())
+        g.close()
+    (at64, apd64), (at32, apd32) = res[ep.EP_FP64], res[ep.EP_FP32_MIXED]
+    n = w.n_tets
+    assert np.isfinite(at64).sum() > 0.99 * n
+    assert (np.isfinite(at32) != np.isfinite(at64)).sum() <= 1e-3 * n
+    # APD90 is about 300 ms: the cells the wave reaches late have not
+    # repolarised by 400 ms (NaN on both paths)
+    assert np.isfinite(apd64).sum() > 0.25 * n
+    assert (np.isfinite(apd32) != np.isfinite(apd64)).sum() <= 1e-3 * n
+    for name, a, b, bar in (("AT", at32, at64, 0.5), ("APD90", apd32, apd64, 1.0)):
+        both = np.isfinite(a) & np.isfinite(b)
+        d = np.abs(a - b)[both]
+        say(f"  FP32 {name} error over {both.sum()} cells: max {d.max():.4f} ms, "
+            f"p99 {np.percentile(d, 99):.4f} ms, mean {d.mean():.5f} ms")
+        assert d.max() <= bar
+
+
 def test_full_heart_fp64_every_cell(ep, oracle_lib):
     w = M.heart(h=0.375, scale=1.0, purkinje_nodes=60000, n_pmj=2000)
     w.stimuli[-1].t0 = 0.0                  # His root driven from the start
