@@ -130,7 +130,7 @@ def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
     el = time.perf_counter() - t0
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
-    s1 = max(2, steps // 10)
+    s1 = max(2, steps // 30)
     t0 = time.perf_counter()
     ref.step(s1)
     el1 = time.perf_counter() - t0
@@ -433,7 +433,7 @@ def main():
     ap.add_argument("--nz", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--only-fp32", action="store_true",
                     help="FP32-mixed only (short profiling runs)")
     ap.add_argument("--only-fp64", action="store_true",
