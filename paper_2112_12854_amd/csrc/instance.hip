@@ -703,29 +703,51 @@ void launch_step(Stepper &s, int32_t off) {
     launch_cells<R>(s, tb, off);
 }
 
-// Graph substeps and junction events of step offset `off` (after the tissue).
+// Graph substeps of step offset `off` on stream `st`.  They read the graph,
+// the junction table (pulses scheduled by earlier steps) and the control
+// block, and write only the graph, so they may run beside the tissue kernels
+// of the same step.
 template <typename R>
-void launch_purkinje(Stepper &s, int32_t off) {
+void launch_substeps(Stepper &s, int32_t off, hipStream_t st) {
     const Tables tb = tables(s);
-    // (no graph tiles when every junction has a source cell)
-    for (int32_t sub = 0; s.n_pt > 0 && sub < s.n_sub_max; ++sub) {
-        if (s.scheme == 2) k_purkinje<R, 2><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
-        else if (s.scheme == 1) k_purkinje<R, 1><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
-        else k_purkinje<R, 0><<<(int)s.n_pt, TILE, 0, s.stream>>>(tb, off, sub);
+    for (int32_t sub = 0; sub < s.n_sub_max; ++sub) {
+        if (s.scheme == 2) k_purkinje<R, 2><<<(int)s.n_pt, TILE, 0, st>>>(tb, off, sub);
+        else if (s.scheme == 1) k_purkinje<R, 1><<<(int)s.n_pt, TILE, 0, st>>>(tb, off, sub);
+        else k_purkinje<R, 0><<<(int)s.n_pt, TILE, 0, st>>>(tb, off, sub);
     }
-    k_junctions<R><<<(int)s.n_pk, TILE, 0, s.stream>>>(tb, off);
 }
 
-void enqueue(Stepper &s, int64_t k) {
-    for (int64_t i = 0; i < k; ++i) {
+// Junction events of step offset `off`: after the tissue and the substeps.
+template <typename R>
+void launch_junctions(Stepper &s, int32_t off) {
+    k_junctions<R><<<(int)s.n_pk, TILE, 0, s.stream>>>(tables(s), off);
+}
+
+std::string enqueue(Stepper &s, int64_t k) {
+    hipError_t e = hipSuccess;
+    for (int64_t i = 0; i < k && e == hipSuccess; ++i) {
+        // (no graph tiles when every junction has a source cell)
+        const bool fork = s.n_pk > 0 && s.n_pt > 0 && s.n_sub_max > 0;
+        if (fork) {
+            if ((e = hipEventRecord(s.ev_fork, s.stream)) != hipSuccess ||
+                (e = hipStreamWaitEvent(s.side, s.ev_fork, 0)) != hipSuccess)
+                break;
+            if (s.rs == 8) launch_substeps<double>(s, (int32_t)i, s.side);
+            else launch_substeps<float>(s, (int32_t)i, s.side);
+        }
         if (s.rs == 8) launch_step<double>(s, (int32_t)i);
         else launch_step<float>(s, (int32_t)i);
+        if (fork && ((e = hipEventRecord(s.ev_join, s.side)) != hipSuccess ||
+                     (e = hipStreamWaitEvent(s.stream, s.ev_join, 0)) != hipSuccess))
+            break;
         if (s.n_pk > 0) {
-            if (s.rs == 8) launch_purkinje<double>(s, (int32_t)i);
-            else launch_purkinje<float>(s, (int32_t)i);
+            if (s.rs == 8) launch_junctions<double>(s, (int32_t)i);
+            else launch_junctions<float>(s, (int32_t)i);
         }
     }
+    if (e != hipSuccess) return std::string("graph substep stream: ") + hipGetErrorString(e);
     k_advance<<<1, 256, 0, s.stream>>>(tables(s), k);
+    return "";
 }
 
 std::string hip_err(const char *what, hipError_t e) {
@@ -740,6 +762,10 @@ std::string stepper_init(Stepper &s, int device, hipStream_t stream, int rs) {
     s.rs = rs;
     hipError_t e = hipEventCreateWithFlags(&s.stage_done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_err("hipEventCreate", e);
+    if ((e = hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s.ev_join, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&s.side, hipStreamNonBlocking)) != hipSuccess)
+        return hip_err("stepper streams and events", e);
     e = hipMalloc((void **)&s.d_counts, 8 * sizeof(int32_t));
     if (e != hipSuccess) return hip_err("hipMalloc", e);
     return "";
@@ -758,6 +784,11 @@ void stepper_free(Stepper &s) {
     s.d_purk = nullptr;
     if (s.h_stage) (void)hipHostFree(s.h_stage);
     if (s.stage_done) (void)hipEventDestroy(s.stage_done);
+    if (s.side) (void)hipStreamSynchronize(s.side);
+    if (s.side) (void)hipStreamDestroy(s.side);
+    if (s.ev_fork) (void)hipEventDestroy(s.ev_fork);
+    if (s.ev_join) (void)hipEventDestroy(s.ev_join);
+    s.side = nullptr; s.ev_fork = s.ev_join = nullptr;
     s.d_desc = nullptr; s.d_ctiles = s.d_ntiles = nullptr; s.d_counts = nullptr;
     s.h_stage = nullptr; s.stage_done = nullptr;
 }
@@ -884,8 +915,12 @@ std::string stepper_run(Stepper &s, int64_t k) {
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_err("hipStreamBeginCapture", e);
-            enqueue(s, glen);
+            const std::string eq = enqueue(s, glen);
             e = hipStreamEndCapture(s.stream, &g);
+            if (!eq.empty()) {
+                if (g) (void)hipGraphDestroy(g);
+                return eq;
+            }
             if (e != hipSuccess) return hip_err("hipStreamEndCapture", e);
             e = hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -904,7 +939,10 @@ std::string stepper_run(Stepper &s, int64_t k) {
             left -= glen;
         }
     }
-    if (left > 0) enqueue(s, left);
+    if (left > 0) {
+        const std::string eq = enqueue(s, left);
+        if (!eq.empty()) return eq;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_err("kernel launch", e);
     for (Inst *I : s.insts) I->host_step = std::min(I->host_step + k, std::max(I->host_step, I->target));
@@ -975,9 +1013,11 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
         if (s.rs == 8) launch_cells<double>(s, tb, 0);
         else launch_cells<float>(s, tb, 0);
         (void)hipEventRecord(ev[2], s.stream);
-        if (s.n_pk > 0) {
-            if (s.rs == 8) launch_purkinje<double>(s, 0);
-            else launch_purkinje<float>(s, 0);
+        if (s.n_pk > 0) {               // one stream here: the timings stay apart
+            if (s.n_pt > 0 && s.rs == 8) launch_substeps<double>(s, 0, s.stream);
+            else if (s.n_pt > 0) launch_substeps<float>(s, 0, s.stream);
+            if (s.rs == 8) launch_junctions<double>(s, 0);
+            else launch_junctions<float>(s, 0);
         }
         k_advance<<<1, 256, 0, s.stream>>>(tb, 1);
         (void)hipEventSynchronize(ev[2]);

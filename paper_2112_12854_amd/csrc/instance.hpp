@@ -161,6 +161,11 @@ size_t estimate_footprint(int64_t n_tets, int64_t n_nodes, int rs, int max_degre
 // A set of instances stepped together on one stream.
 struct Stepper {
     hipStream_t stream = nullptr;
+    // the graph substeps of a step run on a second stream, beside the
+    // tissue kernels of the same step (neither reads what the other writes);
+    // the junction events wait for both
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     int rs = 8;
     int grid_node = 0;                 // one block per tile (set when launching)
