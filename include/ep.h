@@ -310,10 +310,11 @@ ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
 /* Launch-schedule autotuner (batched scheduling is this library's, not the
  * paper's).  Tries every graph length in {0 (direct launches), 10, 25, 50,
  * 100} steps, each with and without the XCD tile remap: one untimed launch
- * (graph capture, warm caches), then trial_steps steps timed with HIP events
- * on the simulation's stream.  Keeps the fastest (as ep_set_launch would)
- * and reports it; any output pointer may be NULL.  The trials are ordinary
- * steps: the simulation advances by 10 * trial_steps + 372 steps, with the
+ * (graph capture, warm caches), then trial_steps steps, rounded up to whole
+ * graphs, timed with HIP events on the simulation's stream.  Keeps the
+ * fastest (as ep_set_launch would) and reports it; any output pointer may be
+ * NULL.  The trials are ordinary steps: the simulation advances by 372 steps
+ * plus twice the sum over the five candidates of their timed steps, with the
  * same results as under any fixed schedule.  EP_ESTATE before ep_init,
  * EP_EINVAL for trial_steps <= 0. */
 ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
@@ -456,11 +457,12 @@ ep_status ep_server_set_time_scheme(ep_server *sv, int32_t scheme);
 /* hold != 0: keep admitting and uploading requests but step none, so that a
  * batch can start together (a UQ sweep); hold == 0 resumes stepping. */
 ep_status ep_server_hold(ep_server *sv, int32_t hold);
-/* Autotune the schedule (as ep_autotune, trial_steps per candidate) on the
- * batch that is live when the driver next steps; with retune != 0, tune again
- * whenever at least 4 requests are live and their number has doubled or
- * halved since the last tuning.  The trials are ordinary steps of the live
- * requests. */
+/* Autotune the schedule (as ep_autotune, trial_steps per candidate, rounded
+ * up to whole graphs) on the batch that is live when the driver next steps;
+ * with retune != 0, tune again whenever at least 4 requests are live, their
+ * number has doubled or halved since the last tuning, and the batch has
+ * advanced at least ten times the steps that tuning took.  The trials are
+ * ordinary steps of the live requests. */
 ep_status ep_server_autotune(ep_server *sv, int64_t trial_steps, int32_t retune);
 void ep_server_destroy(ep_server *sv);    /* waits for running requests */
 const char *ep_server_last_error(ep_server *sv);

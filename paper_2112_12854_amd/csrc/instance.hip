@@ -967,18 +967,20 @@ std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
             s.steps_per_graph = k;
             s.remap = remap;
             const int64_t warm = k > 0 ? k : 1;
+            // whole graphs, so that the trial times the schedule it names
+            const int64_t n = k > 0 ? (trial_steps + k - 1) / k * k : trial_steps;
             err = stepper_run(s, warm);
             if (!err.empty()) break;
             (void)hipEventRecord(e0, s.stream);
-            err = stepper_run(s, trial_steps);
+            err = stepper_run(s, n);
             if (!err.empty()) break;
             (void)hipEventRecord(e1, s.stream);
             (void)hipEventSynchronize(e1);
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
             out.n_trials++;
-            out.steps_used += warm + trial_steps;
-            const double per = ms / trial_steps;
+            out.steps_used += warm + n;
+            const double per = ms / n;
             if (per < best) {
                 best = per;
                 out.steps_per_graph = k;

@@ -84,6 +84,10 @@ struct ep_server {
     bool tune_pending = false, tune_retune = false;
     int64_t tune_trial = 0;
     size_t tuned_live = 0;
+    // steps issued since the last tuning, and the steps that tuning took:
+    // retuning waits until the batch has advanced ten times as far, so that
+    // the trials (each ends in a wait for the device) stay a small share
+    int64_t steps_since_tune = 0, tune_steps = 0;
 };
 
 namespace {
@@ -338,7 +342,8 @@ void driver_main(ep_server *sv) {
             const size_t n = live.size(), m = sv->tuned_live;
             tune = n > 0 && sv->tune_trial > 0 &&
                    (sv->tune_pending ||
-                    (sv->tune_retune && n >= 4 && (n >= 2 * m || 2 * n <= m)));
+                    (sv->tune_retune && n >= 4 && (n >= 2 * m || 2 * n <= m) &&
+                     sv->steps_since_tune >= 10 * sv->tune_steps));
             trial = sv->tune_trial;
         }
         // tet-steps issued by a stepping call (progress of the live batch)
@@ -365,6 +370,8 @@ void driver_main(ep_server *sv) {
             sv->want_remap = r.xcd_remap;
             sv->tune_pending = false;
             sv->tuned_live = live.size();
+            sv->steps_since_tune = 0;
+            sv->tune_steps = r.steps_used;
             sv->stats.autotune_runs++;
             sv->stats.tuned_ms_per_step = r.ms_per_step;
             sv->stats.graph_launches += r.n_trials;
@@ -382,6 +389,7 @@ void driver_main(ep_server *sv) {
             std::lock_guard<std::mutex> g(sv->mu);
             sv->stats.graph_launches++;
             sv->stats.cell_steps += c;
+            sv->steps_since_tune += k;
         }
         // ---- keep at most two launches queued ahead of the host
         while (inflight.size() > 2) {

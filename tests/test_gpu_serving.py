@@ -130,7 +130,9 @@ def test_autotuned_schedule_keeps_results(ep):
     choice = a.autotune(20)
     assert choice["steps_per_graph"] in (0, 10, 25, 50, 100)
     assert choice["xcd_remap"] in (0, 1) and choice["ms_per_step"] > 0
-    used = 10 * 20 + 372
+    # per remap: 20 direct steps, then each graph length k in whole graphs
+    # (20, 25, 50, 100) after one untimed graph (1 + 10 + 25 + 50 + 100)
+    used = 2 * (20 + 20 + 25 + 50 + 100) + 2 * (1 + 10 + 25 + 50 + 100)
     assert a.time()[0] == used
     a.step(1000 - used)
     b = ep.Sim(w)
