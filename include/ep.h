@@ -283,7 +283,11 @@ ep_status ep_get_time(ep_sim *s, int64_t *step, double *t);
 /* Per-cell states as FP64, layout out[slot * n + cell] with n == n_tets,
  * n_slots == EP_MAX_SLOTS.  Slot 0 is V; the model's states follow in the
  * order of ep_model_slot_name(); unused slots read NaN and are ignored on
- * write.  In EP_FP32_MIXED the FP32 slots are rounded on write. */
+ * write.  In EP_FP32_MIXED the FP32 slots are rounded on write.  States set
+ * before the first step also become the resting potential of the APD90
+ * detection; with an Adams-Bashforth scheme the stored previous rates are
+ * not recomputed, so set states before the first step (or restore a
+ * checkpoint) for a clean second-order start.  Graph nodes keep theirs. */
 ep_status ep_get_states(ep_sim *s, double *out, int64_t n, int32_t n_slots);
 ep_status ep_set_states(ep_sim *s, const double *in, int64_t n, int32_t n_slots);
 int ep_model_n_slots(int model);                         /* incl. V, 0 if bad */
