@@ -78,10 +78,15 @@ def run_precision(ep, w, prec, steps, warmup, chunk, profile_steps):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     log(f"prec={prec}: {steps} steps in {elapsed:.3f}s")
-    cell_ms, node_ms = sim.profile_steps(profile_steps)
     node_b, cell_b = sim.algorithmic_bytes()
     at = sim.activation()
     n_sub = sim.purkinje_n_sub() if sim.n_purkinje else 0
+    sim.close()
+    # kernel durations over the same window of the same job: a fresh
+    # simulation, the same untimed warm-up, then event-timed direct launches
+    sim = ep.Sim(w, prec=prec, allocator="torch", trace_every=50)
+    sim.step(warmup)
+    cell_ms, node_ms = sim.profile_steps(profile_steps)
     res = dict(ms_per_step=1e3 * elapsed / steps,
                graph_node_steps_per_s=sim.n_purkinje * n_sub * steps / elapsed,
                graph_substeps=n_sub,
@@ -424,7 +429,8 @@ def run_sheet(ep, meshgen, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=20000,
+                    help="timed steps (default: the slab's whole 400 ms job)")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--chunk", type=int, default=50,
                     help="steps per timed launch (one HIP graph of 50 steps)")
@@ -495,10 +501,9 @@ def main():
     if args.only_fp64:
         run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, args.steps)
         return
-    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, args.steps)
-    f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
-                                                  args.warmup, args.chunk, args.steps)
-    hbm = None if args.only_fp32 else measure_hbm()
+    # the serving and UQ legs first: each starts from the state a serving
+    # process starts in (device memory and streams of the slab runs, still
+    # held by this process, made the stream's latency less repeatable)
     serving = uq = None
     if not (args.only_fp32 or args.serving == "0"):
         nreq, nst = (int(x) for x in args.serving.split("x"))
@@ -520,6 +525,10 @@ def main():
             uq[name] = run_uq(ep, ni, nst, prec)
             log(f"  {uq[name]['cell_steps_per_s']:.3e} cell-steps/s "
                 f"(k={uq[name]['steps_per_graph']}, remap={uq[name]['xcd_remap']})")
+    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, args.steps)
+    f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
+                                                  args.warmup, args.chunk, args.steps)
+    hbm = None if args.only_fp32 else measure_hbm()
     acc = None
     if not (args.only_fp32 or args.no_accuracy):
         log("FP32 accuracy (500 ms runs) ...")
