@@ -493,7 +493,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     }
 
     // ---- cell model
-    const int md = (MSET == 8) ? 5 : at(D.model, c);   // TP06 layer or model id
+    const int md = (MSET == 8) ? 5 : __builtin_nontemporal_load(&D.model[c]);   // TP06 layer or model id
     const R dt = R(D.dt);
     R iion;
     if constexpr (AB2)
@@ -508,25 +508,26 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     if (!(fabs(vnew) < R(1e30))) atomicOr(&D.ctrl->nan_flag, 1);
     if (sample) vol_v = at(D.vol, c) * double(vnew);
 
-    // ---- activation time and APD90
-    const uint8_t st = at(D.dstat, c);
+    // ---- activation time and APD90 (streamed, like the states: the node
+    // values and potentials the gathers reuse keep the cache)
+    const uint8_t st = __builtin_nontemporal_load(&D.dstat[c]);
     if (st == 0) {
         const R thr = R(D.thr);
         if (v <= thr && vnew > thr) {
-            at(D.t_act, c) = (double(n) + double((thr - v) / (vnew - v))) * D.dt;
-            at((R *)D.vmax, c) = vnew;
-            at(D.dstat, c) = 1;
+            __builtin_nontemporal_store((double(n) + double((thr - v) / (vnew - v))) * D.dt, &D.t_act[c]);
+            __builtin_nontemporal_store(vnew, &((R *)D.vmax)[c]);
+            __builtin_nontemporal_store((uint8_t)1, &D.dstat[c]);
         }
     } else if (st == 1) {
-        R vm = at((const R *)D.vmax, c);
+        R vm = __builtin_nontemporal_load(&((const R *)D.vmax)[c]);
         if (vnew > vm) {
             vm = vnew;
-            at((R *)D.vmax, c) = vm;
+            __builtin_nontemporal_store(vm, &((R *)D.vmax)[c]);
         }
-        const R v90 = vm - R(D.repol) * (vm - at((const R *)D.vrest, c));
+        const R v90 = vm - R(D.repol) * (vm - __builtin_nontemporal_load(&((const R *)D.vrest)[c]));
         if (v >= v90 && vnew < v90) {
-            at(D.t_rep, c) = (double(n) + double((v - v90) / (v - vnew))) * D.dt;
-            at(D.dstat, c) = 2;
+            __builtin_nontemporal_store((double(n) + double((v - v90) / (v - vnew))) * D.dt, &D.t_rep[c]);
+            __builtin_nontemporal_store((uint8_t)2, &D.dstat[c]);
         }
     }
 }
