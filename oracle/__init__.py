@@ -17,18 +17,36 @@ MAX_SLOTS = 21
 TP06_ENDO, TP06_MID, TP06_EPI, CRN, STEWART, PASSIVE = range(6)
 
 _lib = None
+_lib_path = LIB_PATH
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 _up = C.POINTER(C.c_uint8)
 
 
+def use_native():
+    """Build the -march=native copy of the oracle on this host and load it
+    instead of the portable one (the timing copy; call before any other use)."""
+    global _lib_path
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    from . import build as _b
+    _lib_path = _b.build(native=True)
+    return _lib_path
+
+
+def build_flags() -> list[str]:
+    """Compiler flags of the loaded copy."""
+    from . import build as _b
+    return ["gcc"] + _b.flags(native=_lib_path != LIB_PATH)
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if not os.path.exists(_lib_path):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(_lib_path)
         L.orc_model_n_slots.argtypes = [C.c_int]
         L.orc_model_slot_name.argtypes = [C.c_int, C.c_int]
         L.orc_model_slot_name.restype = C.c_char_p

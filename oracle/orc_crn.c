@@ -22,10 +22,12 @@ static const double R_GAS = 8.3143, T_K = 310.0, F_C = 96.4867;
 static const double CM = 100.0;                       /* pF            */
 static const double V_I = 13668.0, V_UP = 1109.52, V_RELV = 96.48; /* um^3 */
 static const double K_O = 5.4, NA_O = 140.0, CA_O = 1.8;
+/* maximal conductances and pump rates as printed in the article's parameter
+ * table (nS/pF, pA/pF); published code versions carry more digits */
 static const double G_NA = 7.8, G_K1 = 0.09, G_TO = 0.1652;
-static const double G_KR = 0.029411765, G_KS = 0.12941176, G_CAL = 0.12375;
-static const double G_BCA = 0.001131, G_BNA = 0.0006744375;
-static const double INAK_MAX = 0.59933874, INACA_MAX = 1600.0, IPCA_MAX = 0.275;
+static const double G_KR = 0.0294, G_KS = 0.129, G_CAL = 0.1238;
+static const double G_BCA = 0.00113, G_BNA = 0.000674;
+static const double INAK_MAX = 0.60, INACA_MAX = 1600.0, IPCA_MAX = 0.275;
 static const double IUP_MAX = 0.005, KQ10 = 3.0, GAMMA = 0.35;
 static const double KM_NAI = 10.0, KM_KO = 1.5, KM_NA = 87.5, KM_CA = 1.38;
 static const double K_SAT = 0.1, K_REL = 30.0, K_UP = 0.00092;

@@ -280,11 +280,12 @@ double orc_tp06_step(int celltype, double *y, double dt, double istim,
     b = 200.0 / (1.0 + exp((13.0 - V) / 10.0));
     c = 180.0 / (1.0 + exp((V + 30.0) / 10.0)) + 20.0;
     f = rush_larsen(f, yinf, a + b + c, dt);
-    /* f2 */
+    /* f2: the time constant as printed in the 2006 article's appendix
+     * (562, 27, 240, 80); the authors' distributed code uses another set */
     yinf = 0.67 / (1.0 + exp((V + 35.0) / 7.0)) + 0.33;
-    a = 600.0 * exp(-(V + 25.0) * (V + 25.0) / 170.0);
+    a = 562.0 * exp(-(V + 27.0) * (V + 27.0) / 240.0);
     b = 31.0 / (1.0 + exp((25.0 - V) / 10.0));
-    c = 16.0 / (1.0 + exp((V + 30.0) / 10.0));
+    c = 80.0 / (1.0 + exp((V + 30.0) / 10.0));
     f2 = rush_larsen(f2, yinf, a + b + c, dt);
     /* fCass (calcium dependent, uses Ca_SS at level n) */
     {

@@ -110,6 +110,30 @@ class Bidomain:
     max_iter: int = 2000           # Arnoldi steps per time step at most
 
 
+def workload_sha256(w: Workload) -> str:
+    """Hash of every input of a tissue workload (mesh, fibres, labels,
+    conductivities, ionic scales, stimuli, time step and length), so that
+    results stored for one input are never compared with another."""
+    import hashlib
+    hs = hashlib.sha256()
+
+    def arr(a, dt):
+        hs.update(np.ascontiguousarray(a, dtype=dt).tobytes())
+
+    arr(w.xyz, np.float64)
+    arr(w.tets, np.int32)
+    arr(w.fibre, np.float64)
+    arr(w.model, np.uint8)
+    if w.scale is not None:
+        arr(w.scale, np.float64)
+    for st in w.stimuli:
+        arr(st.ids, np.int32)
+        arr([st.t0, st.dur, st.amp, st.period, st.count, st.domain], np.float64)
+    arr([w.sigma_l, w.sigma_t, w.dt, w.n_steps, w.chi, w.cm, w.time_scheme], np.float64)
+    arr([w.ionic_scale.get(k, 1.0) for k in ("GKr", "GKs", "GCaL", "GNa")], np.float64)
+    return hs.hexdigest()
+
+
 def slab(nx: int, ny: int, nz: int, h: float):
     """Box [0, nx h] x [0, ny h] x [0, nz h] of 5-tet-split hexes.
 

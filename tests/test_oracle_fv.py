@@ -303,3 +303,61 @@ def test_quadratic_mean_sheared_isotropic(oracle_lib, shear):
         L = s.apply_diffusion(q)
         mean = (vol[sel] * L[sel]).sum() / vol[sel].sum()
         assert abs(mean - target / (CHI * CM)) < 1e-9
+
+
+# ------------------------------------------------- alpha off the lattice
+def test_alpha_worked_example_two_tets(oracle_lib):
+    """Face interpolation weight alpha (Sec. 3.2, the weights of eq. gra2bis)
+    pinned where it matters: a face whose centre-to-centre line is not
+    parallel to its normal.  Worked by hand:
+
+    Nodes O = 0, X = e_x, Y = e_y, Z = e_z, Q = (1, 1, 0); tet A = OXYZ,
+    tet B = XYZQ (both volume 1/6); shared face XYZ, outward from A
+    S = (1, 1, 1)/2.  Centroids x_A = (1, 1, 1)/4, x_B = (2, 2, 1)/4,
+    face centroid x_f = (1, 1, 1)/3, so |x_A - x_f| = sqrt(3)/12,
+    |x_B - x_f| = 1/4 and alpha_A = (1/4)/(sqrt(3)/12 + 1/4) = (3 - sqrt 3)/2,
+    alpha_B = (sqrt 3 - 1)/2.  d = |x_B - x_A| = sqrt(2)/4,
+    e = (1, 1, 0)/sqrt 2, S.e = 1/sqrt 2, S - (S.e)e = (0, 0, 1/2).
+
+    v_A = 1, v_B = 0.  Node values by inverse distance to the centroids:
+    O -> 1, Q -> 0; X and Y lie sqrt(11)/4 from x_A and 3/4 from x_B, so
+    p = v_X = v_Y = 3/(3 + sqrt 11); Z lies sqrt(11)/4 and sqrt(17)/4 away,
+    q = v_Z = sqrt 17/(sqrt 17 + sqrt 11).  Cell gradients (the P1
+    gradients of the node values): g_A = (p - 1, p - 1, q - 1),
+    g_B = (-p, -p, q - 2p); their jump is along (1, 1, 1), the face normal.
+
+    Isotropic conductivity sigma scaled by 1 in A and 3 in B: the face tensor
+    is (alpha_A + 3 alpha_B) sigma I = sqrt(3) sigma I.  The stabilised face
+    gradient keeps the part of gbar = alpha_A g_A + alpha_B g_B across e and
+    replaces its e-component by (v_B - v_A)/d, so the flux out of A is
+    sqrt(3) sigma (gbar_z / 2 - 2) with gbar_z = q - alpha_A - 2 p alpha_B,
+    and L_A = 6 F / (chi Cm) = -L_B.
+
+    Swapping alpha for 1 - alpha changes both the face tensor (to
+    (4 - sqrt 3) sigma) and gbar_z (to q - alpha_B - 2 p alpha_A)."""
+    s3, s11, s17 = math.sqrt(3.0), math.sqrt(11.0), math.sqrt(17.0)
+    aA, aB = (3.0 - s3) / 2.0, (s3 - 1.0) / 2.0
+    p, q = 3.0 / (3.0 + s11), s17 / (s17 + s11)
+    sig = 0.1
+    flux = s3 * sig * ((q - aA - 2.0 * p * aB) / 2.0 - 2.0)
+    LA = 6.0 * flux / (CHI * CM)
+
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0]], float)
+    tets = np.array([[0, 1, 2, 3], [1, 2, 3, 4]], np.int32)
+    fib = np.array([[1.0, 0, 0], [0, 1.0, 0]])
+    w = M.Workload("two-tets", xyz, tets, fib, np.full(2, M.PASSIVE, np.uint8),
+                   sigma_l=sig, sigma_t=sig, scale=np.array([1.0, 3.0]), dt=0.01)
+    s = oracle_lib.Sim(w)
+    v = np.array([1.0, 0.0])
+    vol, S, nbr = s.geometry()
+    assert np.allclose(vol, 1.0 / 6.0, rtol=1e-15)
+    assert np.allclose(s.node_values(v), [1.0, p, p, q, 0.0], rtol=1e-14)
+    g = s.gradients(v)
+    assert np.allclose(g[0], [p - 1, p - 1, q - 1], rtol=1e-14)
+    assert np.allclose(g[1], [-p, -p, q - 2 * p], rtol=1e-14)
+    L = s.apply_diffusion(v)
+    assert math.isclose(L[0], LA, rel_tol=1e-13), (L[0], LA)
+    assert math.isclose(L[1], -LA, rel_tol=1e-13)
+    # the swapped reading gives a value the tolerance above excludes
+    swapped = 6.0 * (4.0 - s3) * sig * ((q - aB - 2.0 * p * aA) / 2.0 - 2.0) / (CHI * CM)
+    assert abs(swapped - LA) > 1e-3 * abs(LA)
