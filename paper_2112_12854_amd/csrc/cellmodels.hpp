@@ -270,9 +270,9 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
                     R(200) * sig((R(13) - V) * R(0.1)) + R(180) * sig((V + R(30)) * R(0.1)) + R(20);
         g[9] = rl(f, sig((V + R(20)) * R(1.0 / 7.0)), xrcp(t), dt);
     }
-    {   // f2
-        const R t = R(600) * xexp(-(V + R(25)) * (V + R(25)) * R(1.0 / 170.0)) +
-                    R(31) * sig((R(25) - V) * R(0.1)) + R(16) * sig((V + R(30)) * R(0.1));
+    {   // f2 (time constant as printed in the 2006 article)
+        const R t = R(562) * xexp(-(V + R(27)) * (V + R(27)) * R(1.0 / 240.0)) +
+                    R(31) * sig((R(25) - V) * R(0.1)) + R(80) * sig((V + R(30)) * R(0.1));
         g[10] = rl(f2, R(0.67) * sig((V + R(35)) * R(1.0 / 7.0)) + R(0.33), xrcp(t), dt);
     }
     {   // fCass, driven by Ca_SS^n
@@ -298,7 +298,8 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
 }  // namespace tp06
 
 // ==================================================================== CRN
-// Courtemanche, Ramirez & Nattel, Am J Physiol 275:H301 (1998).
+// Courtemanche, Ramirez & Nattel, Am J Physiol 275:H301 (1998), with the
+// conductances and pump rates of the article's parameter table.
 // Gates (15): m h j oa oi ua ui xr xs d f fCa u v w.
 // Concentrations (FP64): Ca_i Ca_up Ca_rel Na_i K_i, with troponin /
 // calmodulin / calsequestrin buffering folded into the Ca rates.
@@ -334,13 +335,13 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     const R IK1 = R(0.09) * dK * sig(R(0.07) * (V + R(80)));
     const R Ito = R(0.1652) * oa * oa * oa * oi * dK;
     const R IKur = (R(0.005) + R(0.05) * sig((V - R(15)) * R(-1.0 / 13.0))) * ua * ua * ua * ui * dK;
-    const R IKr = R(gs.kr) * R(0.029411765) * xr * dK * sig((V + R(15)) * R(1.0 / 22.4));
-    const R IKs = R(gs.ks) * R(0.12941176) * xs * xs * dK;
-    const R ICaL = R(gs.cal) * R(0.12375) * d * f * fca * (V - R(65));
+    const R IKr = R(gs.kr) * R(0.0294) * xr * dK * sig((V + R(15)) * R(1.0 / 22.4));
+    const R IKs = R(gs.ks) * R(0.129) * xs * xs * dK;
+    const R ICaL = R(gs.cal) * R(0.1238) * d * f * fca * (V - R(65));
     const R ev = xexp(-V * frt);
     const R sigma = R((std::exp(NAO / 67.3) - 1.0) / 7.0);
     const R fNaK = xrcp(R(1) + R(0.1245) * xexp(R(-0.1) * V * frt) + R(0.0365) * sigma * ev);
-    const R INaK = R(0.59933874 * KO / (KO + 1.5)) * fNaK /
+    const R INaK = R(0.60 * KO / (KO + 1.5)) * fNaK /
                    (R(1) + xpow15(xdiv(R(10), R(nai))));
     const R eg = xexp(R(0.35) * V * frt);
     const R eg1 = eg * ev;
@@ -348,8 +349,8 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     const R INaCa = R(1600.0 / ((87.5 * 87.5 * 87.5 + NAO * NAO * NAO) * (1.38 + CAO))) *
                     (eg * nai3 * R(CAO) - eg1 * R(NAO * NAO * NAO) * R(cai)) /
                     (R(1) + R(0.1) * eg1);
-    const R IbNa = R(0.0006744375) * (V - ENa);
-    const R IbCa = R(0.001131) * (V - ECa);
+    const R IbNa = R(0.000674) * (V - ENa);
+    const R IbCa = R(0.00113) * (V - ECa);
     const R IpCa = R(0.275) * R(cai) / (R(0.0005) + R(cai));
     const R Iion = INa + IK1 + Ito + IKur + IKr + IKs + ICaL + IpCa + INaK + INaCa +
                    IbNa + IbCa;
