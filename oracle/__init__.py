@@ -67,7 +67,8 @@ def lib():
         L.orc_get_step.restype = C.c_int64
         L.orc_set_step.argtypes = [C.c_void_p, C.c_int64]
         for name in ("orc_get_vm", "orc_get_activation", "orc_get_apd90",
-                     "orc_get_states", "orc_set_states"):
+                     "orc_get_states", "orc_set_states", "orc_get_detect_state",
+                     "orc_set_detect_state"):
             getattr(L, name).argtypes = [C.c_void_p, _dp]
         L.orc_mean_vm.argtypes = [C.c_void_p]
         L.orc_mean_vm.restype = C.c_double
@@ -295,6 +296,17 @@ class Sim:
         st = np.ascontiguousarray(st, dtype=np.float64)
         assert st.shape == (MAX_SLOTS, self.nc)
         lib().orc_set_states(self.h, _d(st))
+
+    def detection(self) -> np.ndarray:
+        """(4, n_tets): status, activation time, running max of V, repolarisation time."""
+        out = np.empty((4, self.nc))
+        lib().orc_get_detect_state(self.h, _d(out))
+        return out
+
+    def set_detection(self, d: np.ndarray):
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        assert d.shape == (4, self.nc)
+        lib().orc_set_detect_state(self.h, _d(d))
 
     def geometry(self):
         vol = np.empty(self.nc)

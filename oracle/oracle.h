@@ -67,6 +67,8 @@ double orc_mean_vm(const orc_sim *s);                     /* int v dV / V  */
 void orc_get_states(const orc_sim *s, double *out);
 void orc_set_states(orc_sim *s, const double *in);
 void orc_set_step(orc_sim *s, int64_t step);
+void orc_get_detect_state(const orc_sim *s, double *out);
+void orc_set_detect_state(orc_sim *s, const double *in);
 
 /* ------------------------------------------------- Purkinje graph, PMJs */
 /* A 1D Purkinje graph discretised with vertex-centred finite volumes (the

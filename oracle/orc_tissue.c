@@ -1172,6 +1172,31 @@ void orc_set_states(orc_sim *s, const double *in)
                 s->y[c * ORC_MAX_SLOTS + slot] = in[slot * s->nc + c];
 }
 
+/* Detection state of every cell as 4 rows of n_tets: status (0 before
+ * activation, 1 activated, 2 repolarised), activation time, running maximum
+ * of V, repolarisation time.  With the states and the step counter this is
+ * all a monodomain run without graph or bidomain carries from step to step,
+ * so a long run can be stopped and resumed. */
+void orc_get_detect_state(const orc_sim *s, double *out)
+{
+    for (int64_t c = 0; c < s->nc; ++c) {
+        out[c] = (double)s->status[c];
+        out[s->nc + c] = s->t_act[c];
+        out[2 * s->nc + c] = s->v_max[c];
+        out[3 * s->nc + c] = s->t_rep[c];
+    }
+}
+
+void orc_set_detect_state(orc_sim *s, const double *in)
+{
+    for (int64_t c = 0; c < s->nc; ++c) {
+        s->status[c] = (uint8_t)in[c];
+        s->t_act[c] = in[s->nc + c];
+        s->v_max[c] = in[2 * s->nc + c];
+        s->t_rep[c] = in[3 * s->nc + c];
+    }
+}
+
 /* ---------------------------------------------------------- detection -- */
 void orc_detect_waveform(const double *v, int64_t n, double dt,
                          double threshold, double repol_frac, double *t_act,

@@ -18,6 +18,7 @@ The oracle's results do not depend on its thread count.  A full slab run is
 about 1e11 cell-steps (hours on a few cores).
 
 Usage: python tests/golden/make_oracle_golden.py {slab|uq} [--threads N] [--native]
+                                                [--ckpt DIR]
 """
 from __future__ import annotations
 
@@ -72,7 +73,13 @@ def _moments(x):
                 max=float(f.max()) if f.size else None)
 
 
-def make_slab(log):
+def _save_ckpt(path, s, **extra):
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, states=s.states(), detection=s.detection(), step=s.step_index, **extra)
+    os.replace(tmp, path)
+
+
+def make_slab(log, ckpt_dir=None):
     import oracle
     from paper_2112_12854_amd import meshgen
     w = slab_workload()
@@ -80,16 +87,28 @@ def make_slab(log):
     cells = slab_sample(w.n_tets)
     log(f"slab: {w.n_tets} tets, {w.n_steps} steps, key {key[:16]}")
     s = oracle.Sim(w)
-    t0 = time.time()
-    s.step(2500)
-    v50 = s.vm()[cells]
-    log(f"slab: 50 ms after {time.time() - t0:.0f} s")
-    done = 2500
-    while done < w.n_steps:
-        k = min(2500, w.n_steps - done)
+    ck = os.path.join(ckpt_dir, f"slab_{key[:16]}.npz") if ckpt_dir else None
+    v50, spent = None, 0.0
+    if ck and os.path.exists(ck):
+        with np.load(ck, allow_pickle=False) as z:
+            s.set_states(z["states"])
+            s.set_detection(z["detection"])
+            s.set_step(int(z["step"]))
+            spent = float(z["seconds"])
+            if z["v_50ms"].size:
+                v50 = z["v_50ms"]
+        log(f"slab: resumed at step {s.step_index} ({spent:.0f} s spent before)")
+    t0 = time.time() - spent
+    while s.step_index < w.n_steps:
+        k = min(2500 - s.step_index % 2500, w.n_steps - s.step_index)
         s.step(k)
-        done += k
-        log(f"slab: step {done} after {time.time() - t0:.0f} s")
+        if s.step_index == 2500:
+            v50 = s.vm()[cells]
+        log(f"slab: step {s.step_index} after {time.time() - t0:.0f} s")
+        if ck and s.step_index < w.n_steps:
+            os.makedirs(ckpt_dir, exist_ok=True)
+            _save_ckpt(ck, s, seconds=time.time() - t0,
+                       v_50ms=v50 if v50 is not None else np.empty(0))
     at, apd, v400 = s.activation(), s.apd90(), s.vm()
     info = dict(workload=w.name, sha256=key, n_tets=w.n_tets, steps=w.n_steps, dt=w.dt,
                 threads=oracle.num_threads(), seconds=time.time() - t0,
@@ -99,6 +118,8 @@ def make_slab(log):
     np.savez_compressed(SLAB_FILE, cells=cells, t_act=at[cells], apd90=apd[cells],
                         v_50ms=v50, v_end=v400[cells], info=json.dumps(info))
     log(f"slab: wrote {SLAB_FILE} ({info['seconds']:.0f} s)")
+    if ck and os.path.exists(ck):
+        os.remove(ck)
 
 
 def make_uq(log):
@@ -143,6 +164,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=("slab", "uq"))
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--ckpt", default=None,
+                    help="directory for a resumable checkpoint of the slab run")
     ap.add_argument("--native", action="store_true",
                     help="use the -march=native copy of the oracle (same results)")
     a = ap.parse_args()
@@ -155,7 +178,10 @@ def main():
     def log(m):
         print(f"[golden] {m}", flush=True)
 
-    (make_slab if a.which == "slab" else make_uq)(log)
+    if a.which == "slab":
+        make_slab(log, a.ckpt)
+    else:
+        make_uq(log)
 
 
 if __name__ == "__main__":

@@ -97,3 +97,27 @@ def test_thread_count_invariance(oracle_lib):
                            capture_output=True, text=True)
         outs.append(np.array(json.loads(r.stdout)))
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_oracle_resume_bitwise():
+    """States, detection state and step counter carry a run across a restart:
+    stopping mid-action-potential and resuming in a fresh simulation gives
+    the uninterrupted run's results bit for bit."""
+    import oracle
+    from paper_2112_12854_amd import meshgen
+    w = meshgen.config1(n_steps=600, nx=6, ny=5, nz=2)
+    a = oracle.Sim(w)
+    a.step(600)
+    b = oracle.Sim(w)
+    b.step(250)
+    st, det, k = b.states(), b.detection(), b.step_index
+    del b
+    c = oracle.Sim(w)
+    c.set_states(st)
+    c.set_detection(det)
+    c.set_step(k)
+    c.step(350)
+    assert np.array_equal(a.vm(), c.vm())
+    assert np.array_equal(a.activation(), c.activation(), equal_nan=True)
+    assert np.array_equal(a.apd90(), c.apd90(), equal_nan=True)
+    assert np.isfinite(a.activation()).all()
