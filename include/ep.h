@@ -280,6 +280,21 @@ ep_status ep_get_mean_vm_trace(ep_sim *s, double *t, double *vbar,
 /* Current step index and time t = step * dt. */
 ep_status ep_get_time(ep_sim *s, int64_t *step, double *t);
 
+/* The diffusion operator alone (Sec. 3.2: node values by inverse-distance
+ * weights, cell gradients, the face gradient of eq. gra2bis, the sum of the
+ * face fluxes): L_c = (1 / (chi Cm V_c)) sum_f A_f (M_f g_f) . n_f in mV/ms
+ * for the potential v, with this simulation's mesh, fibres, conductivities
+ * and precision (FP32 in the mixed precision) - the L that ep_step adds to
+ * v^n = v.  v and L are DEVICE arrays on the simulation's device, n ==
+ * n_tets doubles each in caller order; L may not alias v; both stay the
+ * caller's.  The simulation's state is not touched.  The library allocates
+ * a workspace of 8 (FP64) or 4 (mixed) bytes per cell and per node (through
+ * dev_alloc when set), runs on the simulation's stream, waits for it and
+ * frees the workspace before returning.  EP_ESTATE before ep_init,
+ * EP_EINVAL for a wrong n, null or aliased arrays, EP_ENOMEM when the
+ * workspace cannot be allocated. */
+ep_status ep_apply_diffusion(ep_sim *s, const double *v, double *L, int64_t n);
+
 /* Per-cell states as FP64, layout out[slot * n + cell] with n == n_tets,
  * n_slots == EP_MAX_SLOTS.  Slot 0 is V; the model's states follow in the
  * order of ep_model_slot_name(); unused slots read NaN and are ignored on
@@ -298,7 +313,9 @@ const char *ep_model_slot_name(int model, int slot);     /* NULL if bad       */
  * built from the same inputs continues bitwise identically.  The image holds
  * the device layout, tagged by a version in its header: ep_set_state returns
  * EP_EINVAL for an image of another layout version, mesh size, precision,
- * time scheme or model configuration. */
+ * time scheme, model configuration or cell order (the header carries the
+ * EP_ORDER_* value and a hash of the internal permutation and of each
+ * cell's model, since the per-cell arrays are stored in internal order). */
 ep_status ep_state_size(ep_sim *s, size_t *bytes);
 ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes);
 ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);

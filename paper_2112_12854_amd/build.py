@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libep.so")
-SOURCES = ["ep_api.hip", "instance.hip", "serve.hip", "bidomain.hip", "prep.cpp", "purkinje.cpp",
+SOURCES = ["ep_api.hip", "instance.hip", "serve.hip", "bidomain.hip", "diffusion.hip", "prep.cpp", "purkinje.cpp",
            "coarse.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -19,8 +19,8 @@ using ep::model_ng;
 
 namespace {
 
-// "EPSMCHK7": states in the tile-major layout
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b37ULL;
+// "EPSMCHK8": states in the tile-major layout, header with the cell order
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b38ULL;
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
@@ -440,6 +440,32 @@ ep_status ep_get_mean_vm_trace(ep_sim *s, double *t, double *vbar, int64_t cap, 
     return st;
 }
 
+static ep_status diffusion_args(ep_sim *s, const double *v, double *L, int64_t n) {
+    if (!s) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    if (!v || !L || n != s->inst.desc.nc) return fail(s, EP_EINVAL, "v and L must hold n_tets values");
+    if (v == L) return fail(s, EP_EINVAL, "L may not alias v");
+    return EP_OK;
+}
+
+ep_status ep_apply_diffusion(ep_sim *s, const double *v, double *L, int64_t n) {
+    ep_status st = diffusion_args(s, v, L, n);
+    if (st != EP_OK) return st;
+    HIP_TRY(s, hipSetDevice(s->opt.device));
+    const size_t bytes = ep::diffusion_workspace_bytes(s->inst);
+    void *ws = nullptr;
+    if (s->opt.dev_alloc) ws = s->opt.dev_alloc(bytes, s->opt.alloc_ctx);
+    else if (hipMalloc(&ws, bytes) != hipSuccess) ws = nullptr;
+    if (!ws) return fail(s, EP_ENOMEM, "diffusion workspace allocation failed");
+    std::string e = ep::diffusion_apply(s->inst, s->stream, v, L, ws);
+    const hipError_t es = hipStreamSynchronize(s->stream);
+    if (s->opt.dev_free) s->opt.dev_free(ws, s->opt.alloc_ctx);
+    else (void)hipFree(ws);
+    if (!e.empty()) return fail(s, EP_EDEVICE, e);
+    if (es != hipSuccess) return fail(s, EP_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(es));
+    return EP_OK;
+}
+
 ep_status ep_get_time(ep_sim *s, int64_t *step, double *t) {
     if (!s) return EP_EINVAL;
     if (step) *step = s->inst.host_step;
@@ -592,7 +618,25 @@ struct CkptHeader {
     int64_t trace_cap, n_purkinje;
     int64_t bidomain;
     int64_t time_scheme;
+    int64_t ordering;         // EP_ORDER_* the image was taken under
+    uint64_t layout_hash;     // of the internal order and each cell's model
 };
+
+// FNV-1a over the internal-to-caller cell permutation and the per-cell
+// model bytes in internal order: the arrays of an image are stored in that
+// order, so an image restores only into a simulation with the same layout
+// (another cell order or another model assignment over the same mesh size
+// would scramble every per-cell array).
+static uint64_t layout_hash(const ep_sim *s) {
+    uint64_t h = 0xcbf29ce484222325ULL;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 0x100000001b3ULL; }
+    };
+    mix(s->inst.prep.perm.data(), s->inst.prep.perm.size() * sizeof(int32_t));
+    mix(s->inst.prep.model.data(), s->inst.prep.model.size());
+    return h;
+}
 
 static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
     const epdev::InstDesc &D = s->inst.desc;
@@ -644,7 +688,7 @@ ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes) {
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     CkptHeader h{CKPT_MAGIC, s->inst.desc.nc, s->inst.desc.nn, s->inst.host_step, s->inst.rs,
                  (int32_t)s->inst.n_pmj, s->inst.trace_cap, s->inst.pk.n, s->inst.bido ? 1 : 0,
-                 s->inst.scheme};
+                 s->inst.scheme, s->spec.ordering, layout_hash(s)};
     char *p = (char *)buf;
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
@@ -667,6 +711,8 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes) {
         h.n_pmj != (int32_t)s->inst.n_pmj || h.bidomain != (s->inst.bido ? 1 : 0) ||
         h.time_scheme != s->inst.scheme)
         return fail(s, EP_EINVAL, "checkpoint does not match this simulation");
+    if (h.ordering != s->spec.ordering || h.layout_hash != layout_hash(s))
+        return fail(s, EP_EINVAL, "checkpoint was taken under another cell order or model layout");
     HIP_TRY(s, hipStreamSynchronize(s->stream));
     const char *p = (const char *)buf + sizeof(h);
     for (auto &a : ckpt_arrays(s)) {

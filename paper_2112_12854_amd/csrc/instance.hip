@@ -124,7 +124,7 @@ size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
     b += round256(tiled_len(c, 8) * 4) + round256(tiled_len(c, 8) * r) + round256(tiled_len(c, 4) * 4) +
          round256(tiled_len(c, 4) * r);
     b += round256(c) + round256(c * 8);                       // model, volume
-    b += round256(c * 4);                                     // stimulus mask
+    b += round256(c * 4) + round256(c * 4);                   // stimulus mask, permutation
     b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);   // states
     b += 2 * round256(c * r) + 3 * round256(c * r) + round256(n * r);   // v0 v1 vrest vmax, vn
     b += round256(c) + 2 * round256(c * 8);                   // detection
@@ -305,7 +305,7 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     else
         b += round256(tiled_len(c, 8) * 4) + round256(tiled_len(c, 4) * 4);
     b += round256(tiled_len(c, 8) * r) + round256(tiled_len(c, 4) * r);
-    b += round256(c) + round256(c * 8) + round256(c * 4);
+    b += round256(c) + round256(c * 8) + round256(c * 4) + round256(c * 4);
     b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);
     b += 4 * round256(c * r) + round256(n * r);
     b += round256(c) + 2 * round256(c * 8);
@@ -466,7 +466,8 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     D.nn = nn;
     auto fail_mem = [&]() { st = EP_ENOMEM; free_instance(I); return std::string("device allocation failed"); };
     if (!up(I, (void **)&D.sell_off, P.sell_off) || !up(I, (void **)&D.sell_cell, P.sell_cell) ||
-        !up(I, (void **)&D.model, P.model) || !up(I, (void **)&D.vol, P.vol))
+        !up(I, (void **)&D.model, P.model) || !up(I, (void **)&D.vol, P.vol) ||
+        !up(I, (void **)&I.d_perm, P.perm))
         return fail_mem();
     bool ok;
     if (I.idx16) {

@@ -107,6 +107,7 @@ struct Inst {
     size_t arena_size = 0, arena_used = 0;
     size_t footprint = 0;
     epdev::InstDesc desc{};            // device pointers and parameters
+    int32_t *d_perm = nullptr;         // [nc] internal cell -> caller cell (device)
     epdev::Ctrl *d_ctrl = nullptr;
     int64_t host_step = 0;             // step index once queued work is done
     int64_t target = INT64_MAX;
@@ -231,5 +232,13 @@ constexpr int kBidoBlocks = 1024;      // blocks of the reduction kernels
 int model_ng(int m);
 int model_nc(int m);
 void model_init(int m, double *y);
+
+// The diffusion operator alone (diffusion.hip).  v and L are device arrays
+// of nc doubles in caller order; ws is a device workspace of
+// diffusion_workspace_bytes(I) bytes (internal-order potentials from offset
+// 0, node values from diffusion_workspace_split).  Enqueued on `st`.
+size_t diffusion_workspace_split(int64_t nc, size_t rs);
+size_t diffusion_workspace_bytes(const Inst &I);
+std::string diffusion_apply(const Inst &I, hipStream_t st, const double *v, double *L, void *ws);
 
 }  // namespace ep

@@ -233,6 +233,29 @@ __device__ __forceinline__ uint32_t active_stimuli(const Ctrl *ctrl, int64_t n) 
 }
 
 // ------------------------------------------------------------ node gather
+// Inverse-distance node value v_n = sum_k w_nk v_k of node `node` from the
+// cell potentials v (sliced ELL: 64 nodes per slice, entry j of a node at
+// slice offset + j * 64).  Four independent gathers in flight per lane and
+// a fixed summation order, so every caller gets the same bits.
+template <typename R>
+__device__ __forceinline__ R node_value(const InstDesc &D, int64_t node, const R *__restrict__ v) {
+    const R *__restrict__ w8 = (const R *)D.sell_w;
+    const int32_t *__restrict__ cell = D.sell_cell;
+    const int64_t e0 = D.sell_off[node >> 6] + (node & 63), e1 = D.sell_off[(node >> 6) + 1];
+    R a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
+    int64_t e = e0;
+    for (; e + 192 < e1; e += 256) {
+        const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
+        const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
+        a0 += x0 * v[c0];
+        a1 += x1 * v[c1];
+        a2 += x2 * v[c2];
+        a3 += x3 * v[c3];
+    }
+    for (; e < e1; e += 64) a0 += w8[e] * v[cell[e]];
+    return (a0 + a1) + (a2 + a3);
+}
+
 // BIDO: node values of v + phi_e (bidomain time step, FP64).
 template <typename R, bool BIDO = false>
 __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_off, int remap) {
@@ -247,14 +270,16 @@ __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_of
     if ((int32_t)threadIdx.x >= T.count) return;
     const int64_t node = T.begin + threadIdx.x;
     const R *__restrict__ v = (const R *)D.v[n & 1];
-    const R *__restrict__ w8 = (const R *)D.sell_w;
-    const int32_t *__restrict__ cell = D.sell_cell;
-    const int64_t e0 = D.sell_off[node >> 6] + (node & 63), e1 = D.sell_off[(node >> 6) + 1];
-    // four independent gathers in flight per lane; fixed summation order
-    R a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
-    int64_t e = e0;
-    if constexpr (BIDO) {
+    if constexpr (!BIDO) {
+        ((R *)D.vn)[node] = node_value<R>(D, node, v);
+    } else {
+        // as node_value, of v + phi_e
+        const R *__restrict__ w8 = (const R *)D.sell_w;
+        const int32_t *__restrict__ cell = D.sell_cell;
         const double *__restrict__ ph = D.phi;
+        const int64_t e0 = D.sell_off[node >> 6] + (node & 63), e1 = D.sell_off[(node >> 6) + 1];
+        R a0 = R(0), a1 = R(0), a2 = R(0), a3 = R(0);
+        int64_t e = e0;
         for (; e + 192 < e1; e += 256) {
             const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
             const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
@@ -264,18 +289,8 @@ __global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_of
             a3 += x3 * (v[c3] + R(ph[c3]));
         }
         for (; e < e1; e += 64) a0 += w8[e] * (v[cell[e]] + R(ph[cell[e]]));
-    } else {
-        for (; e + 192 < e1; e += 256) {
-            const int32_t c0 = cell[e], c1 = cell[e + 64], c2 = cell[e + 128], c3 = cell[e + 192];
-            const R x0 = w8[e], x1 = w8[e + 64], x2 = w8[e + 128], x3 = w8[e + 192];
-            a0 += x0 * v[c0];
-            a1 += x1 * v[c1];
-            a2 += x2 * v[c2];
-            a3 += x3 * v[c3];
-        }
-        for (; e < e1; e += 64) a0 += w8[e] * v[cell[e]];
+        ((R *)D.vn)[node] = (a0 + a1) + (a2 + a3);
     }
-    ((R *)D.vn)[node] = (a0 + a1) + (a2 + a3);
 }
 
 // ------------------------------------------------------------- cell step
@@ -433,17 +448,15 @@ __device__ __forceinline__ R v_update(R v, R dt, R F, void *hv, uint32_t i, bool
     }
 }
 
-template <typename R, int MSET, bool BIDO, int SCH>
-__device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
-                                          uint32_t active, bool sample, double &vol_v) {
-    constexpr bool AB2 = SCH >= 1;
-    const R *__restrict__ vin = (const R *)D.v[n & 1];
-    R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
-    const R *__restrict__ vn = (const R *)D.vn;
+// Face-flux sum of cell c in mV/ms: L_c = sum_f F_f / (chi Cm V_c), from
+// the per-cell fused coefficients (gradient of the node values through the
+// eight node weights, two-point terms along the four neighbours), the node
+// values vn and the cell potentials vin; v = vin[c].  BIDO: the flux of
+// v + phi_e (vn then holds node values of v + phi_e).
+template <typename R, bool BIDO>
+__device__ __forceinline__ R flux_sum(const InstDesc &D, uint32_t c, const R *__restrict__ vin,
+                                      const R *__restrict__ vn, R v) {
     const __amdgpu_buffer_rsrc_t rbeta = rsrc(D.cbeta), rb = rsrc(D.cb);
-
-    // ---- diffusion: fused node-coefficient stencil plus two-point terms
-    const R v = at(vin, c);
     R L = R(0);
     auto stencil = [&](auto node_id, auto nbr_id) {
 #pragma unroll
@@ -471,6 +484,20 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
         stencil([&](int s) { return (uint32_t)sld<int32_t, 8>(rnode, s, c); },
                 [&](int f) { return (uint32_t)sld<int32_t, 4>(rnbr, f, c); });
     }
+    return L;
+}
+
+template <typename R, int MSET, bool BIDO, int SCH>
+__device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
+                                          uint32_t active, bool sample, double &vol_v) {
+    constexpr bool AB2 = SCH >= 1;
+    const R *__restrict__ vin = (const R *)D.v[n & 1];
+    R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
+    const R *__restrict__ vn = (const R *)D.vn;
+
+    // ---- diffusion: fused node-coefficient stencil plus two-point terms
+    const R v = at(vin, c);
+    const R L = flux_sum<R, BIDO>(D, c, vin, vn, v);
 
     // ---- stimulus: protocol pulses, then junction pulses (junction order)
     R istim = R(0);

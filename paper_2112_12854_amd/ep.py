@@ -136,6 +136,7 @@ _SIGS = {
     "ep_get_mean_vm_trace": (C.c_int, [C.c_void_p, _dp, _dp, C.c_int64,
                                        C.POINTER(C.c_int64)]),
     "ep_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), _dp]),
+    "ep_apply_diffusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "ep_get_states": (C.c_int, [C.c_void_p, _dp, C.c_int64, C.c_int32]),
     "ep_set_states": (C.c_int, [C.c_void_p, _dp, C.c_int64, C.c_int32]),
     "ep_model_n_slots": (C.c_int, [C.c_int]),
@@ -300,6 +301,7 @@ class Sim:
         if cell_order is not None:
             _check(L.ep_set_cell_order(h, int(cell_order)), h)
         _check(L.ep_init(h), h)
+        self.device = device
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -322,6 +324,20 @@ class Sim:
     def set_launch(self, block=256, steps_per_graph=50, xcd_remap=1):
         """block: 0 or 256; steps_per_graph: 0 = no graphs."""
         _check(lib().ep_set_launch(self.h, block, steps_per_graph, xcd_remap), self.h)
+
+    def apply_diffusion(self, v, entry: str = "ep_apply_diffusion"):
+        """The simulation's diffusion operator applied to the cell potentials
+        v ([n_tets], caller order): L in mV/ms as a host array.  v and L pass
+        through device tensors; `entry` names the C entry point to call."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        vt = torch.as_tensor(np.ascontiguousarray(v, np.float64)).to(dev)
+        Lt = torch.full_like(vt, float("nan"))
+        torch.cuda.synchronize(dev)
+        _check(getattr(lib(), entry)(self.h, C.c_void_p(vt.data_ptr()),
+                                     C.c_void_p(Lt.data_ptr()), vt.numel()), self.h)
+        torch.cuda.synchronize(dev)
+        return Lt.cpu().numpy()
 
     # ---- readouts
     def _vec(self, fn):

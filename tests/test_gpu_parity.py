@@ -82,6 +82,69 @@ def test_diffusion_operator_parity(ep, oracle_lib, order):
     assert np.abs(sim.vm() - ref.vm()).max() < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("order", ["rcm", "input"])
+def test_apply_diffusion_vs_oracle(ep, oracle_lib, prec, order):
+    """The diffusion operator on its own (ep_apply_diffusion, device arrays
+    in caller order) against the oracle's node values -> gradients -> face
+    gradients -> flux sum, on a jittered mesh with random fibres and
+    per-cell conductivity scales (1,575 tets: six full 256-cell tiles and a
+    ragged seventh).  FP64 within 1e-12 of max|L|; the mixed precision runs
+    the operator in FP32, within 2e-5 of max|L| (a few FP32 ulps of the
+    ~100 mV potentials whose differences the stencil sums)."""
+    w = rotated_fibres(jittered(M.config1(nx=9, ny=7, nz=5)))
+    w.scale = np.random.default_rng(4).uniform(0.5, 2.0, w.n_tets)
+    w.stimuli = []
+    rng = np.random.default_rng(8)
+    v = -80 + 30 * rng.normal(size=w.n_tets)
+    L_ref = oracle_lib.Sim(w).apply_diffusion(v)
+    p = ep.EP_FP64 if prec == "fp64" else ep.EP_FP32_MIXED
+    o = ep.EP_ORDER_RCM if order == "rcm" else ep.EP_ORDER_INPUT
+    sim = ep.Sim(w, prec=p, cell_order=o)
+    L = sim.apply_diffusion(v)
+    err = np.abs(L - L_ref).max() / np.abs(L_ref).max()
+    say(f"apply_diffusion {prec}/{order}: {w.n_tets} tets, max rel error {err:.3e}")
+    assert err < (1e-12 if prec == "fp64" else 2e-5)
+    # the operator leaves the state alone, and the step adds the same L
+    if prec == "fp64":
+        st = sim.states()
+        assert np.array_equal(st[0], sim.vm())
+        st[0] = v
+        sim.set_states(st)
+        sim.apply_diffusion(v + 1.0)        # a constant shift: same flux, state untouched
+        assert np.array_equal(sim.vm(), v)
+        ww = passive(rotated_fibres(jittered(M.config1(nx=9, ny=7, nz=5))))
+        ww.scale, ww.stimuli = w.scale, []
+        ps = ep.Sim(ww, prec=ep.EP_FP64, cell_order=o)
+        st = ps.states()
+        st[0] = v
+        ps.set_states(st)
+        Lp = ps.apply_diffusion(v)
+        ps.step(1)
+        assert np.abs(ps.vm() - (v + ww.dt * Lp)).max() < 1e-12
+
+
+def test_apply_diffusion_null_space_and_errors(ep):
+    """A constant field has zero flux everywhere; under no-flux boundaries
+    the volume-weighted sum of L vanishes for any field (each interior face
+    flux leaves one cell and enters the other); bad arguments are refused."""
+    import torch
+    w = rotated_fibres(jittered(M.config1(nx=7, ny=5, nz=3)))
+    w.stimuli = []
+    sim = ep.Sim(w, prec=ep.EP_FP64)
+    L = sim.apply_diffusion(np.full(w.n_tets, -42.0))
+    assert np.abs(L).max() < 1e-12
+    X = w.xyz[w.tets].mean(axis=1)
+    V = np.abs(np.linalg.det(w.xyz[w.tets][:, 1:] - w.xyz[w.tets][:, :1])) / 6
+    L = sim.apply_diffusion(3.0 * X[:, 0] - 2.0 * X[:, 2] + np.sin(5.0 * X[:, 1]))
+    assert abs((V * L).sum()) < 1e-12 * (V * np.abs(L)).sum()
+    vt = torch.zeros(w.n_tets, dtype=torch.float64, device="cuda")
+    for n, a, b in ((w.n_tets - 1, vt, torch.empty_like(vt)), (w.n_tets, vt, vt)):
+        st = ep.lib().ep_apply_diffusion(sim.h, ep.C.c_void_p(a.data_ptr()),
+                                         ep.C.c_void_p(b.data_ptr()), n)
+        assert st == ep.EP_EINVAL
+
+
 def test_passive_conservation_and_constants(ep):
     w = passive(rotated_fibres(jittered(M.config1(nx=6, ny=6, nz=3))))
     w.stimuli = []
@@ -273,6 +336,31 @@ def test_checkpoint_roundtrip_bitwise(ep):
         assert np.array_equal(a.vm(), b.vm())
         assert np.array_equal(a.apd90(), b.apd90(), equal_nan=True)
         assert b.time()[0] == 300
+
+
+def test_checkpoint_rejects_other_cell_order(ep):
+    """The per-cell arrays of an image are in internal order: an image taken
+    under one cell order (or model layout) is refused by a simulation of the
+    same mesh built under another, instead of scrambling its state."""
+    w = M.config1(nx=8, ny=6, nz=2)
+    a = ep.Sim(w, cell_order=ep.EP_ORDER_RCM)
+    a.step(20)
+    blob = a.checkpoint()
+    for order in (ep.EP_ORDER_MORTON, ep.EP_ORDER_INPUT):
+        b = ep.Sim(w, cell_order=order)
+        with pytest.raises(ep.EPError) as e:
+            b.restore(blob)
+        assert e.value.status == ep.EP_EINVAL
+    w2 = M.config1(nx=8, ny=6, nz=2)
+    w2.model = w2.model.copy()
+    w2.model[: w2.n_tets // 2] = 1          # TP06 mid-myocardial in half the slab
+    c = ep.Sim(w2, cell_order=ep.EP_ORDER_RCM)
+    with pytest.raises(ep.EPError) as e:
+        c.restore(blob)
+    assert e.value.status == ep.EP_EINVAL
+    d = ep.Sim(w, cell_order=ep.EP_ORDER_RCM)
+    d.restore(blob)
+    assert d.time()[0] == 20
 
 
 def test_nan_is_reported(ep):
