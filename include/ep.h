@@ -295,6 +295,23 @@ ep_status ep_get_time(ep_sim *s, int64_t *step, double *t);
  * workspace cannot be allocated. */
 ep_status ep_apply_diffusion(ep_sim *s, const double *v, double *L, int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ep_apply_diffusion with its workspace in a fixed device buffer of
+ * EP_DIFFUSION_SCRATCH_MAX bytes that the library holds on every GPU it
+ * runs on until the process ends (its address is taken at ep_init).  Same
+ * arguments and result; allocates nothing, host or device, and does not
+ * wait: the kernels are enqueued on the simulation's stream and L is ready
+ * once that stream is synchronised.  Every call on one GPU shares that
+ * GPU's buffer (nothing in it needs to start at zero; it keeps the last
+ * call's contents), so calls whose kernels overlap on one GPU - from other
+ * streams or simulations - race and must be ordered by the caller.
+ * EP_EINVAL when the workspace (8 (FP64) or 4 (mixed) bytes per cell and per
+ * node, the cell part rounded up to 256 bytes) exceeds the buffer, with the
+ * other errors of ep_apply_diffusion. */
+#define EP_DIFFUSION_SCRATCH_MAX (64u << 20)
+ep_status ep_apply_diffusion_noalloc(ep_sim *s, const double *v, double *L, int64_t n);
+
 /* Per-cell states as FP64, layout out[slot * n + cell] with n == n_tets,
  * n_slots == EP_MAX_SLOTS.  Slot 0 is V; the model's states follow in the
  * order of ep_model_slot_name(); unused slots read NaN and are ignored on

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "instance.hpp"
@@ -63,6 +64,16 @@ std::string launch(const Inst &I, hipStream_t st, const double *v, double *L, vo
     return e == hipSuccess ? std::string() : std::string("diffusion kernels: ") + hipGetErrorString(e);
 }
 
+// Fixed workspace of the no-allocation entry point, one copy per GPU for the
+// life of the process.  Host code never takes the array's own name as an
+// address: it uses the device address hipGetSymbolAddress gives for the
+// current device (g_scratch).
+constexpr size_t kScratchBytes = (size_t)EP_DIFFUSION_SCRATCH_MAX;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_mu;
+void *g_scratch[kMaxDevices] = {};
+
 }  // namespace
 
 size_t diffusion_workspace_split(int64_t nc, size_t rs) {
@@ -73,8 +84,40 @@ size_t diffusion_workspace_bytes(const Inst &I) {
     return diffusion_workspace_split(I.desc.nc, (size_t)I.rs) + (size_t)I.desc.nn * (size_t)I.rs;
 }
 
+std::string diffusion_scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return "device index beyond the scratch table";
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_scratch[device]) return "";
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // device is current
+    if (e != hipSuccess) return std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    g_scratch[device] = p;
+    return "";
+}
+
 std::string diffusion_apply(const Inst &I, hipStream_t st, const double *v, double *L, void *ws) {
     return I.rs == 8 ? launch<double>(I, st, v, L, ws) : launch<float>(I, st, v, L, ws);
+}
+
+std::string diffusion_apply_noalloc(const Inst &I, int device, hipStream_t st, const double *v,
+                                    double *L, ep_status &code) {
+    const size_t need = diffusion_workspace_bytes(I);
+    if (need > kScratchBytes) {
+        code = EP_EINVAL;
+        return "the operator needs " + std::to_string(need) +
+               " bytes of workspace; the fixed buffer holds " + std::to_string(kScratchBytes);
+    }
+    void *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (device >= 0 && device < kMaxDevices) p = g_scratch[device];
+    }
+    if (!p) {
+        code = EP_ESTATE;
+        return "no workspace address for this device (taken at ep_init)";
+    }
+    code = EP_EDEVICE;
+    return diffusion_apply(I, st, v, L, p);
 }
 
 }  // namespace ep

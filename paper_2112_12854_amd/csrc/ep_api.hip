@@ -294,6 +294,10 @@ ep_status ep_init(ep_sim *s) {
     ep_status st = EP_OK;
     std::string e = ep::build_instance(s->spec, s->stepper.rs, al, s->inst, st);
     if (!e.empty()) return fail(s, st, e);
+    if (!(e = ep::diffusion_scratch_setup(s->opt.device)).empty()) {
+        ep::free_instance(s->inst);
+        return fail(s, EP_EDEVICE, e);
+    }
     s->stepper.insts = {&s->inst};
     s->stepper.dirty = true;
     e = ep::stepper_sync_tables(s->stepper);
@@ -463,6 +467,16 @@ ep_status ep_apply_diffusion(ep_sim *s, const double *v, double *L, int64_t n) {
     else (void)hipFree(ws);
     if (!e.empty()) return fail(s, EP_EDEVICE, e);
     if (es != hipSuccess) return fail(s, EP_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(es));
+    return EP_OK;
+}
+
+ep_status ep_apply_diffusion_noalloc(ep_sim *s, const double *v, double *L, int64_t n) {
+    ep_status st = diffusion_args(s, v, L, n);
+    if (st != EP_OK) return st;
+    HIP_TRY(s, hipSetDevice(s->opt.device));
+    ep_status code = EP_OK;
+    std::string e = ep::diffusion_apply_noalloc(s->inst, s->opt.device, s->stream, v, L, code);
+    if (!e.empty()) return fail(s, code, e);
     return EP_OK;
 }
 

@@ -240,5 +240,13 @@ void model_init(int m, double *y);
 size_t diffusion_workspace_split(int64_t nc, size_t rs);
 size_t diffusion_workspace_bytes(const Inst &I);
 std::string diffusion_apply(const Inst &I, hipStream_t st, const double *v, double *L, void *ws);
+// Once per device, with that device current: the device address of the
+// library's fixed workspace.
+std::string diffusion_scratch_setup(int device);
+// diffusion_apply on the fixed workspace of `device`; fails if the operator
+// needs more than EP_DIFFUSION_SCRATCH_MAX bytes.  Allocates nothing.  On
+// failure `code` is the status to report.
+std::string diffusion_apply_noalloc(const Inst &I, int device, hipStream_t st, const double *v,
+                                    double *L, ep_status &code);
 
 }  // namespace ep

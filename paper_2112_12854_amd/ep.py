@@ -137,6 +137,7 @@ _SIGS = {
                                        C.POINTER(C.c_int64)]),
     "ep_get_time": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), _dp]),
     "ep_apply_diffusion": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "ep_apply_diffusion_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "ep_get_states": (C.c_int, [C.c_void_p, _dp, C.c_int64, C.c_int32]),
     "ep_set_states": (C.c_int, [C.c_void_p, _dp, C.c_int64, C.c_int32]),
     "ep_model_n_slots": (C.c_int, [C.c_int]),
