@@ -57,47 +57,80 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(ep, w, prec, steps, warmup, chunk, profile_steps):
+def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_reps=0):
+    """One precision on workload w.  The timed region is `steps` steps by
+    direct launches with HIP events around every kernel on the simulation's
+    stream (the queue stays 64 steps deep, so the kernels run back to back):
+    the throughput and the kernel durations of the roofline come from the
+    same window.  Then `lat_steps` more event-timed steps give the per-step
+    latency distribution, a window of `steps` steps in the production
+    schedule (HIP graphs of `chunk` steps) gives its throughput beside, and
+    `diffusion_reps` applications of the diffusion operator alone are timed
+    with events on the same stream."""
     import torch
     t0 = time.time()
     sim = ep.Sim(w, prec=prec, allocator="torch", trace_every=50)
     log(f"prec={prec}: init {time.time() - t0:.1f}s, footprint {sim.footprint() / 2**30:.2f} GiB")
+    sim.set_launch(256, chunk, 1)
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
-    lat = []
-    done = 0
     t_start = time.perf_counter()
-    while done < steps:
-        k = min(chunk, steps - done)
-        t1 = time.perf_counter()
-        sim.step(k)
-        sim.sync()
-        lat.append((time.perf_counter() - t1) / k)
-        done += k
+    cell_ms, node_ms, per = sim.profile_steps(steps, per_step=True)
+    sim.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    log(f"prec={prec}: {steps} steps in {elapsed:.3f}s")
-    node_b, cell_b = sim.algorithmic_bytes()
+    log(f"prec={prec}: {steps} steps in {elapsed:.3f}s (event-timed launches)")
+    _, _, lat = sim.profile_steps(lat_steps, per_step=True)
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    graph_elapsed = time.perf_counter() - t1
+    node_b, cell_b, diff_b = sim.algorithmic_bytes(with_diffusion=True)
     at = sim.activation()
     n_sub = sim.purkinje_n_sub() if sim.n_purkinje else 0
+    diff = None
+    if diffusion_reps:
+        diff = time_diffusion(ep, sim, w, diffusion_reps)
+        diff["bytes"] = diff_b
+        diff["GBps"] = diff_b / (diff["ms"] * 1e-3) / 1e9
     sim.close()
-    # kernel durations over the same window of the same job: a fresh
-    # simulation, the same untimed warm-up, then event-timed direct launches
-    sim = ep.Sim(w, prec=prec, allocator="torch", trace_every=50)
-    sim.step(warmup)
-    cell_ms, node_ms = sim.profile_steps(profile_steps)
-    res = dict(ms_per_step=1e3 * elapsed / steps,
-               graph_node_steps_per_s=sim.n_purkinje * n_sub * steps / elapsed,
-               graph_substeps=n_sub,
-               cell_steps_per_s=w.n_tets * steps / elapsed,
-               p50_ms=1e3 * float(np.percentile(lat, 50)),
-               p99_ms=1e3 * float(np.percentile(lat, 99)),
-               cell_kernel_ms=cell_ms, node_kernel_ms=node_ms,
-               cell_bytes=cell_b, node_bytes=node_b,
-               activated=int(np.isfinite(at).sum()))
-    sim.close()
-    return res
+    return dict(ms_per_step=1e3 * elapsed / steps,
+                graph_ms_per_step=1e3 * graph_elapsed / steps,
+                graph_node_steps_per_s=sim.n_purkinje * n_sub * steps / elapsed,
+                graph_substeps=n_sub,
+                cell_steps_per_s=w.n_tets * steps / elapsed,
+                p50_ms=float(np.percentile(lat, 50)),
+                p99_ms=float(np.percentile(lat, 99)),
+                n_latency=int(lat.size),
+                timed_p50_ms=float(np.percentile(per, 50)),
+                cell_kernel_ms=cell_ms, node_kernel_ms=node_ms,
+                cell_bytes=cell_b, node_bytes=node_b,
+                activated=int(np.isfinite(at).sum()), diffusion_op=diff)
+
+
+def time_diffusion(ep, sim, w, reps):
+    """The diffusion operator alone (ep_apply_diffusion_noalloc: three
+    kernels, no allocation, no wait) applied `reps` times to a device field,
+    bracketed by events on the simulation's stream."""
+    import ctypes as C
+    import torch
+    st = sim._stream
+    v = torch.linspace(-85.0, 30.0, w.n_tets, dtype=torch.float64, device="cuda")
+    L = torch.empty_like(v)
+    torch.cuda.synchronize()
+    fn = ep.lib().ep_apply_diffusion_noalloc
+    args = (sim.h, C.c_void_p(v.data_ptr()), C.c_void_p(L.data_ptr()), w.n_tets)
+    assert fn(*args) == ep.EP_OK
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn(*args)
+    e1.record(st)
+    torch.cuda.synchronize()
+    return {"ms": e0.elapsed_time(e1) / reps, "reps": reps,
+            "kernels": "k_diff_in + k_diff_nodes + k_diff_out"}
 
 
 def measure_hbm(mib: int = 2048, reps: int = 20):
@@ -122,11 +155,32 @@ def measure_hbm(mib: int = 2048, reps: int = 20):
     return out
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name, family/model/stepping and core count as the
+    kernel reports them."""
+    info = {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                info[k] = v.strip()
+            if len(info) == 4:
+                break
+    except OSError:
+        pass
+    return (f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, "
+            f"model {info.get('model', '?')}, stepping {info.get('stepping', '?')})")
+
+
 def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
-    """The oracle (as it stands) on a sub-slab of the same recipe, on all host
-    threads, then on one thread (beside the paper's single-core figure)."""
+    """The oracle (as it stands, built -O3 -march=native for this host, no
+    fast-math, no FMA contraction) on a sub-slab of the same recipe, on all
+    host threads, then on one thread (beside the paper's single-core
+    figure)."""
     import oracle
     from paper_2112_12854_amd import meshgen
+    oracle.use_native()
     w = meshgen.scaled_config2(nx, ny, nz, n_steps=steps)
     ref = oracle.Sim(w)
     ref.step(2)
@@ -140,34 +194,58 @@ def cpu_baseline(steps: int, nx: int, ny: int, nz: int):
     ref.step(s1)
     el1 = time.perf_counter() - t0
     oracle.set_num_threads(threads)
-    cpu = "unknown"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
     return dict(value=w.n_tets * steps / el, unit="cell-steps/s",
                 cores=threads, kind="oracle",
                 sample=f"{w.n_tets} tets ({nx}x{ny}x{nz} hexes of the same slab recipe, "
                        f"h=0.25 mm), {steps} FP64 steps after 2 untimed, {el:.1f} s",
                 single_thread={"value": w.n_tets * s1 / el1, "steps": s1},
-                host_cpu=cpu, host_cpus_visible=os.cpu_count())
+                build=" ".join(oracle.build_flags()),
+                host_cpu=host_cpu_model(), host_cpus_visible=os.cpu_count())
 
 
-def run_serving(ep, n_req, n_steps, rate, seed=4, prec=None, one_at_a_time=False, trial=20):
-    """Serving stream: slab requests log-uniform in [1e4, 1e6] tets with
-    Poisson arrivals at a fixed `rate` (requests/s); continuous batching with
-    the autotuned schedule (re-tuned as the batch grows or shrinks), or one
-    request at a time."""
-    from paper_2112_12854_amd import meshgen
-    specs = meshgen.serving_requests(n=n_req, seed=seed)
-    ws = [meshgen.serving_workload(sp, n_steps) for sp in specs]
+def _pct(x):
+    x = np.asarray(x, dtype=np.float64)
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)),
+            "mean": float(x.mean()), "max": float(x.max())}
+
+
+def saturated_rate(ep, ws, n_steps, prec, trial=20):
+    """Cell-steps/s of the server with the workloads ws all resident (held
+    until admitted, autotuned, then measured from the live progress counter
+    up to 90 % of the work issued)."""
+    sv = ep.Server(prec=prec, max_slots=len(ws))
+    sv.hold(True)
+    ids = [sv.submit(w, n_steps) for w in ws]
+    t0 = time.perf_counter()
+    while sv.stats()["running"] < len(ws):
+        if time.perf_counter() - t0 > 300:
+            raise RuntimeError("calibration batch did not become resident")
+        time.sleep(0.01)
+    sv.autotune(trial)
+    sv.hold(False)
+    while sv.stats()["autotune_runs"] < 1:
+        time.sleep(0.005)
+    st1, t1 = sv.stats(), time.perf_counter()
+    goal = 0.9 * sum(w.n_tets for w in ws) * n_steps
+    while True:
+        st2, t2 = sv.stats(), time.perf_counter()
+        if st2["cell_steps"] >= goal or st2["completed"] == len(ws):
+            break
+        time.sleep(0.002)
+    for r in ids:
+        sv.wait(r)
+    sv.close()
+    return (st2["cell_steps"] - st1["cell_steps"]) / (t2 - t1)
+
+
+def run_serving(ep, ws, arrivals, n_steps, prec=None, one_at_a_time=False, trial=20):
+    """Serving stream: the workloads ws submitted at the given arrival times
+    (s); continuous batching with the autotuned schedule (re-tuned as the
+    batch grows or shrinks), or one request at a time.  Latency = completion
+    - submission, split into host precompute, wait for memory or a slot, and
+    the device run."""
+    n_req = len(ws)
     work = np.array([w.n_tets * n_steps for w in ws], dtype=np.float64)
-    lam = rate
-    rng = np.random.default_rng(seed + 1000)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
     sv = ep.Server(prec=prec, max_slots=1 if one_at_a_time else 256)
     if not one_at_a_time:
         sv.autotune(trial, retune=True)
@@ -187,11 +265,55 @@ def run_serving(ep, n_req, n_steps, rate, seed=4, prec=None, one_at_a_time=False
     lat = np.array([r["t_done"] - r["t_submit"] for r in res])
     span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
     return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                mean_s=float(lat.mean()), cell_steps_per_s=float(work.sum() / span),
-                span_s=span, arrival_rate_per_s=lam, n_requests=n_req, steps=n_steps,
+                mean_s=float(lat.mean()), n_requests=n_req, steps=n_steps,
+                cell_steps_per_s=float(work.sum() / span), span_s=span,
+                breakdown_s={"precompute": _pct([r["t_ready"] - r["t_submit"] for r in res]),
+                             "wait": _pct([r["t_admit"] - r["t_ready"] for r in res]),
+                             "device": _pct([r["t_done"] - r["t_admit"] for r in res])},
                 mean_tets=float(np.mean([w.n_tets for w in ws])),
                 steps_per_graph=st["steps_per_graph"], xcd_remap=st["xcd_remap"],
                 autotune_runs=st["autotune_runs"])
+
+
+def serving_leg(ep, meshgen, n_req, n_steps, load, n_fp64, seed=4):
+    """Config-4 stream: n_req slab requests (1e4-1e6 tets log-uniform), each
+    n_steps, Poisson arrivals at `load` x the measured capacity (the
+    saturated FP32-mixed rate of the server on the stream's first 16
+    requests over the stream's mean work per request); batched FP32-mixed
+    on the whole stream, FP64 one request at a time on its first n_fp64
+    requests at the same arrival times."""
+    specs = meshgen.serving_requests(n=n_req, seed=seed)
+    ws = [meshgen.serving_workload(sp, n_steps) for sp in specs]
+    mean_work = float(np.mean([w.n_tets for w in ws])) * n_steps
+    cal_steps = 1500
+    rate = saturated_rate(ep, ws[:16], cal_steps, ep.EP_FP32_MIXED)
+    capacity = rate / mean_work
+    lam = load * capacity
+    log(f"serving: capacity {capacity:.2f} requests/s ({rate:.3e} cell-steps/s saturated), "
+        f"arrivals at {lam:.2f}/s")
+    rng = np.random.default_rng(seed + 1000)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+    log(f"serving stream: {n_req} requests x {n_steps} steps (batched FP32-mixed) ...")
+    bat = run_serving(ep, ws, arrivals, n_steps, prec=ep.EP_FP32_MIXED)
+    log(f"  p50 {bat['p50_s']:.3f}s p99 {bat['p99_s']:.3f}s, {bat['cell_steps_per_s']:.3e} cell-steps/s")
+    one = None
+    if n_fp64:
+        log(f"serving stream: first {n_fp64} requests one at a time, FP64 ...")
+        one = run_serving(ep, ws[:n_fp64], arrivals[:n_fp64], n_steps, prec=ep.EP_FP64,
+                          one_at_a_time=True)
+        log(f"  p50 {one['p50_s']:.3f}s p99 {one['p99_s']:.3f}s, "
+            f"{one['cell_steps_per_s']:.3e} cell-steps/s")
+    return {"workload": f"{n_req} slab requests, 1e4-1e6 tets log-uniform, sigma scale "
+                        f"U[0.5,2], random stimulus face, {n_steps} steps each, Poisson "
+                        f"arrivals at {load:g} x measured capacity",
+            "capacity": {"requests_per_s": capacity, "saturated_cell_steps_per_s": rate,
+                         "calibration": f"first 16 requests of the stream, {cal_steps} steps, "
+                                        "all resident, FP32-mixed"},
+            "arrival_rate_per_s": lam,
+            "batched_fp32": bat,
+            "one_at_a_time_fp64": one,
+            "one_at_a_time_fp64_subset": f"first {n_fp64} requests of the same stream, "
+                                         "same arrival times" if n_fp64 else None}
 
 
 def run_uq(ep, n_inst, n_steps, prec, trial=25, seed=5):
@@ -284,6 +406,73 @@ def fp32_accuracy(ep, meshgen, n_uq=16, uq_steps=25000):
     return out
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        d = {k: z[k] for k in z.files}
+    d["info"] = json.loads(str(d["info"]))
+    return d
+
+
+def _vs(a, b):
+    return {"at_ms": _err_stats(a[0], b[0]), "apd90_ms": _err_stats(a[1], b[1]),
+            "v_end_mV": _err_stats(a[2], b[2]),
+            "nan_pattern_equal": bool(np.array_equal(np.isnan(a[0]), np.isnan(b[0])) and
+                                      np.array_equal(np.isnan(a[1]), np.isnan(b[1])))}
+
+
+def accuracy_vs_oracle(ep, meshgen):
+    """FP32-mixed and FP64 error per result against the FP64 oracle's stored
+    run of the same seeded inputs (tests/golden, keyed by input hash): the
+    benchmark slab's whole 400 ms job (a seeded sample of 100,000 cells) and
+    64 instances of the UQ batch over 500 ms (1,500 sampled cells each)."""
+    out = {}
+    g = _golden("slab_400ms_oracle.npz")
+    if g is not None:
+        w = meshgen.config2(n_steps=g["info"]["steps"])
+        if meshgen.workload_sha256(w) != g["info"]["sha256"]:
+            raise RuntimeError("slab oracle fixture is of other inputs")
+        c = g["cells"]
+        ref = (g["t_act"], g["apd90"], g["v_end"])
+        r = {"workload": f"{w.name}: {w.n_tets} tets, {w.n_steps} steps, "
+                         f"{c.size} sampled cells", "oracle_seconds": g["info"]["seconds"]}
+        for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
+            sim = ep.Sim(w, prec=prec)
+            sim.step(w.n_steps)
+            r[name] = _vs((sim.activation()[c], sim.apd90()[c], sim.vm()[c]), ref)
+            sim.close()
+        out["slab_vs_oracle"] = r
+    g = _golden("uq64_500ms_oracle.npz")
+    if g is not None:
+        specs = meshgen.uq_instances(n=1024, seed=5)
+        idx, offs = g["instance"], g["offsets"]
+        ws = [meshgen.uq_workload(specs[int(i)], g["info"]["steps"]) for i in idx]
+        if [meshgen.workload_sha256(x) for x in ws] != g["info"]["sha256"]:
+            raise RuntimeError("UQ oracle fixture is of other inputs")
+        ref = (g["t_act"], g["apd90"], g["v_end"])
+        r = {"workload": f"{len(ws)} UQ instances ({sum(x.n_tets for x in ws)} tets), "
+                         f"{g['info']['steps']} steps, {g['cells'].size} sampled cells"}
+        for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
+            sv = ep.Server(prec=prec, max_slots=len(ws))
+            ids = [sv.submit(x, g["info"]["steps"]) for x in ws]
+            at, apd, ve = [], [], []
+            for k, i in enumerate(ids):
+                sv.wait(i)
+                cc = g["cells"][offs[k]:offs[k + 1]]
+                at.append(sv.activation(i)[cc])
+                apd.append(sv.apd90(i)[cc])
+                ve.append(sv.vm(i)[cc])
+            sv.close()
+            r[name] = _vs((np.concatenate(at), np.concatenate(apd), np.concatenate(ve)), ref)
+        out["uq_vs_oracle"] = r
+    return out
+
+
 def run_bidomain(ep, meshgen, args):
     """The paper's benchmark box (20 x 7 x 3 mm, fibres along x, TP06, 1.5 mm
     corner stimulus) at dx = 0.5, 0.2, 0.1 mm: wall time of one bidomain step
@@ -330,8 +519,8 @@ def run_heart(ep, meshgen, args):
     w = meshgen.heart(h=0.375, scale=1.0, purkinje_nodes=60000, n_pmj=2000)
     log(f"workload {w.name}: {w.n_tets} tets, {w.purkinje.xyz.shape[0]} graph nodes, "
         f"{len(w.purkinje.pmj_nodes)} junctions ({time.time() - t0:.1f}s)")
-    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, args.steps)
-    f64 = run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, args.steps)
+    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk)
+    f64 = run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk)
     achieved = f32["cell_bytes"] / (f32["cell_kernel_ms"] * 1e-3) / 1e9
     out = {
         "metric": "cell-steps/s (ionic+FV step) FP32 vs FP64; p50/p99 solve latency",
@@ -370,7 +559,7 @@ def run_ab2(ep, meshgen, args):
     log(f"workload {w.name} ({tag}): {w.n_tets} tets ({time.time() - t0:.1f}s)")
     res = {}
     for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
-        r = run_precision(ep, w, prec, args.steps, args.warmup, args.chunk, args.steps)
+        r = run_precision(ep, w, prec, args.steps, args.warmup, args.chunk)
         r["cell_GBps"] = r["cell_bytes"] / (r["cell_kernel_ms"] * 1e-3) / 1e9
         res[name] = r
     f32 = res["fp32"]
@@ -401,7 +590,7 @@ def run_sheet(ep, meshgen, args):
     log(f"workload {w.name}: {w.n_tets} triangles, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")
     res = {}
     for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
-        r = run_precision(ep, w, prec, args.steps, args.warmup, args.chunk, args.steps)
+        r = run_precision(ep, w, prec, args.steps, args.warmup, args.chunk)
         r["cell_GBps"] = r["cell_bytes"] / (r["cell_kernel_ms"] * 1e-3) / 1e9
         res[name] = r
     f32 = res["fp32"]
@@ -444,16 +633,20 @@ def main():
                     help="FP32-mixed only (short profiling runs)")
     ap.add_argument("--only-fp64", action="store_true",
                     help="FP64 only (short profiling runs)")
-    ap.add_argument("--serving", type=str, default="32x2500", metavar="NxSTEPS",
-                    help="serving stream sample (requests x steps each; '0' skips; "
-                         "the full stream is 256x15000)")
-    ap.add_argument("--serve-rate", type=float, default=17.0, metavar="PER_S",
-                    help="Poisson arrival rate of the serving stream (requests/s)")
-    ap.add_argument("--uq", type=str, default="1024x2000", metavar="NxSTEPS",
-                    help="UQ batch sample (instances x steps; '0' skips; the full "
-                         "batch is 1024x25000)")
+    ap.add_argument("--serving", type=str, default="256x15000", metavar="NxSTEPS",
+                    help="serving stream (requests x steps each; '0' skips)")
+    ap.add_argument("--serve-load", type=float, default=0.7, metavar="FRAC",
+                    help="Poisson arrival rate as a fraction of the measured capacity")
+    ap.add_argument("--serve-fp64", type=int, default=32, metavar="N",
+                    help="requests of the stream served one at a time in FP64 (0 skips)")
+    ap.add_argument("--uq", type=str, default="1024x25000", metavar="NxSTEPS",
+                    help="UQ batch, FP32-mixed (instances x steps; '0' skips)")
+    ap.add_argument("--uq-fp64-steps", type=int, default=2500,
+                    help="steps of the FP64 UQ batch (0 skips)")
     ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the FP32-vs-FP64 error distributions")
+                    help="skip the error distributions against the oracle")
+    ap.add_argument("--diffusion-reps", type=int, default=50,
+                    help="applications of the diffusion operator alone to time (0 skips)")
     ap.add_argument("--bidomain", action="store_true",
                     help="bidomain vs monodomain step time on the paper's benchmark box")
     ap.add_argument("--sheet", action="store_true",
@@ -499,7 +692,7 @@ def main():
     log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")
 
     if args.only_fp64:
-        run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, args.steps)
+        run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk)
         return
     # the serving and UQ legs first: each starts from the state a serving
     # process starts in (device memory and streams of the slab runs, still
@@ -507,34 +700,36 @@ def main():
     serving = uq = None
     if not (args.only_fp32 or args.serving == "0"):
         nreq, nst = (int(x) for x in args.serving.split("x"))
-        log(f"serving stream: {nreq} requests x {nst} steps (batched FP32-mixed) ...")
-        bat = run_serving(ep, nreq, nst, args.serve_rate, prec=ep.EP_FP32_MIXED)
-        log(f"  p50 {bat['p50_s']:.3f}s p99 {bat['p99_s']:.3f}s, {bat['cell_steps_per_s']:.3e} cell-steps/s")
-        log("serving stream: one at a time, FP64 ...")
-        one = run_serving(ep, nreq, nst, args.serve_rate, prec=ep.EP_FP64, one_at_a_time=True)
-        log(f"  p50 {one['p50_s']:.3f}s p99 {one['p99_s']:.3f}s, {one['cell_steps_per_s']:.3e} cell-steps/s")
-        serving = {"workload": f"{nreq} slab requests, 1e4-1e6 tets log-uniform, sigma scale "
-                               f"U[0.5,2], random stimulus face, {nst} steps each, Poisson "
-                               f"arrivals at a fixed {args.serve_rate:g} requests/s",
-                   "batched_fp32": bat, "one_at_a_time_fp64": one}
+        serving = serving_leg(ep, meshgen, nreq, nst, args.serve_load, args.serve_fp64)
     if not (args.only_fp32 or args.uq == "0"):
         ni, nst = (int(x) for x in args.uq.split("x"))
         uq = {}
-        for name, prec in (("fp32", ep.EP_FP32_MIXED), ("fp64", ep.EP_FP64)):
-            log(f"UQ batch {name}: {ni} instances x {nst} steps ...")
-            uq[name] = run_uq(ep, ni, nst, prec)
+        for name, prec, k in (("fp32", ep.EP_FP32_MIXED, nst), ("fp64", ep.EP_FP64, args.uq_fp64_steps)):
+            if k <= 0:
+                continue
+            log(f"UQ batch {name}: {ni} instances x {k} steps ...")
+            uq[name] = run_uq(ep, ni, k, prec)
             log(f"  {uq[name]['cell_steps_per_s']:.3e} cell-steps/s "
                 f"(k={uq[name]['steps_per_graph']}, remap={uq[name]['xcd_remap']})")
-    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk, args.steps)
-    f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(ep, w, ep.EP_FP64, args.steps,
-                                                  args.warmup, args.chunk, args.steps)
+    f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk,
+                        diffusion_reps=args.diffusion_reps)
+    f64 = None if (args.no_fp64 or args.only_fp32) else run_precision(
+        ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk, diffusion_reps=args.diffusion_reps)
     hbm = None if args.only_fp32 else measure_hbm()
     acc = None
     if not (args.only_fp32 or args.no_accuracy):
-        log("FP32 accuracy (500 ms runs) ...")
-        acc = fp32_accuracy(ep, meshgen)
-        log(f"  slab: AT max {acc['slab_vs_gpu_fp64']['at_ms']['max']:.4f} ms, "
-            f"APD90 max {acc['slab_vs_gpu_fp64']['apd90_ms']['max']:.4f} ms")
+        log("accuracy against the oracle's stored runs ...")
+        acc = accuracy_vs_oracle(ep, meshgen)
+        if not acc:
+            log("  no oracle fixtures: FP32 against the GPU FP64 path (500 ms runs) ...")
+            acc = fp32_accuracy(ep, meshgen)
+        for k, v in acc.items():
+            if isinstance(v, dict) and "fp32" in v:
+                log(f"  {k}: FP32 AT max {v['fp32']['at_ms']['max']:.4f} ms, "
+                    f"APD90 max {v['fp32']['apd90_ms']['max']:.4f} ms; FP64 V max "
+                    f"{v['fp64']['v_end_mV']['max']:.2e} mV")
+            elif isinstance(v, dict) and "at_ms" in v:
+                log(f"  {k}: AT max {v['at_ms']['max']:.4f} ms, APD90 max {v['apd90_ms']['max']:.4f} ms")
     cpu = None
     if not (args.no_cpu or args.only_fp32):
         log("cpu baseline (oracle) ...")
@@ -542,6 +737,26 @@ def main():
         log(f"cpu baseline {cpu['value']:.3e} cell-steps/s on {cpu['cores']} threads")
 
     achieved = f32["cell_bytes"] / (f32["cell_kernel_ms"] * 1e-3) / 1e9
+
+    def gbps(b, ms):
+        return b / (ms * 1e-3) / 1e9
+
+    def sweep(r):
+        """The diffusion sweep: the node gather of the step (its only kernel
+        that does nothing else) and the operator alone (three kernels)."""
+        d = {"node_gather": {"achieved": gbps(r["node_bytes"], r["node_kernel_ms"]),
+                             "frac": gbps(r["node_bytes"], r["node_kernel_ms"]) / HBM_PEAK_GBS,
+                             "ms": r["node_kernel_ms"], "algorithmic_bytes": r["node_bytes"]},
+             "step": {"achieved": gbps(r["node_bytes"] + r["cell_bytes"],
+                                       r["node_kernel_ms"] + r["cell_kernel_ms"]),
+                      "frac": gbps(r["node_bytes"] + r["cell_bytes"],
+                                   r["node_kernel_ms"] + r["cell_kernel_ms"]) / HBM_PEAK_GBS}}
+        if r["diffusion_op"]:
+            op = r["diffusion_op"]
+            d["operator_alone"] = dict(op, frac=op["GBps"] / HBM_PEAK_GBS)
+        d["peak"], d["unit"] = HBM_PEAK_GBS, "GB/s"
+        return d
+
     out = {
         "metric": "cell-steps/s (ionic+FV step) FP32 vs FP64; p50/p99 solve latency",
         "value": f32["cell_steps_per_s"],
@@ -558,28 +773,33 @@ def main():
         "config": {"workload": w.name, "n_tets": w.n_tets, "n_nodes": w.n_nodes,
                    "dt_ms": w.dt, "cells": "TP06 endo/mid/epi 30/40/30%",
                    "fibres": "-60..+60 deg transmural + 5 deg jitter"},
-        "latency_ms": {"p50": f32["p50_ms"], "p99": f32["p99_ms"],
-                       "per": f"step (timed in chunks of {args.chunk} steps)"},
+        "timed_region": "direct launches, HIP events around every kernel, queue 64 steps deep",
+        "ms_per_step_graphs": f32["graph_ms_per_step"],
+        "latency_ms": {"p50": f32["p50_ms"], "p99": f32["p99_ms"], "n": f32["n_latency"],
+                       "per": "step: device time from its first kernel's start to its last "
+                              "kernel's end, consecutive event-timed steps after the timed region"},
         "fp64": None if f64 is None else {
             "value": f64["cell_steps_per_s"], "ms_per_step": f64["ms_per_step"],
-            "p50_ms": f64["p50_ms"], "p99_ms": f64["p99_ms"],
+            "ms_per_step_graphs": f64["graph_ms_per_step"],
+            "p50_ms": f64["p50_ms"], "p99_ms": f64["p99_ms"], "n_latency": f64["n_latency"],
             "cell_kernel_ms": f64["cell_kernel_ms"], "node_kernel_ms": f64["node_kernel_ms"],
-            "cell_kernel_GBps": f64["cell_bytes"] / (f64["cell_kernel_ms"] * 1e-3) / 1e9,
+            "cell_kernel_GBps": gbps(f64["cell_bytes"], f64["cell_kernel_ms"]),
             "cell_bytes": f64["cell_bytes"], "node_bytes": f64["node_bytes"],
-            "traffic": measured_traffic("fp64")},
+            "traffic": measured_traffic("fp64"), "diffusion_sweep": sweep(f64)},
         "kernels_fp32": {"cell_kernel_ms": f32["cell_kernel_ms"],
                          "node_kernel_ms": f32["node_kernel_ms"],
-                         "node_kernel_GBps": f32["node_bytes"] / (f32["node_kernel_ms"] * 1e-3) / 1e9,
+                         "node_kernel_GBps": gbps(f32["node_bytes"], f32["node_kernel_ms"]),
                          "cell_bytes": f32["cell_bytes"], "node_bytes": f32["node_bytes"]},
         "roofline": {"bound": "hbm", "kernel": "k_cell<float> (fused flux+ionic+update)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("fp32"),
                      "algorithmic_bytes": f32["cell_bytes"]},
+        "diffusion_sweep": sweep(f32),
         "cpu_baseline": cpu,
         "hbm_measured_GBps": hbm,
         "serving": serving,
         "uq_batch": uq,
-        "fp32_error": acc,
+        "accuracy": acc,
     }
     print(json.dumps(out), flush=True)
 

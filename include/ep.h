@@ -358,18 +358,24 @@ ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
 ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
                       int32_t *xcd_remap, double *ms_per_step);
 
-/* Average device duration (ms) of the fused cell kernel and of the node
- * gather kernel over the last ep_profile_steps() call, from HIP events on
- * the simulation's stream. */
+/* Runs n steps by direct launches with HIP events around every kernel on
+ * the simulation's stream, the host waiting only for the step 64 places
+ * back (the kernels run back to back, as without the events).  Reports the
+ * average device duration (ms) of the fused cell kernel and of the node
+ * gather kernel and, when step_ms is not NULL, each step's device time from
+ * the start of its first kernel to the end of its last (step_ms holds n
+ * doubles, caller-owned).  The steps are ordinary steps of the simulation.
+ * Any output pointer may be NULL. */
 ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms,
-                           double *node_ms);
+                           double *node_ms, double *step_ms);
 
 /* Algorithmic bytes moved per step by the node gather and by the cell
- * kernel for this mesh, precision, time scheme and stencil-id width (16-bit
- * offsets from per-block bases when every 256-cell block allows them, else
- * 32-bit ids): the roofline numerators.  EP_ESTATE before ep_init. */
+ * kernel, and by one ep_apply_diffusion call, for this mesh, precision,
+ * time scheme and stencil-id width (16-bit offsets from per-block bases
+ * when every 256-cell block allows them, else 32-bit ids): the roofline
+ * numerators.  Any output pointer may be NULL.  EP_ESTATE before ep_init. */
 ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes,
-                               double *cell_bytes);
+                               double *cell_bytes, double *diffusion_bytes);
 
 const char *ep_last_error(const ep_sim *s);
 
@@ -449,6 +455,10 @@ typedef struct {
     int64_t n_tets, steps;
     size_t footprint;             /* device bytes while resident             */
     double t_submit, t_admit, t_done;   /* seconds since server creation     */
+    double t_ready;               /* host precompute finished (0 if it failed):
+                                     t_ready - t_submit is the precompute,
+                                     t_admit - t_ready the wait for memory or
+                                     a slot, t_done - t_admit the device run */
 } ep_result;
 
 typedef struct {

@@ -753,27 +753,30 @@ ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
     return EP_OK;
 }
 
-ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms, double *node_ms) {
+ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms, double *node_ms,
+                           double *step_ms) {
     if (!s) return EP_EINVAL;
     if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
     if (n <= 0) return fail(s, EP_EINVAL, "n must be positive");
     HIP_TRY(s, hipSetDevice(s->opt.device));
     double a = 0, b = 0;
-    std::string e = ep::stepper_profile(s->stepper, n, a, b);
+    std::string e = ep::stepper_profile(s->stepper, n, a, b, step_ms);
     if (!e.empty()) return fail(s, EP_EDEVICE, e);
     if (cell_ms) *cell_ms = a;
     if (node_ms) *node_ms = b;
     return EP_OK;
 }
 
-ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes, double *cell_bytes) {
+ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes, double *cell_bytes,
+                               double *diffusion_bytes) {
     if (!s) return EP_EINVAL;
     if (!s->inited) return EP_ESTATE;
     const double r = s->inst.rs, nc = (double)s->inst.desc.nc, nn = (double)s->inst.desc.nn;
     // node gather: every incidence (index + weight; 4 per tet, 3 per
     // triangle), every v once, vn write
     const double ninc = (double)s->inst.prep.n_incidences;
-    if (node_bytes) *node_bytes = ninc * (4.0 + r) + nc * r + nn * r + 8.0 * s->inst.n_slices;
+    const double gather = ninc * (4.0 + r) + nc * r + nn * r + 8.0 * s->inst.n_slices;
+    if (node_bytes) *node_bytes = gather;
     // cell kernel: stencil (8 node ids + 8 coefficients + 4 neighbours + 4
     // coefficients; 16-bit ids plus two 32-bit bases per 256 cells when the
     // instance has them), vn once, v^n once, v^{n+1} write, model byte, state
@@ -787,6 +790,11 @@ ep_status ep_algorithmic_bytes(const ep_sim *s, double *node_bytes, double *cell
         if (s->inst.ab2) b += 2.0 * (r + model_nc(m) * 8.0);
     }
     if (cell_bytes) *cell_bytes = b;
+    // ep_apply_diffusion: caller v (FP64) and the permutation in, internal
+    // copy out; the node gather of that copy; the stencil, vn once, the
+    // copy once, the permutation again and L (FP64) out
+    if (diffusion_bytes)
+        *diffusion_bytes = nc * (8.0 + 4.0 + r) + gather + nc * (ids + 12 * r + r + 4.0 + 8.0) + nn * r;
     return EP_OK;
 }
 

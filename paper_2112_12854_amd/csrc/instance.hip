@@ -996,26 +996,49 @@ std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
     return err;
 }
 
-std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms) {
+std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms,
+                            double *step_ms) {
     if (s.dirty) {
         std::string e = stepper_sync_tables(s);
         if (!e.empty()) return e;
     }
     const int gn = grid_for(s.n_nt);
     s.grid_node = gn;
-    hipEvent_t ev[3];
+    // A ring of event quadruples (step start, after the node gather, after
+    // the cell kernel, step end): the host waits only for the step RING
+    // places back before reusing its events, so the queue stays RING - 1
+    // steps deep and the kernels run back to back as in an unprofiled run.
+    constexpr int RING = 64;
+    std::vector<hipEvent_t> ev(4 * RING, nullptr);
     for (auto &x : ev)
-        if (hipEventCreate(&x) != hipSuccess) return "hipEventCreate failed";
+        if (hipEventCreate(&x) != hipSuccess) {
+            for (auto &y : ev)
+                if (y) (void)hipEventDestroy(y);
+            return "hipEventCreate failed";
+        }
     double tc = 0, tn = 0;
+    auto collect = [&](int64_t i) {
+        hipEvent_t *q = &ev[4 * (i % RING)];
+        (void)hipEventSynchronize(q[3]);
+        float a = 0, b = 0, c = 0;
+        (void)hipEventElapsedTime(&a, q[0], q[1]);
+        (void)hipEventElapsedTime(&b, q[1], q[2]);
+        (void)hipEventElapsedTime(&c, q[0], q[3]);
+        tn += a;
+        tc += b;
+        if (step_ms) step_ms[i] = c;
+    };
     const Tables tb = tables(s);
     for (int64_t i = 0; i < n; ++i) {
-        (void)hipEventRecord(ev[0], s.stream);
+        if (i >= RING) collect(i - RING);
+        hipEvent_t *q = &ev[4 * (i % RING)];
+        (void)hipEventRecord(q[0], s.stream);
         if (s.rs == 8) launch_gather<double>(s, tb, 0);
         else launch_gather<float>(s, tb, 0);
-        (void)hipEventRecord(ev[1], s.stream);
+        (void)hipEventRecord(q[1], s.stream);
         if (s.rs == 8) launch_cells<double>(s, tb, 0);
         else launch_cells<float>(s, tb, 0);
-        (void)hipEventRecord(ev[2], s.stream);
+        (void)hipEventRecord(q[2], s.stream);
         if (s.n_pk > 0) {               // one stream here: the timings stay apart
             if (s.n_pt > 0 && s.rs == 8) launch_substeps<double>(s, 0, s.stream);
             else if (s.n_pt > 0) launch_substeps<float>(s, 0, s.stream);
@@ -1023,13 +1046,9 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
             else launch_junctions<float>(s, 0);
         }
         k_advance<<<1, 256, 0, s.stream>>>(tb, 1);
-        (void)hipEventSynchronize(ev[2]);
-        float a = 0, b = 0;
-        (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&b, ev[1], ev[2]);
-        tn += a;
-        tc += b;
+        (void)hipEventRecord(q[3], s.stream);
     }
+    for (int64_t i = std::max<int64_t>(0, n - RING); i < n; ++i) collect(i);
     for (Inst *I : s.insts) I->host_step = std::min(I->host_step + n, std::max(I->host_step, I->target));
     for (auto &x : ev) (void)hipEventDestroy(x);
     cell_ms = tc / n;

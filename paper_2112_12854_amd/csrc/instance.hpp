@@ -206,8 +206,11 @@ std::string stepper_sync_tables(Stepper &s);
 // Enqueue k steps of every live instance (graphs for whole multiples of the
 // graph length, direct launches for the rest).  Updates host_step.
 std::string stepper_run(Stepper &s, int64_t k);
-// Time one node-gather and one cell launch with events (ms).
-std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms);
+// n steps by direct launches, timed with events (ms): the average node
+// gather and cell kernel durations, and (step_ms non-null) each step's
+// device time from its first launch to the end of its last.
+std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms,
+                            double *step_ms = nullptr);
 
 // Launch-schedule autotuner.  Every candidate (steps per graph launch x XCD
 // tile remap) runs one untimed launch (graph capture, warm caches) and then

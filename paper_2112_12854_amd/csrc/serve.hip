@@ -41,7 +41,7 @@ struct Req {
     int state = Q_PREP;
     ep_status status = EP_OK;
     std::string err;
-    double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_submit = 0, t_ready = 0, t_admit = 0, t_done = 0;
     void *h_res = nullptr;             // pinned: t_act, t_rep (f64), v (R), NaN flag,
                                        // then graph t_act (f64) and v (R)
     std::vector<double> vm, tact, apd, pvm, pact;
@@ -137,6 +137,7 @@ void worker_main(ep_server *sv) {
             } else {
                 r->footprint = fp;
                 r->state = Q_READY;
+                r->t_ready = now_s(sv);
                 sv->ready_q.push_back(id);
                 sv->cv_driver.notify_all();
             }
@@ -595,6 +596,7 @@ static void fill_result(const Req *r, ep_result *res) {
     res->t_submit = r->t_submit;
     res->t_admit = r->t_admit;
     res->t_done = r->t_done;
+    res->t_ready = r->t_ready;
 }
 
 ep_status ep_server_poll(ep_server *sv, int64_t id, ep_result *res) {

@@ -76,7 +76,7 @@ class ep_request(C.Structure):
 class ep_result(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int), ("n_tets", C.c_int64),
                 ("steps", C.c_int64), ("footprint", C.c_size_t), ("t_submit", C.c_double),
-                ("t_admit", C.c_double), ("t_done", C.c_double)]
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("t_ready", C.c_double)]
 
 
 class ep_server_stats(C.Structure):
@@ -148,8 +148,8 @@ _SIGS = {
     "ep_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "ep_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), _dp]),
-    "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp]),
-    "ep_algorithmic_bytes": (C.c_int, [C.c_void_p, _dp, _dp]),
+    "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp, _dp]),
+    "ep_algorithmic_bytes": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "ep_last_error": (C.c_char_p, [C.c_void_p]),
     "ep_server_create": (C.c_int, [C.POINTER(ep_options), C.c_size_t, C.c_int32,
                                    C.POINTER(C.c_void_p)]),
@@ -424,15 +424,20 @@ class Sim:
                                  C.byref(ms)), self.h)
         return {"steps_per_graph": k.value, "xcd_remap": r.value, "ms_per_step": ms.value}
 
-    def profile_steps(self, n: int):
+    def profile_steps(self, n: int, per_step: bool = False):
+        """n event-timed steps: (cell kernel ms, node gather ms) averages, and
+        with per_step the device time of every step (ms)."""
         a, b = C.c_double(), C.c_double()
-        _check(lib().ep_profile_steps(self.h, int(n), C.byref(a), C.byref(b)), self.h)
-        return a.value, b.value
+        st = np.empty(int(n)) if per_step else None
+        _check(lib().ep_profile_steps(self.h, int(n), C.byref(a), C.byref(b),
+                                      None if st is None else _d(st)), self.h)
+        return (a.value, b.value, st) if per_step else (a.value, b.value)
 
-    def algorithmic_bytes(self):
-        a, b = C.c_double(), C.c_double()
-        _check(lib().ep_algorithmic_bytes(self.h, C.byref(a), C.byref(b)), self.h)
-        return a.value, b.value
+    def algorithmic_bytes(self, with_diffusion: bool = False):
+        """(node gather, cell kernel[, one apply_diffusion call]) bytes per step."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().ep_algorithmic_bytes(self.h, C.byref(a), C.byref(b), C.byref(c)), self.h)
+        return (a.value, b.value, c.value) if with_diffusion else (a.value, b.value)
 
 
 def model_n_slots(model: int) -> int:
@@ -445,8 +450,8 @@ def model_slot_names(model: int):
 
 def _result_dict(r: ep_result) -> dict:
     return dict(id=r.id, status=r.status, n_tets=r.n_tets, steps=r.steps,
-                footprint=r.footprint, t_submit=r.t_submit, t_admit=r.t_admit,
-                t_done=r.t_done, latency=r.t_done - r.t_submit)
+                footprint=r.footprint, t_submit=r.t_submit, t_ready=r.t_ready,
+                t_admit=r.t_admit, t_done=r.t_done, latency=r.t_done - r.t_submit)
 
 
 class Server:
