@@ -43,15 +43,41 @@ __device__ __forceinline__ double xlog(double x) { return log(x); }
 __device__ __forceinline__ float xlog(float x) { return __logf(x); }
 __device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float xsqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double xrcp(double x) { return 1.0 / x; }
+// FP64 reciprocal: the hardware estimate refined by two Newton steps
+// r <- r + r (1 - x r) (each squares the relative error; within an ulp or
+// two of 1/x), half the instructions of the IEEE division.  Where the
+// refinement is not finite (x = 0, +-inf, NaN, or 1/x beyond the range) the
+// hardware result, which has the IEEE special values there, is kept.
+__device__ __forceinline__ double xrcp(double x) {
+    const double r0 = __builtin_amdgcn_rcp(x);
+    double r = fma(r0, fma(-x, r0, 1.0), r0);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return __builtin_isfinite(r) ? r : r0;
+}
 __device__ __forceinline__ float xrcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double xpow15(double x) { return pow(x, 1.5); }
 __device__ __forceinline__ float xpow15(float x) { return x * sqrtf(x); }
-__device__ __forceinline__ double xdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ double xdiv(double a, double b) { return a * xrcp(b); }
 __device__ __forceinline__ float xdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // logistic 1 / (1 + e^z)
 template <typename R> __device__ __forceinline__ R sig(R z) { return xrcp(R(1) + xexp(z)); }
+
+// Logistic terms of one voltage scale k from a single exponential:
+// e^{(a - V)/k} = e^{a/k} e^{-V/k} and e^{(V - b)/k} = e^{-b/k} e^{V/k},
+// the constant factors folded at compile time, so every gate term with the
+// same k costs a multiply and a reciprocal instead of an exponential.
+template <typename R> struct Vscale {
+    R p, n;    // e^{V/k}, e^{-V/k}
+    __device__ __forceinline__ Vscale(R V, double k) : p(xexp(V * R(1.0 / k))), n(xrcp(p)) {}
+    // e^{(a - V)/k} and the logistic 1 / (1 + e^{(a - V)/k})
+    __device__ __forceinline__ R edown(double a, double k) const { return R(__builtin_exp(a / k)) * n; }
+    __device__ __forceinline__ R down(double a, double k) const { return xrcp(R(1) + edown(a, k)); }
+    // 1 / (1 + e^{(V - b)/k})
+    __device__ __forceinline__ R up(double b, double k) const {
+        return xrcp(R(1) + R(__builtin_exp(-b / k)) * p);
+    }
+};
 
 // Rush-Larsen with rate k = 1/tau
 template <typename R>
@@ -68,7 +94,7 @@ __device__ __forceinline__ double rl(double y, double yinf, double k, double dt)
 template <typename R>
 __device__ __forceinline__ R z_expm1(R z) {
     R e = xexpm1(z);
-    return (fabs(z) < R(1e-6)) ? R(1) - R(0.5) * z : z / e;
+    return (fabs(z) < R(1e-6)) ? R(1) - R(0.5) * z : xdiv(z, e);
 }
 
 // Free concentration under one rapid buffer (capacity B, constant K) that
@@ -77,10 +103,10 @@ __device__ __forceinline__ R z_expm1(R z) {
 __device__ __forceinline__ double buffered_free(double T, double B, double K) {
     const double b = B + K - T;
     const double q = sqrt(b * b + 4.0 * K * T);
-    return b >= 0.0 ? 2.0 * K * T / (q + b) : 0.5 * (q - b);
+    return b >= 0.0 ? xdiv(2.0 * K * T, q + b) : 0.5 * (q - b);
 }
 __device__ __forceinline__ double buffered_total(double c, double B, double K) {
-    return c * (1.0 + B / (c + K));
+    return c * (1.0 + xdiv(B, c + K));
 }
 
 // Rate of a non-gating state (concentrations; Stewart's Rbar) under the time
@@ -146,7 +172,7 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
     const R INa = R(gs.na) * R(14.838) * m * m * m * h * j * (V - ENa);
     const R xca = R(2) * (V - R(15)) * frt;
     const R emx = xexpm1(xca);
-    const R ghk = (fabs(xca) < R(1e-6)) ? R(1) - R(0.5) * xca : xca / emx;
+    const R ghk = (fabs(xca) < R(1e-6)) ? R(1) - R(0.5) * xca : xdiv(xca, emx);
     const R ICaL = R(gs.cal) * R(3.980e-5 * 2.0 * FARADAY) * d * f * f2 * fcass * ghk *
                    (R(0.25) * R(cass) * (emx + R(1)) - R(CAO));
     const R dK = V - EK;
@@ -156,17 +182,18 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
     const R aK1 = R(0.1) * sig(R(0.06) * (dK - R(200)));
     const R bK1 = (R(3) * xexp(R(0.0002) * (dK + R(100))) + xexp(R(0.1) * (dK - R(10)))) *
                   sig(R(-0.5) * dK);
-    const R IK1 = R(5.405 * SQRT_KO) * aK1 / (aK1 + bK1) * dK;
+    const R IK1 = R(5.405 * SQRT_KO) * xdiv(aK1, aK1 + bK1) * dK;
     const R ev = xexp(-V * frt);                  // e^{-VF/RT}
     const R eg = xexp(R(0.35) * V * frt);         // e^{gamma VF/RT}
     const R eg1 = eg * ev;                        // e^{(gamma-1)VF/RT}
     const R nai3 = R(nai) * R(nai) * R(nai);
     const R INaCa = R(1000.0 / ((87.5 * 87.5 * 87.5 + NAO * NAO * NAO) * (1.38 + CAO))) *
-                    (eg * nai3 * R(CAO) - eg1 * R(NAO * NAO * NAO * 2.5) * R(cai)) /
-                    (R(1) + R(0.1) * eg1);
-    const R INaK = R(2.724 * KO / (KO + 1.0)) * R(nai) / (R(nai) + R(40)) /
-                   (R(1) + R(0.1245) * xexp(R(-0.1) * V * frt) + R(0.0353) * ev);
-    const R IpCa = R(0.1238) * R(cai) / (R(0.0005) + R(cai));
+                    xdiv(eg * nai3 * R(CAO) - eg1 * R(NAO * NAO * NAO * 2.5) * R(cai),
+                         R(1) + R(0.1) * eg1);
+    const R INaK = R(2.724 * KO / (KO + 1.0)) *
+                   xdiv(R(nai), (R(nai) + R(40)) *
+                                    (R(1) + R(0.1245) * xexp(R(-0.1) * V * frt) + R(0.0353) * ev));
+    const R IpCa = R(0.1238) * xdiv(R(cai), R(0.0005) + R(cai));
     const R IpK = R(0.0146) * dK * sig((R(25) - V) * R(1.0 / 5.98));
     const R IbNa = R(0.00029) * (V - ENa);
     const R IbCa = R(0.000592) * (V - ECa);
@@ -174,12 +201,12 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
                    IbNa + IbCa;
 
     // ---- calcium handling at level n (FP64)
-    const double ec = 1.5 / casr;
-    const double kcasr = 2.5 - 1.5 / (1.0 + ec * ec);
-    const double k1 = 0.15 / kcasr, k2 = 0.045 * kcasr;
+    const double ec = xdiv(1.5, casr);
+    const double kcasr = 2.5 - xdiv(1.5, 1.0 + ec * ec);
+    const double k1 = xdiv(0.15, kcasr), k2 = 0.045 * kcasr;
     const double cass2 = cass * cass;
-    const double Irel = 0.102 * (k1 * cass2 * double(rbar) / (0.060 + k1 * cass2)) * (casr - cass);
-    const double Iup = 0.006375 / (1.0 + (0.00025 * 0.00025) / (cai * cai));
+    const double Irel = 0.102 * xdiv(k1 * cass2 * double(rbar), 0.060 + k1 * cass2) * (casr - cass);
+    const double Iup = xdiv(0.006375, 1.0 + xdiv(0.00025 * 0.00025, cai * cai));
     const double Ileak = 0.00036 * (casr - cai);
     const double Ixfer = 0.0038 * (cass - cai);
     const double rCai = -double(IbCa + IpCa - R(2) * INaCa) * INV_2VCF +
@@ -198,16 +225,18 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
         cass_g = buffered_free(buffered_total(cass, 0.4, 0.00025) + 0.5 * dtd * rCass, 0.4, 0.00025);
         const double casr_g = buffered_free(buffered_total(casr, 10.0, 0.3) + 0.5 * dtd * rCasr,
                                             10.0, 0.3);
-        const double ecg = 1.5 / casr_g;
-        k2g = 0.045 * (2.5 - 1.5 / (1.0 + ecg * ecg));
+        const double ecg = xdiv(1.5, casr_g);
+        k2g = 0.045 * (2.5 - xdiv(1.5, 1.0 + ecg * ecg));
     }
     {
     const R V = Vg;
     const double cass = cass_g, k2 = k2g;
+    // the voltage scales shared by several gate terms
+    const Vscale<R> e5(V, 5.0), e6(V, 6.0), e7(V, 7.0), e10(V, 10.0), e20(V, 20.0);
     {   // m
         const R s1 = sig((R(-56.86) - V) * R(1.0 / 9.03));
-        const R am = sig((R(-60) - V) * R(0.2));
-        const R bm = R(0.1) * sig((V + R(35)) * R(0.2)) + R(0.1) * sig((V - R(50)) * R(0.005));
+        const R am = e5.down(-60.0, 5.0);
+        const R bm = R(0.1) * e5.up(-35.0, 5.0) + R(0.1) * sig((V - R(50)) * R(0.005));
         g[0] = rl(m, s1 * s1, xrcp(am * bm), dt);
     }
     {   // h, j share the steady state
@@ -217,7 +246,7 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
         if (V >= R(-40)) {
             kh = R(0.13 / 0.77) * (R(1) + xexp((V + R(10.66)) * R(-1.0 / 11.1)));
             kh = xrcp(kh);
-            kj = R(0.6) * xexp(R(0.057) * V) * sig(R(-0.1) * (V + R(32)));
+            kj = R(0.6) * xexp(R(0.057) * V) * e10.down(-32.0, 10.0);
         } else {
             kh = R(0.057) * xexp((V + R(80)) * R(-1.0 / 6.8)) + R(2.7) * xexp(R(0.079) * V) +
                  R(3.1e5) * xexp(R(0.3485) * V);
@@ -229,51 +258,52 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
         g[2] = rl(j, inf, kj, dt);
     }
     {   // xr1
-        const R a = R(450) * sig((R(-45) - V) * R(0.1));
+        const R a = R(450) * e10.down(-45.0, 10.0);
         const R b = R(6) * sig((V + R(30)) * R(1.0 / 11.5));
-        g[3] = rl(xr1, sig((R(-26) - V) * R(1.0 / 7.0)), xrcp(a * b), dt);
+        g[3] = rl(xr1, e7.down(-26.0, 7.0), xrcp(a * b), dt);
     }
     {   // xr2
-        const R a = R(3) * sig((R(-60) - V) * R(0.05));
-        const R b = R(1.12) * sig((V - R(60)) * R(0.05));
+        const R a = R(3) * e20.down(-60.0, 20.0);
+        const R b = R(1.12) * e20.up(60.0, 20.0);
         g[4] = rl(xr2, sig((V + R(88)) * R(1.0 / 24.0)), xrcp(a * b), dt);
     }
     {   // xs
-        const R a = R(1400) / xsqrt(R(1) + xexp((R(5) - V) * R(1.0 / 6.0)));
+        const R a = xdiv(R(1400), xsqrt(R(1) + e6.edown(5.0, 6.0)));
         const R b = sig((V - R(35)) * R(1.0 / 15.0));
         g[5] = rl(xs, sig((R(-5) - V) * R(1.0 / 14.0)), xrcp(a * b + R(80)), dt);
     }
     {   // r
         const R t = R(9.5) * xexp(-(V + R(40)) * (V + R(40)) * R(1.0 / 1800.0)) + R(0.8);
-        g[6] = rl(r, sig((R(20) - V) * R(1.0 / 6.0)), xrcp(t), dt);
+        g[6] = rl(r, e6.down(20.0, 6.0), xrcp(t), dt);
     }
     {   // s (endocardial cells have their own inactivation kinetics)
         R inf, t;
         if (endo) {
-            inf = sig((V + R(28)) * R(0.2));
+            inf = e5.up(-28.0, 5.0);
             t = R(1000) * xexp(-(V + R(67)) * (V + R(67)) * R(0.001)) + R(8);
         } else {
-            inf = sig((V + R(20)) * R(0.2));
+            inf = e5.up(-20.0, 5.0);
             t = R(85) * xexp(-(V + R(45)) * (V + R(45)) * R(1.0 / 320.0)) +
-                R(5) * sig((V - R(20)) * R(0.2)) + R(3);
+                R(5) * e5.up(20.0, 5.0) + R(3);
         }
         g[7] = rl(s, inf, xrcp(t), dt);
     }
     {   // d
         const R a = R(1.4) * sig((R(-35) - V) * R(1.0 / 13.0)) + R(0.25);
-        const R b = R(1.4) * sig((V + R(5)) * R(0.2));
-        const R cc = sig((R(50) - V) * R(0.05));
+        const R b = R(1.4) * e5.up(-5.0, 5.0);
+        const R cc = e20.down(50.0, 20.0);
         g[8] = rl(d, sig((R(-8) - V) * R(1.0 / 7.5)), xrcp(a * b + cc), dt);
     }
+    const R up30 = e10.up(-30.0, 10.0);      // shared by f and f2
     {   // f
         const R t = R(1102.5) * xexp(-(V + R(27)) * (V + R(27)) * R(1.0 / 225.0)) +
-                    R(200) * sig((R(13) - V) * R(0.1)) + R(180) * sig((V + R(30)) * R(0.1)) + R(20);
-        g[9] = rl(f, sig((V + R(20)) * R(1.0 / 7.0)), xrcp(t), dt);
+                    R(200) * e10.down(13.0, 10.0) + R(180) * up30 + R(20);
+        g[9] = rl(f, e7.up(-20.0, 7.0), xrcp(t), dt);
     }
     {   // f2 (time constant as printed in the 2006 article)
         const R t = R(562) * xexp(-(V + R(27)) * (V + R(27)) * R(1.0 / 240.0)) +
-                    R(31) * sig((R(25) - V) * R(0.1)) + R(80) * sig((V + R(30)) * R(0.1));
-        g[10] = rl(f2, R(0.67) * sig((V + R(35)) * R(1.0 / 7.0)) + R(0.33), xrcp(t), dt);
+                    R(31) * e10.down(25.0, 10.0) + R(80) * up30;
+        g[10] = rl(f2, R(0.67) * e7.up(-35.0, 7.0) + R(0.33), xrcp(t), dt);
     }
     {   // fCass, driven by Ca_SS^n
         const R q = R(cass * 400.0 * cass);     // (Ca_SS / 0.05)^2
@@ -514,7 +544,7 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     const R INa = R(gs.na) * R(130.5744) * m * m * m * h * j * (V - ENa);
     const R xca = R(2) * (V - R(15)) * frt;
     const R emx = xexpm1(xca);
-    const R ghk = (fabs(xca) < R(1e-6)) ? R(1) - R(0.5) * xca : xca / emx;
+    const R ghk = (fabs(xca) < R(1e-6)) ? R(1) - R(0.5) * xca : xdiv(xca, emx);
     const R ICaL = R(gs.cal) * R(3.980e-5 * 2.0 * FARADAY) * d * f * f2 * fcass * ghk *
                    (R(0.25) * R(cass) * (emx + R(1)) - R(CAO));
     const R Ito = R(0.08184) * r * s * dK;
@@ -532,20 +562,21 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
     const R eg1 = eg * ev;
     const R nai3 = R(nai) * R(nai) * R(nai);
     const R INaCa = R(1000.0 / ((87.5 * 87.5 * 87.5 + NAO * NAO * NAO) * (1.38 + CAO))) *
-                    (eg * nai3 * R(CAO) - eg1 * R(NAO * NAO * NAO * 2.5) * R(cai)) /
-                    (R(1) + R(0.1) * eg1);
-    const R INaK = R(2.724 * KO / (KO + 1.0)) * R(nai) / (R(nai) + R(40)) /
-                   (R(1) + R(0.1245) * xexp(R(-0.1) * V * frt) + R(0.0353) * ev);
-    const R IpCa = R(0.1238) * R(cai) / (R(0.0005) + R(cai));
+                    xdiv(eg * nai3 * R(CAO) - eg1 * R(NAO * NAO * NAO * 2.5) * R(cai),
+                         R(1) + R(0.1) * eg1);
+    const R INaK = R(2.724 * KO / (KO + 1.0)) *
+                   xdiv(R(nai), (R(nai) + R(40)) *
+                                    (R(1) + R(0.1245) * xexp(R(-0.1) * V * frt) + R(0.0353) * ev));
+    const R IpCa = R(0.1238) * xdiv(R(cai), R(0.0005) + R(cai));
     const R IpK = R(0.0146) * dK * sig((R(25) - V) * R(1.0 / 5.98));
     const R IbNa = R(0.00029) * (V - ENa);
     const R IbCa = R(0.000592) * (V - ECa);
     const R Iion = INa + IK1 + Ito + Isus + IKr + IKs + ICaL + INaCa + INaK + IpCa +
                    IpK + IbNa + IbCa + IfNa + IfK;
 
-    const double ec = 1.5 / casr;
-    const double kcasr = 2.5 - 1.5 / (1.0 + ec * ec);
-    const double k1 = 0.15 / kcasr, k2 = 0.045 * kcasr;
+    const double ec = xdiv(1.5, casr);
+    const double kcasr = 2.5 - xdiv(1.5, 1.0 + ec * ec);
+    const double k1 = xdiv(0.15, kcasr), k2 = 0.045 * kcasr;
     const double cass2 = cass * cass;
     const double Irel = 0.102 * (k1 * cass2 * rbar / (0.060 + k1 * cass2)) * (casr - cass);
     const double Iup = 0.006375 / (1.0 + (0.00025 * 0.00025) / (cai * cai));
