@@ -88,6 +88,9 @@ def lib():
         L.orc_add_purkinje_stimulus.argtypes = [C.c_void_p, C.c_int64, _ip, C.c_double,
                                                 C.c_double, C.c_double, C.c_double, C.c_int32]
         L.orc_set_time_scheme.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_medium_substeps.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_medium_substeps.argtypes = [C.c_void_p]
+        L.orc_medium_substeps.restype = C.c_int32
         L.orc_purkinje_n_sub.argtypes = [C.c_void_p]
         L.orc_purkinje_n_sub.restype = C.c_int32
         L.orc_get_purkinje_vm.argtypes = [C.c_void_p, _dp]
@@ -208,6 +211,8 @@ class Sim:
             L.orc_set_ionic_scale(self.h, _d(gs))
         if getattr(w, "time_scheme", 0):
             assert L.orc_set_time_scheme(self.h, int(w.time_scheme)) == 0
+        if getattr(w, "medium_substeps", None) is not None:
+            assert L.orc_set_medium_substeps(self.h, int(w.medium_substeps)) == 0
         bd = getattr(w, "bidomain", None)
         if bd is not None:
             assert L.orc_set_bidomain(self.h, bd.sigma_el, bd.sigma_et, bd.restart, bd.tol,
@@ -251,6 +256,10 @@ class Sim:
         out = np.empty(self.np)
         lib().orc_get_purkinje_activation(self.h, _d(out))
         return out
+
+    def medium_substeps(self) -> int:
+        """Substeps per step of the 2D medium (1: it steps with the tissue)."""
+        return lib().orc_medium_substeps(self.h)
 
     def purkinje_n_sub(self) -> int:
         return lib().orc_purkinje_n_sub(self.h)

@@ -111,6 +111,12 @@ int32_t orc_purkinje_n_sub(const orc_sim *s);
  * the interval of forward Euler, so a derived substep count uses half the
  * graph bound.  Call before stepping; returns -1 for an unknown scheme. */
 int orc_set_time_scheme(orc_sim *s, int scheme);
+/* Per-medium time step: the 2D medium (triangles) takes n_sub substeps of
+ * dt / n_sub per step; n_sub <= 0 derives the count from the medium's
+ * forward-Euler bound (90 %, 45 % with Adams-Bashforth 2).  Before the first
+ * step only; set the time scheme first.  -1 after the first step. */
+int orc_set_medium_substeps(orc_sim *s, int32_t n_sub);
+int32_t orc_medium_substeps(const orc_sim *s);
 void orc_get_purkinje_vm(const orc_sim *s, double *out);
 void orc_get_purkinje_activation(const orc_sim *s, double *out);
 /* Junction whose source is a cell (the coupling of the 2D Purkinje shell

@@ -84,6 +84,9 @@ struct orc_sim {
     double *pt_act;
     orc_stim *pstims;
     int n_pstims;
+    /* per-medium time step: the 2D medium (triangles) takes n_sub2
+     * substeps of dt / n_sub2 per tissue step (1: none) */
+    int32_t n_sub2;
     /* junctions */
     int n_pmj;
     struct orc_pmj *pmj;
@@ -516,6 +519,7 @@ orc_sim *orc_create(int64_t n_nodes, const double *xyz, int64_t n_tets,
 {
     orc_sim *s = calloc(1, sizeof(orc_sim));
     s->nn = n_nodes; s->nc = n_tets;
+    s->n_sub2 = 1;
     s->xyz = malloc(sizeof(double) * (size_t)n_nodes * 3);
     memcpy(s->xyz, xyz, sizeof(double) * (size_t)n_nodes * 3);
     s->tet = malloc(sizeof(int32_t) * (size_t)n_tets * 4);
@@ -1032,6 +1036,105 @@ int64_t orc_gmres(orc_sim *s, const double *b, double *x, double sl, double st, 
 }
 
 /* ---------------------------------------------------------- time step -- */
+/* Activation time (first upward crossing of the threshold) and APD90 of
+ * cell c over one update vold -> vnew that starts at time t0 * h and lasts h:
+ * the crossing instants are interpolated linearly inside the update. */
+static void detect(orc_sim *s, int64_t c, double vold, double vnew, double t0, double h)
+{
+    if (s->status[c] == 0) {
+        if (vold <= s->thr && vnew > s->thr) {
+            s->t_act[c] = (t0 + (s->thr - vold) / (vnew - vold)) * h;
+            s->v_max[c] = vnew;
+            s->status[c] = 1;
+        }
+    } else if (s->status[c] == 1) {
+        if (vnew > s->v_max[c]) s->v_max[c] = vnew;
+        const double v90 = s->v_max[c] - s->repol * (s->v_max[c] - s->v_rest[c]);
+        if (vold >= v90 && vnew < v90) {
+            s->t_rep[c] = (t0 + (vold - v90) / (vold - vnew)) * h;
+            s->status[c] = 2;
+        }
+    }
+}
+
+/* The 2D medium over tissue step n with a time step of its own (the paper
+ * integrates its Purkinje shell of triangles at a far smaller step than the
+ * myocardium, Sec. 4): n_sub2 explicit substeps of dt / n_sub2, each the
+ * whole monodomain update of the triangles (node values, gradients, face
+ * fluxes, cell model, v, detection) from the substep's own potentials.  The
+ * stimulus currents are those of step n throughout.  Nodes belong to one
+ * medium, so the node values of triangles depend on triangles only. */
+static void medium2_substeps(orc_sim *s, int64_t n)
+{
+    const int64_t nc = s->nc;
+    const int32_t m = s->n_sub2;
+    const double h = s->dt / m;
+    double *u = malloc(sizeof(double) * (size_t)nc);
+    for (int32_t q = 0; q < m; ++q) {
+        for (int64_t c = 0; c < nc; ++c) u[c] = s->y[c * ORC_MAX_SLOTS];
+        orc_node_values(s, u, s->vn);
+        gradients_from_nodes(s, s->vn, s->g);
+        const int first = n == 0 && q == 0;
+#pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < nc; ++c) {
+            if (nverts(s, c) != 3) continue;
+            double *y = s->y + c * ORC_MAX_SLOTS;
+            const double L = cell_flux_sum(s, c, u, s->g);
+            double *hc = s->ab2 ? s->hist + c * ORC_HIST_SLOTS : NULL;
+            orc_hist hh = {hc ? hc + 1 : NULL, first};
+            const orc_mid mid = {L - s->istim[c]};
+            const double iion = model_step(s->model[c], y, h, s->istim[c], s->gscale,
+                                           hc ? &hh : NULL, s->rl2 ? &mid : NULL);
+            const double vnew = u[c] + h * v_rate(s, hc, first, L - iion - s->istim[c]);
+            y[0] = vnew;
+            detect(s, c, u[c], vnew, (double)(n * m + q), h);
+        }
+    }
+    free(u);
+}
+
+/* Forward-Euler bound of the 2D medium's operator from its two-point part:
+ * cell c couples to each edge neighbour with sigma_max |S_f| / (d_f chi Cm
+ * V_c) (sigma_max the larger conductivity times the cell's scale, |S_f| the
+ * edge length, d_f the centroid distance), so by Gershgorin the spectrum
+ * lies in [-2 r_c, 0] with r_c the sum of these couplings and explicit
+ * steps up to 1 / max_c r_c are stable. */
+static double medium2_dtmax(const orc_sim *s)
+{
+    double rmax = 0.0;
+    const double smax = s->sigma_l > s->sigma_t ? s->sigma_l : s->sigma_t;
+    for (int64_t c = 0; c < s->nc; ++c) {
+        if (nverts(s, c) != 3) continue;
+        double r = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const int32_t k = s->nbr[4 * c + j];
+            if (k < 0) continue;
+            double d[3];
+            sub3(s->cen + 3 * (int64_t)k, s->cen + 3 * c, d);
+            r += norm3(s->S + (c * 4 + j) * 3) / norm3(d);
+        }
+        r *= smax * (s->scale ? s->scale[c] : 1.0) / (s->chi * s->cm * s->vol[c]);
+        if (r > rmax) rmax = r;
+    }
+    return rmax > 0.0 ? 1.0 / rmax : HUGE_VAL;
+}
+
+int orc_set_medium_substeps(orc_sim *s, int32_t n_sub)
+{
+    if (s->step != 0) return -1;
+    if (n_sub > 0) {
+        s->n_sub2 = n_sub;
+        return 0;
+    }
+    const double lim = (s->ab2 ? 0.45 : 0.9) * medium2_dtmax(s);
+    int32_t k = 1;
+    while (s->dt / k > lim) ++k;
+    s->n_sub2 = k;
+    return 0;
+}
+
+int32_t orc_medium_substeps(const orc_sim *s) { return s->n_sub2; }
+
 static void one_step(orc_sim *s)
 {
     const int64_t nc = s->nc, n = s->step;
@@ -1074,9 +1177,11 @@ static void one_step(orc_sim *s)
         for (int64_t c = 0; c < nc; ++c) s->L[c] = cell_flux_sum(s, c, v, s->g);
     }
 
-    /* cells: ionic update, v update, detection */
+    /* cells: ionic update, v update, detection (with a time step of its
+     * own the 2D medium follows below) */
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < nc; ++c) {
+        if (s->n_sub2 > 1 && nverts(s, c) == 3) continue;
         double *y = s->y + c * ORC_MAX_SLOTS;
         const double vold = v[c];
         double *hc = s->ab2 ? s->hist + c * ORC_HIST_SLOTS : NULL;
@@ -1086,22 +1191,9 @@ static void one_step(orc_sim *s)
                                        hc ? &h : NULL, s->rl2 ? &mid : NULL);
         const double vnew = vold + dt * v_rate(s, hc, n == 0, s->L[c] - iion - s->istim[c]);
         y[0] = vnew;
-        /* activation: first upward crossing of the threshold */
-        if (s->status[c] == 0) {
-            if (vold <= s->thr && vnew > s->thr) {
-                s->t_act[c] = ((double)n + (s->thr - vold) / (vnew - vold)) * dt;
-                s->v_max[c] = vnew;
-                s->status[c] = 1;
-            }
-        } else if (s->status[c] == 1) {
-            if (vnew > s->v_max[c]) s->v_max[c] = vnew;
-            const double v90 = s->v_max[c] - s->repol * (s->v_max[c] - s->v_rest[c]);
-            if (vold >= v90 && vnew < v90) {
-                s->t_rep[c] = ((double)n + (vold - v90) / (vold - vnew)) * dt;
-                s->status[c] = 2;
-            }
-        }
+        detect(s, c, vold, vnew, (double)n, dt);
     }
+    if (s->n_sub2 > 1) medium2_substeps(s, n);
     if (s->np > 0) purkinje_step(s, v);
     for (int k = 0; k < s->n_pmj; ++k) {
         struct orc_pmj *J = &s->pmj[k];

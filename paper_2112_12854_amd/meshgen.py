@@ -88,6 +88,7 @@ class Workload:
     landmarks: dict = field(default_factory=dict)   # name -> [3] point (mm)
     time_scheme: int = 0               # 0 forward Euler, 1 AB2, 2 AB2 + second-order RL
     cell_junctions: list = field(default_factory=list)   # CellJunction, after the graph's
+    medium_substeps: int | None = None  # 2D medium: substeps per step (0: from its bound)
 
     @property
     def n_tets(self) -> int:
@@ -130,6 +131,8 @@ def workload_sha256(w: Workload) -> str:
         arr(st.ids, np.int32)
         arr([st.t0, st.dur, st.amp, st.period, st.count, st.domain], np.float64)
     arr([w.sigma_l, w.sigma_t, w.dt, w.n_steps, w.chi, w.cm, w.time_scheme], np.float64)
+    if getattr(w, "medium_substeps", None) is not None:
+        arr([w.medium_substeps], np.float64)
     arr([w.ionic_scale.get(k, 1.0) for k in ("GKr", "GKs", "GCaL", "GNa")], np.float64)
     return hs.hexdigest()
 

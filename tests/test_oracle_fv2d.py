@@ -274,3 +274,131 @@ def test_cell_junction_two_way(oracle_lib):
     s1 = oracle_lib.Sim(M.shell_on_slab(drive="slab", two_way=False))
     s1.step(750)
     assert np.isnan(s1.activation()[N3:]).all()
+
+
+# ------------------------------------- the 2D medium's own time step
+def _fine(w, m):
+    """The same workload stepping at dt / m (as m substeps would)."""
+    import copy
+    f = copy.copy(w)
+    f.dt = w.dt / m
+    f.medium_substeps = None
+    return f
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_medium_substeps_equal_a_sheet_at_the_small_step(oracle_lib, scheme):
+    """A sheet with n_sub substeps per step of dt is the sheet stepped at
+    dt / n_sub (Sec. 4: the shell runs at its own, smaller time step): the
+    same potentials, activation times and APD90 bit for bit, with forward
+    Euler, Adams-Bashforth 2 and the second-order Rush-Larsen variant."""
+    m = 5
+    w = M.sheet_workload(24, 6, 0.5, model=M.STEWART, dt=0.02)
+    w.time_scheme = scheme
+    w.medium_substeps = m
+    a = oracle_lib.Sim(w)
+    assert a.medium_substeps() == m
+    b = oracle_lib.Sim(_fine(w, m))
+    a.step(1300)
+    b.step(1300 * m)
+    assert np.array_equal(a.vm(), b.vm())
+    assert np.array_equal(a.activation(), b.activation(), equal_nan=True)
+    assert np.array_equal(a.apd90(), b.apd90(), equal_nan=True)
+    assert np.isfinite(a.activation()).mean() > 0.9
+
+
+def test_medium_substeps_leave_the_3d_medium_alone(oracle_lib):
+    """In a mesh of tets and a separate sheet, substepping the sheet changes
+    nothing in the tets (which step at dt) and makes the sheet evolve as it
+    does alone at dt / n_sub."""
+    m = 4
+    w3 = M.config1(n_steps=0, nx=8, ny=6, nz=2)
+    w2 = M.sheet_workload(12, 6, 0.5, model=M.CRN, n_steps=0)
+    mix = M.mixed_workload(w3, w2)
+    mix.medium_substeps = m
+    a, b, c = oracle_lib.Sim(mix), oracle_lib.Sim(w3), oracle_lib.Sim(_fine(w2, m))
+    a.step(400)
+    b.step(400)
+    c.step(400 * m)
+    v = a.vm()
+    assert np.array_equal(v[:w3.n_tets], b.vm())
+    assert np.array_equal(v[w3.n_tets:], c.vm())
+    at = a.activation()
+    assert np.array_equal(at[w3.n_tets:], c.activation(), equal_nan=True)
+    assert np.isfinite(at[w3.n_tets:]).any() and np.isfinite(at[:w3.n_tets]).any()
+
+
+def _operator_matrix(s, n):
+    A = np.empty((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        A[:, j] = s.apply_diffusion(e)
+    return A
+
+
+@pytest.mark.parametrize("angle", [0.0, 30.0])
+def test_derived_substeps_make_the_step_stable(oracle_lib, angle):
+    """With n_sub <= 0 the count comes from the medium's own forward-Euler
+    bound: on a fine, highly conducting sheet the step dt alone is unstable
+    (some eigenvalue of the assembled operator has |1 + dt lambda| > 1), the
+    derived substep dt / n_sub is stable for every eigenvalue, and the count
+    is the smallest within 90 % of the bound computed here from the
+    geometry (edge lengths, centroid distances, areas)."""
+    w = passive_sheet(8, 6, 0.1, angle=angle, scale=np.full(96, 4.0))
+    w.medium_substeps = 0
+    s = oracle_lib.Sim(w)
+    m = s.medium_substeps()
+    lam = np.linalg.eigvals(_operator_matrix(s, w.n_tets))
+    assert np.abs(1 + w.dt * lam).max() > 1.0
+    assert np.abs(1 + (w.dt / m) * lam).max() <= 1.0 + 1e-12
+    # the bound from the geometry
+    T = w.tets[:, :3]
+    P = w.xyz[T]
+    cen = P.mean(axis=1)
+    area = 0.5 * np.linalg.norm(np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), axis=1)
+    owner = {}
+    for c in range(w.n_tets):
+        for j in range(3):
+            owner.setdefault(frozenset((T[c, (j + 1) % 3], T[c, (j + 2) % 3])), []).append(c)
+    r = np.zeros(w.n_tets)
+    for c in range(w.n_tets):
+        for j in range(3):
+            a, b = T[c, (j + 1) % 3], T[c, (j + 2) % 3]
+            other = [k for k in owner[frozenset((a, b))] if k != c]
+            if not other:
+                continue
+            edge = np.linalg.norm(w.xyz[b] - w.xyz[a])
+            r[c] += edge / np.linalg.norm(cen[other[0]] - cen[c])
+    r *= max(w.sigma_l, w.sigma_t) * 4.0 / (CHI * CM * area)
+    dtmax = 1.0 / r.max()
+    expect = 1
+    while w.dt / expect > 0.9 * dtmax:
+        expect += 1
+    assert m == expect and m > 1
+    # and the bound is one: every eigenvalue lies in [-2 max r, 0] (real part)
+    assert lam.real.min() >= -2 * r.max() * (1 + 1e-9)
+
+
+def test_passive_mode_decays_at_the_substep_rate(oracle_lib):
+    """A passive sheet started on an eigenvector phi of its operator
+    (eigenvalue lambda < 0) is (1 + h lambda)^k phi after k substeps of
+    h = dt / n_sub: the substep count and size, checked on the potential."""
+    m = 3
+    w = passive_sheet(8, 4, 0.5)
+    s0 = oracle_lib.Sim(w)
+    A = _operator_matrix(s0, w.n_tets)
+    lam, vec = np.linalg.eig(A)
+    real = np.abs(lam.imag) < 1e-12
+    i = np.argmin(np.where(real, lam.real, 0.0))
+    phi, l = vec[:, i].real, lam[i].real
+    assert l < 0
+    w.medium_substeps = m
+    s = oracle_lib.Sim(w)
+    st = s.states()
+    st[0] = phi
+    s.set_states(st)
+    n = 7
+    s.step(n)
+    expect = (1 + (w.dt / m) * l) ** (n * m) * phi
+    assert np.abs(s.vm() - expect).max() < 1e-10 * np.abs(phi).max()
