@@ -231,6 +231,27 @@ ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme);
 typedef enum { EP_ORDER_RCM = 0, EP_ORDER_MORTON = 1, EP_ORDER_INPUT = 2 } ep_cell_order;
 ep_status ep_set_cell_order(ep_sim *s, int32_t order);
 
+/* The 2D medium (the triangles, e.g. the Purkinje shell) at a time step of
+ * its own, as the paper integrates its Purkinje networks at a step far
+ * below the myocardium's (Sec. 4): each step of dt, its cells take n_sub
+ * explicit substeps of dt / n_sub, each the whole monodomain update of the
+ * medium (node values, face fluxes, cell model, v, activation / APD90
+ * interpolated inside the substep); stimuli and junction pulses of the step
+ * hold through its substeps, junction events see the medium's v^n and
+ * v^{n+1}.  n_sub = 1: the medium steps with the rest (the default);
+ * n_sub > 1: given; n_sub <= 0: the smallest count within 90 % (45 % with
+ * Adams-Bashforth 2) of the medium's forward-Euler bound 1 / max_c r_c,
+ * r_c = sum over its edges of sigma_max scale_c |S_f| / (d_f chi Cm V_c)
+ * (sigma_max the larger conductivity, |S_f| the edge length, d_f the
+ * distance of the triangle centroids).  The tets always step at dt.  Before
+ * ep_init; set the time scheme first.  EP_EINVAL with the bidomain model
+ * (at ep_init) or above 2^20 substeps.  The medium's cells take the last
+ * internal indices (their own tiles, stepped beside the tets on a second
+ * stream). */
+ep_status ep_set_medium_substeps(ep_sim *s, int32_t n_sub);
+/* Substeps per step of the 2D medium after ep_init (1: none). */
+ep_status ep_get_medium_substeps(ep_sim *s, int32_t *n_sub);
+
 /* Bidomain model (Sec. 3.1 eq. electro, Sec. 3.2 eq. electro2_3d) instead of
  * the monodomain one: the conductivities of ep_set_conductivity become the
  * intracellular ones M_i; sigma_el / sigma_et (mS/mm) give the extracellular
@@ -446,6 +467,9 @@ typedef struct {
     int32_t n_cell_junctions;     /* junctions with a source cell, after the
                                      graph's (as ep_add_cell_junction)       */
     const ep_cell_junction *cell_junctions;
+    int32_t medium_substeps;      /* the 2D medium's substeps per step (as
+                                     ep_set_medium_substeps): 0 or 1 none,
+                                     > 1 given, < 0 from its bound           */
 } ep_request;
 
 typedef struct {

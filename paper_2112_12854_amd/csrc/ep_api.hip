@@ -275,6 +275,21 @@ ep_status ep_set_time_scheme(ep_sim *s, int32_t scheme) {
     return EP_OK;
 }
 
+ep_status ep_set_medium_substeps(ep_sim *s, int32_t n_sub) {
+    if (!s) return EP_EINVAL;
+    if (s->inited) return fail(s, EP_ESTATE, "the substeps are frozen after ep_init");
+    if (n_sub > (1 << 20)) return fail(s, EP_EINVAL, "more than 2^20 substeps");
+    s->spec.medium_substeps = n_sub;
+    return EP_OK;
+}
+
+ep_status ep_get_medium_substeps(ep_sim *s, int32_t *n_sub) {
+    if (!s || !n_sub) return EP_EINVAL;
+    if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
+    *n_sub = s->inst.c2 < s->inst.desc.nc ? s->inst.sub2 : 1;
+    return EP_OK;
+}
+
 ep_status ep_set_cell_order(ep_sim *s, int32_t order) {
     if (!s) return EP_EINVAL;
     if (s->inited) return fail(s, EP_ESTATE, "the cell order is frozen after ep_init");
@@ -649,6 +664,7 @@ static uint64_t layout_hash(const ep_sim *s) {
     };
     mix(s->inst.prep.perm.data(), s->inst.prep.perm.size() * sizeof(int32_t));
     mix(s->inst.prep.model.data(), s->inst.prep.model.size());
+    mix(&s->inst.sub2, sizeof(s->inst.sub2));
     return h;
 }
 

@@ -240,8 +240,23 @@ std::string prep_instance(const InstSpec &sp, Inst &I, ep_status &st) {
     in.elliptic = sp.bido;
     in.sigma_el = sp.sigma_el;
     in.sigma_et = sp.sigma_et;
+    in.split_media = sp.medium_substeps != 1;
     std::string e = prepare(in, I.prep);
     if (!e.empty()) { st = EP_EINVAL; return e; }
+    I.c2 = I.prep.cell_2d;
+    I.n2 = I.prep.node_2d;
+    I.sub2 = 1;
+    if (I.c2 < I.prep.n_tets) {
+        if (sp.bido) { st = EP_EINVAL; return "a 2D medium with substeps is not available with the bidomain model"; }
+        if (sp.medium_substeps > 1) {
+            I.sub2 = sp.medium_substeps;
+        } else {
+            const double lim = (sp.scheme >= 1 ? 0.45 : 0.9) * I.prep.dtmax_2d;
+            int32_t k = 1;
+            while (sp.dt / k > lim && k < (1 << 20)) ++k;
+            I.sub2 = k;
+        }
+    }
     // 16-bit stencil ids when every block allows them (the elliptic operator
     // of the bidomain model reads the 32-bit ones)
     I.idx16 = !sp.bido && block_bases(I.prep.cnode, 8, I.prep.n_tets, nullptr) &&
@@ -324,6 +339,7 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
         b += round256(c * r) + round256(tiled_len(c, NC_MAX) * 8);
         if (I.pk.n > 0) b += round256((size_t)I.pk.n * r) + round256(tiled_len(I.pk.n, NC_MAX) * 8);
     }
+    if (I.c2 < P.n_tets) b += 2 * round256((size_t)(P.n_tets - I.c2) * r);   // substep potentials
     return b + purkinje_bytes(I, rs);
 }
 
@@ -445,18 +461,23 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     for (uint8_t m : P.model) present |= m <= 2 ? 1 : (m == 3 ? 2 : (m == 4 ? 4 : 8));
     I.mset = present;
     // class ranges (the host groups cells by class: TP06, CRN, Stewart, passive)
-    {
+    {   // per medium: [0, c2) and the 2D medium with substeps [c2, nc)
         auto cls = [](uint8_t m) { return m <= 2 ? 0 : (m == 3 ? 1 : (m == 4 ? 2 : 3)); };
-        for (int k = 0; k < 4; ++k) I.cls_begin[k] = I.cls_end[k] = 0;
         int64_t i = 0;
         for (int k = 0; k < 4; ++k) {
             I.cls_begin[k] = i;
-            while (i < nc && cls(P.model[i]) == k) ++i;
+            while (i < I.c2 && cls(P.model[i]) == k) ++i;
             I.cls_end[k] = i;
         }
-        if (i != nc) {
+        const int64_t i1 = i;
+        for (int k = 0; k < 4; ++k) {
+            I.cls2_begin[k] = i;
+            while (i < nc && cls(P.model[i]) == k) ++i;
+            I.cls2_end[k] = i;
+        }
+        if (i1 != I.c2 || i != nc) {
             st = EP_EINVAL;
-            return "cells are not grouped by model class";
+            return "cells are not grouped by medium and model class";
         }
     }
 
@@ -526,7 +547,15 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     // per cell tile (tiles do not straddle model classes)
     D.n_cell_tiles = 0;
     for (int k = 0; k < 4; ++k)
-        D.n_cell_tiles += (int32_t)((I.cls_end[k] - I.cls_begin[k] + TILE - 1) / TILE);
+        D.n_cell_tiles += (int32_t)((I.cls_end[k] - I.cls_begin[k] + TILE - 1) / TILE) +
+                          (int32_t)((I.cls2_end[k] - I.cls2_begin[k] + TILE - 1) / TILE);
+    if (I.c2 < nc) {   // potentials between substeps, indexed by internal cell
+        char *w0 = (char *)dalloc(I, (size_t)(nc - I.c2) * rs);
+        char *w1 = (char *)dalloc(I, (size_t)(nc - I.c2) * rs);
+        if (!w0 || !w1) return fail_mem();
+        D.w[0] = w0 - (size_t)I.c2 * rs;
+        D.w[1] = w1 - (size_t)I.c2 * rs;
+    }
     I.trace_cap = 4096;
     if (sp.trace_every > 0 && sp.target != INT64_MAX)
         I.trace_cap = std::max<int64_t>(2, sp.target / sp.trace_every + 2);
@@ -662,19 +691,21 @@ Tables tables(const Stepper &s) {
 
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
-// Cell kernels of step offset `off`, one launch per model class present.
+// Cell kernels of step offset `off`, one launch per model class present:
+// the step's tiles (sub < 0) or substep `sub` of the 2D media with
+// substeps, on stream `st`.
 template <typename R, bool BIDO, int SCH>
-void launch_cells_v(Stepper &s, const Tables &tb, int32_t off) {
+void launch_cells_v(Stepper &s, const Tables &tb, int32_t off, int32_t sub = -1,
+                    hipStream_t st = nullptr) {
+    if (!st) st = s.stream;
+    const int64_t *base = sub < 0 ? s.cls_base : s.cls2_base;
+    const int64_t *cnt = sub < 0 ? s.cls_tiles : s.cls2_tiles;
     Tables t[4] = {tb, tb, tb, tb};
-    for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + s.cls_base[k];
-    if (s.cls_tiles[0])
-        k_cell<R, 1, BIDO, SCH><<<(int)s.cls_tiles[0], TILE, 0, s.stream>>>(t[0], off, s.remap);
-    if (s.cls_tiles[1])
-        k_cell<R, 2, BIDO, SCH><<<(int)s.cls_tiles[1], TILE, 0, s.stream>>>(t[1], off, s.remap);
-    if (s.cls_tiles[2])
-        k_cell<R, 4, BIDO, SCH><<<(int)s.cls_tiles[2], TILE, 0, s.stream>>>(t[2], off, s.remap);
-    if (s.cls_tiles[3])
-        k_cell<R, 8, BIDO, SCH><<<(int)s.cls_tiles[3], TILE, 0, s.stream>>>(t[3], off, s.remap);
+    for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + base[k];
+    if (cnt[0]) k_cell<R, 1, BIDO, SCH><<<(int)cnt[0], TILE, 0, st>>>(t[0], off, s.remap, sub);
+    if (cnt[1]) k_cell<R, 2, BIDO, SCH><<<(int)cnt[1], TILE, 0, st>>>(t[1], off, s.remap, sub);
+    if (cnt[2]) k_cell<R, 4, BIDO, SCH><<<(int)cnt[2], TILE, 0, st>>>(t[2], off, s.remap, sub);
+    if (cnt[3]) k_cell<R, 8, BIDO, SCH><<<(int)cnt[3], TILE, 0, st>>>(t[3], off, s.remap, sub);
 }
 
 // bidomain instances run in FP64 with forward Euler only (checked at
@@ -691,17 +722,29 @@ void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
 
 template <typename R>
 void launch_gather(Stepper &s, const Tables &tb, int32_t off) {
+    if (s.n_nt == 0) return;
     if constexpr (sizeof(R) == 8) {
-        if (s.bido) { k_node_gather<R, true><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap); return; }
+        if (s.bido) { k_node_gather<R, true><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap, -1); return; }
     }
-    k_node_gather<R, false><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap);
+    k_node_gather<R, false><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap, -1);
 }
 
+// The substeps of step offset `off` of the 2D media that have them, on
+// stream `st`: per substep their node values, then their cells.  They read
+// and write only those media (and v^n of their cells), so they may run
+// beside the other kernels of the step.
 template <typename R>
-void launch_step(Stepper &s, int32_t off) {
-    const Tables tb = tables(s);
-    launch_gather<R>(s, tb, off);
-    launch_cells<R>(s, tb, off);
+void launch_medium2(Stepper &s, int32_t off, hipStream_t st) {
+    if (s.sub2_max <= 0 || s.n_nt2 == 0) return;
+    Tables tb = tables(s);
+    Tables tn = tb;
+    tn.node_tiles = tb.node_tiles + s.nt2_base;
+    for (int32_t q = 0; q < s.sub2_max; ++q) {
+        k_node_gather<R, false><<<(int)s.n_nt2, TILE, 0, st>>>(tn, off, s.remap, q);
+        if (s.scheme == 2) launch_cells_v<R, false, 2>(s, tb, off, q, st);
+        else if (s.scheme == 1) launch_cells_v<R, false, 1>(s, tb, off, q, st);
+        else launch_cells_v<R, false, 0>(s, tb, off, q, st);
+    }
 }
 
 // Graph substeps of step offset `off` on stream `st`.  They read the graph,
@@ -726,18 +769,31 @@ void launch_junctions(Stepper &s, int32_t off) {
 
 std::string enqueue(Stepper &s, int64_t k) {
     hipError_t e = hipSuccess;
+    const Tables tb = tables(s);
     for (int64_t i = 0; i < k && e == hipSuccess; ++i) {
-        // (no graph tiles when every junction has a source cell)
-        const bool fork = s.n_pk > 0 && s.n_pt > 0 && s.n_sub_max > 0;
+        // graph substeps (none when every junction has a source cell) and 2D
+        // media with substeps go to the side stream after the node gather (its
+        // tile 0 may reduce the vbar partials the substeps write)
+        const bool graph = s.n_pk > 0 && s.n_pt > 0 && s.n_sub_max > 0;
+        const bool med2 = s.sub2_max > 0 && s.n_nt2 > 0;
+        const bool fork = graph || med2;
+        if (s.rs == 8) launch_gather<double>(s, tb, (int32_t)i);
+        else launch_gather<float>(s, tb, (int32_t)i);
         if (fork) {
             if ((e = hipEventRecord(s.ev_fork, s.stream)) != hipSuccess ||
                 (e = hipStreamWaitEvent(s.side, s.ev_fork, 0)) != hipSuccess)
                 break;
-            if (s.rs == 8) launch_substeps<double>(s, (int32_t)i, s.side);
-            else launch_substeps<float>(s, (int32_t)i, s.side);
+            if (med2) {
+                if (s.rs == 8) launch_medium2<double>(s, (int32_t)i, s.side);
+                else launch_medium2<float>(s, (int32_t)i, s.side);
+            }
+            if (graph) {
+                if (s.rs == 8) launch_substeps<double>(s, (int32_t)i, s.side);
+                else launch_substeps<float>(s, (int32_t)i, s.side);
+            }
         }
-        if (s.rs == 8) launch_step<double>(s, (int32_t)i);
-        else launch_step<float>(s, (int32_t)i);
+        if (s.rs == 8) launch_cells<double>(s, tb, (int32_t)i);
+        else launch_cells<float>(s, tb, (int32_t)i);
         if (fork && ((e = hipEventRecord(s.ev_join, s.side)) != hipSuccess ||
                      (e = hipStreamWaitEvent(s.stream, s.ev_join, 0)) != hipSuccess))
             break;
@@ -806,7 +862,8 @@ std::string stepper_sync_tables(Stepper &s) {
         s.bido = s.bido || I->bido;
         s.scheme = std::max(s.scheme, I->scheme);
     }
-    // cell tiles class by class; tile `local` numbers run over the instance
+    // cell tiles class by class, those of 2D media with substeps after the
+    // others; tile `local` numbers run over the instance
     std::vector<int32_t> next_local(s.insts.size(), 0);
     for (int k = 0; k < 4; ++k) {
         s.cls_base[k] = (int64_t)ct.size();
@@ -814,9 +871,20 @@ std::string stepper_sync_tables(Stepper &s) {
             const Inst &I = *s.insts[i];
             for (int64_t b = I.cls_begin[k]; b < I.cls_end[k]; b += TILE)
                 ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.cls_end[k] - b),
-                                  next_local[i]++});
+                                  next_local[i]++, 1, 0});
         }
         s.cls_tiles[k] = (int64_t)ct.size() - s.cls_base[k];
+    }
+    s.sub2_max = 0;
+    for (int k = 0; k < 4; ++k) {
+        s.cls2_base[k] = (int64_t)ct.size();
+        for (size_t i = 0; i < s.insts.size(); ++i) {
+            const Inst &I = *s.insts[i];
+            for (int64_t b = I.cls2_begin[k]; b < I.cls2_end[k]; b += TILE)
+                ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.cls2_end[k] - b),
+                                  next_local[i]++, I.sub2, 0});
+        }
+        s.cls2_tiles[k] = (int64_t)ct.size() - s.cls2_base[k];
     }
     for (size_t i = 0; i < s.insts.size(); ++i) {
         const Inst &I = *s.insts[i];
@@ -827,8 +895,22 @@ std::string stepper_sync_tables(Stepper &s) {
             for (int64_t b = 0, t = 0; b < I.pdesc.np; b += TILE, ++t)
                 pt.push_back(PTile{I.pdesc, b, (int32_t)std::min<int64_t>(TILE, I.pdesc.np - b), (int32_t)t});
         }
-        for (int64_t b = 0, t = 0; b < I.desc.nn; b += TILE, ++t)
-            nt.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nn - b), (int32_t)t});
+    }
+    // node tiles: the step's, then those of 2D media with substeps; local
+    // numbers run over the instance (tile 0 reduces the vbar trace)
+    std::vector<int32_t> next_node(s.insts.size(), 0);
+    for (size_t i = 0; i < s.insts.size(); ++i) {
+        const Inst &I = *s.insts[i];
+        for (int64_t b = 0; b < I.n2; b += TILE)
+            nt.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.n2 - b), next_node[i]++, 1, 0});
+    }
+    s.nt2_base = (int64_t)nt.size();
+    for (size_t i = 0; i < s.insts.size(); ++i) {
+        const Inst &I = *s.insts[i];
+        if (I.c2 < I.desc.nc) s.sub2_max = std::max(s.sub2_max, I.sub2);
+        for (int64_t b = I.n2; b < I.desc.nn; b += TILE)
+            nt.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.desc.nn - b), next_node[i]++,
+                              I.sub2, 0});
     }
     // grow device tables geometrically; growth invalidates the graph
     auto grow = [&](void **p, size_t &cap, size_t need, size_t elem) -> hipError_t {
@@ -888,7 +970,8 @@ std::string stepper_sync_tables(Stepper &s) {
         return hip_err("hipMemcpyAsync(tables)", e);
     (void)hipEventRecord(s.stage_done, s.stream);
     s.n_ct = (int64_t)ct.size();
-    s.n_nt = (int64_t)nt.size();
+    s.n_nt = s.nt2_base;
+    s.n_nt2 = (int64_t)nt.size() - s.nt2_base;
     s.n_pt = (int64_t)pt.size();
     s.n_pk = (int64_t)pk.size();
     s.n_sub_max = nsub;
@@ -909,8 +992,10 @@ std::string stepper_run(Stepper &s, int64_t k) {
     int64_t left = k;
     if (glen > 0 && left >= glen) {
         if (s.graph && (s.graph_k != glen || !std::equal(s.cls_tiles, s.cls_tiles + 4, s.graph_cls) ||
+                        !std::equal(s.cls2_tiles, s.cls2_tiles + 4, s.graph_cls2) ||
                         s.graph_gn != s.grid_node || s.graph_remap != s.remap ||
-                        s.graph_pt != s.n_pt || s.graph_pk != s.n_pk || s.graph_nsub != s.n_sub_max))
+                        s.graph_pt != s.n_pt || s.graph_pk != s.n_pk || s.graph_nsub != s.n_sub_max ||
+                        s.graph_nt2 != s.n_nt2 || s.graph_sub2 != s.sub2_max))
             drop_graph(s);
         if (!s.graph) {
             hipGraph_t g = nullptr;
@@ -928,6 +1013,9 @@ std::string stepper_run(Stepper &s, int64_t k) {
             if (e != hipSuccess) { s.graph = nullptr; return hip_err("hipGraphInstantiate", e); }
             s.graph_k = (int)glen;
             std::copy(s.cls_tiles, s.cls_tiles + 4, s.graph_cls);
+            std::copy(s.cls2_tiles, s.cls2_tiles + 4, s.graph_cls2);
+            s.graph_nt2 = s.n_nt2;
+            s.graph_sub2 = s.sub2_max;
             s.graph_gn = s.grid_node;
             s.graph_remap = s.remap;
             s.graph_pt = s.n_pt;
@@ -1039,6 +1127,8 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
         if (s.rs == 8) launch_cells<double>(s, tb, 0);
         else launch_cells<float>(s, tb, 0);
         (void)hipEventRecord(q[2], s.stream);
+        if (s.rs == 8) launch_medium2<double>(s, 0, s.stream);
+        else launch_medium2<float>(s, 0, s.stream);
         if (s.n_pk > 0) {               // one stream here: the timings stay apart
             if (s.n_pt > 0 && s.rs == 8) launch_substeps<double>(s, 0, s.stream);
             else if (s.n_pt > 0) launch_substeps<float>(s, 0, s.stream);

@@ -56,6 +56,9 @@ struct InstSpec {
     // for the non-gating states, 2 also with midpoint-rate (second-order)
     // Rush-Larsen gates
     int scheme = 0;
+    // the 2D medium's substeps per step: 1 none, > 1 given, <= 0 from its
+    // forward-Euler bound (90 %, 45 % with Adams-Bashforth 2)
+    int32_t medium_substeps = 1;
 };
 
 // Device arrays of the extracellular solve of one bidomain instance.
@@ -98,6 +101,12 @@ struct Inst {
     // internal cells of each model class (bits 1 TP06, 2 CRN, 4 Stewart,
     // 8 passive, in that order): cells are grouped by class on the host
     int64_t cls_begin[4] = {0, 0, 0, 0}, cls_end[4] = {0, 0, 0, 0};
+    // a 2D medium with a time step of its own (sub2 substeps per step): its
+    // cells [c2, nc), grouped by class likewise, and nodes [n2, nn); without
+    // one c2 = nc, n2 = nn and sub2 = 1
+    int64_t cls2_begin[4] = {0, 0, 0, 0}, cls2_end[4] = {0, 0, 0, 0};
+    int64_t c2 = 0, n2 = 0;
+    int32_t sub2 = 1;
     Allocator al;
     std::vector<std::pair<void *, size_t>> allocs;
     // one device block per instance, carved in 256-byte aligned pieces (one
@@ -173,6 +182,12 @@ struct Stepper {
     // cell tiles are listed class by class; one cell-kernel launch per class
     // present, specialised to that class's cell model
     int64_t cls_tiles[4] = {0, 0, 0, 0}, cls_base[4] = {0, 0, 0, 0};
+    // tiles of the 2D media with substeps (after the others in the tables):
+    // cell tiles class by class, node tiles; sub2_max substep launches per
+    // step, on the side stream
+    int64_t cls2_tiles[4] = {0, 0, 0, 0}, cls2_base[4] = {0, 0, 0, 0};
+    int64_t nt2_base = 0, n_nt2 = 0;
+    int32_t sub2_max = 0;
     int remap = 1;
     int steps_per_graph = 50;
     std::vector<Inst *> insts;
@@ -194,6 +209,9 @@ struct Stepper {
     hipGraphExec_t graph = nullptr;
     int graph_k = 0, graph_gn = -1, graph_remap = -1;
     int64_t graph_cls[4] = {-1, -1, -1, -1};
+    int64_t graph_cls2[4] = {-1, -1, -1, -1};
+    int64_t graph_nt2 = -1;
+    int32_t graph_sub2 = -1;
     int64_t graph_pt = -1, graph_pk = -1;
     int32_t graph_nsub = -1;
     bool dirty = true;

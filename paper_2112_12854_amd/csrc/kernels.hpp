@@ -116,7 +116,33 @@ struct InstDesc {
     // states (FP64, tile-major, NC_MAX slots)
     void *hv;
     double *hc;
+    // a 2D medium with a time step of its own: the potentials between its
+    // substeps (R, indexed by internal cell; only its cells are valid)
+    void *w[2];
 };
+
+// The potentials a substep reads and writes.  Substep q of m (m = 1: the
+// plain step) reads v^n (q = 0) or w[(q - 1) & 1] and writes v^{n+1}
+// (q = m - 1) or w[q & 1]; the step's level-n buffers stay untouched until
+// its last substep, so junction events still see v^n.
+struct Sub {
+    const void *vin;
+    void *vout;
+    double dt;                    // dt / m
+    int64_t t;                    // n m + q: start of the substep in units of dt / m
+    bool first;                   // the instance's first update (n = 0, q = 0)
+    bool last;                    // q = m - 1
+};
+__device__ __forceinline__ Sub substep(const InstDesc &D, int64_t n, int32_t q, int32_t m) {
+    Sub sb;
+    sb.vin = q == 0 ? D.v[n & 1] : D.w[(q - 1) & 1];
+    sb.vout = q == m - 1 ? D.v[(n + 1) & 1] : D.w[q & 1];
+    sb.dt = m == 1 ? D.dt : D.dt / m;
+    sb.t = n * m + q;
+    sb.first = n == 0 && q == 0;
+    sb.last = q == m - 1;
+    return sb;
+}
 
 // A Purkinje graph (vertex-centred finite volumes on a 1D graph) coupled to
 // an instance: CSR operator, states, detection and junctions.
@@ -150,6 +176,8 @@ struct Tile {
     int64_t begin;                // first cell / node of the tile
     int32_t count;                // cells / nodes in the tile (<= TILE)
     int32_t local;                // tile index inside its instance
+    int32_t sub_m;                // substeps per step of the tile's medium (1: none)
+    int32_t pad;
 };
 
 // The launch grids always equal the tile counts (graphs are re-captured when
@@ -257,19 +285,24 @@ __device__ __forceinline__ R node_value(const InstDesc &D, int64_t node, const R
 }
 
 // BIDO: node values of v + phi_e (bidomain time step, FP64).
+// sub < 0: the step's node values (every tile of the launch steps once);
+// sub = q >= 0: those of substep q of a medium with substeps (tiles whose
+// medium takes q or fewer substeps sit it out).
 template <typename R, bool BIDO = false>
-__global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_off, int remap) {
+__global__ void __launch_bounds__(TILE) k_node_gather(Tables tb, int32_t step_off, int remap,
+                                                      int32_t sub) {
     const Tile &T = tb.node_tiles[my_tile(remap)];
     const InstDesc &D = T.d;
     int64_t n;
     if (!stepping(D.ctrl, step_off, n)) return;
-    if (T.local == 0 && D.trace_every > 0 && n > 0 && n % D.trace_every == 0) {
+    if (sub >= T.sub_m) return;
+    if (T.local == 0 && sub <= 0 && D.trace_every > 0 && n > 0 && n % D.trace_every == 0) {
         __shared__ double red[TILE];
         reduce_trace(D, n / D.trace_every, red);
     }
     if ((int32_t)threadIdx.x >= T.count) return;
     const int64_t node = T.begin + threadIdx.x;
-    const R *__restrict__ v = (const R *)D.v[n & 1];
+    const R *__restrict__ v = (const R *)(sub <= 0 ? D.v[n & 1] : D.w[(sub - 1) & 1]);
     if constexpr (!BIDO) {
         ((R *)D.vn)[node] = node_value<R>(D, node, v);
     } else {
@@ -489,10 +522,11 @@ __device__ __forceinline__ R flux_sum(const InstDesc &D, uint32_t c, const R *__
 
 template <typename R, int MSET, bool BIDO, int SCH>
 __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t n,
-                                          uint32_t active, bool sample, double &vol_v) {
+                                          uint32_t active, bool sample, double &vol_v,
+                                          const Sub &sb) {
     constexpr bool AB2 = SCH >= 1;
-    const R *__restrict__ vin = (const R *)D.v[n & 1];
-    R *__restrict__ vout = (R *)D.v[(n + 1) & 1];
+    const R *__restrict__ vin = (const R *)sb.vin;
+    R *__restrict__ vout = (R *)sb.vout;
     const R *__restrict__ vn = (const R *)D.vn;
 
     // ---- diffusion: fused node-coefficient stencil plus two-point terms
@@ -521,16 +555,16 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 
     // ---- cell model
     const int md = (MSET == 8) ? 5 : __builtin_nontemporal_load(&D.model[c]);   // TP06 layer or model id
-    const R dt = R(D.dt);
+    const R dt = R(sb.dt);
     R iion;
     if constexpr (AB2)
-        iion = ionic<R, MSET, SCH>(md, v, rsrc(D.gate), rsrc(D.conc), c, dt, D.dt, istim,
-                                   D.gs, rsrc(D.hc), n == 0, L - istim);
+        iion = ionic<R, MSET, SCH>(md, v, rsrc(D.gate), rsrc(D.conc), c, dt, sb.dt, istim,
+                                   D.gs, rsrc(D.hc), sb.first, L - istim);
     else
-        iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), c, dt, D.dt, istim, D.gs);
+        iion = ionic<R, MSET>(md, v, rsrc(D.gate), rsrc(D.conc), c, dt, sb.dt, istim, D.gs);
 
     // ---- explicit update of v
-    const R vnew = v_update<R, AB2>(v, dt, L - iion - istim, D.hv, c, n == 0);
+    const R vnew = v_update<R, AB2>(v, dt, L - iion - istim, D.hv, c, sb.first);
     at(vout, c) = vnew;
     if (!(fabs(vnew) < R(1e30))) atomicOr(&D.ctrl->nan_flag, 1);
     if (sample) vol_v = at(D.vol, c) * double(vnew);
@@ -541,7 +575,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
     if (st == 0) {
         const R thr = R(D.thr);
         if (v <= thr && vnew > thr) {
-            __builtin_nontemporal_store((double(n) + double((thr - v) / (vnew - v))) * D.dt, &D.t_act[c]);
+            __builtin_nontemporal_store((double(sb.t) + double((thr - v) / (vnew - v))) * sb.dt, &D.t_act[c]);
             __builtin_nontemporal_store(vnew, &((R *)D.vmax)[c]);
             __builtin_nontemporal_store((uint8_t)1, &D.dstat[c]);
         }
@@ -553,7 +587,7 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
         }
         const R v90 = vm - R(D.repol) * (vm - __builtin_nontemporal_load(&((const R *)D.vrest)[c]));
         if (v >= v90 && vnew < v90) {
-            __builtin_nontemporal_store((double(n) + double((v - v90) / (v - vnew))) * D.dt, &D.t_rep[c]);
+            __builtin_nontemporal_store((double(sb.t) + double((v - v90) / (v - vnew))) * sb.dt, &D.t_rep[c]);
             __builtin_nontemporal_store((uint8_t)2, &D.dstat[c]);
         }
     }
@@ -561,18 +595,23 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 
 // One launch per model class: the host passes tb.cell_tiles pointing at the
 // first tile of the class in the class-ordered tile list.
+// sub < 0: one step of every tile of the launch; sub = q >= 0: substep q of
+// the tiles of a medium with substeps (as in k_node_gather).
 template <typename R, int MSET, bool BIDO = false, int SCH = 0>
-__global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap) {
+__global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap,
+                                               int32_t sub) {
     __shared__ double red[TILE];
     const Tile &T = tb.cell_tiles[my_tile(remap)];
     const InstDesc &D = T.d;
     int64_t n;
     if (!stepping(D.ctrl, step_off, n)) return;
+    if (sub >= T.sub_m) return;
+    const Sub sb = substep(D, n, sub < 0 ? 0 : sub, sub < 0 ? 1 : T.sub_m);
     const uint32_t active = active_stimuli(D.ctrl, n);
     double x = 0.0;
-    const bool sample = D.trace_every > 0 && (n + 1) % D.trace_every == 0;
+    const bool sample = sb.last && D.trace_every > 0 && (n + 1) % D.trace_every == 0;
     if ((int32_t)threadIdx.x < T.count)
-        cell_step<R, MSET, BIDO, SCH>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x);
+        cell_step<R, MSET, BIDO, SCH>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x, sb);
     if (sample) tile_partial(D, T, x, red);
 }
 

@@ -342,10 +342,34 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
     if (in.ordering == ORDER_RCM) order = rcm_order(g);
     else if (in.ordering == ORDER_MORTON) order = morton_order(g);
     else { order.resize(nc); for (int64_t i = 0; i < nc; ++i) order[i] = (int32_t)i; }
-    if (in.model) {
-        auto cls = [&](int32_t c) { int m = in.model[c]; return m <= 2 ? 0 : m; };
+    if (in.model || in.split_media) {
+        auto cls = [&](int32_t c) {
+            const int m = in.model ? in.model[c] : 0;
+            const int medium = in.split_media && nverts(in, c) == 3 ? 1 : 0;
+            return medium * 8 + (m <= 2 ? 0 : m);
+        };
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t a, int32_t b) { return cls(a) < cls(b); });
+    }
+    out.cell_2d = nc;
+    if (in.split_media)
+        for (int64_t i = 0; i < nc; ++i)
+            if (nverts(in, order[i]) == 3) { out.cell_2d = i; break; }
+    {   // the 2D medium's forward-Euler bound from its two-point couplings
+        double rmax = 0.0;
+        const double smax = std::max(in.sigma_l, in.sigma_t);
+        for (int64_t c = 0; c < nc; ++c) {
+            if (nverts(in, c) != 3) continue;
+            double r = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const int32_t c2 = g.nb[c][k];
+                if (c2 < 0) continue;
+                r += len(g.S[c][k]) / len(sub(g.cen[c2], g.cen[c]));
+            }
+            r *= smax * (in.scale ? in.scale[c] : 1.0) / (in.chi * in.cm * g.vol[c]);
+            rmax = std::max(rmax, r);
+        }
+        out.dtmax_2d = rmax > 0.0 ? 1.0 / rmax : HUGE_VAL;
     }
     out.n_tets = nc;
     out.n_nodes = nn;
@@ -363,6 +387,15 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
         }
     for (int64_t n = 0; n < nn; ++n)      // nodes no tet uses go last
         if (nperm[n] < 0) nperm[n] = nnext++;
+    // nodes belong to one medium: the 2D medium's, first touched by its
+    // cells, follow the tets' (counted up to its first cell)
+    out.node_2d = nn;
+    if (in.split_media && out.cell_2d < nc) {
+        int32_t first = nn;
+        for (int k = 0; k < nverts(in, order[out.cell_2d]); ++k)
+            first = std::min(first, nperm[in.tets[4 * (int64_t)order[out.cell_2d] + k]]);
+        out.node_2d = first;
+    }
     std::vector<int32_t> ninv(nn);
     for (int64_t n = 0; n < nn; ++n) ninv[nperm[n]] = (int32_t)n;
     {   // within windows of 1024 nodes, order by valence so that the 64-node
@@ -372,8 +405,9 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
         for (int64_t c = 0; c < nc; ++c)
             for (int k = 0; k < nverts(in, c); ++k) degree[in.tets[4 * c + k]]++;
         const int64_t W = 1024;
-        for (int64_t a = 0; a < nn; a += W) {
-            const int64_t b = std::min(nn, a + W);
+        for (int64_t a = 0, b; a < nn; a = b) {
+            b = std::min(nn, a + W);
+            if (a < out.node_2d && b > out.node_2d) b = out.node_2d;   // windows stay in one medium
             std::stable_sort(ninv.begin() + a, ninv.begin() + b,
                              [&](int32_t x, int32_t y) { return degree[x] > degree[y]; });
         }
@@ -426,6 +460,13 @@ std::string prepare(const PrepIn &in, PrepOut &out) {
             out.sell_cell[out.sell_off[k] + 64 * s + l] = icell[e];
             out.sell_w[out.sell_off[k] + 64 * s + l] = iw[e];
         }
+        // padding (weight 0) names a cell of the node's own medium, whose
+        // potential the gather may read from that medium's substep buffers
+        const int32_t pad = ioff[n + 1] > ioff[n] ? icell[ioff[n]]
+                                                  : (int32_t)(n >= out.node_2d ? out.cell_2d : 0);
+        const int64_t width = (out.sell_off[k + 1] - out.sell_off[k]) / 64;
+        for (int64_t s = ioff[n + 1] - ioff[n]; s < width; ++s)
+            out.sell_cell[out.sell_off[k] + 64 * s + l] = pad;
     }
 
     // ---- fused per-cell stencil (steps b-f)

@@ -22,6 +22,10 @@ struct PrepIn {
     // of conductivities (sigma_l + sigma_el, sigma_t + sigma_et)
     bool elliptic = false;
     double sigma_el = 0.0, sigma_et = 0.0;
+    // a 2D medium with a time step of its own: its cells (triangles) and
+    // nodes take the last internal indices, grouped by model class like
+    // the tets before them
+    bool split_media = false;
 };
 
 // Node gather in sliced ELL with slices of 64 nodes (one wavefront): slice
@@ -56,6 +60,12 @@ struct PrepOut {
     double sell_padding = 0.0;        // padded / real incidences - 1
     int64_t n_incidences = 0;         // (cell, vertex) pairs: 4 per tet, 3 per triangle
     double max_abs_L_row = 0.0;       // max_c sum of |coefficients| (stability hint)
+    // with split_media: the first internal cell and node of the 2D medium
+    // (n_tets / n_nodes when it has none); always: the forward-Euler bound
+    // of the 2D medium's two-point operator, 1 / max_c sum_f sigma_max
+    // scale_c |S_f| / (d_f chi Cm V_c) (infinite without triangles)
+    int64_t cell_2d = 0, node_2d = 0;
+    double dtmax_2d = 0.0;
 };
 
 // Returns an empty string on success, else the reason for EP_EINVAL.

@@ -493,6 +493,8 @@ ep_status copy_request(const ep_request *rq, const ep_options &o, int32_t scheme
         if (!err.empty()) return EP_EINVAL;
     }
     sp.scheme = scheme;
+    if (rq->medium_substeps > (1 << 20)) { err = "more than 2^20 substeps"; return EP_EINVAL; }
+    sp.medium_substeps = rq->medium_substeps == 0 ? 1 : (rq->medium_substeps < 0 ? 0 : rq->medium_substeps);
     for (int k = 0; k < rq->n_stimuli; ++k) {
         const ep_stimulus &q = rq->stimuli[k];
         if (q.domain == 1 && sp.purk.n == 0) {

@@ -70,7 +70,8 @@ class ep_request(C.Structure):
                 ("model", C.POINTER(C.c_uint8)), ("n_stimuli", C.c_int32),
                 ("stimuli", C.POINTER(ep_stimulus)), ("ionic_scale", C.c_double * 4),
                 ("n_steps", C.c_int64), ("purkinje", C.POINTER(ep_purkinje)),
-                ("n_cell_junctions", C.c_int32), ("cell_junctions", C.POINTER(ep_cell_junction))]
+                ("n_cell_junctions", C.c_int32), ("cell_junctions", C.POINTER(ep_cell_junction)),
+                ("medium_substeps", C.c_int32)]
 
 
 class ep_result(C.Structure):
@@ -114,6 +115,8 @@ _SIGS = {
     "ep_set_purkinje_scale": (C.c_int, [C.c_void_p, C.c_int64, _dp]),
     "ep_set_time_scheme": (C.c_int, [C.c_void_p, C.c_int32]),
     "ep_set_cell_order": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ep_set_medium_substeps": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ep_get_medium_substeps": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "ep_add_cell_junction": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
                                        C.c_int32, C.c_double, C.c_double]),
     "ep_add_pmj": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
@@ -301,6 +304,8 @@ class Sim:
             self.set_launch(*launch)
         if cell_order is not None:
             _check(L.ep_set_cell_order(h, int(cell_order)), h)
+        if getattr(w, "medium_substeps", None) is not None:
+            _check(L.ep_set_medium_substeps(h, int(w.medium_substeps)), h)
         _check(L.ep_init(h), h)
         self.device = device
 
@@ -325,6 +330,12 @@ class Sim:
     def set_launch(self, block=256, steps_per_graph=50, xcd_remap=1):
         """block: 0 or 256; steps_per_graph: 0 = no graphs."""
         _check(lib().ep_set_launch(self.h, block, steps_per_graph, xcd_remap), self.h)
+
+    def medium_substeps(self) -> int:
+        """Substeps per step of the 2D medium (1: it steps with the tets)."""
+        n = C.c_int32()
+        _check(lib().ep_get_medium_substeps(self.h, C.byref(n)), self.h)
+        return n.value
 
     def apply_diffusion(self, v, entry: str = "ep_apply_diffusion"):
         """The simulation's diffusion operator applied to the cell potentials
@@ -535,6 +546,9 @@ class Server:
                                           cj.delay_anti, cj.amp, cj.dur)
             rq.n_cell_junctions, rq.cell_junctions = len(cjs), arr
             keep.append(arr)
+        ms = getattr(w, "medium_substeps", None)
+        if ms is not None:
+            rq.medium_substeps = -1 if ms <= 0 else int(ms)
         rid = C.c_int64()
         self._chk(lib().ep_server_submit(self.h, C.byref(rq), C.byref(rid)))
         del keep

@@ -188,3 +188,100 @@ def test_cell_junction_abi_errors(ep):
     t.cell_junctions = [M.CellJunction(cell=5)]
     with pytest.raises(ep.EPError):
         ep.Sim(t)
+
+
+# ------------------------------------------ the 2D medium's own time step
+def _with_substeps(w, m, scheme=0):
+    w.medium_substeps = m
+    w.time_scheme = scheme
+    return w
+
+
+@pytest.mark.parametrize("name,m,scheme,order", [
+    ("bent-stewart", 5, 0, "rcm"), ("mixed-tp06+crn", 4, 0, "rcm"),
+    ("mixed-tp06+crn", 3, 1, "input"), ("flat-tp06", 2, 2, "morton")])
+def test_medium_substeps_parity(ep, oracle_lib, name, m, scheme, order):
+    """The 2D medium at dt / m inside steps of dt (Sec. 4: the Purkinje
+    shell runs at a step far below the myocardium's): FP64 against the
+    oracle on the bent Stewart sheet, the mixed tets + triangles mesh (the
+    tets stepping at dt beside it) under forward Euler and Adams-Bashforth 2,
+    and the flat sheet under the second-order Rush-Larsen variant, in three
+    cell orders; FP32-mixed activation times within 0.5 ms."""
+    w = _with_substeps(sheets()[name], m, scheme)
+    o = {"rcm": ep.EP_ORDER_RCM, "input": ep.EP_ORDER_INPUT, "morton": ep.EP_ORDER_MORTON}[order]
+    say(f"2D substeps {name} m={m} scheme={scheme} order={order}: {w.n_tets} cells")
+    g = ep.Sim(w, prec=ep.EP_FP64, cell_order=o)
+    f = ep.Sim(w, prec=ep.EP_FP32_MIXED, cell_order=o)
+    r = oracle_lib.Sim(w)
+    assert g.medium_substeps() == m == r.medium_substeps()
+    worst = 0.0
+    for chunk in range(4):
+        g.step(250)
+        f.step(250)
+        r.step(250)
+        dv = np.max(np.abs(g.vm() - r.vm()))
+        worst = max(worst, dv)
+        assert dv <= TOL_MV, (chunk, dv)
+    ta = r.activation()
+    assert np.isfinite(ta).sum() > 0.3 * w.n_tets
+    assert same_times(g.activation(), ta) <= 1e-6
+    assert same_times(g.apd90(), r.apd90()) <= 1e-6
+    assert same_times(f.activation(), ta) <= 0.5
+    say(f"  max|dV| {worst:.2e} mV, {np.isfinite(ta).sum()} activated")
+
+
+def test_medium_substeps_derived_and_shell_junctions(ep, oracle_lib):
+    """The shell on the slab with the shell's substeps from its forward-Euler
+    bound (the same count as the oracle's), its communication nodes driving
+    the slab: FP64 parity, and a checkpoint that restores bitwise."""
+    w = M.shell_on_slab(drive="sheet", two_way=True)
+    w.medium_substeps = 0
+    g = ep.Sim(w, prec=ep.EP_FP64)
+    r = oracle_lib.Sim(w)
+    m = r.medium_substeps()
+    say(f"shell on slab, derived substeps {g.medium_substeps()} (oracle {m})")
+    assert g.medium_substeps() == m and m > 1
+    for chunk in range(5):
+        g.step(150)
+        r.step(150)
+        assert np.max(np.abs(g.vm() - r.vm())) <= TOL_MV, chunk
+    ta = r.activation()
+    assert np.isfinite(ta).all()
+    assert same_times(g.activation(), ta) <= 1e-6
+    blob = g.checkpoint()
+    g.step(100)
+    c = ep.Sim(w, prec=ep.EP_FP64)
+    c.restore(blob)
+    c.step(100)
+    assert np.array_equal(g.vm(), c.vm())
+    w1 = M.shell_on_slab(drive="sheet", two_way=True)
+    w1.medium_substeps = m + 1
+    d = ep.Sim(w1, prec=ep.EP_FP64)
+    with pytest.raises(ep.EPError):
+        d.restore(blob)
+
+
+def test_medium_substeps_through_server(ep):
+    """Requests whose 2D medium has substeps, batched with a plain slab and
+    a sheet without substeps: each result bitwise the one it gives alone."""
+    ws = [_with_substeps(sheets()["bent-stewart"], 4), M.config1(n_steps=0),
+          sheets()["flat-tp06"], _with_substeps(sheets()["mixed-tp06+crn"], 3)]
+    sv = ep.Server(prec=ep.EP_FP32_MIXED, max_slots=8)
+    try:
+        ids = [sv.submit(w, 400) for w in ws]
+        assert all(sv.wait(i)["status"] == ep.EP_OK for i in ids)
+        for rid, w in zip(ids, ws):
+            solo = ep.Sim(w, prec=ep.EP_FP32_MIXED)
+            solo.step(400)
+            assert np.array_equal(sv.vm(rid), solo.vm())
+            assert np.array_equal(sv.activation(rid), solo.activation(), equal_nan=True)
+    finally:
+        sv.close()
+
+
+def test_medium_substeps_refused_with_bidomain(ep):
+    w = _with_substeps(sheets()["flat-tp06"], 3)
+    w.bidomain = M.Bidomain()
+    with pytest.raises(ep.EPError) as e:
+        ep.Sim(w, prec=ep.EP_FP64)
+    assert e.value.status == ep.EP_EINVAL
