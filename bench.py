@@ -73,6 +73,9 @@ def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_re
     log(f"prec={prec}: init {time.time() - t0:.1f}s, footprint {sim.footprint() / 2**30:.2f} GiB")
     sim.set_launch(256, chunk, 1)
     sim.step(warmup)
+    # schedule and cell tile shape from the autotuner (its trials are
+    # ordinary steps of the same job, before the timed region)
+    tuned = sim.autotune(20)
     sim.sync()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -87,6 +90,7 @@ def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_re
     sim.sync()
     torch.cuda.synchronize()
     graph_elapsed = time.perf_counter() - t1
+    launch = sim.launch()
     node_b, cell_b, diff_b = sim.algorithmic_bytes(with_diffusion=True)
     at = sim.activation()
     n_sub = sim.purkinje_n_sub() if sim.n_purkinje else 0
@@ -107,7 +111,8 @@ def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_re
                 timed_p50_ms=float(np.percentile(per, 50)),
                 cell_kernel_ms=cell_ms, node_kernel_ms=node_ms,
                 cell_bytes=cell_b, node_bytes=node_b,
-                activated=int(np.isfinite(at).sum()), diffusion_op=diff)
+                activated=int(np.isfinite(at).sum()), diffusion_op=diff,
+                launch=launch, tuned_ms_per_step=tuned["ms_per_step"])
 
 
 def time_diffusion(ep, sim, w, reps):
@@ -272,6 +277,7 @@ def run_serving(ep, ws, arrivals, n_steps, prec=None, one_at_a_time=False, trial
                              "device": _pct([r["t_done"] - r["t_admit"] for r in res])},
                 mean_tets=float(np.mean([w.n_tets for w in ws])),
                 steps_per_graph=st["steps_per_graph"], xcd_remap=st["xcd_remap"],
+                tile_cells=st["tile_cells"],
                 autotune_runs=st["autotune_runs"])
 
 
@@ -359,6 +365,7 @@ def run_uq(ep, n_inst, n_steps, prec, trial=25, seed=5):
                 tuned_ms_per_step=st1["tuned_ms_per_step"],
                 tuned_cell_steps_per_s=total / (st1["tuned_ms_per_step"] * 1e-3),
                 steps_per_graph=st1["steps_per_graph"], xcd_remap=st1["xcd_remap"],
+                tile_cells=st1["tile_cells"],
                 resident_after_s=t_res)
 
 
@@ -774,13 +781,14 @@ def main():
                    "dt_ms": w.dt, "cells": "TP06 endo/mid/epi 30/40/30%",
                    "fibres": "-60..+60 deg transmural + 5 deg jitter"},
         "timed_region": "direct launches, HIP events around every kernel, queue 64 steps deep",
+        "launch": f32["launch"],
         "ms_per_step_graphs": f32["graph_ms_per_step"],
         "latency_ms": {"p50": f32["p50_ms"], "p99": f32["p99_ms"], "n": f32["n_latency"],
                        "per": "step: device time from its first kernel's start to its last "
                               "kernel's end, consecutive event-timed steps after the timed region"},
         "fp64": None if f64 is None else {
             "value": f64["cell_steps_per_s"], "ms_per_step": f64["ms_per_step"],
-            "ms_per_step_graphs": f64["graph_ms_per_step"],
+            "ms_per_step_graphs": f64["graph_ms_per_step"], "launch": f64["launch"],
             "p50_ms": f64["p50_ms"], "p99_ms": f64["p99_ms"], "n_latency": f64["n_latency"],
             "cell_kernel_ms": f64["cell_kernel_ms"], "node_kernel_ms": f64["node_kernel_ms"],
             "cell_kernel_GBps": gbps(f64["cell_bytes"], f64["cell_kernel_ms"]),

@@ -358,24 +358,39 @@ ep_status ep_state_size(ep_sim *s, size_t *bytes);
 ep_status ep_get_state(ep_sim *s, void *buf, size_t bytes);
 ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);
 
-/* Launch controls used by the autotuner: block is 0 or 256 (one block per
- * tile of 256 cells or nodes), steps_per_graph is the number of steps
- * captured per HIP graph launch (0 = direct launches only), xcd_remap
- * remaps blocks so that each XCD gets a contiguous range of tiles.  May be
- * called any time after ep_create(). */
+/* Launch controls used by the autotuner: block is the cells (= lanes) of a
+ * cell-kernel tile, 64, 128 or 256 (0 keeps the current; node tiles are
+ * always 256 nodes), steps_per_graph is the number of steps captured per HIP graph
+ * launch (0 = direct launches only), xcd_remap remaps blocks so that each
+ * XCD gets a contiguous range of tiles.  May be called any time after
+ * ep_create(). */
 ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
                         int32_t xcd_remap);
 
+/* Cell tile size (batched scheduling, not the paper's): a cell-kernel block
+ * takes a tile of 64, 128 or 256 consecutive cells of one model class, one
+ * per lane.  No result depends on it: every cell's arithmetic is its own,
+ * and the vbar trace is summed from partials of 64 cells in a fixed order.
+ * EP_EINVAL for other sizes. */
+ep_status ep_set_tile_size(ep_sim *s, int32_t cells);
+/* The schedule in effect (after ep_autotune: the one it chose); any output
+ * pointer may be NULL. */
+ep_status ep_get_launch(ep_sim *s, int32_t *tile_cells, int32_t *steps_per_graph,
+                        int32_t *xcd_remap);
+
 /* Launch-schedule autotuner (batched scheduling is this library's, not the
  * paper's).  Tries every graph length in {0 (direct launches), 10, 25, 50,
- * 100} steps, each with and without the XCD tile remap: one untimed launch
- * (graph capture, warm caches), then trial_steps steps, rounded up to whole
- * graphs, timed with HIP events on the simulation's stream.  Keeps the
- * fastest (as ep_set_launch would) and reports it; any output pointer may be
- * NULL.  The trials are ordinary steps: the simulation advances by 372 steps
- * plus twice the sum over the five candidates of their timed steps, with the
- * same results as under any fixed schedule.  EP_ESTATE before ep_init,
- * EP_EINVAL for trial_steps <= 0. */
+ * 100} steps, each with and without the XCD tile remap, then at the fastest
+ * of those the cell tile sizes 256, 128 and 64: each candidate one untimed
+ * launch (graph capture, warm caches), then trial_steps steps, rounded up to
+ * whole graphs, timed with HIP events on the simulation's stream.  Keeps the
+ * fastest schedule and tile size (as ep_set_launch / ep_set_tile_size would;
+ * ep_get_launch reads them) and reports the schedule; any output pointer may
+ * be NULL.  The trials are ordinary steps, with the same results as under
+ * any fixed schedule: the simulation advances by 372 steps plus twice the
+ * sum over the five graph lengths of their timed steps, plus three times
+ * the chosen length's untimed and timed steps.  EP_ESTATE before ep_init, EP_EINVAL for
+ * trial_steps <= 0. */
 ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
                       int32_t *xcd_remap, double *ms_per_step);
 
@@ -494,6 +509,8 @@ typedef struct {
     int32_t steps_per_graph, xcd_remap;   /* schedule in effect              */
     int64_t autotune_runs;
     double tuned_ms_per_step;     /* batch step time of the last tuning      */
+    int32_t tile_cells;           /* cell tile size in effect (64/128/256)   */
+    int32_t pad;
 } ep_server_stats;
 
 typedef struct ep_server ep_server;

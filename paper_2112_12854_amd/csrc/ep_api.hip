@@ -19,8 +19,9 @@ using ep::model_ng;
 
 namespace {
 
-// "EPSMCHK8": states in the tile-major layout, header with the cell order
-constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b38ULL;
+// "EPSMCHK9": states in the tile-major layout, header with the cell order,
+// trace partials per wave of 64 cells
+constexpr uint64_t CKPT_MAGIC = 0x4550534d43484b39ULL;
 
 const char *const TP06_NAMES[] = {"V", "m", "h", "j", "xr1", "xr2", "xs", "r", "s", "d",
                                   "f", "f2", "fCass", "Rbar", "Ca_i", "Ca_SR", "Ca_SS",
@@ -336,11 +337,35 @@ ep_status ep_footprint(const ep_sim *s, size_t *bytes) {
 
 ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph, int32_t xcd_remap) {
     if (!s) return EP_EINVAL;
-    if (block != 0 && block != epdev::TILE)
-        return fail(s, EP_EINVAL, "block must be 0 or 256 (the tile size)");
+    if (block != 0 && block != 64 && block != 128 && block != 256)
+        return fail(s, EP_EINVAL, "block must be 0 (keep), 64, 128 or 256");
     if (steps_per_graph < 0) return fail(s, EP_EINVAL, "steps_per_graph must be >= 0");
     s->stepper.steps_per_graph = steps_per_graph;
     s->stepper.remap = xcd_remap ? 1 : 0;
+    if (block && block != s->stepper.cell_threads) {
+        s->stepper.cell_threads = block;
+        s->stepper.dirty = true;
+    }
+    return EP_OK;
+}
+
+ep_status ep_set_tile_size(ep_sim *s, int32_t cells) {
+    if (!s) return EP_EINVAL;
+    if (cells != 64 && cells != 128 && cells != 256)
+        return fail(s, EP_EINVAL, "a cell tile holds 64, 128 or 256 cells");
+    if (cells != s->stepper.cell_threads) {
+        s->stepper.cell_threads = cells;
+        s->stepper.dirty = true;
+    }
+    return EP_OK;
+}
+
+ep_status ep_get_launch(ep_sim *s, int32_t *tile_cells, int32_t *steps_per_graph,
+                        int32_t *xcd_remap) {
+    if (!s) return EP_EINVAL;
+    if (tile_cells) *tile_cells = s->stepper.cell_threads;
+    if (steps_per_graph) *steps_per_graph = s->stepper.steps_per_graph;
+    if (xcd_remap) *xcd_remap = s->stepper.remap;
     return EP_OK;
 }
 
@@ -438,13 +463,14 @@ ep_status ep_get_mean_vm_trace(ep_sim *s, double *t, double *vbar, int64_t cap, 
     // device's order
     const int64_t hs = s->inst.host_step;
     if (every > 0 && hs > 0 && hs % every == 0 && hs / every < m) {
-        const int nt = s->inst.desc.n_cell_tiles;
-        std::vector<double> part(nt);
-        HIP_TRY(s, hipMemcpy(part.data(), s->inst.desc.part, (size_t)nt * 8, hipMemcpyDeviceToHost));
+        const int ng = (s->inst.desc.n_waves + 3) / 4;   // groups of four wave partials
+        std::vector<double> part(4 * (size_t)ng);
+        HIP_TRY(s, hipMemcpy(part.data(), s->inst.desc.part, part.size() * 8, hipMemcpyDeviceToHost));
         double red[epdev::TILE];
         for (int t = 0; t < epdev::TILE; ++t) {
             double acc = 0.0;
-            for (int i = t; i < nt; i += epdev::TILE) acc += part[i];
+            for (int g = t; g < ng; g += epdev::TILE)
+                acc += (part[4 * g] + part[4 * g + 1]) + (part[4 * g + 2] + part[4 * g + 3]);
             red[t] = acc;
         }
         for (int w = epdev::TILE / 2; w > 0; w >>= 1)
@@ -675,7 +701,7 @@ static std::vector<std::pair<void *, size_t>> ckpt_arrays(ep_sim *s) {
         {D.v[0], nc * r},           {D.v[1], nc * r},        {D.gate, tiled_len(nc, NG_MAX) * r},
         {D.conc, tiled_len(nc, NC_MAX) * 8},  {D.dstat, nc}, {D.t_act, nc * 8},
         {D.t_rep, nc * 8},          {D.vmax, nc * r},        {(void *)D.vrest, nc * r},
-        {D.trace, (size_t)s->inst.trace_cap * 8}, {D.part, (size_t)D.n_cell_tiles * 8},
+        {D.trace, (size_t)s->inst.trace_cap * 8}, {D.part, (size_t)(D.n_waves + 3) / 4 * 32},
         {s->inst.d_ctrl, sizeof(epdev::Ctrl)}};
     if (s->inst.bido) a.push_back({s->inst.bd.phi, nc * 8});
     if (s->inst.ab2) {

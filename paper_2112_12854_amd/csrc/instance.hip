@@ -128,7 +128,7 @@ size_t estimate_footprint(int64_t nc, int64_t nn, int rs, int max_degree_hint) {
     b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);   // states
     b += 2 * round256(c * r) + 3 * round256(c * r) + round256(n * r);   // v0 v1 vrest vmax, vn
     b += round256(c) + 2 * round256(c * 8);                   // detection
-    b += round256(((c + TILE - 1) / TILE + 3) * 8) + round256(8 * 4096) + round256(sizeof(Ctrl));
+    b += round256(((c + 63) / 64 + 12) * 8) + round256(8 * 4096) + round256(sizeof(Ctrl));
     return b;
 }
 
@@ -324,7 +324,7 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
     b += round256(tiled_len(c, NC_MAX) * 8) + round256(tiled_len(c, NG_MAX) * r);
     b += 4 * round256(c * r) + round256(n * r);
     b += round256(c) + 2 * round256(c * 8);
-    b += round256((size_t)cap * 8) + round256(((c + TILE - 1) / TILE + 3) * 8) + round256(sizeof(Ctrl));
+    b += round256((size_t)cap * 8) + round256(((c + 63) / 64 + 12) * 8) + round256(sizeof(Ctrl));
     if (sp.bido) {
         const size_t m1 = (size_t)sp.bido_restart + 1;
         b += round256(tiled_len(c, 8) * 8) + round256(tiled_len(c, 4) * 8) + 3 * round256(c * 8) +
@@ -545,10 +545,10 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
 
     // vbar trace: sample 0 now, then one every trace_every steps; one partial
     // per cell tile (tiles do not straddle model classes)
-    D.n_cell_tiles = 0;
+    D.n_waves = 0;
     for (int k = 0; k < 4; ++k)
-        D.n_cell_tiles += (int32_t)((I.cls_end[k] - I.cls_begin[k] + TILE - 1) / TILE) +
-                          (int32_t)((I.cls2_end[k] - I.cls2_begin[k] + TILE - 1) / TILE);
+        D.n_waves += (int32_t)((I.cls_end[k] - I.cls_begin[k] + 63) / 64) +
+                     (int32_t)((I.cls2_end[k] - I.cls2_begin[k] + 63) / 64);
     if (I.c2 < nc) {   // potentials between substeps, indexed by internal cell
         char *w0 = (char *)dalloc(I, (size_t)(nc - I.c2) * rs);
         char *w1 = (char *)dalloc(I, (size_t)(nc - I.c2) * rs);
@@ -566,9 +566,10 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
     std::vector<double> trace(I.trace_cap, nan);
     trace[0] = vt / tv;
     if (!up(I, (void **)&D.trace, trace) ||
-        !up(I, (void **)&D.part, std::vector<double>((nc + TILE - 1) / TILE + 3, 0.0)))
+        !up(I, (void **)&D.part, std::vector<double>((nc + 63) / 64 + 12, 0.0)))
         return fail_mem();
     D.dt = sp.dt;
+    D.dt2 = sp.dt / I.sub2;
     D.thr = sp.thr;
     D.repol = sp.repol;
     D.inv_total_vol = 1.0 / tv;
@@ -702,10 +703,11 @@ void launch_cells_v(Stepper &s, const Tables &tb, int32_t off, int32_t sub = -1,
     const int64_t *cnt = sub < 0 ? s.cls_tiles : s.cls2_tiles;
     Tables t[4] = {tb, tb, tb, tb};
     for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + base[k];
-    if (cnt[0]) k_cell<R, 1, BIDO, SCH><<<(int)cnt[0], TILE, 0, st>>>(t[0], off, s.remap, sub);
-    if (cnt[1]) k_cell<R, 2, BIDO, SCH><<<(int)cnt[1], TILE, 0, st>>>(t[1], off, s.remap, sub);
-    if (cnt[2]) k_cell<R, 4, BIDO, SCH><<<(int)cnt[2], TILE, 0, st>>>(t[2], off, s.remap, sub);
-    if (cnt[3]) k_cell<R, 8, BIDO, SCH><<<(int)cnt[3], TILE, 0, st>>>(t[3], off, s.remap, sub);
+    const int B = s.cell_threads;
+    if (cnt[0]) k_cell<R, 1, BIDO, SCH><<<(int)cnt[0], B, 0, st>>>(t[0], off, s.remap, sub);
+    if (cnt[1]) k_cell<R, 2, BIDO, SCH><<<(int)cnt[1], B, 0, st>>>(t[1], off, s.remap, sub);
+    if (cnt[2]) k_cell<R, 4, BIDO, SCH><<<(int)cnt[2], B, 0, st>>>(t[2], off, s.remap, sub);
+    if (cnt[3]) k_cell<R, 8, BIDO, SCH><<<(int)cnt[3], B, 0, st>>>(t[3], off, s.remap, sub);
 }
 
 // bidomain instances run in FP64 with forward Euler only (checked at
@@ -863,15 +865,25 @@ std::string stepper_sync_tables(Stepper &s) {
         s.scheme = std::max(s.scheme, I->scheme);
     }
     // cell tiles class by class, those of 2D media with substeps after the
-    // others; tile `local` numbers run over the instance
-    std::vector<int32_t> next_local(s.insts.size(), 0);
+    // others; wave partials numbered per instance over its class ranges in
+    // the order medium 0 classes 0-3, medium 1 classes 0-3 (as n_waves)
+    const int64_t TS = s.cell_threads;
+    auto wave_base = [](const Inst &I, int medium, int k) {
+        int64_t w = 0;
+        for (int m = 0; m <= medium; ++m)
+            for (int q = 0; q < 4 && (m < medium || q < k); ++q)
+                w += m == 0 ? (I.cls_end[q] - I.cls_begin[q] + 63) / 64
+                            : (I.cls2_end[q] - I.cls2_begin[q] + 63) / 64;
+        return w;
+    };
     for (int k = 0; k < 4; ++k) {
         s.cls_base[k] = (int64_t)ct.size();
         for (size_t i = 0; i < s.insts.size(); ++i) {
             const Inst &I = *s.insts[i];
-            for (int64_t b = I.cls_begin[k]; b < I.cls_end[k]; b += TILE)
-                ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.cls_end[k] - b),
-                                  next_local[i]++, 1, 0});
+            const int64_t w0 = wave_base(I, 0, k);
+            for (int64_t b = I.cls_begin[k]; b < I.cls_end[k]; b += TS)
+                ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TS, I.cls_end[k] - b), 0, 1,
+                                  (int32_t)(w0 + (b - I.cls_begin[k]) / 64)});
         }
         s.cls_tiles[k] = (int64_t)ct.size() - s.cls_base[k];
     }
@@ -880,9 +892,10 @@ std::string stepper_sync_tables(Stepper &s) {
         s.cls2_base[k] = (int64_t)ct.size();
         for (size_t i = 0; i < s.insts.size(); ++i) {
             const Inst &I = *s.insts[i];
-            for (int64_t b = I.cls2_begin[k]; b < I.cls2_end[k]; b += TILE)
-                ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TILE, I.cls2_end[k] - b),
-                                  next_local[i]++, I.sub2, 0});
+            const int64_t w0 = wave_base(I, 1, k);
+            for (int64_t b = I.cls2_begin[k]; b < I.cls2_end[k]; b += TS)
+                ct.push_back(Tile{I.desc, b, (int32_t)std::min<int64_t>(TS, I.cls2_end[k] - b), 0,
+                                  I.sub2, (int32_t)(w0 + (b - I.cls2_begin[k]) / 64)});
         }
         s.cls2_tiles[k] = (int64_t)ct.size() - s.cls2_base[k];
     }
@@ -995,7 +1008,8 @@ std::string stepper_run(Stepper &s, int64_t k) {
                         !std::equal(s.cls2_tiles, s.cls2_tiles + 4, s.graph_cls2) ||
                         s.graph_gn != s.grid_node || s.graph_remap != s.remap ||
                         s.graph_pt != s.n_pt || s.graph_pk != s.n_pk || s.graph_nsub != s.n_sub_max ||
-                        s.graph_nt2 != s.n_nt2 || s.graph_sub2 != s.sub2_max))
+                        s.graph_nt2 != s.n_nt2 || s.graph_sub2 != s.sub2_max ||
+                        s.graph_threads != s.cell_threads))
             drop_graph(s);
         if (!s.graph) {
             hipGraph_t g = nullptr;
@@ -1016,6 +1030,7 @@ std::string stepper_run(Stepper &s, int64_t k) {
             std::copy(s.cls2_tiles, s.cls2_tiles + 4, s.graph_cls2);
             s.graph_nt2 = s.n_nt2;
             s.graph_sub2 = s.sub2_max;
+            s.graph_threads = s.cell_threads;
             s.graph_gn = s.grid_node;
             s.graph_remap = s.remap;
             s.graph_pt = s.n_pt;
@@ -1076,11 +1091,46 @@ std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
                 out.xcd_remap = remap;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     s.steps_per_graph = out.steps_per_graph;
     s.remap = out.xcd_remap;
-    out.ms_per_step = best;
+    // cell tile sizes at that schedule; a new size rebuilds the tile tables
+    static const int32_t kTile[] = {256, 128, 64};
+    const int32_t t0 = s.cell_threads;
+    out.cell_threads = t0;
+    double best_shape = HUGE_VAL;
+    for (const int32_t tile : kTile) {
+        if (!err.empty()) break;
+        if (s.cell_threads != tile) {
+            s.cell_threads = tile;
+            s.dirty = true;
+        }
+        const int32_t k = out.steps_per_graph;
+        const int64_t warm = k > 0 ? k : 1;
+        const int64_t n = k > 0 ? (trial_steps + k - 1) / k * k : trial_steps;
+        err = stepper_run(s, warm);
+        if (!err.empty()) break;
+        (void)hipEventRecord(e0, s.stream);
+        err = stepper_run(s, n);
+        if (!err.empty()) break;
+        (void)hipEventRecord(e1, s.stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        out.n_trials++;
+        out.steps_used += warm + n;
+        const double per = ms / n;
+        if (per < best_shape) {
+            best_shape = per;
+            out.cell_threads = tile;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s.cell_threads != out.cell_threads) {
+        s.cell_threads = out.cell_threads;
+        s.dirty = true;
+    }
+    out.ms_per_step = std::min(best, best_shape);
     return err;
 }
 

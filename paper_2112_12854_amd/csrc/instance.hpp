@@ -190,6 +190,9 @@ struct Stepper {
     int32_t sub2_max = 0;
     int remap = 1;
     int steps_per_graph = 50;
+    // cell tile shape: tiles of cell_threads cells (64, 128 or 256), one
+    // per lane of a block; node tiles are always TILE nodes
+    int32_t cell_threads = 256;
     std::vector<Inst *> insts;
     // device tables
     epdev::InstDesc *d_desc = nullptr;
@@ -212,6 +215,7 @@ struct Stepper {
     int64_t graph_cls2[4] = {-1, -1, -1, -1};
     int64_t graph_nt2 = -1;
     int32_t graph_sub2 = -1;
+    int32_t graph_threads = -1;
     int64_t graph_pt = -1, graph_pk = -1;
     int32_t graph_nsub = -1;
     bool dirty = true;
@@ -231,12 +235,14 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
                             double *step_ms = nullptr);
 
 // Launch-schedule autotuner.  Every candidate (steps per graph launch x XCD
-// tile remap) runs one untimed launch (graph capture, warm caches) and then
-// `trial_steps` timed steps of the live instances; the fastest per step is
-// kept in the stepper.  Results do not depend on the schedule, so the trial
-// steps are ordinary steps of the simulations.
+// tile remap, then the cell tile sizes at the best of those) runs one
+// untimed launch (graph capture, warm caches) and then `trial_steps` timed
+// steps of the live instances; the fastest per step is kept in the stepper.
+// Results do not depend on the schedule, so the trial steps are ordinary
+// steps of the simulations.
 struct TuneResult {
     int32_t steps_per_graph = 50, xcd_remap = 1;
+    int32_t cell_threads = 256;
     double ms_per_step = 0;
     int32_t n_trials = 0;
     int64_t steps_used = 0;

@@ -96,14 +96,14 @@ struct InstDesc {
     void *vmax;
     const void *vrest;
     const double *vol;
-    double *part;                 // one partial sum per cell tile
+    double *part;                 // one partial sum per wave of 64 cells (zero-padded to 4)
     double *trace;                // vbar samples
     Ctrl *ctrl;
     double dt, thr, repol, inv_total_vol;
     GScale gs;
     int64_t trace_cap;
     int32_t trace_every;
-    int32_t n_cell_tiles;
+    int32_t n_waves;              // wave partials: ceil(len / 64) per class range
     // bidomain: the extracellular potential phi_e^n (FP64; null otherwise);
     // the flux of the time step is then that of v + phi_e
     const double *phi;
@@ -117,8 +117,10 @@ struct InstDesc {
     void *hv;
     double *hc;
     // a 2D medium with a time step of its own: the potentials between its
-    // substeps (R, indexed by internal cell; only its cells are valid)
+    // substeps (R, indexed by internal cell; only its cells are valid) and
+    // its substep dt / n_sub
     void *w[2];
+    double dt2;
 };
 
 // The potentials a substep reads and writes.  Substep q of m (m = 1: the
@@ -137,7 +139,7 @@ __device__ __forceinline__ Sub substep(const InstDesc &D, int64_t n, int32_t q, 
     Sub sb;
     sb.vin = q == 0 ? D.v[n & 1] : D.w[(q - 1) & 1];
     sb.vout = q == m - 1 ? D.v[(n + 1) & 1] : D.w[q & 1];
-    sb.dt = m == 1 ? D.dt : D.dt / m;
+    sb.dt = m == 1 ? D.dt : D.dt2;
     sb.t = n * m + q;
     sb.first = n == 0 && q == 0;
     sb.last = q == m - 1;
@@ -177,7 +179,7 @@ struct Tile {
     int32_t count;                // cells / nodes in the tile (<= TILE)
     int32_t local;                // tile index inside its instance
     int32_t sub_m;                // substeps per step of the tile's medium (1: none)
-    int32_t pad;
+    int32_t wave0;                // cell tiles: index of the wave partial of its first cell
 };
 
 // The launch grids always equal the tile counts (graphs are re-captured when
@@ -216,26 +218,28 @@ __device__ __forceinline__ bool stepping(const Ctrl *ctrl, int32_t off, int64_t 
     return n < ctrl->target;
 }
 
-// Trace of vbar.  On a sample step every cell tile stores the sum of
-// V_c v_c over its cells; the first node tile of the next step adds the
-// partials (the partials are complete by then: the two kernels are stream
-// ordered), so no tile waits on another and the order of the additions is
-// fixed: lane t adds partials t, t + TILE, ... in order, then a fixed tree.
-// A sample taken by the last step issued is reduced the same way on the host.
-__device__ __forceinline__ void tile_partial(const InstDesc &D, const Tile &T, double x,
-                                             double *red) {
-    red[threadIdx.x] = x;
-    __syncthreads();
-    for (int s = TILE / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) D.part[T.local] = red[0];
+// Trace of vbar.  On a sample step every wave of cells (64 consecutive
+// cells of one class range) stores the sum of V_c v_c over its cells,
+// reduced across the wave by a fixed butterfly (lane 0's result); the first
+// node tile of the next step adds the wave partials (complete by then: the
+// kernels are stream ordered), so no tile waits on another and the order of
+// the additions is fixed: lane t adds the groups of four partials t,
+// t + 256, ..., each as (p0 + p1) + (p2 + p3), then a fixed tree.  Neither
+// the partials nor their sum depend on the cell tile shape.  A sample taken
+// by the last step issued is reduced the same way on the host.
+__device__ __forceinline__ void wave_partial(const InstDesc &D, int64_t idx, double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) D.part[idx] = x;
 }
 
 __device__ __forceinline__ void reduce_trace(const InstDesc &D, int64_t idx, double *red) {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < D.n_cell_tiles; i += TILE) acc += D.part[i];
+    const int ng = (D.n_waves + 3) / 4;
+    for (int g = threadIdx.x; g < ng; g += TILE) {
+        const double *p = D.part + 4 * (int64_t)g;
+        acc += (p[0] + p[1]) + (p[2] + p[3]);
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = TILE / 2; s > 0; s >>= 1) {
@@ -596,11 +600,12 @@ __device__ __forceinline__ void cell_step(const InstDesc &D, uint32_t c, int64_t
 // One launch per model class: the host passes tb.cell_tiles pointing at the
 // first tile of the class in the class-ordered tile list.
 // sub < 0: one step of every tile of the launch; sub = q >= 0: substep q of
-// the tiles of a medium with substeps (as in k_node_gather).
+// the tiles of a medium with substeps (as in k_node_gather).  A cell tile
+// holds up to blockDim.x cells, one per lane (64, 128 or 256: the tile shape
+// is a launch choice, and no result depends on it).
 template <typename R, int MSET, bool BIDO = false, int SCH = 0>
 __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int remap,
                                                int32_t sub) {
-    __shared__ double red[TILE];
     const Tile &T = tb.cell_tiles[my_tile(remap)];
     const InstDesc &D = T.d;
     int64_t n;
@@ -608,11 +613,12 @@ __global__ void __launch_bounds__(TILE) k_cell(Tables tb, int32_t step_off, int 
     if (sub >= T.sub_m) return;
     const Sub sb = substep(D, n, sub < 0 ? 0 : sub, sub < 0 ? 1 : T.sub_m);
     const uint32_t active = active_stimuli(D.ctrl, n);
-    double x = 0.0;
     const bool sample = sb.last && D.trace_every > 0 && (n + 1) % D.trace_every == 0;
-    if ((int32_t)threadIdx.x < T.count)
-        cell_step<R, MSET, BIDO, SCH>(D, (uint32_t)(T.begin + threadIdx.x), n, active, sample, x, sb);
-    if (sample) tile_partial(D, T, x, red);
+    const int32_t i = (int32_t)threadIdx.x;
+    double x = 0.0;
+    if (i < T.count)
+        cell_step<R, MSET, BIDO, SCH>(D, (uint32_t)(T.begin + i), n, active, sample, x, sb);
+    if (sample && (i & ~63) < T.count) wave_partial(D, T.wave0 + (i >> 6), x);
 }
 
 // ------------------------------------------------------- Purkinje graph

@@ -78,6 +78,7 @@ struct ep_server {
     std::string err;
     std::string driver_err;
     int32_t want_k = 50, want_remap = 1;   // launch settings, applied by the driver
+    int32_t tile_cells = 256;                // cell tile size in effect (set by the driver)
     int32_t scheme = 0;                    // time scheme of every request
     // autotuning requests, served by the driver on the live batch
     bool hold = false;                     // admit and upload, but do not step
@@ -369,6 +370,7 @@ void driver_main(ep_server *sv) {
             if (!e.empty()) sv->driver_err = e;
             sv->want_k = r.steps_per_graph;
             sv->want_remap = r.xcd_remap;
+            sv->tile_cells = r.cell_threads;
             sv->tune_pending = false;
             sv->tuned_live = live.size();
             sv->steps_since_tune = 0;
@@ -674,6 +676,7 @@ ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st) {
     st->bytes_in_use = sv->in_use;
     st->steps_per_graph = sv->want_k;
     st->xcd_remap = sv->want_remap;
+    st->tile_cells = sv->tile_cells;
     if (!sv->driver_err.empty()) { sv->err = sv->driver_err; return EP_EDEVICE; }
     return EP_OK;
 }

@@ -86,7 +86,8 @@ class ep_server_stats(C.Structure):
                 ("bytes_in_use", C.c_size_t), ("bytes_budget", C.c_size_t),
                 ("graph_launches", C.c_int64), ("table_updates", C.c_int64),
                 ("steps_per_graph", C.c_int32), ("xcd_remap", C.c_int32),
-                ("autotune_runs", C.c_int64), ("tuned_ms_per_step", C.c_double)]
+                ("autotune_runs", C.c_int64), ("tuned_ms_per_step", C.c_double),
+                ("tile_cells", C.c_int32), ("pad", C.c_int32)]
 
 
 class EPError(RuntimeError):
@@ -149,6 +150,9 @@ _SIGS = {
     "ep_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ep_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ep_set_launch": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "ep_set_tile_size": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ep_get_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32)]),
     "ep_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), _dp]),
     "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp, _dp]),
@@ -328,8 +332,17 @@ class Sim:
         _check(lib().ep_sync(self.h), self.h)
 
     def set_launch(self, block=256, steps_per_graph=50, xcd_remap=1):
-        """block: 0 or 256; steps_per_graph: 0 = no graphs."""
+        """block: cells per cell tile 64/128/256 (0 keeps); steps_per_graph: 0 = no graphs."""
         _check(lib().ep_set_launch(self.h, block, steps_per_graph, xcd_remap), self.h)
+
+    def set_tile_size(self, cells: int = 256):
+        _check(lib().ep_set_tile_size(self.h, int(cells)), self.h)
+
+    def launch(self) -> dict:
+        """The schedule and cell tile size in effect."""
+        a, c, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().ep_get_launch(self.h, C.byref(a), C.byref(c), C.byref(d)), self.h)
+        return {"tile_cells": a.value, "steps_per_graph": c.value, "xcd_remap": d.value}
 
     def medium_substeps(self) -> int:
         """Substeps per step of the 2D medium (1: it steps with the tets)."""
@@ -433,7 +446,9 @@ class Sim:
         k, r, ms = C.c_int32(), C.c_int32(), C.c_double()
         _check(lib().ep_autotune(self.h, int(trial_steps), C.byref(k), C.byref(r),
                                  C.byref(ms)), self.h)
-        return {"steps_per_graph": k.value, "xcd_remap": r.value, "ms_per_step": ms.value}
+        out = self.launch()
+        out["ms_per_step"] = ms.value
+        return out
 
     def profile_steps(self, n: int, per_step: bool = False):
         """n event-timed steps: (cell kernel ms, node gather ms) averages, and

@@ -309,6 +309,34 @@ def test_graph_replay_equals_direct_launch(ep):
     assert np.array_equal(va, vb)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tile_sizes_bitwise(ep, prec):
+    """Every cell tile size the autotuner can choose gives the same bits: potentials, activation times, APD90 and the
+    vbar trace, on a mesh of three model classes with ragged class ranges
+    (tets and a 2D medium with substeps), graphs and direct launches."""
+    w3 = M.config1(n_steps=0, nx=9, ny=7, nz=2)
+    rng = np.random.default_rng(3)
+    w3.model = rng.choice([M.TP06_ENDO, M.TP06_EPI, M.CRN], w3.n_tets).astype(np.uint8)
+    w2 = M.sheet_workload(14, 6, 0.5, model=M.STEWART, n_steps=0)
+    w = M.mixed_workload(w3, w2)
+    w.medium_substeps = 3
+    p = ep.EP_FP64 if prec == "fp64" else ep.EP_FP32_MIXED
+    ref = None
+    for tile in (256, 128, 64):
+        a = ep.Sim(w, prec=p, trace_every=10)
+        a.set_tile_size(tile)
+        for n in (7, 100, 243):
+            a.step(n)
+        got = (a.vm(), a.activation(), a.apd90(), a.mean_vm_trace()[1])
+        assert a.launch()["tile_cells"] == tile
+        if ref is None:
+            ref = got
+            assert np.isfinite(got[1]).sum() > 0.3 * w.n_tets
+            continue
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y, equal_nan=True), tile
+
+
 def test_trace_sample_same_from_host_and_device(ep):
     """A vbar sample taken by the last step issued is added up on the host;
     once the next step runs, the device adds the same partials: both give

@@ -130,13 +130,18 @@ def test_autotuned_schedule_keeps_results(ep):
     choice = a.autotune(20)
     assert choice["steps_per_graph"] in (0, 10, 25, 50, 100)
     assert choice["xcd_remap"] in (0, 1) and choice["ms_per_step"] > 0
+    assert choice["tile_cells"] in (256, 128, 64)
     # per remap: 20 direct steps, then each graph length k in whole graphs
-    # (20, 25, 50, 100) after one untimed graph (1 + 10 + 25 + 50 + 100)
-    used = 2 * (20 + 20 + 25 + 50 + 100) + 2 * (1 + 10 + 25 + 50 + 100)
+    # (20, 25, 50, 100) after one untimed graph (1 + 10 + 25 + 50 + 100);
+    # then three tile sizes at the chosen k, each an untimed graph (or one
+    # direct step) and whole graphs covering 20 steps
+    k = choice["steps_per_graph"]
+    shape = (k if k > 0 else 1) + (-(-20 // k) * k if k > 0 else 20)
+    used = 2 * (20 + 20 + 25 + 50 + 100) + 2 * (1 + 10 + 25 + 50 + 100) + 3 * shape
     assert a.time()[0] == used
-    a.step(1000 - used)
+    a.step(2000 - used)
     b = ep.Sim(w)
-    b.step(1000)
+    b.step(2000)
     assert np.array_equal(a.vm(), b.vm())
     assert np.array_equal(a.apd90(), b.apd90(), equal_nan=True)
 
@@ -149,6 +154,7 @@ def test_autotuned_schedule_keeps_results(ep):
     assert all(r["status"] == ep.EP_OK for r in res)
     st = sv.stats()
     assert st["autotune_runs"] >= 1 and st["steps_per_graph"] in (10, 25, 50, 100)
+    assert st["tile_cells"] in (256, 128, 64)
     for x, i in zip(ws, ids):
         vm, at, _ = alone(ep, x, ep.EP_FP32_MIXED, steps)
         assert np.array_equal(sv.vm(i), vm)
