@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/ep.h"
+#include "admission.hpp"
 #include "instance.hpp"
 
 namespace {
@@ -261,18 +262,22 @@ void driver_main(ep_server *sv) {
             sv->stepper.steps_per_graph = sv->want_k;
             sv->stepper.remap = sv->want_remap;
             size_t used = sv->in_use;
-            size_t slots = live.size();
-            for (auto it = sv->ready_q.begin(); it != sv->ready_q.end();) {
-                if ((int)(slots + admit.size()) >= sv->max_slots) break;
-                Req *r = sv->reqs[*it].get();
-                if (used + r->footprint <= sv->budget) {
-                    used += r->footprint;
-                    admit.push_back(r);
-                    it = sv->ready_q.erase(it);
+            const size_t slots = live.size();
+            std::vector<size_t> fp;
+            fp.reserve(sv->ready_q.size());
+            for (int64_t id : sv->ready_q) fp.push_back(sv->reqs[id]->footprint);
+            const size_t free_slots = (size_t)std::max<int64_t>(0, (int64_t)sv->max_slots - (int64_t)slots);
+            const std::vector<size_t> pick = ep::admit_ready(fp, used, sv->budget, free_slots);
+            std::deque<int64_t> rest;
+            for (size_t i = 0, k = 0; i < sv->ready_q.size(); ++i) {
+                if (k < pick.size() && pick[k] == i) {
+                    admit.push_back(sv->reqs[sv->ready_q[i]].get());
+                    ++k;
                 } else {
-                    ++it;
+                    rest.push_back(sv->ready_q[i]);
                 }
             }
+            sv->ready_q.swap(rest);
             sv->in_use = used;
         }
         bool changed = false;
