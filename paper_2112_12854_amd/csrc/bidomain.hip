@@ -8,9 +8,12 @@
 // basis is orthogonalised by classical Gram-Schmidt applied twice (batched
 // dot products instead of the j + 1 dependent passes of the modified
 // variant); dot products are per-block partials added in a fixed order, so a
-// solve gives the same bits on every run.  Only the (restart + 1) x restart
-// Hessenberg least-squares problem (Givens rotations, back substitution) is
-// advanced on the host, from a few numbers read back per Arnoldi step.
+// solve gives the same bits on every run.  The (restart + 1) x restart
+// Hessenberg least-squares problem (Givens rotations, the convergence test,
+// back substitution) is advanced on the device by one-lane kernels, and the
+// Arnoldi steps run in captured graphs of a few steps each whose kernels
+// return at once after a device flag ends the cycle: the host reads the
+// state back once per chunk and once per restart, never per Arnoldi step.
 // GMRES is preconditioned on the right by a two-level additive method (the
 // residual it monitors stays the true one): Jacobi plus a dense solve on
 // aggregates of cells, which removes the growth of the iteration count with
@@ -35,11 +38,18 @@ constexpr int NQ = 8;          // dot products per pass of the reduction kernel
 constexpr int G = kBidoBlocks; // blocks of the reduction kernels
 
 // node values by inverse-distance weights (sliced ELL, one lane per node)
+// Kernels given a stop flag return at once while it is set (the Arnoldi
+// steps enqueued past the end of a cycle).
+__device__ __forceinline__ bool stopped(const int32_t *stop) { return stop && *stop; }
+
+// (x scaled by *xs when xs is given)
 __global__ void __launch_bounds__(BT) k_gather(const int64_t *__restrict__ off,
                                                const int32_t *__restrict__ cell,
                                                const double *__restrict__ w,
                                                const double *__restrict__ x,
-                                               double *__restrict__ xn, int64_t nn) {
+                                               double *__restrict__ xn, int64_t nn,
+                                               const int32_t *stop, const double *xs = nullptr) {
+    if (stopped(stop)) return;
     const int64_t node = blockIdx.x * (int64_t)BT + threadIdx.x;
     if (node >= nn) return;
     const int64_t e0 = off[node >> 6] + (node & 63), e1 = off[(node >> 6) + 1];
@@ -52,7 +62,7 @@ __global__ void __launch_bounds__(BT) k_gather(const int64_t *__restrict__ off,
         a3 += w[e + 192] * x[cell[e + 192]];
     }
     for (; e < e1; e += 64) a0 += w[e] * x[cell[e]];
-    xn[node] = (a0 + a1) + (a2 + a3);
+    xn[node] = xs ? *xs * ((a0 + a1) + (a2 + a3)) : (a0 + a1) + (a2 + a3);
 }
 
 // y_c = f_c (sum_s beta_s x_n[node_s] + sum_f b_f (x[nbr_f] - x_c)) with the
@@ -65,7 +75,9 @@ __global__ void __launch_bounds__(BT) k_flux(const int32_t *__restrict__ cnode,
                                              const double *__restrict__ x,
                                              const double *__restrict__ xn,
                                              const double *__restrict__ vol, double factor,
-                                             double *__restrict__ y, int64_t nc) {
+                                             double *__restrict__ y, int64_t nc,
+                                             const int32_t *stop) {
+    if (stopped(stop)) return;
     const int64_t c = blockIdx.x * (int64_t)BT + threadIdx.x;
     if (c >= nc) return;
     const double xc = x[c];
@@ -80,7 +92,8 @@ __global__ void __launch_bounds__(BT) k_flux(const int32_t *__restrict__ cnode,
 // per-block partial sums of cnt <= NQ dot products <w, V_q>, V_q = V + q n
 __global__ void __launch_bounds__(BT) k_dots(const double *__restrict__ w,
                                              const double *__restrict__ V, int cnt, int64_t n,
-                                             double *__restrict__ part) {
+                                             double *__restrict__ part, const int32_t *stop) {
+    if (stopped(stop)) return;
     __shared__ double red[NQ][BT];
     double acc[NQ];
 #pragma unroll
@@ -104,7 +117,8 @@ __global__ void __launch_bounds__(BT) k_dots(const double *__restrict__ w,
 
 // out[q] = sum of the G partials of row q (one block per row, fixed order)
 __global__ void __launch_bounds__(BT) k_reduce(const double *__restrict__ part,
-                                               double *__restrict__ out) {
+                                               double *__restrict__ out, const int32_t *stop) {
+    if (stopped(stop)) return;
     __shared__ double red[BT];
     const double *p = part + (int64_t)blockIdx.x * G;
     double acc = 0.0;
@@ -120,7 +134,9 @@ __global__ void __launch_bounds__(BT) k_reduce(const double *__restrict__ part,
 
 // w -= sum_{q < cnt} h_q V_q
 __global__ void __launch_bounds__(BT) k_sub(double *__restrict__ w, const double *__restrict__ V,
-                                            const double *__restrict__ h, int cnt, int64_t n) {
+                                            const double *__restrict__ h, int cnt, int64_t n,
+                                            const int32_t *stop) {
+    if (stopped(stop)) return;
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
     if (e >= n) return;
     double x = w[e];
@@ -128,21 +144,27 @@ __global__ void __launch_bounds__(BT) k_sub(double *__restrict__ w, const double
     w[e] = x;
 }
 
-// x += sum_{q < cnt} y_q V_q
-__global__ void __launch_bounds__(BT) k_update(double *__restrict__ x, const double *__restrict__ V,
-                                               const double *__restrict__ y, int cnt, int64_t n) {
+// x += sum_{q < *cnt} y_q s_q U_q (the count of the cycle's steps on the
+// device; the basis vectors V_q = s_q U_q)
+__global__ void __launch_bounds__(BT) k_update(double *__restrict__ x, const double *__restrict__ U,
+                                               const double *__restrict__ y,
+                                               const double *__restrict__ sc, const int32_t *cnt,
+                                               int64_t n) {
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
-    if (e >= n) return;
+    const int k = *cnt;
+    if (e >= n || k == 0) return;
     double acc = x[e];
-    for (int q = 0; q < cnt; ++q) acc += y[q] * V[q * n + e];
+    for (int q = 0; q < k; ++q) acc += y[q] * sc[q] * U[q * n + e];
     x[e] = acc;
 }
 
-// dst = a src
+// dst = a src, with a (a, or *ad when given) read on the device
 __global__ void __launch_bounds__(BT) k_scale(double *__restrict__ dst, const double *__restrict__ src,
-                                              double a, int64_t n) {
+                                              double a, const double *ad, int64_t n,
+                                              const int32_t *stop) {
+    if (stopped(stop)) return;
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
-    if (e < n) dst[e] = a * src[e];
+    if (e < n) dst[e] = (ad ? *ad : a) * src[e];
 }
 
 // w = b - w
@@ -164,7 +186,9 @@ __global__ void __launch_bounds__(BT) k_shift(double *__restrict__ x, const doub
 __global__ void __launch_bounds__(BT) k_restrict(const double *__restrict__ r,
                                                  const int32_t *__restrict__ off,
                                                  const int32_t *__restrict__ cells,
-                                                 double *__restrict__ rc) {
+                                                 double *__restrict__ rc, const int32_t *stop,
+                                                 const double *rs = nullptr) {
+    if (stopped(stop)) return;
     __shared__ double red[BT];
     double acc = 0.0;
     for (int32_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += BT) acc += r[cells[i]];
@@ -174,13 +198,15 @@ __global__ void __launch_bounds__(BT) k_restrict(const double *__restrict__ r,
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) rc[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) rc[blockIdx.x] = rs ? *rs * red[0] : red[0];
 }
 
 // zc = A_c^{-1} rc (dense, row-major; one block per row)
 __global__ void __launch_bounds__(BT) k_coarse(const double *__restrict__ cinv,
                                                const double *__restrict__ rc,
-                                               double *__restrict__ zc, int32_t na) {
+                                               double *__restrict__ zc, int32_t na,
+                                               const int32_t *stop) {
+    if (stopped(stop)) return;
     __shared__ double red[BT];
     const double *row = cinv + (int64_t)blockIdx.x * na;
     double acc = 0.0;
@@ -199,29 +225,275 @@ __global__ void __launch_bounds__(BT) k_smooth(const double *__restrict__ r,
                                                const double *__restrict__ dinv,
                                                const int32_t *__restrict__ agg_of,
                                                const double *__restrict__ zc, double omega,
-                                               double *__restrict__ z, int64_t n) {
+                                               double *__restrict__ z, int64_t n,
+                                               const int32_t *stop, const double *rs = nullptr) {
+    if (stopped(stop)) return;
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
-    if (e < n) z[e] = omega * dinv[e] * r[e] + zc[agg_of[e]];
+    if (e < n) z[e] = omega * dinv[e] * (rs ? *rs * r[e] : r[e]) + zc[agg_of[e]];
 }
 
-// t = sum_{q < cnt} y_q V_q
-__global__ void __launch_bounds__(BT) k_combine(double *__restrict__ t, const double *__restrict__ V,
-                                                const double *__restrict__ y, int cnt, int64_t n) {
+// t = sum_{q < *cnt} y_q s_q U_q
+__global__ void __launch_bounds__(BT) k_combine(double *__restrict__ t, const double *__restrict__ U,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ sc, const int32_t *cnt,
+                                                int64_t n, const int32_t *stop) {
+    if (stopped(stop)) return;
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
     if (e >= n) return;
+    const int k = *cnt;
     double acc = 0.0;
-    for (int q = 0; q < cnt; ++q) acc += y[q] * V[q * n + e];
+    for (int q = 0; q < k; ++q) acc += y[q] * sc[q] * U[q * n + e];
     t[e] = acc;
 }
 
 // x += z
 __global__ void __launch_bounds__(BT) k_add(double *__restrict__ x, const double *__restrict__ z,
-                                            int64_t n) {
+                                            int64_t n, const int32_t *stop) {
+    if (stopped(stop)) return;
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
     if (e < n) x[e] += z[e];
 }
 
+// ---- GMRES state on the device: one lane advances the Hessenberg
+// least-squares problem exactly as the textbook method does on the host
+struct GmCtl {
+    double bnorm, beta, relres, pad0;  // |b|, |r| at the cycle start, |r|/|b|
+    int32_t it, k, stop, done;         // Arnoldi steps so far, steps of this cycle, cycle over, solve over
+    int32_t noupd;                     // no update this cycle (k = 0)
+    uint32_t count[3];                 // blocks done, per fused reduction kernel
+};
+static_assert(sizeof(GmCtl) == 64, "the control block takes the first 8 doubles");
+
+// The basis is kept unnormalised: V_q = s_q U_q, s_q = 1 / |U_q|.
+struct GmView {
+    GmCtl *c;
+    double *H, *cs, *sn, *g, *y, *s;   // H row-major (m + 1) x m; s: m + 1 scales
+};
+GmView gm_view(double *gm, int m) {
+    GmView v;
+    v.c = (GmCtl *)gm;
+    v.H = gm + 8;
+    v.cs = v.H + (size_t)(m + 1) * m;
+    v.sn = v.cs + m;
+    v.g = v.sn + m;
+    v.y = v.g + (m + 1);
+    v.s = v.y + m;
+    return v;
+}
+
+__global__ void k_gm_init(GmCtl *c, const double *bb) {
+    if (threadIdx.x) return;
+    c->bnorm = sqrt(bb[0]);
+    c->it = 0;
+    c->k = 0;
+    c->noupd = 1;
+    c->relres = 0.0;
+    c->count[0] = c->count[1] = c->count[2] = 0;
+    c->done = c->stop = c->bnorm == 0.0;
+}
+
+// start of a restart cycle from the true residual's squared norm rr
+__global__ void k_gm_start(GmView v, const double *rr, double tol, int32_t max_iter, int m) {
+    if (threadIdx.x) return;
+    GmCtl *c = v.c;
+    c->k = 0;
+    c->noupd = 1;
+    if (c->done) { c->stop = 1; return; }
+    c->beta = sqrt(rr[0]);
+    c->relres = c->beta / c->bnorm;
+    if (c->beta <= tol * c->bnorm || c->it >= max_iter) {
+        c->done = c->stop = 1;
+        return;
+    }
+    c->stop = 0;
+    v.g[0] = c->beta;
+    for (int i = 1; i <= m; ++i) v.g[i] = 0.0;
+    v.s[0] = 1.0 / c->beta;
+}
+
+// Arnoldi step j (one lane): column j of H from the two Gram-Schmidt
+// passes and the new norm (hd: pass 1 at [0, j], pass 2 at [m + 1,
+// m + 1 + j], |U_{j+1}|^2 at 2 (m + 1)), the earlier rotations, a new one,
+// the reduced right-hand side, the test, and the next basis scale
+__device__ void gm_step(const GmView &v, const double *hd, int j, int m, double tol,
+                        int32_t max_iter) {
+    GmCtl *c = v.c;
+    double *H = v.H;
+    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hd[i] + hd[m + 1 + i];
+    const double hn = sqrt(hd[2 * (m + 1)]);
+    H[(size_t)(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = v.cs[i] * a + v.sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -v.sn[i] * a + v.cs[i] * b;
+    }
+    const double den = hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+    v.cs[j] = den > 0.0 ? H[(size_t)j * m + j] / den : 1.0;
+    v.sn[j] = den > 0.0 ? H[(size_t)(j + 1) * m + j] / den : 0.0;
+    H[(size_t)j * m + j] = den;
+    H[(size_t)(j + 1) * m + j] = 0.0;
+    v.g[j + 1] = -v.sn[j] * v.g[j];
+    v.g[j] = v.cs[j] * v.g[j];
+    c->it += 1;
+    c->k = j + 1;
+    c->noupd = 0;
+    if (fabs(v.g[j + 1]) <= tol * c->bnorm || hn == 0.0 || c->it >= max_iter || j == m - 1)
+        c->stop = 1;
+    else
+        v.s[j + 1] = 1.0 / hn;
+}
+
+// R y = g for the cycle's k steps (back substitution)
+__global__ void k_gm_solve(GmView v, int m) {
+    if (threadIdx.x) return;
+    const int k = v.c->k;
+    for (int i = k - 1; i >= 0; --i) {
+        double acc = v.g[i];
+        for (int l = i + 1; l < k; ++l) acc -= v.H[(size_t)i * m + l] * v.y[l];
+        v.y[i] = acc / v.H[(size_t)i * m + i];
+    }
+}
+
+// ---- Arnoldi-step kernels: the vector update of a step and the block
+// partials of its dot products in one pass (one lane per cell), the rows
+// then added by k_rows, one block per row, in a fixed order (so a solve
+// still gives the same bits on every run)
+constexpr int NW = BT / 64;    // waves per block
+
+// a wave's 64 values added by a fixed butterfly (lane 0's result)
+__device__ __forceinline__ double wave_sum(double a) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return a;
+}
+
+// block partials <w, U_q> for q < cnt of this block's cells (w_e and the
+// rows at element e = the lane's cell, 0 past n), in groups of NQ rows:
+// each wave adds its lanes by the butterfly, then the NW wave sums in a
+// fixed tree; row q's partial of block b at part[q * gridDim.x + b]
+__device__ void dot_rows(double we, const double *__restrict__ U, int cnt, int64_t n, int64_t e,
+                         double *part, double (*red)[NW]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q0 = 0; q0 < cnt; q0 += NQ) {
+        const int k = min(NQ, cnt - q0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < k) {
+                const double a = wave_sum(e < n ? we * U[(int64_t)(q0 + q) * n + e] : 0.0);
+                if (lane == 0) red[q][wave] = a;
+            }
+        __syncthreads();
+        if ((int)threadIdx.x < k)
+            part[(int64_t)(q0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+                (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+        __syncthreads();
+    }
+}
+
+// w = A z (flux-sum form; node values zn already formed, z scaled by *zs
+// when given), with the partials of <w, U_q>, q < cnt
+__global__ void __launch_bounds__(BT) k_op_dots(const int32_t *__restrict__ cnode,
+                                                const double *__restrict__ beta,
+                                                const int32_t *__restrict__ cnbr,
+                                                const double *__restrict__ bf,
+                                                const double *__restrict__ z, const double *zs,
+                                                const double *__restrict__ zn,
+                                                double *__restrict__ w, const double *__restrict__ U,
+                                                int cnt, int64_t nc, double *part, const int32_t *stop) {
+    if (stopped(stop)) return;
+    __shared__ double red[NQ][NW];
+    const int64_t c = blockIdx.x * (int64_t)BT + threadIdx.x;
+    double y = 0.0;
+    if (c < nc) {
+        const double xc = z[c];
+        double acc = 0.0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc += beta[tix(c, s, 8)] * zn[cnode[tix(c, s, 8)]];
+        double two = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) two += bf[tix(c, q, 4)] * (z[cnbr[tix(c, q, 4)]] - xc);
+        y = acc + (zs ? *zs : 1.0) * two;
+        w[c] = y;
+    }
+    dot_rows(y, U, cnt, nc, c, part, red);
+}
+
+// w -= sum_{q < cnt} h_q V_q (in place), with the partials of <w, U_q>
+__global__ void __launch_bounds__(BT) k_sub_dots(double *__restrict__ w, const double *__restrict__ U,
+                                                 const double *__restrict__ sc,
+                                                 const double *__restrict__ h, int cnt, int64_t n,
+                                                 double *part, const int32_t *stop) {
+    if (stopped(stop)) return;
+    __shared__ double red[NQ][NW];
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    double x = 0.0;
+    if (e < n) {
+        x = w[e];
+        for (int q = 0; q < cnt; ++q) x -= h[q] * sc[q] * U[(int64_t)q * n + e];
+        w[e] = x;
+    }
+    dot_rows(x, U, cnt, n, e, part, red);
+}
+
+// U_{j+1} = w - sum_{q <= j} h_q V_q, with the partials of |U_{j+1}|^2
+__global__ void __launch_bounds__(BT) k_sub_norm(const double *__restrict__ w, double *__restrict__ U,
+                                                 const double *__restrict__ sc,
+                                                 const double *__restrict__ h, int j, int64_t n,
+                                                 double *part, const int32_t *stop) {
+    if (stopped(stop)) return;
+    __shared__ double red[NQ][NW];
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    double *un = U + (int64_t)(j + 1) * n;
+    double x = 0.0;
+    if (e < n) {
+        x = w[e];
+        for (int q = 0; q <= j; ++q) x -= h[q] * sc[q] * U[(int64_t)q * n + e];
+        un[e] = x;
+    }
+    dot_rows(x, un, 1, n, e, part, red);
+}
+
+// out[q] = sc[q] * (sum of the np partials of row q) (or the sum); one block
+// per row, lane t adding partials t, t + BT, ... in order, then a fixed tree
+__global__ void __launch_bounds__(BT) k_rows(const double *__restrict__ part, int64_t np,
+                                             const double *__restrict__ sc, double *__restrict__ out,
+                                             const int32_t *stop) {
+    if (stopped(stop)) return;
+    __shared__ double red[BT];
+    const double *p = part + (int64_t)blockIdx.x * np;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += BT) acc += p[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sc ? sc[blockIdx.x] * red[0] : red[0];
+}
+
+// |U_{j+1}|^2 from its partials, then the step's least-squares update
+__global__ void __launch_bounds__(BT) k_norm_step(const double *__restrict__ part, int64_t np, GmView v,
+                                                  double *hd, int j, int m, double tol,
+                                                  int32_t max_iter) {
+    if (v.c->stop) return;
+    __shared__ double red[BT];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += BT) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        hd[2 * (m + 1)] = red[0];
+        gm_step(v, hd, j, m, tol, max_iter);
+    }
+}
+
 constexpr double kOmega = 0.7;   // Jacobi weight of the preconditioner
+constexpr int kChunk = 4;        // Arnoldi steps per captured graph
 
 struct Solver {
     Inst &I;
@@ -230,28 +502,63 @@ struct Solver {
     int grid_c, grid_n;
 
     // partial rows [row0, row0 + cnt) <- <w, V + q n>, then reduced into out[0..cnt)
-    void dots(const double *w, const double *V, int cnt, double *out) {
+    void dots(const double *w, const double *V, int cnt, double *out, const int32_t *stop = nullptr) {
         for (int q0 = 0; q0 < cnt; q0 += NQ) {
             const int k = std::min(NQ, cnt - q0);
-            k_dots<<<G, BT, 0, st>>>(w, V + (int64_t)q0 * nc, k, nc, I.bd.part + (int64_t)q0 * G);
+            k_dots<<<G, BT, 0, st>>>(w, V + (int64_t)q0 * nc, k, nc, I.bd.part + (int64_t)q0 * G, stop);
         }
-        k_reduce<<<cnt, BT, 0, st>>>(I.bd.part, out);
+        k_reduce<<<cnt, BT, 0, st>>>(I.bd.part, out, stop);
     }
     // y = A x (elliptic operator, flux-sum form)
-    void apply(const double *x, double *y) {
+    void apply(const double *x, double *y, const int32_t *stop = nullptr) {
         const InstDesc &D = I.desc;
-        k_gather<<<grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, x, I.bd.xn, nn);
-        k_flux<<<grid_c, BT, 0, st>>>(D.cnode, I.bd.ebeta, D.cnbr, I.bd.eb, x, I.bd.xn, nullptr, 1.0, y, nc);
+        k_gather<<<grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, x, I.bd.xn, nn,
+                                        stop);
+        k_flux<<<grid_c, BT, 0, st>>>(D.cnode, I.bd.ebeta, D.cnbr, I.bd.eb, x, I.bd.xn, nullptr, 1.0, y, nc,
+                                      stop);
     }
     // z = M^{-1} r
-    void prec(const double *r, double *z) {
+    void prec(const double *r, double *z, const int32_t *stop = nullptr) {
         const Bido &B = I.bd;
-        k_restrict<<<B.n_agg, BT, 0, st>>>(r, B.agg_off, B.agg_cells, B.rc);
-        k_coarse<<<B.n_agg, BT, 0, st>>>(B.cinv, B.rc, B.zc, B.n_agg);
-        k_smooth<<<grid_c, BT, 0, st>>>(r, B.dinv, B.agg_of, B.zc, kOmega, z, nc);
+        k_restrict<<<B.n_agg, BT, 0, st>>>(r, B.agg_off, B.agg_cells, B.rc, stop);
+        k_coarse<<<B.n_agg, BT, 0, st>>>(B.cinv, B.rc, B.zc, B.n_agg, stop);
+        k_smooth<<<grid_c, BT, 0, st>>>(r, B.dinv, B.agg_of, B.zc, kOmega, z, nc, stop);
     }
-    hipError_t read(const double *dev, int cnt) {
-        hipError_t e = hipMemcpyAsync(I.bd.h_host, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, st);
+    // Arnoldi steps [j0, j1) of a cycle, each a no-op once the cycle is over:
+    // 7 kernels each with the preconditioner (4 without)
+    void steps(int j0, int j1, const GmView &gv) {
+        Bido &B = I.bd;
+        const InstDesc &D = I.desc;
+        const int m = B.restart;
+        const int32_t *stop = &gv.c->stop;
+        double *hd = B.h;
+        for (int j = j0; j < j1; ++j) {
+            const double *uj = B.V + (int64_t)j * nc;
+            const double *sj = gv.s + j;
+            const double *z = uj, *zs = sj;
+            if (B.precond) {                     // right preconditioning: z = M^{-1} V_j
+                k_restrict<<<B.n_agg, BT, 0, st>>>(uj, B.agg_off, B.agg_cells, B.rc, stop, sj);
+                k_coarse<<<B.n_agg, BT, 0, st>>>(B.cinv, B.rc, B.zc, B.n_agg, stop);
+                k_smooth<<<grid_c, BT, 0, st>>>(uj, B.dinv, B.agg_of, B.zc, kOmega, B.z, nc, stop, sj);
+                z = B.z;
+                zs = nullptr;
+            }
+            k_gather<<<grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, z, B.xn, nn,
+                                            stop, zs);
+            // w = A z with pass 1 of classical Gram-Schmidt, pass 2, then the
+            // new vector, its norm and the least-squares update
+            k_op_dots<<<grid_c, BT, 0, st>>>(D.cnode, B.ebeta, D.cnbr, B.eb, z, zs, B.xn, B.w, B.V, j + 1,
+                                             nc, B.part, stop);
+            k_rows<<<j + 1, BT, 0, st>>>(B.part, grid_c, gv.s, hd, stop);
+            k_sub_dots<<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd, j + 1, nc, B.part, stop);
+            k_rows<<<j + 1, BT, 0, st>>>(B.part, grid_c, gv.s, hd + (m + 1), stop);
+            k_sub_norm<<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd + (m + 1), j, nc, B.part, stop);
+            k_norm_step<<<1, BT, 0, st>>>(B.part, grid_c, gv, hd, j, m, B.tol, B.max_iter);
+        }
+    }
+    // the state's control block to the host
+    hipError_t read(const GmView &gv) {
+        hipError_t e = hipMemcpyAsync(I.bd.h_host, gv.c, sizeof(GmCtl), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return e;
         return hipStreamSynchronize(st);
     }
@@ -265,100 +572,68 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
     Solver S{I, st, D.nc, D.nn, (int)((D.nc + BT - 1) / BT), (int)((D.nn + BT - 1) / BT)};
     const int64_t nc = D.nc;
     const int m = B.restart;
+    const GmView gv = gm_view(B.gm, m);
     const double *v = (const double *)D.v[I.host_step & 1];
-    double *hd = B.h;                       // [0, m] pass 1, [m+1, 2m+1] pass 2, then norms
-    double *const h_norm = B.h + 2 * (m + 1);
+    double *const h_norm = B.h + 2 * (m + 1);   // |b|^2, |r|^2 (the steps' |w|^2 slot), then the mean
+    const GmCtl *hc = (const GmCtl *)B.h_host;
     hipError_t e;
     auto fail = [&](const char *what) { return std::string(what) + ": " + hipGetErrorString(e); };
 
     // right-hand side: -chi Cm V_c L_i(v) = -(flux sums of v with M_i)
-    k_gather<<<S.grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, v, B.xn, D.nn);
+    k_gather<<<S.grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, v, B.xn, D.nn,
+                                      nullptr);
     k_flux<<<S.grid_c, BT, 0, st>>>(D.cnode, (const double *)D.cbeta, D.cnbr, (const double *)D.cb, v,
-                                    B.xn, D.vol, -B.chi_cm, B.b, nc);
+                                    B.xn, D.vol, -B.chi_cm, B.b, nc, nullptr);
     S.dots(B.b, B.b, 1, h_norm);
-    if ((e = S.read(h_norm, 1)) != hipSuccess) return fail("bidomain readback");
-    const double bnorm = std::sqrt(B.h_host[0]);
-    int64_t it = 0;
-    double relres = 0.0;
-    if (bnorm == 0.0) {
-        k_scale<<<S.grid_c, BT, 0, st>>>(B.phi, B.phi, 0.0, nc);
+    k_gm_init<<<1, 64, 0, st>>>(gv.c, h_norm);
+    if ((e = S.read(gv)) != hipSuccess) return fail("bidomain readback");
+    if (hc->done) {
+        k_scale<<<S.grid_c, BT, 0, st>>>(B.phi, B.phi, 0.0, nullptr, nc, nullptr);
     } else {
-        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+        const int n_chunks = (m + kChunk - 1) / kChunk;
+        if ((int)B.chunk_graphs.size() != n_chunks) B.chunk_graphs.assign(n_chunks, nullptr);
         for (;;) {
-            S.apply(B.phi, B.w);
-            k_resid<<<S.grid_c, BT, 0, st>>>(B.w, B.b, nc);
-            S.dots(B.w, B.w, 1, h_norm);
-            if ((e = S.read(h_norm, 1)) != hipSuccess) return fail("bidomain readback");
-            const double beta = std::sqrt(B.h_host[0]);
-            relres = beta / bnorm;
-            if (beta <= B.tol * bnorm || it >= B.max_iter) break;
-            k_scale<<<S.grid_c, BT, 0, st>>>(B.V, B.w, 1.0 / beta, nc);
-            std::fill(g.begin(), g.end(), 0.0);
-            g[0] = beta;
-            int k = 0;
-            for (int j = 0; j < m && it < B.max_iter; ++j) {
-                const double *vj = B.V + (int64_t)j * nc;
-                if (B.precond) {                     // right preconditioning: A M^{-1} v_j
-                    S.prec(vj, B.z);
-                    S.apply(B.z, B.w);
-                } else {
-                    S.apply(vj, B.w);
+            // the true residual r = b - A phi starts a cycle (or ends the
+            // solve) as U_0, V_0 = r / |r|
+            S.apply(B.phi, B.V);
+            k_resid<<<S.grid_c, BT, 0, st>>>(B.V, B.b, nc);
+            S.dots(B.V, B.V, 1, h_norm);
+            k_gm_start<<<1, 64, 0, st>>>(gv, h_norm, B.tol, B.max_iter, m);
+            if ((e = S.read(gv)) != hipSuccess) return fail("bidomain readback");
+            if (hc->done) break;
+            for (int q = 0; q < n_chunks; ++q) {
+                if (!B.chunk_graphs[q]) {
+                    hipGraph_t g = nullptr;
+                    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                        return fail("bidomain capture");
+                    S.steps(q * kChunk, std::min(m, (q + 1) * kChunk), gv);
+                    if ((e = hipStreamEndCapture(st, &g)) != hipSuccess) return fail("bidomain capture");
+                    e = hipGraphInstantiate(&B.chunk_graphs[q], g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    if (e != hipSuccess) { B.chunk_graphs[q] = nullptr; return fail("bidomain graph"); }
                 }
-                // classical Gram-Schmidt, twice
-                S.dots(B.w, B.V, j + 1, hd);
-                k_sub<<<S.grid_c, BT, 0, st>>>(B.w, B.V, hd, j + 1, nc);
-                S.dots(B.w, B.V, j + 1, hd + (m + 1));
-                k_sub<<<S.grid_c, BT, 0, st>>>(B.w, B.V, hd + (m + 1), j + 1, nc);
-                S.dots(B.w, B.w, 1, h_norm);
-                if ((e = hipMemcpyAsync(B.h_host, hd, (2 * (m + 1) + 1) * sizeof(double),
-                                        hipMemcpyDeviceToHost, st)) != hipSuccess ||
-                    (e = hipStreamSynchronize(st)) != hipSuccess)
-                    return fail("bidomain readback");
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = B.h_host[i] + B.h_host[m + 1 + i];
-                const double hn = std::sqrt(B.h_host[2 * (m + 1)]);
-                H[(size_t)(j + 1) * m + j] = hn;
-                for (int i = 0; i < j; ++i) {       // earlier rotations
-                    const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                    H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                    H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-                }
-                const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
-                cs[j] = den > 0.0 ? H[(size_t)j * m + j] / den : 1.0;
-                sn[j] = den > 0.0 ? H[(size_t)(j + 1) * m + j] / den : 0.0;
-                H[(size_t)j * m + j] = den;
-                H[(size_t)(j + 1) * m + j] = 0.0;
-                g[j + 1] = -sn[j] * g[j];
-                g[j] = cs[j] * g[j];
-                ++it;
-                k = j + 1;
-                if (std::fabs(g[j + 1]) <= B.tol * bnorm || hn == 0.0) break;
-                k_scale<<<S.grid_c, BT, 0, st>>>(B.V + (int64_t)(j + 1) * nc, B.w, 1.0 / hn, nc);
+                if ((e = hipGraphLaunch(B.chunk_graphs[q], st)) != hipSuccess) return fail("bidomain graph launch");
+                if ((e = S.read(gv)) != hipSuccess) return fail("bidomain readback");
+                if (hc->stop) break;
             }
-            for (int i = k - 1; i >= 0; --i) {      // R y = g
-                double acc = g[i];
-                for (int l = i + 1; l < k; ++l) acc -= H[(size_t)i * m + l] * y[l];
-                y[i] = acc / H[(size_t)i * m + i];
-            }
-            if ((e = hipMemcpyAsync(B.y, y.data(), k * sizeof(double), hipMemcpyHostToDevice, st)) != hipSuccess)
-                return fail("bidomain upload");
+            k_gm_solve<<<1, 64, 0, st>>>(gv, m);
             if (B.precond) {                         // x += M^{-1} V y
-                k_combine<<<S.grid_c, BT, 0, st>>>(B.t, B.V, B.y, k, nc);
-                S.prec(B.t, B.z);
-                k_add<<<S.grid_c, BT, 0, st>>>(B.phi, B.z, nc);
+                k_combine<<<S.grid_c, BT, 0, st>>>(B.t, B.V, gv.y, gv.s, &gv.c->k, nc, &gv.c->noupd);
+                S.prec(B.t, B.z, &gv.c->noupd);
+                k_add<<<S.grid_c, BT, 0, st>>>(B.phi, B.z, nc, &gv.c->noupd);
             } else {
-                k_update<<<S.grid_c, BT, 0, st>>>(B.phi, B.V, B.y, k, nc);
+                k_update<<<S.grid_c, BT, 0, st>>>(B.phi, B.V, gv.y, gv.s, &gv.c->k, nc);
             }
-            // y is pageable host memory: wait before it is rewritten
-            if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail("bidomain update");
         }
     }
     // zero volume-weighted mean
     S.dots(B.phi, D.vol, 1, h_norm + 1);
     k_shift<<<S.grid_c, BT, 0, st>>>(B.phi, h_norm + 1, 1.0 / B.total_vol, nc);
     if ((e = hipGetLastError()) != hipSuccess) return fail("bidomain kernels");
+    const int64_t it = hc->it;
     B.last_iters = it;
     B.total_iters += it;
-    B.last_relres = relres;
+    B.last_relres = hc->relres;
     return "";
 }
 

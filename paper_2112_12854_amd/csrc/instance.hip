@@ -329,7 +329,8 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
         const size_t m1 = (size_t)sp.bido_restart + 1;
         b += round256(tiled_len(c, 8) * 8) + round256(tiled_len(c, 4) * 8) + 3 * round256(c * 8) +
              round256(n * 8) + round256(m1 * c * 8);
-        b += round256(m1 * kBidoBlocks * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8);
+        b += round256(m1 * bido_part_cols((int64_t)c) * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8) +
+             round256(gmres_state_doubles((int)m1 - 1) * 8);
         const size_t na = (size_t)I.coarse.n_agg;
         if (na > 0)
             b += 2 * round256(c * 4) + round256((na + 1) * 4) + round256(c * 8) +
@@ -625,11 +626,13 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         B.w = (double *)dalloc(I, nc * 8);
         B.xn = (double *)dalloc(I, nn * 8);
         B.V = (double *)dalloc(I, m1 * nc * 8);
-        B.part = (double *)dalloc(I, m1 * kBidoBlocks * 8);
+        B.part = (double *)dalloc(I, m1 * bido_part_cols(nc) * 8);
         B.h = (double *)dalloc(I, (2 * m1 + 2) * 8);
         B.y = (double *)dalloc(I, m1 * 8);
-        if (!B.b || !B.w || !B.xn || !B.V || !B.part || !B.h || !B.y) return fail_mem();
-        if (hipHostMalloc((void **)&B.h_host, (2 * m1 + 2) * 8) != hipSuccess) return fail_mem();
+        B.gm = (double *)dalloc(I, gmres_state_doubles((int)m1 - 1) * 8);
+        if (!B.b || !B.w || !B.xn || !B.V || !B.part || !B.h || !B.y || !B.gm) return fail_mem();
+        if (hipHostMalloc((void **)&B.h_host, std::max<size_t>((2 * m1 + 2) * 8, 64)) != hipSuccess)
+            return fail_mem();
         D.phi = B.phi;
         const Coarse &Cs = I.coarse;
         B.n_agg = Cs.n_agg;
@@ -668,6 +671,9 @@ void free_instance(Inst &I) {
     }
     I.allocs.clear();
     if (I.bd.h_host) (void)hipHostFree(I.bd.h_host);
+    for (hipGraphExec_t g : I.bd.chunk_graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    I.bd.chunk_graphs.clear();
     I.bd = Bido();
     if (I.arena) {
         if (I.al.free) I.al.free(I.arena, I.al.ctx);

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -77,6 +78,11 @@ struct Bido {
     int64_t last_iters = 0, total_iters = 0;
     double last_relres = 0;
     double *h_host = nullptr;          // pinned readback of h
+    // GMRES state on the device (control block, Hessenberg matrix, Givens
+    // rotations, reduced right-hand side, update coefficients) and the
+    // captured graphs of the Arnoldi-step chunks (built at the first solve)
+    double *gm = nullptr;
+    std::vector<hipGraphExec_t> chunk_graphs;
     // two-level preconditioner
     int32_t n_agg = 0;
     const int32_t *agg_of = nullptr, *agg_off = nullptr, *agg_cells = nullptr;
@@ -250,11 +256,19 @@ struct TuneResult {
 std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
                              bool allow_direct = true);
 
+// Doubles of the device GMRES state for restart length m.
+inline size_t gmres_state_doubles(int m) {
+    return 8 + (size_t)(m + 1) * m + 2 * (size_t)m + (m + 1) + m + (m + 1);
+}
+
 // Bidomain: solve the extracellular equation for the instance's current
 // v^{n} (after a step), from its phi_e (instance must be synchronised with
 // nothing pending that writes v); enqueued on `stream`, synchronises it.
 std::string bidomain_solve(Inst &I, hipStream_t stream);
 constexpr int kBidoBlocks = 1024;      // blocks of the reduction kernels
+// partial sums per dot-product row of the bidomain solve: one per block of
+// 256 cells, at least kBidoBlocks
+inline size_t bido_part_cols(int64_t nc) { return std::max<size_t>(kBidoBlocks, (size_t)((nc + 255) / 256)); }
 
 int model_ng(int m);
 int model_nc(int m);
