@@ -523,7 +523,7 @@ def run_heart(ep, meshgen, args):
     """Three coupled media: the synthetic biventricle + atrial cap + Purkinje
     tree (~11.6M tets, 60k graph nodes, dt 0.01 ms), FP32-mixed and FP64."""
     t0 = time.time()
-    w = meshgen.heart(h=0.375, scale=1.0, purkinje_nodes=60000, n_pmj=2000)
+    w = meshgen.config3()
     log(f"workload {w.name}: {w.n_tets} tets, {w.purkinje.xyz.shape[0]} graph nodes, "
         f"{len(w.purkinje.pmj_nodes)} junctions ({time.time() - t0:.1f}s)")
     f32 = run_precision(ep, w, ep.EP_FP32_MIXED, args.steps, args.warmup, args.chunk)

@@ -541,7 +541,8 @@ def _ellipsoid_depth(p, a_in, c_in, a_out, c_out, iters=30):
 
 
 def heart(h: float = 0.5, seed: int = 3, scale: float = 1.0, purkinje_nodes: int = 60000,
-          n_pmj: int = 2000, seg: float = 0.1, with_atria: bool = True):
+          n_pmj: int = 2000, seg: float = 0.1, with_atria: bool = True,
+          branch_mm: tuple = (1.0, 4.0)):
     """Synthetic three-media heart (stand-in for the paper's anatomical
     meshes, Sec. 2): a biventricle of two truncated prolate-ellipsoidal
     shells (LV, and an RV shell fused to it through the septum) with TP06
@@ -650,7 +651,7 @@ def heart(h: float = 0.5, seed: int = 3, scale: float = 1.0, purkinje_nodes: int
     w = Workload(f"heart-h{h}-s{scale}", xyz, tets, fibre, model, sigma_l=SIGMA_L,
                  sigma_t=SIGMA_T, scale=scale_arr, stimuli=stimuli, dt=0.01,
                  n_steps=80000, hex_ijk=None, dims=())
-    pk = purkinje_tree(lv, rv, rv_off, n_nodes=purkinje_nodes, n_pmj=n_pmj, seg=seg,
+    pk = purkinje_tree(lv, rv, rv_off, n_nodes=purkinje_nodes, n_pmj=n_pmj, seg=seg, branch_mm=branch_mm,
                        seed=seed, z_base=z_base)
     w.purkinje = pk
     # the His-bundle root is stimulated at 130 ms (AV conduction, Sec. 1); a
@@ -673,10 +674,18 @@ def heart(h: float = 0.5, seed: int = 3, scale: float = 1.0, purkinje_nodes: int
     return w
 
 
-def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_base=0.0):
+def config3() -> Workload:
+    """The three-media heart at full size: ~9.6M TP06 + ~2M CRN tets at
+    h = 0.375 mm, a 60,000-node Stewart tree at 0.1 mm whose branches of
+    0.6-2.4 mm end in 2,000 junctions, dt = 0.01 ms."""
+    return heart(h=0.375, scale=1.0, purkinje_nodes=60000, n_pmj=2000, branch_mm=(0.6, 2.4))
+
+
+def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_base=0.0,
+                  branch_mm=(1.0, 4.0)):
     """Seeded fractal tree on the LV and RV endocardium: from a root near the
-    base of the septum, branches of random length (1-4 mm, x4 for the two
-    bundle branches and their first split; segments of
+    base of the septum, branches of random length (branch_mm, 1-4 mm by
+    default, x4 for the two bundle branches and their first split; segments of
     `seg` mm) split into two at +-20..50 deg, each point projected back onto
     the endocardial ellipsoid, until n_nodes nodes exist.  Leaves become the
     junctions, except those within 4 mm of the septal plane (the paper places
@@ -707,7 +716,7 @@ def purkinje_tree(lv, rv, rv_off, n_nodes=60000, n_pmj=2000, seg=0.1, seed=3, z_
         stack.append((0, side, direc / np.linalg.norm(direc), 0))
     while stack and len(pts) < n_nodes:
         start, side, direc, depth = stack.pop(0)
-        length = rng.uniform(1.0, 4.0) * (4.0 if depth < 2 else 1.0)
+        length = rng.uniform(*branch_mm) * (4.0 if depth < 2 else 1.0)
         nseg = max(2, int(length / seg))
         prev = start
         for _ in range(nseg):

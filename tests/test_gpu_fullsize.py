@@ -97,7 +97,8 @@ def test_full_slab_400ms_fp32_error_per_cell(ep):
 
 
 def test_full_heart_fp64_every_cell(ep, oracle_lib):
-    w = M.heart(h=0.375, scale=1.0, purkinje_nodes=60000, n_pmj=2000)
+    w = M.config3()
+    assert len(w.purkinje.pmj_nodes) == 2000      # the configuration's ~2,000 junctions
     w.stimuli[-1].t0 = 0.0                  # His root driven from the start
     say(f"full heart: {w.n_tets} tets, {w.purkinje.xyz.shape[0]} graph nodes; oracle 20 steps ...")
     o = oracle_lib.Sim(w)
