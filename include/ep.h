@@ -262,10 +262,11 @@ ep_status ep_get_medium_substeps(ep_sim *s, int32_t *n_sub);
  * for phi_e^{n+1} by restarted GMRES(restart) started from phi_e^n, until the
  * residual is at most tol times the right-hand side's norm or max_iter Arnoldi
  * steps, and shifts phi_e to zero volume-weighted mean (phi_e^0 = 0, exact for
- * a uniform initial potential).  EP_FP64 and forward Euler only (EP_EINVAL
- * otherwise); call
- * before ep_init.  Each ep_step of a bidomain simulation synchronises its
- * stream once per Arnoldi step. */
+ * a uniform initial potential).  1 <= restart <= 64, EP_FP64 and forward Euler
+ * only (EP_EINVAL otherwise); call before ep_init.  The solve runs on the
+ * device; each ep_step of a bidomain simulation waits for its stream once per
+ * four Arnoldi steps and once per restart cycle, to read the solver's stop
+ * flag. */
 ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t restart,
                           double tol, int32_t max_iter);
 /* phi_e in caller numbering (n == n_tets) */

@@ -36,6 +36,7 @@ namespace {
 constexpr int BT = 256;        // threads per block
 constexpr int NQ = 8;          // dot products per pass of the reduction kernel
 constexpr int G = kBidoBlocks; // blocks of the reduction kernels
+constexpr int RMAX = kBidoMaxRestart;   // the longest restart the LDS staging holds
 
 // node values by inverse-distance weights (sliced ELL, one lane per node)
 // Kernels given a stop flag return at once while it is set (the Arnoldi
@@ -201,16 +202,16 @@ __global__ void __launch_bounds__(BT) k_restrict(const double *__restrict__ r,
     if (threadIdx.x == 0) rc[blockIdx.x] = rs ? *rs * red[0] : red[0];
 }
 
-// zc = A_c^{-1} rc (dense, row-major; one block per row)
-__global__ void __launch_bounds__(BT) k_coarse(const double *__restrict__ cinv,
+// zc = A_c^{-1} rc (dense, row-major, FP32 entries, FP64 sums; one block per row)
+__global__ void __launch_bounds__(BT) k_coarse(const float *__restrict__ cinv,
                                                const double *__restrict__ rc,
                                                double *__restrict__ zc, int32_t na,
                                                const int32_t *stop) {
     if (stopped(stop)) return;
     __shared__ double red[BT];
-    const double *row = cinv + (int64_t)blockIdx.x * na;
+    const float *row = cinv + (int64_t)blockIdx.x * na;
     double acc = 0.0;
-    for (int32_t j = threadIdx.x; j < na; j += BT) acc += row[j] * rc[j];
+    for (int32_t j = threadIdx.x; j < na; j += BT) acc += (double)row[j] * rc[j];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = BT / 2; s > 0; s >>= 1) {
@@ -246,6 +247,13 @@ __global__ void __launch_bounds__(BT) k_combine(double *__restrict__ t, const do
     t[e] = acc;
 }
 
+// x = 0 where *flag is set
+__global__ void __launch_bounds__(BT) k_zero_if(double *__restrict__ x, const int32_t *flag, int64_t n) {
+    if (!*flag) return;
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    if (e < n) x[e] = 0.0;
+}
+
 // x += z
 __global__ void __launch_bounds__(BT) k_add(double *__restrict__ x, const double *__restrict__ z,
                                             int64_t n, const int32_t *stop) {
@@ -259,8 +267,7 @@ __global__ void __launch_bounds__(BT) k_add(double *__restrict__ x, const double
 struct GmCtl {
     double bnorm, beta, relres, pad0;  // |b|, |r| at the cycle start, |r|/|b|
     int32_t it, k, stop, done;         // Arnoldi steps so far, steps of this cycle, cycle over, solve over
-    int32_t noupd;                     // no update this cycle (k = 0)
-    uint32_t count[3];                 // blocks done, per fused reduction kernel
+    int32_t noupd, pad1[3];            // no update this cycle (k = 0)
 };
 static_assert(sizeof(GmCtl) == 64, "the control block takes the first 8 doubles");
 
@@ -288,7 +295,6 @@ __global__ void k_gm_init(GmCtl *c, const double *bb) {
     c->k = 0;
     c->noupd = 1;
     c->relres = 0.0;
-    c->count[0] = c->count[1] = c->count[2] = 0;
     c->done = c->stop = c->bnorm == 0.0;
 }
 
@@ -311,54 +317,68 @@ __global__ void k_gm_start(GmView v, const double *rr, double tol, int32_t max_i
     v.s[0] = 1.0 / c->beta;
 }
 
-// Arnoldi step j (one lane): column j of H from the two Gram-Schmidt
-// passes and the new norm (hd: pass 1 at [0, j], pass 2 at [m + 1,
-// m + 1 + j], |U_{j+1}|^2 at 2 (m + 1)), the earlier rotations, a new one,
-// the reduced right-hand side, the test, and the next basis scale
-__device__ void gm_step(const GmView &v, const double *hd, int j, int m, double tol,
-                        int32_t max_iter) {
+// Arnoldi step j (one lane, reading what the block staged in LDS): column j
+// of H from the two Gram-Schmidt passes and the new norm (col: pass 1 +
+// pass 2 for rows [0, j], cs/sn: the earlier rotations), the earlier
+// rotations applied, a new one, the reduced right-hand side, the test, and
+// the next basis scale, all written back to the device state
+__device__ void gm_step(const GmView &v, double *col, const double *cs, const double *sn, double hn,
+                        int j, int m, double tol, int32_t max_iter) {
     GmCtl *c = v.c;
-    double *H = v.H;
-    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hd[i] + hd[m + 1 + i];
-    const double hn = sqrt(hd[2 * (m + 1)]);
-    H[(size_t)(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
-        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
-        H[(size_t)i * m + j] = v.cs[i] * a + v.sn[i] * b;
-        H[(size_t)(i + 1) * m + j] = -v.sn[i] * a + v.cs[i] * b;
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
     }
-    const double den = hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
-    v.cs[j] = den > 0.0 ? H[(size_t)j * m + j] / den : 1.0;
-    v.sn[j] = den > 0.0 ? H[(size_t)(j + 1) * m + j] / den : 0.0;
-    H[(size_t)j * m + j] = den;
-    H[(size_t)(j + 1) * m + j] = 0.0;
-    v.g[j + 1] = -v.sn[j] * v.g[j];
-    v.g[j] = v.cs[j] * v.g[j];
+    const double hjj = col[j];
+    const double den = hypot(hjj, hn);
+    const double cj = den > 0.0 ? hjj / den : 1.0;
+    const double sj = den > 0.0 ? hn / den : 0.0;
+    col[j] = den;
+    for (int i = 0; i <= j; ++i) v.H[(size_t)i * m + j] = col[i];
+    v.H[(size_t)(j + 1) * m + j] = 0.0;
+    v.cs[j] = cj;
+    v.sn[j] = sj;
+    const double gj = v.g[j];
+    v.g[j + 1] = -sj * gj;
+    v.g[j] = cj * gj;
     c->it += 1;
     c->k = j + 1;
     c->noupd = 0;
-    if (fabs(v.g[j + 1]) <= tol * c->bnorm || hn == 0.0 || c->it >= max_iter || j == m - 1)
+    if (fabs(sj * gj) <= tol * c->bnorm || hn == 0.0 || c->it >= max_iter || j == m - 1)
         c->stop = 1;
     else
         v.s[j + 1] = 1.0 / hn;
 }
 
-// R y = g for the cycle's k steps (back substitution)
-__global__ void k_gm_solve(GmView v, int m) {
-    if (threadIdx.x) return;
+// R y = g for the cycle's k steps (back substitution), R and g staged in
+// LDS by the block first
+__global__ void __launch_bounds__(BT) k_gm_solve(GmView v, int m) {
+    __shared__ double R[RMAX * RMAX], gl[RMAX], yl[RMAX];
     const int k = v.c->k;
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) R[t] = v.H[(size_t)(t / k) * m + t % k];
+    for (int t = threadIdx.x; t < k; t += blockDim.x) gl[t] = v.g[t];
+    __syncthreads();
+    if (threadIdx.x) return;
     for (int i = k - 1; i >= 0; --i) {
-        double acc = v.g[i];
-        for (int l = i + 1; l < k; ++l) acc -= v.H[(size_t)i * m + l] * v.y[l];
-        v.y[i] = acc / v.H[(size_t)i * m + i];
+        double acc = gl[i];
+        for (int l = i + 1; l < k; ++l) acc -= R[i * k + l] * yl[l];
+        yl[i] = acc / R[i * k + i];
     }
+    for (int i = 0; i < k; ++i) v.y[i] = yl[i];
 }
 
 // ---- Arnoldi-step kernels: the vector update of a step and the block
 // partials of its dot products in one pass (one lane per cell), the rows
 // then added by k_rows, one block per row, in a fixed order (so a solve
-// still gives the same bits on every run)
+// still gives the same bits on every run).  A lane loads the basis values
+// of R rows at once, so a pass waits for memory once per R rows: R = 32 on
+// small grids, where the wait is what a pass costs, and R = 8 on large
+// ones, where 32 rows at once would stream from 32 distant ranges of the
+// basis (slower there than 8).
 constexpr int NW = BT / 64;    // waves per block
+constexpr int RB = 32;         // the most rows per pass
+static_assert(NW == 4, "the wave totals are added as (w0 + w1) + (w2 + w3)");
 
 // a wave's 64 values added by a fixed butterfly (lane 0's result)
 __device__ __forceinline__ double wave_sum(double a) {
@@ -367,31 +387,76 @@ __device__ __forceinline__ double wave_sum(double a) {
     return a;
 }
 
-// block partials <w, U_q> for q < cnt of this block's cells (w_e and the
-// rows at element e = the lane's cell, 0 past n), in groups of NQ rows:
-// each wave adds its lanes by the butterfly, then the NW wave sums in a
-// fixed tree; row q's partial of block b at part[q * gridDim.x + b]
-__device__ void dot_rows(double we, const double *__restrict__ U, int cnt, int64_t n, int64_t e,
-                         double *part, double (*red)[NW]) {
+// Block partials of R sums at once: a[q] holds the lane's term of row q.
+// Within a wave, log2 R exchange steps (offsets 32, 16, ...) each hand half
+// of the remaining rows to the partner lane and add, then the groups of
+// 64 / R lanes that hold the same row add by a butterfly: lanes
+// [r 64 / R, (r + 1) 64 / R) end with row r's wave total (one exchange per
+// row and step instead of a butterfly per row).  The NW wave totals are
+// added in a fixed order; row q < cnt of block b goes to
+// part[q * gridDim.x + b].  Every addition has a fixed place, so the bits
+// do not depend on timing.
+template <int R>
+__device__ __forceinline__ void block_rows(double (&a)[R], int cnt, double *part, double (*red)[RB]) {
+    static_assert(R == 8 || R == 16 || R == 32, "R rows over 64 lanes");
+    constexpr int G = 64 / R;  // lanes per row at the end
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q0 = 0; q0 < cnt; q0 += NQ) {
-        const int k = min(NQ, cnt - q0);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            if (q < k) {
-                const double a = wave_sum(e < n ? we * U[(int64_t)(q0 + q) * n + e] : 0.0);
-                if (lane == 0) red[q][wave] = a;
-            }
-        __syncthreads();
-        if ((int)threadIdx.x < k)
-            part[(int64_t)(q0 + threadIdx.x) * gridDim.x + blockIdx.x] =
-                (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
-        __syncthreads();
+    for (int w = R / 2, o = 32; w >= 1; w >>= 1, o >>= 1) {
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < w; ++i) {
+            const double keep = hi ? a[i + w] : a[i];
+            const double give = hi ? a[i] : a[i + w];
+            a[i] = keep + __shfl_xor(give, o, 64);
+        }
     }
+    double t = a[0];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((lane & (G - 1)) == 0) red[wave][lane / G] = t;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt)
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    __syncthreads();
+}
+
+// the lane's values of basis rows [q0, q0 + R) at element e (0 past cnt or n)
+template <int R>
+__device__ __forceinline__ void load_rows(double (&u)[R], const double *__restrict__ U, int q0,
+                                          int cnt, int64_t n, int64_t e) {
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        u[q] = (e < n && q0 + q < cnt) ? U[(int64_t)(q0 + q) * n + e] : 0.0;
+}
+
+// Row sums of the previous pass inside its consumer (small grids, cnt <=
+// RB rows): thread t adds partials t % 8, t % 8 + 8, ... of row t / 8, then
+// the 8 lanes of the row add by a fixed butterfly, so every block holds the
+// same bits; the sums times the scales go to hs (LDS) and, from block 0, to
+// the global h read by the least-squares update.
+__device__ __forceinline__ void rows_in_block(const double *__restrict__ hp, int64_t np,
+                                              const double *__restrict__ sc, int cnt,
+                                              double *__restrict__ h, double *hs) {
+    const int q = threadIdx.x >> 3, sg = threadIdx.x & 7;
+    double acc = 0.0;
+    if (q < cnt)
+        for (int64_t i = sg; i < np; i += 8) acc += hp[(int64_t)q * np + i];
+    acc += __shfl_xor(acc, 4, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    acc += __shfl_xor(acc, 1, 64);
+    if (sg == 0 && q < cnt) {
+        const double v = sc[q] * acc;
+        hs[q] = v;
+        if (blockIdx.x == 0) h[q] = v;
+    }
+    __syncthreads();
 }
 
 // w = A z (flux-sum form; node values zn already formed, z scaled by *zs
 // when given), with the partials of <w, U_q>, q < cnt
+template <int R>
 __global__ void __launch_bounds__(BT) k_op_dots(const int32_t *__restrict__ cnode,
                                                 const double *__restrict__ beta,
                                                 const int32_t *__restrict__ cnbr,
@@ -401,7 +466,7 @@ __global__ void __launch_bounds__(BT) k_op_dots(const int32_t *__restrict__ cnod
                                                 double *__restrict__ w, const double *__restrict__ U,
                                                 int cnt, int64_t nc, double *part, const int32_t *stop) {
     if (stopped(stop)) return;
-    __shared__ double red[NQ][NW];
+    __shared__ double red[NW][RB];
     const int64_t c = blockIdx.x * (int64_t)BT + threadIdx.x;
     double y = 0.0;
     if (c < nc) {
@@ -415,42 +480,90 @@ __global__ void __launch_bounds__(BT) k_op_dots(const int32_t *__restrict__ cnod
         y = acc + (zs ? *zs : 1.0) * two;
         w[c] = y;
     }
-    dot_rows(y, U, cnt, nc, c, part, red);
+    for (int q0 = 0; q0 < cnt; q0 += R) {
+        double a[R];
+        load_rows<R>(a, U, q0, cnt, nc, c);
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[q] *= y;
+        block_rows<R>(a, min(R, cnt - q0), part + (int64_t)q0 * gridDim.x, red);
+    }
 }
 
-// w -= sum_{q < cnt} h_q V_q (in place), with the partials of <w, U_q>
+// w -= sum_{q < cnt} h_q V_q (in place), with the partials of <w, U_q>;
+// with hp the h_q are first summed here from the previous pass's partials
+template <int R>
 __global__ void __launch_bounds__(BT) k_sub_dots(double *__restrict__ w, const double *__restrict__ U,
                                                  const double *__restrict__ sc,
-                                                 const double *__restrict__ h, int cnt, int64_t n,
-                                                 double *part, const int32_t *stop) {
+                                                 double *__restrict__ h, int cnt, int64_t n,
+                                                 double *part, const int32_t *stop,
+                                                 const double *__restrict__ hp) {
     if (stopped(stop)) return;
-    __shared__ double red[NQ][NW];
-    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
-    double x = 0.0;
-    if (e < n) {
-        x = w[e];
-        for (int q = 0; q < cnt; ++q) x -= h[q] * sc[q] * U[(int64_t)q * n + e];
-        w[e] = x;
+    __shared__ double red[NW][RB];
+    __shared__ double hs[RB];
+    if (hp) {
+        rows_in_block(hp, gridDim.x, sc, cnt, h, hs);
+        h = hs;
     }
-    dot_rows(x, U, cnt, n, e, part, red);
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    double x = e < n ? w[e] : 0.0;
+    if (cnt <= R) {                // the rows stay in registers for the dots
+        double u[R];
+        load_rows<R>(u, U, 0, cnt, n, e);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q < cnt) x -= h[q] * sc[q] * u[q];
+        if (e < n) w[e] = x;
+#pragma unroll
+        for (int q = 0; q < R; ++q) u[q] *= x;
+        block_rows<R>(u, cnt, part, red);
+        return;
+    }
+    for (int q0 = 0; q0 < cnt; q0 += R) {
+        double u[R];
+        load_rows<R>(u, U, q0, cnt, n, e);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q0 + q < cnt) x -= h[q0 + q] * sc[q0 + q] * u[q];
+    }
+    if (e < n) w[e] = x;
+    for (int q0 = 0; q0 < cnt; q0 += R) {
+        double u[R];
+        load_rows<R>(u, U, q0, cnt, n, e);
+#pragma unroll
+        for (int q = 0; q < R; ++q) u[q] *= x;
+        block_rows<R>(u, min(R, cnt - q0), part + (int64_t)q0 * gridDim.x, red);
+    }
 }
 
-// U_{j+1} = w - sum_{q <= j} h_q V_q, with the partials of |U_{j+1}|^2
+// U_{j+1} = w - sum_{q <= j} h_q V_q, with the partials of |U_{j+1}|^2;
+// with hp the h_q are first summed here from the previous pass's partials
+template <int R>
 __global__ void __launch_bounds__(BT) k_sub_norm(const double *__restrict__ w, double *__restrict__ U,
                                                  const double *__restrict__ sc,
-                                                 const double *__restrict__ h, int j, int64_t n,
-                                                 double *part, const int32_t *stop) {
+                                                 double *__restrict__ h, int j, int64_t n,
+                                                 double *part, const int32_t *stop,
+                                                 const double *__restrict__ hp) {
     if (stopped(stop)) return;
-    __shared__ double red[NQ][NW];
-    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
-    double *un = U + (int64_t)(j + 1) * n;
-    double x = 0.0;
-    if (e < n) {
-        x = w[e];
-        for (int q = 0; q <= j; ++q) x -= h[q] * sc[q] * U[(int64_t)q * n + e];
-        un[e] = x;
+    __shared__ double red[NW];
+    __shared__ double hs[RB];
+    if (hp) {
+        rows_in_block(hp, gridDim.x, sc, j + 1, h, hs);
+        h = hs;
     }
-    dot_rows(x, un, 1, n, e, part, red);
+    const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
+    double x = e < n ? w[e] : 0.0;
+    for (int q0 = 0; q0 <= j; q0 += R) {
+        double u[R];
+        load_rows<R>(u, U, q0, j + 1, n, e);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q0 + q <= j) x -= h[q0 + q] * sc[q0 + q] * u[q];
+    }
+    if (e < n) U[(int64_t)(j + 1) * n + e] = x;
+    const double t = wave_sum(e < n ? x * x : 0.0);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // out[q] = sc[q] * (sum of the np partials of row q) (or the sum); one block
@@ -472,15 +585,22 @@ __global__ void __launch_bounds__(BT) k_rows(const double *__restrict__ part, in
     if (threadIdx.x == 0) out[blockIdx.x] = sc ? sc[blockIdx.x] * red[0] : red[0];
 }
 
-// |U_{j+1}|^2 from its partials, then the step's least-squares update
+// |U_{j+1}|^2 from its partials, then the step's least-squares update (the
+// column, the earlier rotations and the norm staged in LDS by all lanes)
 __global__ void __launch_bounds__(BT) k_norm_step(const double *__restrict__ part, int64_t np, GmView v,
                                                   double *hd, int j, int m, double tol,
                                                   int32_t max_iter) {
     if (v.c->stop) return;
     __shared__ double red[BT];
+    __shared__ double col[RMAX + 1], cs[RMAX], sn[RMAX];
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < np; i += BT) acc += part[i];
     red[threadIdx.x] = acc;
+    for (int i = threadIdx.x; i <= j; i += BT) col[i] = hd[i] + hd[m + 1 + i];
+    for (int i = threadIdx.x; i < j; i += BT) {
+        cs[i] = v.cs[i];
+        sn[i] = v.sn[i];
+    }
     __syncthreads();
     for (int s = BT / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
@@ -488,12 +608,13 @@ __global__ void __launch_bounds__(BT) k_norm_step(const double *__restrict__ par
     }
     if (threadIdx.x == 0) {
         hd[2 * (m + 1)] = red[0];
-        gm_step(v, hd, j, m, tol, max_iter);
+        gm_step(v, col, cs, sn, sqrt(red[0]), j, m, tol, max_iter);
     }
 }
 
 constexpr double kOmega = 0.7;   // Jacobi weight of the preconditioner
 constexpr int kChunk = 4;        // Arnoldi steps per captured graph
+constexpr int kFuseBlocks = 512; // grids up to this many blocks sum rows in the consumer
 
 struct Solver {
     Inst &I;
@@ -525,13 +646,20 @@ struct Solver {
         k_smooth<<<grid_c, BT, 0, st>>>(r, B.dinv, B.agg_of, B.zc, kOmega, z, nc, stop);
     }
     // Arnoldi steps [j0, j1) of a cycle, each a no-op once the cycle is over:
-    // 7 kernels each with the preconditioner (4 without)
+    // 10 kernels each with the preconditioner (7 without); on small grids
+    // the row sums of the two Gram-Schmidt passes happen inside their
+    // consumers (8 kernels), the passes then alternating between two
+    // partials buffers so that no block overwrites partials another still
+    // reads
     void steps(int j0, int j1, const GmView &gv) {
         Bido &B = I.bd;
         const InstDesc &D = I.desc;
         const int m = B.restart;
         const int32_t *stop = &gv.c->stop;
         double *hd = B.h;
+        const bool fuse = m + 1 <= RB && grid_c <= kFuseBlocks;
+        double *pa = B.part;
+        double *pb = fuse ? B.part + (size_t)(m + 1) * bido_part_cols(nc) : B.part;
         for (int j = j0; j < j1; ++j) {
             const double *uj = B.V + (int64_t)j * nc;
             const double *sj = gv.s + j;
@@ -547,13 +675,20 @@ struct Solver {
                                             stop, zs);
             // w = A z with pass 1 of classical Gram-Schmidt, pass 2, then the
             // new vector, its norm and the least-squares update
-            k_op_dots<<<grid_c, BT, 0, st>>>(D.cnode, B.ebeta, D.cnbr, B.eb, z, zs, B.xn, B.w, B.V, j + 1,
-                                             nc, B.part, stop);
-            k_rows<<<j + 1, BT, 0, st>>>(B.part, grid_c, gv.s, hd, stop);
-            k_sub_dots<<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd, j + 1, nc, B.part, stop);
-            k_rows<<<j + 1, BT, 0, st>>>(B.part, grid_c, gv.s, hd + (m + 1), stop);
-            k_sub_norm<<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd + (m + 1), j, nc, B.part, stop);
-            k_norm_step<<<1, BT, 0, st>>>(B.part, grid_c, gv, hd, j, m, B.tol, B.max_iter);
+            if (fuse) {
+                k_op_dots<RB><<<grid_c, BT, 0, st>>>(D.cnode, B.ebeta, D.cnbr, B.eb, z, zs, B.xn, B.w, B.V,
+                                                     j + 1, nc, pa, stop);
+                k_sub_dots<RB><<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd, j + 1, nc, pb, stop, pa);
+                k_sub_norm<RB><<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd + (m + 1), j, nc, pa, stop, pb);
+            } else {
+                k_op_dots<8><<<grid_c, BT, 0, st>>>(D.cnode, B.ebeta, D.cnbr, B.eb, z, zs, B.xn, B.w, B.V,
+                                                    j + 1, nc, pa, stop);
+                k_rows<<<j + 1, BT, 0, st>>>(pa, grid_c, gv.s, hd, stop);
+                k_sub_dots<8><<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd, j + 1, nc, pb, stop, nullptr);
+                k_rows<<<j + 1, BT, 0, st>>>(pb, grid_c, gv.s, hd + (m + 1), stop);
+                k_sub_norm<8><<<grid_c, BT, 0, st>>>(B.w, B.V, gv.s, hd + (m + 1), j, nc, pa, stop, nullptr);
+            }
+            k_norm_step<<<1, BT, 0, st>>>(pa, grid_c, gv, hd, j, m, B.tol, B.max_iter);
         }
     }
     // the state's control block to the host
@@ -579,6 +714,7 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
     hipError_t e;
     auto fail = [&](const char *what) { return std::string(what) + ": " + hipGetErrorString(e); };
 
+
     // right-hand side: -chi Cm V_c L_i(v) = -(flux sums of v with M_i)
     k_gather<<<S.grid_n, BT, 0, st>>>(D.sell_off, D.sell_cell, (const double *)D.sell_w, v, B.xn, D.nn,
                                       nullptr);
@@ -586,12 +722,13 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
                                     B.xn, D.vol, -B.chi_cm, B.b, nc, nullptr);
     S.dots(B.b, B.b, 1, h_norm);
     k_gm_init<<<1, 64, 0, st>>>(gv.c, h_norm);
-    if ((e = S.read(gv)) != hipSuccess) return fail("bidomain readback");
-    if (hc->done) {
-        k_scale<<<S.grid_c, BT, 0, st>>>(B.phi, B.phi, 0.0, nullptr, nc, nullptr);
-    } else {
+    k_zero_if<<<S.grid_c, BT, 0, st>>>(B.phi, &gv.c->done, nc);   // b = 0: phi = 0
+    {
         const int n_chunks = (m + kChunk - 1) / kChunk;
         if ((int)B.chunk_graphs.size() != n_chunks) B.chunk_graphs.assign(n_chunks, nullptr);
+        // the previous solve's Arnoldi steps: the stop flag is read only from
+        // two steps before that count on (every chunk in the first solve)
+        const int64_t pred = B.last_iters;
         for (;;) {
             // the true residual r = b - A phi starts a cycle (or ends the
             // solve) as U_0, V_0 = r / |r|
@@ -601,6 +738,7 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
             k_gm_start<<<1, 64, 0, st>>>(gv, h_norm, B.tol, B.max_iter, m);
             if ((e = S.read(gv)) != hipSuccess) return fail("bidomain readback");
             if (hc->done) break;
+            const int64_t it0 = hc->it;
             for (int q = 0; q < n_chunks; ++q) {
                 if (!B.chunk_graphs[q]) {
                     hipGraph_t g = nullptr;
@@ -613,10 +751,11 @@ std::string bidomain_solve(Inst &I, hipStream_t st) {
                     if (e != hipSuccess) { B.chunk_graphs[q] = nullptr; return fail("bidomain graph"); }
                 }
                 if ((e = hipGraphLaunch(B.chunk_graphs[q], st)) != hipSuccess) return fail("bidomain graph launch");
+                if (q == n_chunks - 1 || it0 + std::min(m, (q + 1) * kChunk) + 2 < pred) continue;
                 if ((e = S.read(gv)) != hipSuccess) return fail("bidomain readback");
                 if (hc->stop) break;
             }
-            k_gm_solve<<<1, 64, 0, st>>>(gv, m);
+            k_gm_solve<<<1, BT, 0, st>>>(gv, m);
             if (B.precond) {                         // x += M^{-1} V y
                 k_combine<<<S.grid_c, BT, 0, st>>>(B.t, B.V, gv.y, gv.s, &gv.c->k, nc, &gv.c->noupd);
                 S.prec(B.t, B.z, &gv.c->noupd);

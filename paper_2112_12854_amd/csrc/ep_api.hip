@@ -252,7 +252,7 @@ ep_status ep_set_bidomain(ep_sim *s, double sigma_el, double sigma_et, int32_t r
     if (s->inited) return fail(s, EP_ESTATE, "the model is frozen after ep_init");
     if (s->opt.prec != EP_FP64) return fail(s, EP_EINVAL, "the bidomain model runs in EP_FP64 only");
     if (!(sigma_el >= 0) || !(sigma_et >= 0) || !std::isfinite(sigma_el) || !std::isfinite(sigma_et) ||
-        restart < 1 || restart > 1000 || !(tol > 0) || max_iter < 1)
+        restart < 1 || restart > ep::kBidoMaxRestart || !(tol > 0) || max_iter < 1)
         return fail(s, EP_EINVAL, "bad bidomain parameters");
     ep::InstSpec &sp = s->spec;
     if (sp.scheme != 0) return fail(s, EP_EINVAL, "the bidomain model steps by forward Euler only");

@@ -1,6 +1,8 @@
 // Building instances on the device and stepping sets of them.
 #include "instance.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -329,12 +331,12 @@ size_t instance_footprint(const Inst &I, int rs, const InstSpec &sp) {
         const size_t m1 = (size_t)sp.bido_restart + 1;
         b += round256(tiled_len(c, 8) * 8) + round256(tiled_len(c, 4) * 8) + 3 * round256(c * 8) +
              round256(n * 8) + round256(m1 * c * 8);
-        b += round256(m1 * bido_part_cols((int64_t)c) * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8) +
+        b += round256(2 * m1 * bido_part_cols((int64_t)c) * 8) + round256((2 * m1 + 2) * 8) + round256(m1 * 8) +
              round256(gmres_state_doubles((int)m1 - 1) * 8);
         const size_t na = (size_t)I.coarse.n_agg;
         if (na > 0)
             b += 2 * round256(c * 4) + round256((na + 1) * 4) + round256(c * 8) +
-                 round256(na * na * 8) + 2 * round256(c * 8) + 2 * round256(na * 8);
+                 round256(na * na * 4) + 2 * round256(c * 8) + 2 * round256(na * 8);
     }
     if (sp.scheme >= 1) {
         b += round256(c * r) + round256(tiled_len(c, NC_MAX) * 8);
@@ -626,7 +628,7 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         B.w = (double *)dalloc(I, nc * 8);
         B.xn = (double *)dalloc(I, nn * 8);
         B.V = (double *)dalloc(I, m1 * nc * 8);
-        B.part = (double *)dalloc(I, m1 * bido_part_cols(nc) * 8);
+        B.part = (double *)dalloc(I, 2 * m1 * bido_part_cols(nc) * 8);   // two passes' partials
         B.h = (double *)dalloc(I, (2 * m1 + 2) * 8);
         B.y = (double *)dalloc(I, m1 * 8);
         B.gm = (double *)dalloc(I, gmres_state_doubles((int)m1 - 1) * 8);
@@ -638,9 +640,13 @@ std::string upload_instance(const InstSpec &sp, int rs, const Allocator &al, Ins
         B.n_agg = Cs.n_agg;
         B.precond = Cs.n_agg > 0;
         if (B.precond) {
+            // A_c^{-1} in FP32: the preconditioner only has to be a fixed
+            // linear map (GMRES reaches the same solution to its tolerance),
+            // and its dense product is the largest read of an Arnoldi step
+            const std::vector<float> cinv32(Cs.cinv.begin(), Cs.cinv.end());
             if (!up(I, (void **)&B.agg_of, Cs.agg_of) || !up(I, (void **)&B.agg_cells, Cs.agg_cells) ||
                 !up(I, (void **)&B.agg_off, Cs.agg_off) || !up(I, (void **)&B.dinv, Cs.dinv) ||
-                !up(I, (void **)&B.cinv, Cs.cinv))
+                !up(I, (void **)&B.cinv, cinv32))
                 return fail_mem();
             B.z = (double *)dalloc(I, nc * 8);
             B.t = (double *)dalloc(I, nc * 8);
@@ -698,43 +704,73 @@ Tables tables(const Stepper &s) {
 
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
+// Events that a profiled launch sets from the dispatches' own timestamps:
+// `start` at the first kernel's start, `stop` at the last one's end (both
+// null: an ordinary launch, the only kind that graphs capture).
+struct Span {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <typename... A, typename... B>
+void launch_k(void (*kern)(A...), int grid, int block, hipStream_t st, hipEvent_t e0,
+              hipEvent_t e1, B... args) {
+    if (e0 || e1) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, st, e0, e1, 0, args...);
+    else kern<<<grid, block, 0, st>>>(args...);
+}
+
 // Cell kernels of step offset `off`, one launch per model class present:
 // the step's tiles (sub < 0) or substep `sub` of the 2D media with
 // substeps, on stream `st`.
 template <typename R, bool BIDO, int SCH>
 void launch_cells_v(Stepper &s, const Tables &tb, int32_t off, int32_t sub = -1,
-                    hipStream_t st = nullptr) {
+                    hipStream_t st = nullptr, Span sp = {}) {
     if (!st) st = s.stream;
     const int64_t *base = sub < 0 ? s.cls_base : s.cls2_base;
     const int64_t *cnt = sub < 0 ? s.cls_tiles : s.cls2_tiles;
     Tables t[4] = {tb, tb, tb, tb};
     for (int k = 0; k < 4; ++k) t[k].cell_tiles = tb.cell_tiles + base[k];
+    int first = -1, last = -1;
+    for (int k = 0; k < 4; ++k)
+        if (cnt[k]) {
+            if (first < 0) first = k;
+            last = k;
+        }
     const int B = s.cell_threads;
-    if (cnt[0]) k_cell<R, 1, BIDO, SCH><<<(int)cnt[0], B, 0, st>>>(t[0], off, s.remap, sub);
-    if (cnt[1]) k_cell<R, 2, BIDO, SCH><<<(int)cnt[1], B, 0, st>>>(t[1], off, s.remap, sub);
-    if (cnt[2]) k_cell<R, 4, BIDO, SCH><<<(int)cnt[2], B, 0, st>>>(t[2], off, s.remap, sub);
-    if (cnt[3]) k_cell<R, 8, BIDO, SCH><<<(int)cnt[3], B, 0, st>>>(t[3], off, s.remap, sub);
+    auto go = [&](void (*kern)(Tables, int32_t, int, int32_t), int k) {
+        if (cnt[k])
+            launch_k(kern, (int)cnt[k], B, st, k == first ? sp.start : nullptr,
+                     k == last ? sp.stop : nullptr, t[k], off, s.remap, sub);
+    };
+    go(k_cell<R, 1, BIDO, SCH>, 0);
+    go(k_cell<R, 2, BIDO, SCH>, 1);
+    go(k_cell<R, 4, BIDO, SCH>, 2);
+    go(k_cell<R, 8, BIDO, SCH>, 3);
 }
 
 // bidomain instances run in FP64 with forward Euler only (checked at
 // creation); Adams-Bashforth 2 applies to every instance of a stepper or none
 template <typename R>
-void launch_cells(Stepper &s, const Tables &tb, int32_t off) {
+void launch_cells(Stepper &s, const Tables &tb, int32_t off, Span sp = {}) {
     if constexpr (sizeof(R) == 8) {
-        if (s.bido) { launch_cells_v<R, true, 0>(s, tb, off); return; }
+        if (s.bido) { launch_cells_v<R, true, 0>(s, tb, off, -1, nullptr, sp); return; }
     }
-    if (s.scheme == 2) launch_cells_v<R, false, 2>(s, tb, off);
-    else if (s.scheme == 1) launch_cells_v<R, false, 1>(s, tb, off);
-    else launch_cells_v<R, false, 0>(s, tb, off);
+    if (s.scheme == 2) launch_cells_v<R, false, 2>(s, tb, off, -1, nullptr, sp);
+    else if (s.scheme == 1) launch_cells_v<R, false, 1>(s, tb, off, -1, nullptr, sp);
+    else launch_cells_v<R, false, 0>(s, tb, off, -1, nullptr, sp);
 }
 
 template <typename R>
-void launch_gather(Stepper &s, const Tables &tb, int32_t off) {
+void launch_gather(Stepper &s, const Tables &tb, int32_t off, Span sp = {}) {
     if (s.n_nt == 0) return;
     if constexpr (sizeof(R) == 8) {
-        if (s.bido) { k_node_gather<R, true><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap, -1); return; }
+        if (s.bido) {
+            launch_k(k_node_gather<R, true>, s.grid_node, TILE, s.stream, sp.start, sp.stop, tb, off,
+                     s.remap, -1);
+            return;
+        }
     }
-    k_node_gather<R, false><<<s.grid_node, TILE, 0, s.stream>>>(tb, off, s.remap, -1);
+    launch_k(k_node_gather<R, false>, s.grid_node, TILE, s.stream, sp.start, sp.stop, tb, off,
+             s.remap, -1);
 }
 
 // The substeps of step offset `off` of the 2D media that have them, on
@@ -1148,12 +1184,17 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
     }
     const int gn = grid_for(s.n_nt);
     s.grid_node = gn;
-    // A ring of event quadruples (step start, after the node gather, after
-    // the cell kernel, step end): the host waits only for the step RING
-    // places back before reusing its events, so the queue stays RING - 1
-    // steps deep and the kernels run back to back as in an unprofiled run.
-    constexpr int RING = 64;
-    std::vector<hipEvent_t> ev(4 * RING, nullptr);
+    // A ring of six events per step, all but one set from the dispatches'
+    // own timestamps (so a kernel's time is its execution alone, as a
+    // kernel trace reports it, and no marker packet sits between kernels):
+    // start and end of the node gather and of the cell kernels, and the
+    // end of the step's last kernel; the step starts at the node gather's
+    // start (a recorded event only when the step has no node gather).  The
+    // host waits only for the step RING places back before reusing its
+    // events, so the queue stays RING - 1 steps deep and the kernels run
+    // back to back as in an unprofiled run.
+    constexpr int RING = 64, NE = 6;
+    std::vector<hipEvent_t> ev(NE * RING, nullptr);
     for (auto &x : ev)
         if (hipEventCreate(&x) != hipSuccess) {
             for (auto &y : ev)
@@ -1161,13 +1202,15 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
             return "hipEventCreate failed";
         }
     double tc = 0, tn = 0;
+    const bool gathers = s.n_nt > 0;
+    const bool cells = s.cls_tiles[0] + s.cls_tiles[1] + s.cls_tiles[2] + s.cls_tiles[3] > 0;
     auto collect = [&](int64_t i) {
-        hipEvent_t *q = &ev[4 * (i % RING)];
-        (void)hipEventSynchronize(q[3]);
+        hipEvent_t *q = &ev[NE * (i % RING)];
+        (void)hipEventSynchronize(q[5]);
         float a = 0, b = 0, c = 0;
-        (void)hipEventElapsedTime(&a, q[0], q[1]);
-        (void)hipEventElapsedTime(&b, q[1], q[2]);
-        (void)hipEventElapsedTime(&c, q[0], q[3]);
+        if (gathers) (void)hipEventElapsedTime(&a, q[1], q[2]);
+        if (cells) (void)hipEventElapsedTime(&b, q[3], q[4]);
+        (void)hipEventElapsedTime(&c, gathers ? q[1] : q[0], q[5]);
         tn += a;
         tc += b;
         if (step_ms) step_ms[i] = c;
@@ -1175,14 +1218,12 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
     const Tables tb = tables(s);
     for (int64_t i = 0; i < n; ++i) {
         if (i >= RING) collect(i - RING);
-        hipEvent_t *q = &ev[4 * (i % RING)];
-        (void)hipEventRecord(q[0], s.stream);
-        if (s.rs == 8) launch_gather<double>(s, tb, 0);
-        else launch_gather<float>(s, tb, 0);
-        (void)hipEventRecord(q[1], s.stream);
-        if (s.rs == 8) launch_cells<double>(s, tb, 0);
-        else launch_cells<float>(s, tb, 0);
-        (void)hipEventRecord(q[2], s.stream);
+        hipEvent_t *q = &ev[NE * (i % RING)];
+        if (!gathers) (void)hipEventRecord(q[0], s.stream);
+        if (s.rs == 8) launch_gather<double>(s, tb, 0, Span{q[1], q[2]});
+        else launch_gather<float>(s, tb, 0, Span{q[1], q[2]});
+        if (s.rs == 8) launch_cells<double>(s, tb, 0, Span{q[3], q[4]});
+        else launch_cells<float>(s, tb, 0, Span{q[3], q[4]});
         if (s.rs == 8) launch_medium2<double>(s, 0, s.stream);
         else launch_medium2<float>(s, 0, s.stream);
         if (s.n_pk > 0) {               // one stream here: the timings stay apart
@@ -1191,8 +1232,7 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
             if (s.rs == 8) launch_junctions<double>(s, 0);
             else launch_junctions<float>(s, 0);
         }
-        k_advance<<<1, 256, 0, s.stream>>>(tb, 1);
-        (void)hipEventRecord(q[3], s.stream);
+        launch_k(k_advance, 1, 256, s.stream, nullptr, q[5], tb, (int64_t)1);
     }
     for (int64_t i = std::max<int64_t>(0, n - RING); i < n; ++i) collect(i);
     for (Inst *I : s.insts) I->host_step = std::min(I->host_step + n, std::max(I->host_step, I->target));

@@ -70,7 +70,7 @@ struct Bido {
     double *xn = nullptr;              // [nn] node values of the operand
     double *b = nullptr, *w = nullptr; // [nc] right-hand side, work vector
     double *V = nullptr;               // [(restart+1)][nc] Krylov basis
-    double *part = nullptr;            // [(restart+1)][blocks] reduction partials
+    double *part = nullptr;            // [2][(restart+1)][blocks] reduction partials (two passes)
     double *h = nullptr;               // [2 restart + 4] reduced dot products
     double *y = nullptr;               // [restart] update coefficients
     int32_t restart = 30, max_iter = 2000;
@@ -86,7 +86,8 @@ struct Bido {
     // two-level preconditioner
     int32_t n_agg = 0;
     const int32_t *agg_of = nullptr, *agg_off = nullptr, *agg_cells = nullptr;
-    const double *dinv = nullptr, *cinv = nullptr;
+    const double *dinv = nullptr;
+    const float *cinv = nullptr;       // [n_agg][n_agg] A_c^{-1}, FP32
     double *z = nullptr, *t = nullptr; // [nc] preconditioned vector, update
     double *rc = nullptr, *zc = nullptr;   // [n_agg] coarse residual, correction
     bool precond = true;
@@ -262,10 +263,12 @@ inline size_t gmres_state_doubles(int m) {
 }
 
 // Bidomain: solve the extracellular equation for the instance's current
-// v^{n} (after a step), from its phi_e (instance must be synchronised with
-// nothing pending that writes v); enqueued on `stream`, synchronises it.
+// v^{n} (after a step), from its phi_e, enqueued on `stream` after the step:
+// captured chunks of four Arnoldi steps, the host waiting for the stream
+// once per chunk and once per restart cycle to read the stop flag.
 std::string bidomain_solve(Inst &I, hipStream_t stream);
 constexpr int kBidoBlocks = 1024;      // blocks of the reduction kernels
+constexpr int kBidoMaxRestart = 64;    // longest GMRES restart (its state is staged in LDS)
 // partial sums per dot-product row of the bidomain solve: one per block of
 // 256 cells, at least kBidoBlocks
 inline size_t bido_part_cols(int64_t nc) { return std::max<size_t>(kBidoBlocks, (size_t)((nc + 255) / 256)); }

@@ -17,8 +17,8 @@ makes the GPU tests that read it fail instead of comparing other inputs.
 The oracle's results do not depend on its thread count.  A full slab run is
 about 1e11 cell-steps (hours on a few cores).
 
-Usage: python tests/golden/make_oracle_golden.py {slab|uq} [--threads N] [--native]
-                                                [--ckpt DIR]
+Usage: python tests/golden/make_oracle_golden.py {slab|uq|merge-uq} [--threads N]
+           [--native] [--ckpt DIR] [--shard i/n]
 """
 from __future__ import annotations
 
@@ -122,13 +122,18 @@ def make_slab(log, ckpt_dir=None):
         os.remove(ck)
 
 
-def make_uq(log):
+def make_uq(log, shard=(0, 1)):
+    """The UQ subset, or with shard (i, n) the instances k = i, i + n, ...
+    of it into a part file (merged by `merge_uq`)."""
     import oracle
     from paper_2112_12854_amd import meshgen
+    i_sh, n_sh = shard
     sub = uq_subset()
     keys, idx, offs, cells, at, apd, vend = [], [], [0], [], [], [], []
     t0 = time.time()
     for n, (i, sp) in enumerate(sub):
+        if n % n_sh != i_sh:
+            continue
         w = meshgen.uq_workload(sp, 25000)
         keys.append(meshgen.workload_sha256(w))
         s = oracle.Sim(w)
@@ -145,11 +150,38 @@ def make_uq(log):
     info = dict(batch="uq_instances(n=1024, seed=5)", steps=25000, dt=0.02,
                 threads=oracle.num_threads(), seconds=time.time() - t0,
                 oracle_flags=" ".join(oracle.build_flags()), sha256=keys)
-    np.savez_compressed(UQ_FILE, instance=np.array(idx, np.int64),
+    out = UQ_FILE if n_sh == 1 else UQ_FILE.replace(".npz", f".part{i_sh}of{n_sh}.npz")
+    np.savez_compressed(out, instance=np.array(idx, np.int64),
                         offsets=np.array(offs, np.int64), cells=np.concatenate(cells),
                         t_act=np.concatenate(at), apd90=np.concatenate(apd),
                         v_end=np.concatenate(vend), info=json.dumps(info))
-    log(f"uq: wrote {UQ_FILE} ({info['seconds']:.0f} s)")
+    log(f"uq: wrote {out} ({info['seconds']:.0f} s)")
+
+
+def merge_uq(n_sh, log):
+    """The part files of n_sh shards merged into one fixture, instances in
+    the subset's order."""
+    parts = [load(UQ_FILE.replace(".npz", f".part{i}of{n_sh}.npz")) for i in range(n_sh)]
+    rows = []
+    for p in parts:
+        for k, inst in enumerate(p["instance"]):
+            a, b = p["offsets"][k], p["offsets"][k + 1]
+            rows.append((int(inst), p["info"]["sha256"][k], p["cells"][a:b], p["t_act"][a:b],
+                         p["apd90"][a:b], p["v_end"][a:b]))
+    order = {i: n for n, (i, _) in enumerate(uq_subset())}
+    rows.sort(key=lambda r: order[r[0]])
+    offs = np.cumsum([0] + [r[2].size for r in rows])
+    info = dict(batch="uq_instances(n=1024, seed=5)", steps=25000, dt=0.02,
+                threads=sum(p["info"]["threads"] for p in parts),
+                seconds=max(p["info"]["seconds"] for p in parts),
+                oracle_flags=parts[0]["info"]["oracle_flags"], sha256=[r[1] for r in rows],
+                shards=n_sh)
+    np.savez_compressed(UQ_FILE, instance=np.array([r[0] for r in rows], np.int64),
+                        offsets=offs.astype(np.int64), cells=np.concatenate([r[2] for r in rows]),
+                        t_act=np.concatenate([r[3] for r in rows]),
+                        apd90=np.concatenate([r[4] for r in rows]),
+                        v_end=np.concatenate([r[5] for r in rows]), info=json.dumps(info))
+    log(f"uq: merged {n_sh} parts into {UQ_FILE} ({len(rows)} instances)")
 
 
 def load(path):
@@ -162,7 +194,8 @@ def load(path):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=("slab", "uq"))
+    ap.add_argument("which", choices=("slab", "uq", "merge-uq"))
+    ap.add_argument("--shard", default="0/1", help="i/n: the UQ instances k with k % n == i")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--ckpt", default=None,
                     help="directory for a resumable checkpoint of the slab run")
@@ -178,10 +211,13 @@ def main():
     def log(m):
         print(f"[golden] {m}", flush=True)
 
+    i_sh, n_sh = (int(x) for x in a.shard.split("/"))
     if a.which == "slab":
         make_slab(log, a.ckpt)
+    elif a.which == "uq":
+        make_uq(log, (i_sh, n_sh))
     else:
-        make_uq(log)
+        merge_uq(n_sh, log)
 
 
 if __name__ == "__main__":

@@ -36,9 +36,14 @@ def slab(n_steps=300, tol=1e-12, **kw):
     return w
 
 
-def test_bidomain_fp64_parity(ep, oracle_lib):
-    w = slab(restart=20)
-    say(f"bidomain parity: {w.n_tets} tets, random fibres, GMRES(20) to 1e-12")
+@pytest.mark.parametrize("restart", [20, 40])
+def test_bidomain_fp64_parity(ep, oracle_lib, restart):
+    """Both variants of the Arnoldi step against the oracle's plain GMRES:
+    GMRES(20) on this small grid sums the Gram-Schmidt rows inside their
+    consumer kernels (32 basis rows per pass), GMRES(40) (more rows than one
+    pass holds) takes the separate row-sum kernels and 8-row passes."""
+    w = slab(restart=restart)
+    say(f"bidomain parity: {w.n_tets} tets, random fibres, GMRES({restart}) to 1e-12")
     g = ep.Sim(w, prec=ep.EP_FP64)
     o = oracle_lib.Sim(w)
     for chunk in range(3):
@@ -86,3 +91,14 @@ def test_bidomain_checkpoint_and_errors(ep):
     with pytest.raises(ep.EPError) as e:
         mono.phi_e()
     assert e.value.status == ep.EP_ESTATE
+    # the solver's state is staged in LDS: restarts up to 64
+    for restart, ok in ((64, True), (65, False)):
+        x = slab(n_steps=10, restart=restart)
+        if ok:
+            s = ep.Sim(x, prec=ep.EP_FP64)
+            s.step(3)
+            assert np.isfinite(s.phi_e()).all()
+        else:
+            with pytest.raises(ep.EPError) as e:
+                ep.Sim(x, prec=ep.EP_FP64)
+            assert e.value.status == ep.EP_EINVAL

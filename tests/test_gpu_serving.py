@@ -162,6 +162,40 @@ def test_autotuned_schedule_keeps_results(ep):
     sv.close()
 
 
+@pytest.mark.parametrize("which", ["slab", "mixed-substeps", "graph"])
+def test_profiled_steps_keep_results(ep, which):
+    """Steps timed by ep_profile_steps (kernels launched with events set
+    from their own dispatch) are ordinary steps: bitwise the results of
+    plain stepping, on a slab, a mixed tets + triangles mesh whose sheet
+    takes substeps, and a slab with a Purkinje graph; every kernel time is
+    positive and the two kernels fit inside their step."""
+    if which == "slab":
+        w = M.config1(nx=10, ny=8, nz=2)
+    elif which == "mixed-substeps":
+        w = M.mixed_workload(M.config1(n_steps=0, nx=8, ny=6, nz=2),
+                             M.sheet_workload(12, 6, 0.5, model=M.CRN, n_steps=0))
+        w.medium_substeps = 3
+    else:
+        w = M.purkinje_slab()
+    n = 300
+    for prec in (ep.EP_FP32_MIXED, ep.EP_FP64):
+        a = ep.Sim(w, prec=prec)
+        a.step(5)
+        cell_ms, node_ms, per = a.profile_steps(n, per_step=True)
+        b = ep.Sim(w, prec=prec)
+        b.step(5 + n)
+        assert a.time()[0] == b.time()[0] == 5 + n
+        assert np.array_equal(a.vm(), b.vm())
+        assert np.array_equal(a.activation(), b.activation(), equal_nan=True)
+        if which == "graph":
+            assert np.array_equal(a.purkinje_vm(), b.purkinje_vm())
+        assert per.shape == (n,) and (per > 0).all()
+        assert cell_ms > 0 and node_ms > 0
+        assert cell_ms + node_ms <= float(np.median(per)) * 1.01
+        say(f"{which} prec {prec}: cell {cell_ms * 1e3:.1f} us, node {node_ms * 1e3:.1f} us, "
+            f"step p50 {np.median(per) * 1e3:.1f} us")
+
+
 @pytest.mark.parametrize("scheme", [1, 2])
 def test_server_time_scheme_and_cell_junctions(ep, scheme):
     """A server whose requests step with Adams-Bashforth 2 (1) or the
