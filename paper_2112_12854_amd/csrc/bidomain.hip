@@ -34,6 +34,7 @@ using epdev::tix;
 namespace {
 
 constexpr int BT = 256;        // threads per block
+constexpr int NW = BT / 64;    // waves per block
 constexpr int NQ = 8;          // dot products per pass of the reduction kernel
 constexpr int G = kBidoBlocks; // blocks of the reduction kernels
 constexpr int RMAX = kBidoMaxRestart;   // the longest restart the LDS staging holds
@@ -183,23 +184,39 @@ __global__ void __launch_bounds__(BT) k_shift(double *__restrict__ x, const doub
 }
 
 // ---- two-level preconditioner z = omega D^{-1} r + P A_c^{-1} P^T r
-// rc[I] = sum of r over aggregate I (one block per aggregate, fixed order)
+// rc[I] = sum of r over aggregate I (times *rs when given), in a fixed order.
+// WAVE: one wave per aggregate (NW per block; small aggregates), lane l
+// adding cells l, l + 64, ... of its list, then a butterfly; else one block
+// per aggregate (large ones), thread t adding cells t, t + BT, ..., then a
+// tree
+template <bool WAVE>
 __global__ void __launch_bounds__(BT) k_restrict(const double *__restrict__ r,
                                                  const int32_t *__restrict__ off,
                                                  const int32_t *__restrict__ cells,
-                                                 double *__restrict__ rc, const int32_t *stop,
-                                                 const double *rs = nullptr) {
+                                                 double *__restrict__ rc, int32_t na, const int32_t *stop,
+                                                 const double *rs) {
     if (stopped(stop)) return;
-    __shared__ double red[BT];
-    double acc = 0.0;
-    for (int32_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += BT) acc += r[cells[i]];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if constexpr (WAVE) {
+        const int lane = threadIdx.x & 63;
+        const int32_t ag = blockIdx.x * NW + (threadIdx.x >> 6);
+        if (ag >= na) return;
+        double acc = 0.0;
+        for (int32_t i = off[ag] + lane; i < off[ag + 1]; i += 64) acc += r[cells[i]];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) rc[ag] = rs ? *rs * acc : acc;
+    } else {
+        __shared__ double red[BT];
+        double acc = 0.0;
+        for (int32_t i = off[blockIdx.x] + threadIdx.x; i < off[blockIdx.x + 1]; i += BT) acc += r[cells[i]];
+        red[threadIdx.x] = acc;
         __syncthreads();
+        for (int s = BT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) rc[blockIdx.x] = rs ? *rs * red[0] : red[0];
     }
-    if (threadIdx.x == 0) rc[blockIdx.x] = rs ? *rs * red[0] : red[0];
 }
 
 // zc = A_c^{-1} rc (dense, row-major, FP32 entries, FP64 sums; one block per row)
@@ -211,7 +228,19 @@ __global__ void __launch_bounds__(BT) k_coarse(const float *__restrict__ cinv,
     __shared__ double red[BT];
     const float *row = cinv + (int64_t)blockIdx.x * na;
     double acc = 0.0;
-    for (int32_t j = threadIdx.x; j < na; j += BT) acc += (double)row[j] * rc[j];
+    for (int32_t j0 = threadIdx.x; j0 < na; j0 += 8 * BT) {   // 8 loads in flight per lane
+        float c[8];
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t j = min(j0 + k * BT, na - 1);
+            c[k] = row[j];
+            x[k] = rc[j];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (j0 + k * BT < na) acc += (double)c[k] * x[k];
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = BT / 2; s > 0; s >>= 1) {
@@ -376,7 +405,6 @@ __global__ void __launch_bounds__(BT) k_gm_solve(GmView v, int m) {
 // small grids, where the wait is what a pass costs, and R = 8 on large
 // ones, where 32 rows at once would stream from 32 distant ranges of the
 // basis (slower there than 8).
-constexpr int NW = BT / 64;    // waves per block
 constexpr int RB = 32;         // the most rows per pass
 static_assert(NW == 4, "the wave totals are added as (w0 + w1) + (w2 + w3)");
 
@@ -385,6 +413,19 @@ __device__ __forceinline__ double wave_sum(double a) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     return a;
+}
+
+// one exchange step of block_rows: rows [0, 2W) of a become rows [0, W),
+// the lane keeping the half its bit O selects and adding the partner's
+template <int W, int O, int R>
+__device__ __forceinline__ void xstep(double (&a)[R], int lane) {
+    const bool hi = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const double keep = hi ? a[i + W] : a[i];
+        const double give = hi ? a[i] : a[i + W];
+        a[i] = keep + __shfl_xor(give, O, 64);
+    }
 }
 
 // Block partials of R sums at once: a[q] holds the lane's term of row q.
@@ -401,16 +442,11 @@ __device__ __forceinline__ void block_rows(double (&a)[R], int cnt, double *part
     static_assert(R == 8 || R == 16 || R == 32, "R rows over 64 lanes");
     constexpr int G = 64 / R;  // lanes per row at the end
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int w = R / 2, o = 32; w >= 1; w >>= 1, o >>= 1) {
-        const bool hi = (lane & o) != 0;
-#pragma unroll
-        for (int i = 0; i < w; ++i) {
-            const double keep = hi ? a[i + w] : a[i];
-            const double give = hi ? a[i] : a[i + w];
-            a[i] = keep + __shfl_xor(give, o, 64);
-        }
-    }
+    xstep<R / 2, 32>(a, lane);
+    xstep<R / 4, 16>(a, lane);
+    xstep<R / 8, 8>(a, lane);
+    if constexpr (R >= 16) xstep<R / 16, 4>(a, lane);
+    if constexpr (R >= 32) xstep<R / 32, 2>(a, lane);
     double t = a[0];
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
@@ -422,33 +458,63 @@ __device__ __forceinline__ void block_rows(double (&a)[R], int cnt, double *part
     __syncthreads();
 }
 
-// the lane's values of basis rows [q0, q0 + R) at element e (0 past cnt or n)
+// the lane's values of basis rows [q0, q0 + R) at element e (0 past cnt or
+// n; cnt, n >= 1).  The loads themselves are unconditional, from the row and
+// element clamped into range (rows past cnt re-read row cnt - 1 from the
+// cache), so all R of them are in flight at once instead of one branch and
+// one wait per row.
 template <int R>
 __device__ __forceinline__ void load_rows(double (&u)[R], const double *__restrict__ U, int q0,
                                           int cnt, int64_t n, int64_t e) {
+    const int64_t ec = e < n ? e : n - 1;
+    const double me = e < n ? 1.0 : 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q)
-        u[q] = (e < n && q0 + q < cnt) ? U[(int64_t)(q0 + q) * n + e] : 0.0;
+        u[q] = U[(int64_t)min(q0 + q, cnt - 1) * n + ec];
+    // the mask as a product of finite values (every load read real data)
+#pragma unroll
+    for (int q = 0; q < R; ++q) u[q] *= q0 + q < cnt ? me : 0.0;
+}
+
+// the coefficients h_q s_q of rows [q0, q0 + R) (0 past cnt; sc null: h holds
+// the products), loaded the same way
+template <int R>
+__device__ __forceinline__ void load_coef(double (&f)[R], const double *h, const double *__restrict__ sc,
+                                          int q0, int cnt) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int qq = min(q0 + q, cnt - 1);
+        const double x = sc ? h[qq] * sc[qq] : h[qq];
+        f[q] = q0 + q < cnt ? x : 0.0;
+    }
 }
 
 // Row sums of the previous pass inside its consumer (small grids, cnt <=
 // RB rows): thread t adds partials t % 8, t % 8 + 8, ... of row t / 8, then
 // the 8 lanes of the row add by a fixed butterfly, so every block holds the
-// same bits; the sums times the scales go to hs (LDS) and, from block 0, to
-// the global h read by the least-squares update.
+// same bits; the sums times the scales (h_q) go, from block 0, to the global
+// h read by the least-squares update, and h_q s_q to hs (LDS).
 __device__ __forceinline__ void rows_in_block(const double *__restrict__ hp, int64_t np,
                                               const double *__restrict__ sc, int cnt,
                                               double *__restrict__ h, double *hs) {
     const int q = threadIdx.x >> 3, sg = threadIdx.x & 7;
+    const double *p = hp + (int64_t)min(q, cnt - 1) * np;
     double acc = 0.0;
-    if (q < cnt)
-        for (int64_t i = sg; i < np; i += 8) acc += hp[(int64_t)q * np + i];
+    for (int64_t i0 = sg; i0 < np; i0 += 64) {   // 8 loads in flight per lane
+        double x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = p[min(i0 + 8 * k, np - 1)];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (i0 + 8 * k < np) acc += x[k];
+    }
+    if (q >= cnt) acc = 0.0;
     acc += __shfl_xor(acc, 4, 64);
     acc += __shfl_xor(acc, 2, 64);
     acc += __shfl_xor(acc, 1, 64);
     if (sg == 0 && q < cnt) {
         const double v = sc[q] * acc;
-        hs[q] = v;
+        hs[q] = v * sc[q];            // the coefficient h_q s_q of U_q
         if (blockIdx.x == 0) h[q] = v;
     }
     __syncthreads();
@@ -500,18 +566,20 @@ __global__ void __launch_bounds__(BT) k_sub_dots(double *__restrict__ w, const d
     if (stopped(stop)) return;
     __shared__ double red[NW][RB];
     __shared__ double hs[RB];
+    const double *hc = h, *scc = sc;
     if (hp) {
         rows_in_block(hp, gridDim.x, sc, cnt, h, hs);
-        h = hs;
+        hc = hs;
+        scc = nullptr;
     }
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
     double x = e < n ? w[e] : 0.0;
     if (cnt <= R) {                // the rows stay in registers for the dots
-        double u[R];
+        double u[R], f[R];
+        load_coef<R>(f, hc, scc, 0, cnt);
         load_rows<R>(u, U, 0, cnt, n, e);
 #pragma unroll
-        for (int q = 0; q < R; ++q)
-            if (q < cnt) x -= h[q] * sc[q] * u[q];
+        for (int q = 0; q < R; ++q) x -= f[q] * u[q];
         if (e < n) w[e] = x;
 #pragma unroll
         for (int q = 0; q < R; ++q) u[q] *= x;
@@ -519,11 +587,11 @@ __global__ void __launch_bounds__(BT) k_sub_dots(double *__restrict__ w, const d
         return;
     }
     for (int q0 = 0; q0 < cnt; q0 += R) {
-        double u[R];
+        double u[R], f[R];
+        load_coef<R>(f, hc, scc, q0, cnt);
         load_rows<R>(u, U, q0, cnt, n, e);
 #pragma unroll
-        for (int q = 0; q < R; ++q)
-            if (q0 + q < cnt) x -= h[q0 + q] * sc[q0 + q] * u[q];
+        for (int q = 0; q < R; ++q) x -= f[q] * u[q];
     }
     if (e < n) w[e] = x;
     for (int q0 = 0; q0 < cnt; q0 += R) {
@@ -546,18 +614,20 @@ __global__ void __launch_bounds__(BT) k_sub_norm(const double *__restrict__ w, d
     if (stopped(stop)) return;
     __shared__ double red[NW];
     __shared__ double hs[RB];
+    const double *hc = h, *scc = sc;
     if (hp) {
         rows_in_block(hp, gridDim.x, sc, j + 1, h, hs);
-        h = hs;
+        hc = hs;
+        scc = nullptr;
     }
     const int64_t e = blockIdx.x * (int64_t)BT + threadIdx.x;
     double x = e < n ? w[e] : 0.0;
     for (int q0 = 0; q0 <= j; q0 += R) {
-        double u[R];
+        double u[R], f[R];
+        load_coef<R>(f, hc, scc, q0, j + 1);
         load_rows<R>(u, U, q0, j + 1, n, e);
 #pragma unroll
-        for (int q = 0; q < R; ++q)
-            if (q0 + q <= j) x -= h[q0 + q] * sc[q0 + q] * u[q];
+        for (int q = 0; q < R; ++q) x -= f[q] * u[q];
     }
     if (e < n) U[(int64_t)(j + 1) * n + e] = x;
     const double t = wave_sum(e < n ? x * x : 0.0);
@@ -638,10 +708,20 @@ struct Solver {
         k_flux<<<grid_c, BT, 0, st>>>(D.cnode, I.bd.ebeta, D.cnbr, I.bd.eb, x, I.bd.xn, nullptr, 1.0, y, nc,
                                       stop);
     }
+    // rc = P^T r (times *rs): a wave per aggregate up to 128 cells per
+    // aggregate on average, else a block
+    void restrict_(const double *r, const double *rs, const int32_t *stop) {
+        const Bido &B = I.bd;
+        if (nc <= 128 * (int64_t)B.n_agg)
+            k_restrict<true><<<(B.n_agg + NW - 1) / NW, BT, 0, st>>>(r, B.agg_off, B.agg_cells, B.rc, B.n_agg,
+                                                                    stop, rs);
+        else
+            k_restrict<false><<<B.n_agg, BT, 0, st>>>(r, B.agg_off, B.agg_cells, B.rc, B.n_agg, stop, rs);
+    }
     // z = M^{-1} r
     void prec(const double *r, double *z, const int32_t *stop = nullptr) {
         const Bido &B = I.bd;
-        k_restrict<<<B.n_agg, BT, 0, st>>>(r, B.agg_off, B.agg_cells, B.rc, stop);
+        restrict_(r, nullptr, stop);
         k_coarse<<<B.n_agg, BT, 0, st>>>(B.cinv, B.rc, B.zc, B.n_agg, stop);
         k_smooth<<<grid_c, BT, 0, st>>>(r, B.dinv, B.agg_of, B.zc, kOmega, z, nc, stop);
     }
@@ -665,7 +745,7 @@ struct Solver {
             const double *sj = gv.s + j;
             const double *z = uj, *zs = sj;
             if (B.precond) {                     // right preconditioning: z = M^{-1} V_j
-                k_restrict<<<B.n_agg, BT, 0, st>>>(uj, B.agg_off, B.agg_cells, B.rc, stop, sj);
+                restrict_(uj, sj, stop);
                 k_coarse<<<B.n_agg, BT, 0, st>>>(B.cinv, B.rc, B.zc, B.n_agg, stop);
                 k_smooth<<<grid_c, BT, 0, st>>>(uj, B.dinv, B.agg_of, B.zc, kOmega, B.z, nc, stop, sj);
                 z = B.z;
