@@ -59,6 +59,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+FIXED_LAUNCH = None   # (tile cells, steps per graph, XCD remap) from --launch, else autotuned
+
+
 def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_reps=0):
     """One precision on workload w.  The timed region is `steps` steps by
     direct launches on the simulation's stream, each kernel timed by the
@@ -81,7 +84,11 @@ def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_re
     sim.step(warmup)
     # schedule and cell tile shape from the autotuner (its trials are
     # ordinary steps of the same job, before the timed region)
-    tuned = sim.autotune(20)
+    if FIXED_LAUNCH is None:
+        tuned = sim.autotune(20)
+    else:
+        sim.set_launch(*FIXED_LAUNCH)
+        tuned = {"ms_per_step": None}
     sim.sync()
     start_step, _ = sim.time()
     torch.cuda.synchronize()
@@ -646,6 +653,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20000,
                     help="timed steps (default: the slab's whole 400 ms job)")
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--launch", default=None, metavar="TILE,K,REMAP",
+                    help="fix the slab legs' launch (cell tile size, steps per HIP graph, "
+                         "XCD remap 0/1/2) instead of autotuning it")
     ap.add_argument("--chunk", type=int, default=50,
                     help="steps per timed launch (one HIP graph of 50 steps)")
     ap.add_argument("--nx", type=int, default=160)
@@ -685,6 +695,9 @@ def main():
                     help="only run a plain device copy of MIB MiB ten times "
                          "(calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.launch:
+        global FIXED_LAUNCH
+        FIXED_LAUNCH = tuple(int(x) for x in args.launch.split(","))
     if args.copy_calib:
         import torch
         x = torch.ones(args.copy_calib * 2**20 // 4, dtype=torch.float32, device="cuda")
@@ -717,7 +730,13 @@ def main():
     log(f"workload {w.name}: {w.n_tets} tets, {w.n_nodes} nodes ({time.time() - t0:.1f}s)")
 
     if args.only_fp64:
-        run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk)
+        r = run_precision(ep, w, ep.EP_FP64, args.steps, args.warmup, args.chunk)
+        print(json.dumps({"metric": "cell-steps/s (ionic+FV step), FP64 only", "value": r["cell_steps_per_s"],
+                          "unit": "cell-steps/s", "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r["ms_per_step"], "ms_per_step_production": r["graph_ms_per_step"],
+                          "launch": r["launch"], "cell_kernel_ms": r["cell_kernel_ms"],
+                          "node_kernel_ms": r["node_kernel_ms"], "cell_bytes": r["cell_bytes"],
+                          "node_bytes": r["node_bytes"], "config": {"workload": w.name}}), flush=True)
         return
     # the serving and UQ legs first: each starts from the state a serving
     # process starts in (device memory and streams of the slab runs, still

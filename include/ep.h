@@ -362,8 +362,11 @@ ep_status ep_set_state(ep_sim *s, const void *buf, size_t bytes);
 /* Launch controls used by the autotuner: block is the cells (= lanes) of a
  * cell-kernel tile, 64, 128 or 256 (0 keeps the current; node tiles are
  * always 256 nodes), steps_per_graph is the number of steps captured per HIP graph
- * launch (0 = direct launches only), xcd_remap remaps blocks so that each
- * XCD gets a contiguous range of tiles.  May be called any time after
+ * launch (0 = direct launches only), xcd_remap remaps blocks to tiles: 0
+ * none (the hardware deals consecutive blocks to the 8 XCDs in turn), 1 each
+ * XCD one contiguous range of tiles, 2 each XCD every eighth of 32 chunks of
+ * contiguous tiles, 3 none for the cell kernels and the chunks of 2 for
+ * the node gather (EP_EINVAL otherwise).  May be called any time after
  * ep_create(). */
 ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph,
                         int32_t xcd_remap);
@@ -381,15 +384,15 @@ ep_status ep_get_launch(ep_sim *s, int32_t *tile_cells, int32_t *steps_per_graph
 
 /* Launch-schedule autotuner (batched scheduling is this library's, not the
  * paper's).  Tries every graph length in {0 (direct launches), 10, 25, 50,
- * 100} steps, each with and without the XCD tile remap, then at the fastest
+ * 100} steps, each with the XCD tile remaps 0 to 3, then at the fastest
  * of those the cell tile sizes 256, 128 and 64: each candidate one untimed
  * launch (graph capture, warm caches), then trial_steps steps, rounded up to
  * whole graphs, timed with HIP events on the simulation's stream.  Keeps the
  * fastest schedule and tile size (as ep_set_launch / ep_set_tile_size would;
  * ep_get_launch reads them) and reports the schedule; any output pointer may
  * be NULL.  The trials are ordinary steps, with the same results as under
- * any fixed schedule: the simulation advances by 372 steps plus twice the
- * sum over the five graph lengths of their timed steps, plus three times
+ * any fixed schedule: the simulation advances by 744 steps plus four times
+ * the sum over the five graph lengths of their timed steps, plus three times
  * the chosen length's untimed and timed steps.  EP_ESTATE before ep_init, EP_EINVAL for
  * trial_steps <= 0. */
 ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,

@@ -340,8 +340,9 @@ ep_status ep_set_launch(ep_sim *s, int32_t block, int32_t steps_per_graph, int32
     if (block != 0 && block != 64 && block != 128 && block != 256)
         return fail(s, EP_EINVAL, "block must be 0 (keep), 64, 128 or 256");
     if (steps_per_graph < 0) return fail(s, EP_EINVAL, "steps_per_graph must be >= 0");
+    if (xcd_remap < 0 || xcd_remap > 3) return fail(s, EP_EINVAL, "xcd_remap must be 0, 1, 2 or 3");
     s->stepper.steps_per_graph = steps_per_graph;
-    s->stepper.remap = xcd_remap ? 1 : 0;
+    s->stepper.remap = xcd_remap;
     if (block && block != s->stepper.cell_threads) {
         s->stepper.cell_threads = block;
         s->stepper.dirty = true;

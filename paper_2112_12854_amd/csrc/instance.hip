@@ -704,6 +704,14 @@ Tables tables(const Stepper &s) {
 
 int grid_for(int64_t n_tiles) { return (int)std::max<int64_t>(n_tiles, 1); }
 
+// The launch's XCD remap mode as each kernel takes it: modes 0-2 apply to
+// both kernels; mode 3 leaves the cell kernels unremapped (their streams do
+// best with every XCD in one band of tiles) and gives the node gather the
+// chunked ranges of mode 2 (neighbouring node tiles share cells, whose
+// potentials then stay in one L2).
+int cell_remap(int mode) { return mode == 3 ? 0 : mode; }
+int node_remap(int mode) { return mode == 3 ? 2 : mode; }
+
 // Events that a profiled launch sets from the dispatches' own timestamps:
 // `start` at the first kernel's start, `stop` at the last one's end (both
 // null: an ordinary launch, the only kind that graphs capture).
@@ -739,7 +747,7 @@ void launch_cells_v(Stepper &s, const Tables &tb, int32_t off, int32_t sub = -1,
     auto go = [&](void (*kern)(Tables, int32_t, int, int32_t), int k) {
         if (cnt[k])
             launch_k(kern, (int)cnt[k], B, st, k == first ? sp.start : nullptr,
-                     k == last ? sp.stop : nullptr, t[k], off, s.remap, sub);
+                     k == last ? sp.stop : nullptr, t[k], off, cell_remap(s.remap), sub);
     };
     go(k_cell<R, 1, BIDO, SCH>, 0);
     go(k_cell<R, 2, BIDO, SCH>, 1);
@@ -765,12 +773,12 @@ void launch_gather(Stepper &s, const Tables &tb, int32_t off, Span sp = {}) {
     if constexpr (sizeof(R) == 8) {
         if (s.bido) {
             launch_k(k_node_gather<R, true>, s.grid_node, TILE, s.stream, sp.start, sp.stop, tb, off,
-                     s.remap, -1);
+                     node_remap(s.remap), -1);
             return;
         }
     }
     launch_k(k_node_gather<R, false>, s.grid_node, TILE, s.stream, sp.start, sp.stop, tb, off,
-             s.remap, -1);
+             node_remap(s.remap), -1);
 }
 
 // The substeps of step offset `off` of the 2D media that have them, on
@@ -784,7 +792,7 @@ void launch_medium2(Stepper &s, int32_t off, hipStream_t st) {
     Tables tn = tb;
     tn.node_tiles = tb.node_tiles + s.nt2_base;
     for (int32_t q = 0; q < s.sub2_max; ++q) {
-        k_node_gather<R, false><<<(int)s.n_nt2, TILE, 0, st>>>(tn, off, s.remap, q);
+        k_node_gather<R, false><<<(int)s.n_nt2, TILE, 0, st>>>(tn, off, node_remap(s.remap), q);
         if (s.scheme == 2) launch_cells_v<R, false, 2>(s, tb, off, q, st);
         else if (s.scheme == 1) launch_cells_v<R, false, 1>(s, tb, off, q, st);
         else launch_cells_v<R, false, 0>(s, tb, off, q, st);
@@ -1107,7 +1115,7 @@ std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
     out = TuneResult();
     double best = HUGE_VAL;
     std::string err;
-    for (int32_t remap = 0; remap <= 1 && err.empty(); ++remap)
+    for (int32_t remap = 0; remap <= 3 && err.empty(); ++remap)
         for (int32_t k : kGraph) {
             if (k == 0 && !allow_direct) continue;
             s.steps_per_graph = k;

@@ -209,8 +209,25 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Remap 2: the contiguous ranges of remap 1 taken over chunks of tiles
+// instead of tiles: the first 8 R whole chunks (R per XCD, kXcdChunks = 8 R
+// chunks of nb / (8 R) tiles) are transposed so that XCD x works on chunks
+// x, x + 8, x + 16, ... spread over the whole tile range (the work of a
+// region that costs more per cell is shared by all XCDs), each chunk still
+// a contiguous range whose neighbour data stays in that XCD's L2; tiles
+// past the whole chunks keep their place.  A bijection of [0, nb).
+constexpr int kXcdRows = 4;
+__device__ __forceinline__ int64_t chunk_tile(int64_t t, int64_t nb) {
+    const int64_t K = nb / (8 * kXcdRows);          // tiles per chunk
+    if (K == 0 || t >= 8 * kXcdRows * K) return t;
+    const int64_t c = t / K, o = t - c * K;
+    return ((c % kXcdRows) * 8 + c / kXcdRows) * K + o;
+}
+
 __device__ __forceinline__ int64_t my_tile(int remap) {
-    return remap ? xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    if (remap == 0) return (int64_t)blockIdx.x;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    return remap == 1 ? t : chunk_tile(t, gridDim.x);
 }
 
 __device__ __forceinline__ bool stepping(const Ctrl *ctrl, int32_t off, int64_t &n) {

@@ -687,10 +687,10 @@ ep_status ep_server_get_stats(ep_server *sv, ep_server_stats *st) {
 }
 
 ep_status ep_server_set_launch(ep_server *sv, int32_t steps_per_graph, int32_t xcd_remap) {
-    if (!sv || steps_per_graph <= 0) return EP_EINVAL;
+    if (!sv || steps_per_graph <= 0 || xcd_remap < 0 || xcd_remap > 3) return EP_EINVAL;
     std::lock_guard<std::mutex> g(sv->mu);
     sv->want_k = steps_per_graph;           // applied by the driver between launches
-    sv->want_remap = xcd_remap ? 1 : 0;
+    sv->want_remap = xcd_remap;
     return EP_OK;
 }
 

@@ -337,6 +337,36 @@ def test_tile_sizes_bitwise(ep, prec):
             assert np.array_equal(x, y, equal_nan=True), tile
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_xcd_remaps_bitwise(ep, prec):
+    """The block-to-tile remaps are bijections over the tiles: on a slab
+    of 75 cell tiles (300 at 64 cells; the chunked remap transposes its
+    first 64 / 288 tiles and leaves a ragged tail), every remap and tile size
+    gives the same bits, in graphs and direct launches; other remap values
+    are refused."""
+    w = M.config1(n_steps=0, nx=24, ny=20, nz=8)
+    p = ep.EP_FP64 if prec == "fp64" else ep.EP_FP32_MIXED
+    ref = None
+    for remap in (0, 1, 2, 3):
+        for tile, k in ((256, 10), (64, 0)):
+            a = ep.Sim(w, prec=p, trace_every=10)
+            a.set_launch(tile, k, remap)
+            for n in (7, 60, 113):
+                a.step(n)
+            got = (a.vm(), a.activation(), a.mean_vm_trace()[1])
+            assert a.launch() == {"tile_cells": tile, "steps_per_graph": k, "xcd_remap": remap}
+            if ref is None:
+                ref = got
+                assert np.isfinite(got[1]).sum() > 0.1 * w.n_tets
+                continue
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y, equal_nan=True), (remap, tile)
+            a.close()
+    with pytest.raises(ep.EPError) as e:
+        ep.Sim(w, prec=p).set_launch(256, 10, 4)
+    assert e.value.status == ep.EP_EINVAL
+
+
 def test_trace_sample_same_from_host_and_device(ep):
     """A vbar sample taken by the last step issued is added up on the host;
     once the next step runs, the device adds the same partials: both give

@@ -129,7 +129,7 @@ def test_autotuned_schedule_keeps_results(ep):
     a = ep.Sim(w)
     choice = a.autotune(20)
     assert choice["steps_per_graph"] in (0, 10, 25, 50, 100)
-    assert choice["xcd_remap"] in (0, 1) and choice["ms_per_step"] > 0
+    assert choice["xcd_remap"] in (0, 1, 2, 3) and choice["ms_per_step"] > 0
     assert choice["tile_cells"] in (256, 128, 64)
     # per remap: 20 direct steps, then each graph length k in whole graphs
     # (20, 25, 50, 100) after one untimed graph (1 + 10 + 25 + 50 + 100);
@@ -137,11 +137,11 @@ def test_autotuned_schedule_keeps_results(ep):
     # direct step) and whole graphs covering 20 steps
     k = choice["steps_per_graph"]
     shape = (k if k > 0 else 1) + (-(-20 // k) * k if k > 0 else 20)
-    used = 2 * (20 + 20 + 25 + 50 + 100) + 2 * (1 + 10 + 25 + 50 + 100) + 3 * shape
+    used = 4 * (20 + 20 + 25 + 50 + 100) + 4 * (1 + 10 + 25 + 50 + 100) + 3 * shape
     assert a.time()[0] == used
-    a.step(2000 - used)
+    a.step(3000 - used)
     b = ep.Sim(w)
-    b.step(2000)
+    b.step(3000)
     assert np.array_equal(a.vm(), b.vm())
     assert np.array_equal(a.apd90(), b.apd90(), equal_nan=True)
 
