@@ -32,10 +32,13 @@ __global__ void __launch_bounds__(256) k_diff_in(const double *__restrict__ v,
     if (c < nc) vi[c] = R(v[perm[c]]);
 }
 
+// node tiles in the chunked XCD ranges of the step's node gather
+// (neighbouring node tiles share cells, whose potentials then stay in one L2)
 template <typename R>
 __global__ void __launch_bounds__(256) k_diff_nodes(InstDesc D, const R *__restrict__ vi,
                                                      R *__restrict__ vn) {
-    const int64_t node = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t tile = epdev::chunk_tile(epdev::xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
+    const int64_t node = tile * 256 + threadIdx.x;
     if (node < D.nn) vn[node] = epdev::node_value<R>(D, node, vi);
 }
 
