@@ -398,14 +398,15 @@ ep_status ep_get_launch(ep_sim *s, int32_t *tile_cells, int32_t *steps_per_graph
 ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
                       int32_t *xcd_remap, double *ms_per_step);
 
-/* Runs n steps by direct launches with HIP events around every kernel on
- * the simulation's stream, the host waiting only for the step 64 places
- * back (the kernels run back to back, as without the events).  Reports the
- * average device duration (ms) of the fused cell kernel and of the node
- * gather kernel and, when step_ms is not NULL, each step's device time from
- * the start of its first kernel to the end of its last (step_ms holds n
- * doubles, caller-owned).  The steps are ordinary steps of the simulation.
- * Any output pointer may be NULL. */
+/* Runs n steps by direct launches on the simulation's stream, each timed
+ * kernel carrying HIP events that its launch sets from the dispatch's own
+ * start and end (no marker between kernels), the host waiting only for the
+ * step 64 places back (the kernels run back to back, as without the
+ * events).  Reports the average device duration (ms) of the fused cell
+ * kernel(s) and of the node gather kernel and, when step_ms is not NULL,
+ * each step's device time from the start of its first kernel to the end of
+ * its last (step_ms holds n doubles, caller-owned).  The steps are ordinary
+ * steps of the simulation.  Any output pointer may be NULL. */
 ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms,
                            double *node_ms, double *step_ms);
 
