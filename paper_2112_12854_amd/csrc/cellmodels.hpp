@@ -25,12 +25,43 @@ struct GScale {
 };
 
 // --------------------------------------------------------------- helpers
-// FP64: the library exp, expm1, log and sqrt (within an ulp) and the
-// Newton-refined reciprocal below (within an ulp or two).  FP32 (the
+// FP64: exp64 below and the library expm1, log and sqrt (within an ulp),
+// and the Newton-refined reciprocal below (within an ulp or two).  FP32 (the
 // mixed path, whose bar is activation time and APD90): the hardware exp2 / log2 /
 // reciprocal instructions, a few ulp each, which cuts the instruction count
 // of the cell kernel by about a fifth.
-__device__ __forceinline__ double xexp(double x) { return exp(x); }
+
+// e^x in FP64, within about an ulp for |x| < 700 (the model's arguments are
+// voltages over a few mV, tens at most).  Cody and Waite's reduction
+// x = n ln2 + r, |r| <= ln2 / 2, with ln2 split into a 53-bit head (so that
+// the first fused multiply-add is exact) and its tail; e^r from the degree-11
+// Chebyshev fit of e^r on |r| <= ln2 / 2 (truncation error 3.2e-18, well
+// under the rounding of its Horner evaluation), coefficients rounded to
+// FP64; then the scaling by 2^n, whose saturation gives inf and 0 (through
+// the subnormals) at the ends of the range.  The library exp adds range
+// tests with three selects around the same steps: 17 instructions here
+// against 25.  NaN stays NaN; arguments beyond about 1e9 in size are
+// outside its domain.
+__host__ __device__ inline double exp64(double x) {
+    const double n = rint(x * 0x1.71547652b82fep+0);          // x / ln2
+    double r = fma(-n, 0x1.62e42fefa39efp-1, x);              // ln2 head
+    r = fma(-n, 0x1.abc9e3b39803fp-56, r);                    // ln2 tail
+    double p = 0x1.af631d00624dap-26;
+    p = fma(p, r, 0x1.28b4057f4b090p-22);
+    p = fma(p, r, 0x1.71ddf5749d0dcp-19);
+    p = fma(p, r, 0x1.a01991ac87291p-16);
+    p = fma(p, r, 0x1.a01a01b14378fp-13);
+    p = fma(p, r, 0x1.6c16c187fbe02p-10);
+    p = fma(p, r, 0x1.111111110f225p-7);
+    p = fma(p, r, 0x1.555555554f0cfp-5);
+    p = fma(p, r, 0x1.555555555555ap-3);
+    p = fma(p, r, 0x1.0000000000011p-1);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ double xexp(double x) { return exp64(x); }
 __device__ __forceinline__ float xexp(float x) { return __expf(x); }
 __device__ __forceinline__ double xexpm1(double x) { return expm1(x); }
 // e^x - 1 in FP32: below |x| = 1/8 the Taylor series to x^5 (relative
@@ -44,16 +75,19 @@ __device__ __forceinline__ double xlog(double x) { return log(x); }
 __device__ __forceinline__ float xlog(float x) { return __logf(x); }
 __device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float xsqrt(float x) { return sqrtf(x); }
-// FP64 reciprocal: the hardware estimate refined by two Newton steps
-// r <- r + r (1 - x r) (each squares the relative error; within an ulp or
-// two of 1/x), half the instructions of the IEEE division.  Where the
-// refinement is not finite (x = 0, +-inf, NaN, or 1/x beyond the range) the
-// hardware result, which has the IEEE special values there, is kept.
+// FP64 reciprocal: the hardware estimate r0 (relative error e = 1 - x r0
+// below 2^-22) refined by one third-order step r = r0 (1 + e + e^2), which
+// takes the error to e^3 < 2^-66, so that the result is within an ulp of 1/x
+// (the last fused multiply-add's rounding): four instructions, against
+// about ten for the IEEE division.  x = 0 and x = +-inf give NaN (the step
+// forms 0 * inf); every argument here is finite and nonzero (1 + e^z for
+// bounded z, e^{V/k}, sums of positive concentrations), and a cell whose
+// voltage leaves the range where that holds is reported by the step's
+// finiteness check of V.
 __device__ __forceinline__ double xrcp(double x) {
     const double r0 = __builtin_amdgcn_rcp(x);
-    double r = fma(r0, fma(-x, r0, 1.0), r0);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return __builtin_isfinite(r) ? r : r0;
+    const double e = fma(-x, r0, 1.0);
+    return fma(r0, fma(e, e, e), r0);
 }
 __device__ __forceinline__ float xrcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double xpow15(double x) { return pow(x, 1.5); }
@@ -61,8 +95,12 @@ __device__ __forceinline__ float xpow15(float x) { return x * sqrtf(x); }
 __device__ __forceinline__ double xdiv(double a, double b) { return a * xrcp(b); }
 __device__ __forceinline__ float xdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
-// logistic 1 / (1 + e^z)
+// logistic 1 / (1 + e^z).  In FP64 z is capped at 708 so that e^z stays
+// finite for xrcp (the result there is below 1e-307 either way): the
+// calcium-release gates of the CRN model scale a small flux by 1/1.367e-15,
+// and their z passes 709 whenever that flux is slightly negative.
 template <typename R> __device__ __forceinline__ R sig(R z) { return xrcp(R(1) + xexp(z)); }
+template <> __device__ __forceinline__ double sig(double z) { return xrcp(1.0 + xexp(fmin(z, 708.0))); }
 
 // Logistic terms of one voltage scale k from a single exponential:
 // e^{(a - V)/k} = e^{a/k} e^{-V/k} and e^{(V - b)/k} = e^{-b/k} e^{V/k},
@@ -88,7 +126,7 @@ __device__ __forceinline__ R rl(R y, R yinf, R k, R dt) {
 // FP64 has the digits for the plain form, and exp is cheaper than expm1
 template <>
 __device__ __forceinline__ double rl(double y, double yinf, double k, double dt) {
-    return yinf + (y - yinf) * exp(-dt * k);
+    return yinf + (y - yinf) * exp64(-dt * k);
 }
 
 // z / (e^z - 1), continuous at 0
