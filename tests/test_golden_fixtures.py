@@ -46,16 +46,25 @@ def test_slab_fixture_physiology():
     c = g["cells"]
     assert c.size == 100_000 and np.all(np.diff(c) > 0) and c[-1] < w.n_tets
     at, apd, v50, vend = g["t_act"], g["apd90"], g["v_50ms"], g["v_end"]
-    # everything activates within the 400 ms, from the corner outwards
+    # everything activates within the 400 ms, from the corner outwards: the
+    # stimulated cube first (during its pulse), the cells farthest from it
+    # last.  The front is elongated along the fibres, which turn through
+    # 120 degrees across the wall, so Euclidean distance orders activation
+    # only roughly (rank correlation well above 0.8, not near 1).
     assert np.isfinite(at).all() and at.min() >= 0.0 and at.max() < 400.0
-    d = np.linalg.norm(centroids(w, c), axis=1)
+    xyz = centroids(w, c)
+    d = np.linalg.norm(xyz, axis=1)
+    cube = np.all(xyz <= 1.5, axis=1)
+    assert cube.any() and at[cube].max() < 3.0
     rho = np.corrcoef(ranks(d), ranks(at))[0, 1]
-    assert rho > 0.9, rho
-    # apparent speed from the corner to the far cells: between the
-    # transverse and the longitudinal speed of this tissue (0.2-0.8 m/s)
-    far = d > 0.8 * d.max()
-    speed = (d[far] - 1.5) / at[far]            # mm/ms = m/s
-    assert 0.1 < np.median(speed) < 1.0
+    assert rho > 0.8, rho
+    assert d[at >= np.percentile(at, 99)].min() > 0.7 * d.max()
+    # apparent speed from the corner of every cell beyond 5 mm: between the
+    # transverse and the longitudinal conduction speed of ventricular
+    # tissue (0.2-0.8 m/s)
+    far = d > 5.0
+    speed = d[far] / at[far]                    # mm/ms = m/s
+    assert speed.min() > 0.2 and speed.max() < 0.8, (speed.min(), speed.max())
     # APD90 of the cells that repolarise: ventricular TP06 lengths, mid-wall
     # cells longest
     ok = np.isfinite(apd)
