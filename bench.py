@@ -60,15 +60,18 @@ def log(msg):
 
 
 FIXED_LAUNCH = None   # (tile cells, steps per graph, XCD remap) from --launch, else autotuned
+PROFILE_EVERY = 8     # timed region: the kernels of every PROFILE_EVERY-th step carry events
 
 
 def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_reps=0):
     """One precision on workload w.  The timed region is `steps` steps by
-    direct launches on the simulation's stream, each kernel timed by the
-    start and end timestamps of its own dispatch (HIP events set by the
-    launch) and each step by events recorded around it; the queue stays 64
-    steps deep, so the kernels run back to back.  The throughput and the
-    kernel durations of the roofline come from the same window.  Then
+    direct launches on the simulation's stream; the kernels of every
+    PROFILE_EVERY-th step of it are timed by the start and end timestamps of
+    their own dispatch (HIP events set by the launch; the others launch
+    plainly, which keeps the events' own cost out of the throughput); the
+    queue stays at least 64 timed steps deep, so the kernels run back to
+    back.  The throughput and the kernel durations of the roofline come from
+    the same window.  Then
     `lat_steps` more event-timed steps give the per-step latency
     distribution and `diffusion_reps` applications of the diffusion operator
     alone are timed with events on the same stream.  Last, a fresh
@@ -93,7 +96,7 @@ def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_re
     start_step, _ = sim.time()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    cell_ms, node_ms, per = sim.profile_steps(steps, per_step=True)
+    cell_ms, node_ms, per = sim.profile_steps(steps, per_step=True, every=PROFILE_EVERY)
     sim.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -130,7 +133,7 @@ def run_precision(ep, w, prec, steps, warmup, chunk, lat_steps=200, diffusion_re
                 p50_ms=float(np.percentile(lat, 50)),
                 p99_ms=float(np.percentile(lat, 99)),
                 n_latency=int(lat.size),
-                timed_p50_ms=float(np.percentile(per, 50)),
+                timed_p50_ms=float(np.percentile(per, 50)), timed_kernel_steps=int(per.size),
                 cell_kernel_ms=cell_ms, node_kernel_ms=node_ms,
                 cell_bytes=cell_b, node_bytes=node_b,
                 activated=int(np.isfinite(at).sum()), diffusion_op=diff,
@@ -648,6 +651,7 @@ def run_sheet(ep, meshgen, args):
 
 
 def main():
+    global FIXED_LAUNCH, PROFILE_EVERY
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000,
@@ -656,6 +660,9 @@ def main():
     ap.add_argument("--launch", default=None, metavar="TILE,K,REMAP",
                     help="fix the slab legs' launch (cell tile size, steps per HIP graph, "
                          "XCD remap 0/1/2) instead of autotuning it")
+    ap.add_argument("--profile-every", type=int, default=PROFILE_EVERY, metavar="N",
+                    help="time the kernels of every N-th step of the timed region with "
+                         "dispatch events (1: every step)")
     ap.add_argument("--chunk", type=int, default=50,
                     help="steps per timed launch (one HIP graph of 50 steps)")
     ap.add_argument("--nx", type=int, default=160)
@@ -696,8 +703,10 @@ def main():
                          "(calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.launch:
-        global FIXED_LAUNCH
         FIXED_LAUNCH = tuple(int(x) for x in args.launch.split(","))
+    if args.profile_every < 1:
+        sys.exit("--profile-every must be at least 1")
+    PROFILE_EVERY = args.profile_every
     if args.copy_calib:
         import torch
         x = torch.ones(args.copy_calib * 2**20 // 4, dtype=torch.float32, device="cuda")
@@ -817,9 +826,11 @@ def main():
         "config": {"workload": w.name, "n_tets": w.n_tets, "n_nodes": w.n_nodes,
                    "dt_ms": w.dt, "cells": "TP06 endo/mid/epi 30/40/30%",
                    "fibres": "-60..+60 deg transmural + 5 deg jitter"},
-        "timed_region": "direct launches, queue 64 steps deep; each kernel timed by its own "
-                        "dispatch's start and end (HIP events set by the launch), each step by "
-                        "events around it",
+        "timed_region": f"direct launches in the autotuned tile size and XCD remap; the kernels "
+                        f"of every {PROFILE_EVERY}th step ({f32['timed_kernel_steps']} steps) "
+                        f"carry HIP events set from their own dispatch's start and end (the "
+                        f"roofline's kernel durations), the others launch plainly; wall clock "
+                        f"between device synchronisations",
         "timed_from_step": f32["timed_from_step"],
         "launch": f32["launch"],
         "ms_per_step_production": f32["graph_ms_per_step"],

@@ -398,16 +398,19 @@ ep_status ep_get_launch(ep_sim *s, int32_t *tile_cells, int32_t *steps_per_graph
 ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
                       int32_t *xcd_remap, double *ms_per_step);
 
-/* Runs n steps by direct launches on the simulation's stream, each timed
- * kernel carrying HIP events that its launch sets from the dispatch's own
- * start and end (no marker between kernels), the host waiting only for the
- * step 64 places back (the kernels run back to back, as without the
- * events).  Reports the average device duration (ms) of the fused cell
- * kernel(s) and of the node gather kernel and, when step_ms is not NULL,
- * each step's device time from the start of its first kernel to the end of
- * its last (step_ms holds n doubles, caller-owned).  The steps are ordinary
- * steps of the simulation.  Any output pointer may be NULL. */
-ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms,
+/* Runs n steps by direct launches on the simulation's stream.  The
+ * kernels of steps 0, every, 2 every, ... (the timed steps; every = 1 times
+ * them all) carry HIP events that their launch sets from the dispatch's own
+ * start and end (no marker between kernels); the other steps are launched
+ * plainly.  The host waits only for the timed step 64 places back (the
+ * kernels run back to back, as without the events).  Reports the average
+ * device duration (ms) over the timed steps of the fused cell kernel(s) and
+ * of the node gather kernel and, when step_ms is not NULL, each timed
+ * step's device time from the start of its first kernel to the end of its
+ * last (step_ms holds ceil(n / every) doubles, caller-owned).  The steps
+ * are ordinary steps of the simulation.  Any output pointer may be NULL.
+ * EP_EINVAL for n <= 0 or every <= 0, EP_ESTATE before ep_init. */
+ep_status ep_profile_steps(ep_sim *s, int64_t n, int32_t every, double *cell_ms,
                            double *node_ms, double *step_ms);
 
 /* Algorithmic bytes moved per step by the node gather and by the cell

@@ -796,14 +796,15 @@ ep_status ep_autotune(ep_sim *s, int64_t trial_steps, int32_t *steps_per_graph,
     return EP_OK;
 }
 
-ep_status ep_profile_steps(ep_sim *s, int64_t n, double *cell_ms, double *node_ms,
-                           double *step_ms) {
+ep_status ep_profile_steps(ep_sim *s, int64_t n, int32_t every, double *cell_ms,
+                           double *node_ms, double *step_ms) {
     if (!s) return EP_EINVAL;
     if (!s->inited) return fail(s, EP_ESTATE, "ep_init first");
     if (n <= 0) return fail(s, EP_EINVAL, "n must be positive");
+    if (every <= 0) return fail(s, EP_EINVAL, "every must be positive");
     HIP_TRY(s, hipSetDevice(s->opt.device));
     double a = 0, b = 0;
-    std::string e = ep::stepper_profile(s->stepper, n, a, b, step_ms);
+    std::string e = ep::stepper_profile(s->stepper, n, every, a, b, step_ms);
     if (!e.empty()) return fail(s, EP_EDEVICE, e);
     if (cell_ms) *cell_ms = a;
     if (node_ms) *node_ms = b;

@@ -1184,23 +1184,25 @@ std::string stepper_autotune(Stepper &s, int64_t trial_steps, TuneResult &out,
     return err;
 }
 
-std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms,
-                            double *step_ms) {
+std::string stepper_profile(Stepper &s, int64_t n, int64_t every, double &cell_ms,
+                            double &node_ms, double *step_ms) {
     if (s.dirty) {
         std::string e = stepper_sync_tables(s);
         if (!e.empty()) return e;
     }
     const int gn = grid_for(s.n_nt);
     s.grid_node = gn;
-    // A ring of six events per step, all but one set from the dispatches'
-    // own timestamps (so a kernel's time is its execution alone, as a
-    // kernel trace reports it, and no marker packet sits between kernels):
-    // start and end of the node gather and of the cell kernels, and the
-    // end of the step's last kernel; the step starts at the node gather's
-    // start (a recorded event only when the step has no node gather).  The
-    // host waits only for the step RING places back before reusing its
-    // events, so the queue stays RING - 1 steps deep and the kernels run
-    // back to back as in an unprofiled run.
+    // The timed steps are steps 0, every, 2 every, ... of the n (the others
+    // are launched plainly).  A ring of six events per timed step, all but
+    // one set from the dispatches' own timestamps (so a kernel's time is
+    // its execution alone, as a kernel trace reports it, and no marker
+    // packet sits between kernels): start and end of the node gather and of
+    // the cell kernels, and the end of the step's last kernel; the step
+    // starts at the node gather's start (a recorded event only when the
+    // step has no node gather).  The host waits only for the timed step
+    // RING places back before reusing its events, so the queue stays at
+    // least RING - 1 steps deep and the kernels run back to back as in an
+    // unprofiled run.
     constexpr int RING = 64, NE = 6;
     std::vector<hipEvent_t> ev(NE * RING, nullptr);
     for (auto &x : ev)
@@ -1224,14 +1226,18 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
         if (step_ms) step_ms[i] = c;
     };
     const Tables tb = tables(s);
+    const int64_t nt = (n + every - 1) / every;     // timed steps
     for (int64_t i = 0; i < n; ++i) {
-        if (i >= RING) collect(i - RING);
-        hipEvent_t *q = &ev[NE * (i % RING)];
-        if (!gathers) (void)hipEventRecord(q[0], s.stream);
-        if (s.rs == 8) launch_gather<double>(s, tb, 0, Span{q[1], q[2]});
-        else launch_gather<float>(s, tb, 0, Span{q[1], q[2]});
-        if (s.rs == 8) launch_cells<double>(s, tb, 0, Span{q[3], q[4]});
-        else launch_cells<float>(s, tb, 0, Span{q[3], q[4]});
+        const bool timed = i % every == 0;
+        const int64_t j = i / every;
+        if (timed && j >= RING) collect(j - RING);
+        hipEvent_t *q = timed ? &ev[NE * (j % RING)] : nullptr;
+        const Span g = timed ? Span{q[1], q[2]} : Span{}, c = timed ? Span{q[3], q[4]} : Span{};
+        if (timed && !gathers) (void)hipEventRecord(q[0], s.stream);
+        if (s.rs == 8) launch_gather<double>(s, tb, 0, g);
+        else launch_gather<float>(s, tb, 0, g);
+        if (s.rs == 8) launch_cells<double>(s, tb, 0, c);
+        else launch_cells<float>(s, tb, 0, c);
         if (s.rs == 8) launch_medium2<double>(s, 0, s.stream);
         else launch_medium2<float>(s, 0, s.stream);
         if (s.n_pk > 0) {               // one stream here: the timings stay apart
@@ -1240,13 +1246,13 @@ std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node
             if (s.rs == 8) launch_junctions<double>(s, 0);
             else launch_junctions<float>(s, 0);
         }
-        launch_k(k_advance, 1, 256, s.stream, nullptr, q[5], tb, (int64_t)1);
+        launch_k(k_advance, 1, 256, s.stream, nullptr, timed ? q[5] : nullptr, tb, (int64_t)1);
     }
-    for (int64_t i = std::max<int64_t>(0, n - RING); i < n; ++i) collect(i);
+    for (int64_t j = std::max<int64_t>(0, nt - RING); j < nt; ++j) collect(j);
     for (Inst *I : s.insts) I->host_step = std::min(I->host_step + n, std::max(I->host_step, I->target));
     for (auto &x : ev) (void)hipEventDestroy(x);
-    cell_ms = tc / n;
-    node_ms = tn / n;
+    cell_ms = tc / nt;
+    node_ms = tn / nt;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? "" : hip_err("kernel launch", e);
 }

@@ -235,11 +235,12 @@ std::string stepper_sync_tables(Stepper &s);
 // Enqueue k steps of every live instance (graphs for whole multiples of the
 // graph length, direct launches for the rest).  Updates host_step.
 std::string stepper_run(Stepper &s, int64_t k);
-// n steps by direct launches, timed with events (ms): the average node
-// gather and cell kernel durations, and (step_ms non-null) each step's
-// device time from its first launch to the end of its last.
-std::string stepper_profile(Stepper &s, int64_t n, double &cell_ms, double &node_ms,
-                            double *step_ms = nullptr);
+// n steps by direct launches, those of steps 0, every, 2 every, ... timed
+// with events (ms): the average node gather and cell kernel durations over
+// the timed steps, and (step_ms non-null, ceil(n / every) entries) each
+// timed step's device time from its first launch to the end of its last.
+std::string stepper_profile(Stepper &s, int64_t n, int64_t every, double &cell_ms,
+                            double &node_ms, double *step_ms = nullptr);
 
 // Launch-schedule autotuner.  Every candidate (steps per graph launch x XCD
 // tile remap, then the cell tile sizes at the best of those) runs one

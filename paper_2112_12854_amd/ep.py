@@ -155,7 +155,7 @@ _SIGS = {
                                 C.POINTER(C.c_int32)]),
     "ep_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), _dp]),
-    "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, _dp, _dp, _dp]),
+    "ep_profile_steps": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, _dp, _dp, _dp]),
     "ep_algorithmic_bytes": (C.c_int, [C.c_void_p, _dp, _dp, _dp]),
     "ep_last_error": (C.c_char_p, [C.c_void_p]),
     "ep_server_create": (C.c_int, [C.POINTER(ep_options), C.c_size_t, C.c_int32,
@@ -450,12 +450,13 @@ class Sim:
         out["ms_per_step"] = ms.value
         return out
 
-    def profile_steps(self, n: int, per_step: bool = False):
-        """n event-timed steps: (cell kernel ms, node gather ms) averages, and
-        with per_step the device time of every step (ms)."""
+    def profile_steps(self, n: int, per_step: bool = False, every: int = 1):
+        """n steps, those of steps 0, every, 2 every, ... event-timed: (cell
+        kernel ms, node gather ms) averages over the timed steps, and with
+        per_step the device time of every timed step (ms)."""
         a, b = C.c_double(), C.c_double()
-        st = np.empty(int(n)) if per_step else None
-        _check(lib().ep_profile_steps(self.h, int(n), C.byref(a), C.byref(b),
+        st = np.empty((int(n) + int(every) - 1) // int(every)) if per_step and every > 0 else None
+        _check(lib().ep_profile_steps(self.h, int(n), int(every), C.byref(a), C.byref(b),
                                       None if st is None else _d(st)), self.h)
         return (a.value, b.value, st) if per_step else (a.value, b.value)
 

@@ -167,8 +167,10 @@ def test_profiled_steps_keep_results(ep, which):
     """Steps timed by ep_profile_steps (kernels launched with events set
     from their own dispatch) are ordinary steps: bitwise the results of
     plain stepping, on a slab, a mixed tets + triangles mesh whose sheet
-    takes substeps, and a slab with a Purkinje graph; every kernel time is
-    positive and the two kernels fit inside their step."""
+    takes substeps, and a slab with a Purkinje graph, with every step timed
+    and with every third (100 timed steps, more than the ring of 64 events
+    the host cycles through); every kernel time is positive and the two
+    kernels fit inside their step."""
     if which == "slab":
         w = M.config1(nx=10, ny=8, nz=2)
     elif which == "mixed-substeps":
@@ -178,10 +180,11 @@ def test_profiled_steps_keep_results(ep, which):
     else:
         w = M.purkinje_slab()
     n = 300
-    for prec in (ep.EP_FP32_MIXED, ep.EP_FP64):
+    for prec, every in ((ep.EP_FP32_MIXED, 1), (ep.EP_FP64, 1), (ep.EP_FP32_MIXED, 3),
+                        (ep.EP_FP64, 3)):
         a = ep.Sim(w, prec=prec)
         a.step(5)
-        cell_ms, node_ms, per = a.profile_steps(n, per_step=True)
+        cell_ms, node_ms, per = a.profile_steps(n, per_step=True, every=every)
         b = ep.Sim(w, prec=prec)
         b.step(5 + n)
         assert a.time()[0] == b.time()[0] == 5 + n
@@ -189,11 +192,13 @@ def test_profiled_steps_keep_results(ep, which):
         assert np.array_equal(a.activation(), b.activation(), equal_nan=True)
         if which == "graph":
             assert np.array_equal(a.purkinje_vm(), b.purkinje_vm())
-        assert per.shape == (n,) and (per > 0).all()
+        assert per.shape == ((n + every - 1) // every,) and (per > 0).all()
         assert cell_ms > 0 and node_ms > 0
         assert cell_ms + node_ms <= float(np.median(per)) * 1.01
-        say(f"{which} prec {prec}: cell {cell_ms * 1e3:.1f} us, node {node_ms * 1e3:.1f} us, "
-            f"step p50 {np.median(per) * 1e3:.1f} us")
+        say(f"{which} prec {prec} every {every}: cell {cell_ms * 1e3:.1f} us, "
+            f"node {node_ms * 1e3:.1f} us, step p50 {np.median(per) * 1e3:.1f} us")
+        with pytest.raises(ep.EPError):
+            a.profile_steps(10, every=0)
 
 
 @pytest.mark.parametrize("scheme", [1, 2])
