@@ -26,7 +26,7 @@ struct GScale {
 
 // --------------------------------------------------------------- helpers
 // FP64: exp64 below and the library expm1, log and sqrt (within an ulp),
-// and the Newton-refined reciprocal below (within an ulp or two).  FP32 (the
+// and the refined reciprocal below (within an ulp).  FP32 (the
 // mixed path, whose bar is activation time and APD90): the hardware exp2 / log2 /
 // reciprocal instructions, a few ulp each, which cuts the instruction count
 // of the cell kernel by about a fifth.
