@@ -1225,28 +1225,38 @@ std::string stepper_profile(Stepper &s, int64_t n, int64_t every, double &cell_m
         tc += b;
         if (step_ms) step_ms[i] = c;
     };
+    // Steps go out as in enqueue(): at step offsets from the device's step
+    // counter, which one k_advance moves on over the steps launched since the
+    // previous one; here each timed step ends with that advance (its end is
+    // the step's end), and the last step too.
     const Tables tb = tables(s);
     const int64_t nt = (n + every - 1) / every;     // timed steps
+    int64_t pend = 0;                               // steps since the last advance
     for (int64_t i = 0; i < n; ++i) {
         const bool timed = i % every == 0;
         const int64_t j = i / every;
         if (timed && j >= RING) collect(j - RING);
         hipEvent_t *q = timed ? &ev[NE * (j % RING)] : nullptr;
         const Span g = timed ? Span{q[1], q[2]} : Span{}, c = timed ? Span{q[3], q[4]} : Span{};
+        const int32_t off = (int32_t)pend;
         if (timed && !gathers) (void)hipEventRecord(q[0], s.stream);
-        if (s.rs == 8) launch_gather<double>(s, tb, 0, g);
-        else launch_gather<float>(s, tb, 0, g);
-        if (s.rs == 8) launch_cells<double>(s, tb, 0, c);
-        else launch_cells<float>(s, tb, 0, c);
-        if (s.rs == 8) launch_medium2<double>(s, 0, s.stream);
-        else launch_medium2<float>(s, 0, s.stream);
+        if (s.rs == 8) launch_gather<double>(s, tb, off, g);
+        else launch_gather<float>(s, tb, off, g);
+        if (s.rs == 8) launch_cells<double>(s, tb, off, c);
+        else launch_cells<float>(s, tb, off, c);
+        if (s.rs == 8) launch_medium2<double>(s, off, s.stream);
+        else launch_medium2<float>(s, off, s.stream);
         if (s.n_pk > 0) {               // one stream here: the timings stay apart
-            if (s.n_pt > 0 && s.rs == 8) launch_substeps<double>(s, 0, s.stream);
-            else if (s.n_pt > 0) launch_substeps<float>(s, 0, s.stream);
-            if (s.rs == 8) launch_junctions<double>(s, 0);
-            else launch_junctions<float>(s, 0);
+            if (s.n_pt > 0 && s.rs == 8) launch_substeps<double>(s, off, s.stream);
+            else if (s.n_pt > 0) launch_substeps<float>(s, off, s.stream);
+            if (s.rs == 8) launch_junctions<double>(s, off);
+            else launch_junctions<float>(s, off);
         }
-        launch_k(k_advance, 1, 256, s.stream, nullptr, timed ? q[5] : nullptr, tb, (int64_t)1);
+        ++pend;
+        if (timed || i == n - 1) {
+            launch_k(k_advance, 1, 256, s.stream, nullptr, timed ? q[5] : nullptr, tb, pend);
+            pend = 0;
+        }
     }
     for (int64_t j = std::max<int64_t>(0, nt - RING); j < nt; ++j) collect(j);
     for (Inst *I : s.insts) I->host_step = std::min(I->host_step + n, std::max(I->host_step, I->target));
