@@ -25,8 +25,8 @@ struct GScale {
 };
 
 // --------------------------------------------------------------- helpers
-// FP64: exp64 below and the library expm1, log and sqrt (within an ulp),
-// and the refined reciprocal below (within an ulp).  FP32 (the
+// FP64: exp64 and log64 below and the library expm1 and sqrt (within an
+// ulp), and the refined reciprocal below (within an ulp).  FP32 (the
 // mixed path, whose bar is activation time and APD90): the hardware exp2 / log2 /
 // reciprocal instructions, a few ulp each, which cuts the instruction count
 // of the cell kernel by about a fifth.
@@ -61,6 +61,39 @@ __host__ __device__ inline double exp64(double x) {
     return ldexp(p, (int)n);
 }
 
+// ln x in FP64 for positive finite x (NaN for 0, negative, infinite or NaN
+// x; the models take it of concentrations), within an ulp.
+// x = 2^k m with m in [sqrt(1/2), sqrt(2)), u = m - 1 (exact); ln m =
+// 2 atanh f with f = u / (2 + u), |f| <= 0.1716, and 2 atanh f = 2f + f z Q(z),
+// z = f^2, where Q is the degree-6 Chebyshev fit of
+// 2 (atanh(sqrt z) / sqrt z - 1) / z on [0, 0.0295] (its share of the
+// relative error of ln m is 5e-18).  Since 2f = u - f u, ln m = u - f (u - z Q):
+// u carries no rounding and f's rounding enters only the correction, at most
+// a fifth of u.  k ln2 is added with ln2 split into a 42-bit head, whose
+// product with k is exact, and a tail that joins the correction.  About 30
+// instructions, against about 90 for the library log, which carries a
+// double-double evaluation.
+__host__ __device__ inline double log64(double x) {
+    int k;
+    double m = frexp(x, &k);                            // x = m 2^k, m in [1/2, 1)
+    if (m < 0x1.6a09e667f3bcdp-1) { m += m; --k; }      // m in [sqrt(1/2), sqrt(2))
+    const double u = m - 1.0;
+    const double f = u / (2.0 + u);
+    const double z = f * f;
+    double q = 0x1.2b584aaef00b2p-3;
+    q = fma(q, z, 0x1.39fe606539350p-3);
+    q = fma(q, z, 0x1.7462b4ab2f411p-3);
+    q = fma(q, z, 0x1.c71c62e580090p-3);
+    q = fma(q, z, 0x1.2492492df148dp-2);
+    q = fma(q, z, 0x1.99999999952e2p-2);
+    q = fma(q, z, 0x1.5555555555558p-1);
+    const double kd = (double)k;
+    // ln m + k ln2 tail = u - (f (u - z Q) - k ln2 tail), then + k ln2 head
+    const double c = fma(f, fma(-z, q, u), -kd * 0x1.ef35793c76730p-45);
+    const double r = fma(kd, 0x1.62e42fefa3800p-1, u - c);
+    return (x > 0.0 && x < HUGE_VAL) ? r : __builtin_nan("");
+}
+
 __device__ __forceinline__ double xexp(double x) { return exp64(x); }
 __device__ __forceinline__ float xexp(float x) { return __expf(x); }
 __device__ __forceinline__ double xexpm1(double x) { return expm1(x); }
@@ -71,7 +104,7 @@ __device__ __forceinline__ float xexpm1(float x) {
     const float p = x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f)))));
     return fabsf(x) < 0.125f ? p : __expf(x) - 1.0f;
 }
-__device__ __forceinline__ double xlog(double x) { return log(x); }
+__device__ __forceinline__ double xlog(double x) { return log64(x); }
 __device__ __forceinline__ float xlog(float x) { return __logf(x); }
 __device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float xsqrt(float x) { return sqrtf(x); }
@@ -94,6 +127,15 @@ __device__ __forceinline__ double xpow15(double x) { return pow(x, 1.5); }
 __device__ __forceinline__ float xpow15(float x) { return x * sqrtf(x); }
 __device__ __forceinline__ double xdiv(double a, double b) { return a * xrcp(b); }
 __device__ __forceinline__ float xdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// ln(a / b) for a constant a (Nernst potentials): in FP64 ln a (folded at
+// compile time) - ln b, which saves the division.
+template <typename R> __device__ __forceinline__ R lnratio(double a, double b) {
+    return xlog(xdiv(R(a), R(b)));
+}
+template <> __device__ __forceinline__ double lnratio(double a, double b) {
+    return __builtin_log(a) - log64(b);
+}
 
 // logistic 1 / (1 + e^z).  In FP64 z is capped at 708 so that e^z stays
 // finite for xrcp (the result there is below 1e-307 either way): the
@@ -196,10 +238,10 @@ __device__ __forceinline__ R step(int type, R V, R *g, double *c, R dt,
     const R frt = R(1.0 / RTF);
     const double cai = c[0], casr = c[1], cass = c[2], nai = c[3], ki = c[4];
     const R rtf = R(RTF);
-    const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
-    const R EK = rtf * xlog(xdiv(R(KO), R(ki)));
-    const R ECa = R(0.5) * rtf * xlog(xdiv(R(CAO), R(cai)));
-    const R EKs = rtf * xlog(xdiv(R(KO + 0.03 * NAO), R(ki + 0.03 * nai)));
+    const R ENa = rtf * lnratio<R>(NAO, nai);
+    const R EK = rtf * lnratio<R>(KO, ki);
+    const R ECa = R(0.5) * rtf * lnratio<R>(CAO, cai);
+    const R EKs = rtf * lnratio<R>(KO + 0.03 * NAO, ki + 0.03 * nai);
     const R m = g[0], h = g[1], j = g[2], xr1 = g[3], xr2 = g[4], xs = g[5];
     const R r = g[6], s = g[7], d = g[8], f = g[9], f2 = g[10], fcass = g[11];
     const R rbar = g[12];
@@ -392,9 +434,9 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
                                   const GScale &gs, const E &e = E(), R lmi = R(0)) {
     const R frt = R(1.0 / RTF), rtf = R(RTF);
     const double cai = c[0], caup = c[1], carel = c[2], nai = c[3], ki = c[4];
-    const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
-    const R EK = rtf * xlog(xdiv(R(KO), R(ki)));
-    const R ECa = R(0.5) * rtf * xlog(xdiv(R(CAO), R(cai)));
+    const R ENa = rtf * lnratio<R>(NAO, nai);
+    const R EK = rtf * lnratio<R>(KO, ki);
+    const R ECa = R(0.5) * rtf * lnratio<R>(CAO, cai);
     const R m = g[0], h = g[1], j = g[2], oa = g[3], oi = g[4], ua = g[5], ui = g[6];
     const R xr = g[7], xs = g[8], d = g[9], f = g[10], fca = g[11];
     const R u = g[12], vv = g[13], w = g[14];
@@ -571,10 +613,10 @@ __device__ __forceinline__ R step(R V, R *g, double *c, R dt, double dtd,
                                   R istim, const GScale &gs, const E &e = E(), R lmi = R(0)) {
     const R frt = R(1.0 / RTF), rtf = R(RTF);
     const double rbar = c[0], cai = c[1], casr = c[2], cass = c[3], nai = c[4], ki = c[5];
-    const R ENa = rtf * xlog(xdiv(R(NAO), R(nai)));
-    const R EK = rtf * xlog(xdiv(R(KO), R(ki)));
-    const R ECa = R(0.5) * rtf * xlog(xdiv(R(CAO), R(cai)));
-    const R EKs = rtf * xlog(xdiv(R(KO + 0.03 * NAO), R(ki + 0.03 * nai)));
+    const R ENa = rtf * lnratio<R>(NAO, nai);
+    const R EK = rtf * lnratio<R>(KO, ki);
+    const R ECa = R(0.5) * rtf * lnratio<R>(CAO, cai);
+    const R EKs = rtf * lnratio<R>(KO + 0.03 * NAO, ki + 0.03 * nai);
     const R m = g[0], h = g[1], j = g[2], xr1 = g[3], xr2 = g[4], xs = g[5];
     const R r = g[6], s = g[7], d = g[8], f = g[9], f2 = g[10], fcass = g[11];
     const R y = g[12];
